@@ -1,0 +1,226 @@
+"""Plain FP64 CPU oracle for the Moebius domain-wall operator and its red/black CG.
+
+TEST INFRASTRUCTURE ONLY: the product package never imports this module.  Only
+the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` use it.  It shares no code with the HIP path.
+
+The arithmetic lives in ``mobius_oracle.c`` (plain C, FP64, natural layout);
+this module only loads it with ctypes and marshals numpy arrays.  See
+``mobius_oracle.h`` for the layouts and sign conventions.
+"""
+from __future__ import annotations
+
+import contextlib
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mobius_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+               "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32 * 4), ("Ls", ctypes.c_int32), ("M5", ctypes.c_double),
+                ("mf", ctypes.c_double), ("b5", ctypes.c_double), ("c5", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("rel_resid", ctypes.c_double), ("true_resid", ctypes.c_double)]
+
+
+def _bind(path):
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER(_Params)
+    vp = ctypes.c_void_p
+    L.orc_num_threads.restype = ctypes.c_int
+    L.orc_wilson.argtypes = [P, vp, vp, vp, ctypes.c_int]
+    L.orc_dw.argtypes = [P, vp, vp, vp, ctypes.c_int]
+    L.orc_dw_sites.argtypes = [P, vp, vp, ctypes.c_int, ctypes.c_int64, vp, vp, ctypes.c_int]
+    L.orc_hop.argtypes = [P, vp, ctypes.c_int, vp, vp, ctypes.c_int]
+    L.orc_m5.argtypes = [P, vp, vp, vp, ctypes.c_int]
+    L.orc_m5inv.argtypes = [P, vp, vp, ctypes.c_int]
+    L.orc_schur.argtypes = [P, vp, vp, vp, ctypes.c_int]
+    L.orc_cgls.argtypes = [P, vp, ctypes.c_int, vp, vp, ctypes.c_double, ctypes.c_int32,
+                           ctypes.POINTER(_Info)]
+    L.orc_solve.argtypes = [P, vp, vp, vp, ctypes.c_double, ctypes.c_int32,
+                            ctypes.POINTER(_Info)]
+    for f in ("orc_wilson", "orc_dw", "orc_dw_sites", "orc_hop", "orc_m5", "orc_m5inv",
+              "orc_schur", "orc_cgls", "orc_solve"):
+        getattr(L, f).restype = None
+    return L
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _lib = _bind(_LIB_PATH)
+    return _lib
+
+
+@contextlib.contextmanager
+def using(path):
+    """Temporarily route every oracle call through another build of the same
+    source (used by the tests that plant a mistake in a copy of the oracle)."""
+    global _lib
+    saved = _lib
+    _lib = _bind(path)
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
+@dataclass(frozen=True)
+class Params:
+    """Operator parameters: dims (Lx,Ly,Lz,Lt), Ls, M5 (> 0), mf, b5, c5."""
+    dims: tuple
+    Ls: int
+    M5: float
+    mf: float
+    b5: float
+    c5: float
+
+    def c(self) -> _Params:
+        return _Params((ctypes.c_int32 * 4)(*self.dims), self.Ls, self.M5, self.mf, self.b5, self.c5)
+
+    @property
+    def V(self) -> int:
+        return int(np.prod(self.dims))
+
+    def shape5(self):
+        Lx, Ly, Lz, Lt = self.dims
+        return (self.Ls, Lt, Lz, Ly, Lx, 4, 3)
+
+    def shape4(self):
+        Lx, Ly, Lz, Lt = self.dims
+        return (Lt, Lz, Ly, Lx, 4, 3)
+
+    def link_shape(self):
+        Lx, Ly, Lz, Lt = self.dims
+        return (4, Lt, Lz, Ly, Lx, 3, 3)
+
+
+@dataclass
+class Info:
+    iters: int
+    converged: bool
+    rel_resid: float
+    true_resid: float
+
+
+def _c128(a):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def wilson(p: Params, U, psi4, dag=False):
+    U, psi4 = _c128(U), _c128(psi4)
+    out = np.empty_like(psi4)
+    lib().orc_wilson(ctypes.byref(p.c()), _ptr(U), _ptr(psi4), _ptr(out), int(dag))
+    return out
+
+
+def dw(p: Params, U, psi, dag=False):
+    U, psi = _c128(U), _c128(psi)
+    out = np.empty_like(psi)
+    lib().orc_dw(ctypes.byref(p.c()), _ptr(U), _ptr(psi), _ptr(out), int(dag))
+    return out
+
+
+def dw_sites(p: Params, U, psi, sites, in_parity=-1, dag=False):
+    """D_DW psi (or D_DW^+ psi) at the listed canonical 4d site indices -> [n][Ls][4][3]."""
+    U, psi = _c128(U), _c128(psi)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.empty((len(sites), p.Ls, 4, 3), np.complex128)
+    lib().orc_dw_sites(ctypes.byref(p.c()), _ptr(U), _ptr(psi), int(in_parity), len(sites),
+                       _ptr(sites), _ptr(out), int(dag))
+    return out
+
+
+def hop(p: Params, U, psi, out_parity, dag=False):
+    U, psi = _c128(U), _c128(psi)
+    out = np.empty_like(psi)
+    lib().orc_hop(ctypes.byref(p.c()), _ptr(U), int(out_parity), _ptr(psi), _ptr(out), int(dag))
+    return out
+
+
+def m5(p: Params, U, psi, dag=False):
+    U, psi = _c128(U), _c128(psi)
+    out = np.empty_like(psi)
+    lib().orc_m5(ctypes.byref(p.c()), _ptr(U), _ptr(psi), _ptr(out), int(dag))
+    return out
+
+
+def m5inv(p: Params, psi, dag=False):
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    lib().orc_m5inv(ctypes.byref(p.c()), _ptr(psi), _ptr(out), int(dag))
+    return out
+
+
+def schur(p: Params, U, psi, dag=False):
+    U, psi = _c128(U), _c128(psi)
+    out = np.empty_like(psi)
+    lib().orc_schur(ctypes.byref(p.c()), _ptr(U), _ptr(psi), _ptr(out), int(dag))
+    return out
+
+
+def cgls(p: Params, U, b, tol=1e-12, maxiter=10000, which="schur"):
+    U, b = _c128(U), _c128(b)
+    x = np.empty_like(b)
+    info = _Info()
+    lib().orc_cgls(ctypes.byref(p.c()), _ptr(U), 0 if which == "schur" else 1, _ptr(b), _ptr(x),
+                   float(tol), int(maxiter), ctypes.byref(info))
+    return x, Info(info.iters, bool(info.converged), info.rel_resid, info.true_resid)
+
+
+def solve(p: Params, U, eta, tol=1e-12, maxiter=10000):
+    """Red/black solve of D_DW psi = eta; returns (psi, Info) with the true residual."""
+    U, eta = _c128(U), _c128(eta)
+    psi = np.empty_like(eta)
+    info = _Info()
+    lib().orc_solve(ctypes.byref(p.c()), _ptr(U), _ptr(eta), _ptr(psi), float(tol), int(maxiter),
+                    ctypes.byref(info))
+    return psi, Info(info.iters, bool(info.converged), info.rel_resid, info.true_resid)
+
+
+def parity_mask(p: Params):
+    """Boolean [Lt][Lz][Ly][Lx] mask of odd sites ((x+y+z+t) mod 2 == 1)."""
+    Lx, Ly, Lz, Lt = p.dims
+    t, z, y, x = np.meshgrid(np.arange(Lt), np.arange(Lz), np.arange(Ly), np.arange(Lx),
+                             indexing="ij")
+    return ((x + y + z + t) % 2) == 1
+
+
+def restrict(p: Params, psi, parity):
+    """Copy of a 5d field with the sites of the other parity set to zero."""
+    m = parity_mask(p) if parity == 1 else ~parity_mask(p)
+    out = np.array(psi, copy=True)
+    out[:, ~m] = 0
+    return out

@@ -1,0 +1,550 @@
+/*
+ * mobius_oracle.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+ *
+ * Slow and literal on purpose: each function follows one definition of the
+ * paper (cited in its comment), with explicit 4x4 gamma matrices and 3x3 colour
+ * products, no spin projection, no blocking and no fusion.  The only
+ * parallelism is an OpenMP loop over 4d sites.  See mobius_oracle.h for the
+ * layouts and conventions.
+ */
+#include "mobius_oracle.h"
+
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+#define NSPIN 4
+#define NCOL 3
+#define SITE_DOF (NSPIN * NCOL) /* complex numbers per 4d spinor site */
+
+/* ------------------------------------------------------------------------ */
+/* lattice geometry                                                          */
+
+static int64_t vol4(const orc_params *p)
+{
+    return (int64_t)p->L[0] * p->L[1] * p->L[2] * p->L[3];
+}
+
+static void site_coords(const orc_params *p, int64_t i, int c[4])
+{
+    for (int mu = 0; mu < 4; ++mu) {
+        c[mu] = (int)(i % p->L[mu]);
+        i /= p->L[mu];
+    }
+}
+
+static int64_t site_index(const orc_params *p, const int c[4])
+{
+    return (((int64_t)c[3] * p->L[2] + c[2]) * p->L[1] + c[1]) * p->L[0] + c[0];
+}
+
+/* neighbour x + dir * mu-hat with periodic wrap (dir = +1 or -1) */
+static int64_t neighbour(const orc_params *p, int64_t i, int mu, int dir)
+{
+    int c[4];
+    site_coords(p, i, c);
+    c[mu] = (c[mu] + dir + p->L[mu]) % p->L[mu];
+    return site_index(p, c);
+}
+
+static int site_parity(const orc_params *p, int64_t i)
+{
+    int c[4];
+    site_coords(p, i, c);
+    return (c[0] + c[1] + c[2] + c[3]) & 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* gamma matrices, chiral basis                                              */
+
+static cplx gam[4][NSPIN][NSPIN];
+
+static void init_gammas(void)
+{
+    static int done = 0;
+    if (done) return;
+    memset(gam, 0, sizeof(gam));
+    /* Pauli matrices */
+    cplx sig[3][2][2] = {
+        {{0, 1}, {1, 0}},
+        {{0, -I}, {I, 0}},
+        {{1, 0}, {0, -1}},
+    };
+    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                gam[k][a][2 + b] = -I * sig[k][a][b]; /* upper-right block -i sigma_k */
+                gam[k][2 + a][b] = I * sig[k][a][b];  /* lower-left block  +i sigma_k */
+            }
+    for (int a = 0; a < 2; ++a) {
+        gam[3][a][2 + a] = 1;
+        gam[3][2 + a][a] = 1;
+    }
+    done = 1;
+}
+
+/* chirality of spin index: +1 for P+ (spins 0,1), -1 for P- (spins 2,3) */
+static int chirality(int spin) { return spin < 2 ? +1 : -1; }
+
+/* ------------------------------------------------------------------------ */
+/* 4d building blocks                                                        */
+
+/* v[spin][a] = sum_b M[a][b] w[spin][b]   (M = U or U^+) */
+static void colour_mul(const cplx *M, int dagger, const cplx *w, cplx *v)
+{
+    for (int sp = 0; sp < NSPIN; ++sp)
+        for (int a = 0; a < NCOL; ++a) {
+            cplx acc = 0;
+            for (int b = 0; b < NCOL; ++b) {
+                cplx m = dagger ? conj(M[b * NCOL + a]) : M[a * NCOL + b];
+                acc += m * w[sp * NCOL + b];
+            }
+            v[sp * NCOL + a] = acc;
+        }
+}
+
+/* v = (1 + sign * gamma_mu) w */
+static void one_pm_gamma(int mu, double sign, const cplx *w, cplx *v)
+{
+    for (int sp = 0; sp < NSPIN; ++sp)
+        for (int a = 0; a < NCOL; ++a) {
+            cplx acc = w[sp * NCOL + a];
+            for (int sq = 0; sq < NSPIN; ++sq)
+                acc += sign * gam[mu][sp][sq] * w[sq * NCOL + a];
+            v[sp * NCOL + a] = acc;
+        }
+}
+
+/* D_W at one 4d site x.  Wilson operator of Sec. 2 (and App. A):
+ *   D_W psi(x) = (4-M5) psi(x) - 1/2 sum_mu [(1-g_mu) U_mu(x) psi(x+mu)
+ *                                           + (1+g_mu) U_mu(x-mu)^+ psi(x-mu)].
+ * Its adjoint, read off as the conjugate transpose of that matrix (gamma_mu
+ * Hermitian), swaps the two projectors:
+ *   D_W^+ psi(x) = (4-M5) psi(x) - 1/2 sum_mu [(1+g_mu) U_mu(x) psi(x+mu)
+ *                                             + (1-g_mu) U_mu(x-mu)^+ psi(x-mu)]. */
+static void wilson_site(const orc_params *p, const cplx *U, const cplx *in, int64_t x,
+                        cplx *out, int dag)
+{
+    const int64_t V = vol4(p);
+    const double sgn = dag ? -1.0 : 1.0;
+    cplx v[SITE_DOF], w[SITE_DOF];
+    for (int k = 0; k < SITE_DOF; ++k) out[k] = (4.0 - p->M5) * in[x * SITE_DOF + k];
+    for (int mu = 0; mu < 4; ++mu) {
+        int64_t xf = neighbour(p, x, mu, +1);
+        int64_t xb = neighbour(p, x, mu, -1);
+        /* forward hop: (1 - sgn g_mu) U_mu(x) psi(x+mu) */
+        colour_mul(U + ((int64_t)mu * V + x) * 9, 0, in + xf * SITE_DOF, v);
+        one_pm_gamma(mu, -sgn, v, w);
+        for (int k = 0; k < SITE_DOF; ++k) out[k] -= 0.5 * w[k];
+        /* backward hop: (1 + sgn g_mu) U_mu(x-mu)^+ psi(x-mu) */
+        colour_mul(U + ((int64_t)mu * V + xb) * 9, 1, in + xb * SITE_DOF, v);
+        one_pm_gamma(mu, +sgn, v, w);
+        for (int k = 0; k < SITE_DOF; ++k) out[k] -= 0.5 * w[k];
+    }
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_wilson(const orc_params *p, const double *Ud, const double *ind, double *outd, int dag)
+{
+    init_gammas();
+    const cplx *U = (const cplx *)Ud;
+    const cplx *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+    const int64_t V = vol4(p);
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < V; ++x) wilson_site(p, U, in, x, out + x * SITE_DOF, dag);
+}
+
+/* ------------------------------------------------------------------------ */
+/* 5d Moebius operator                                                       */
+
+/* chiral projection of a 4d site vector: keep components of chirality `chi` */
+static void chiral_part(const cplx *w, int chi, double scale, cplx *acc)
+{
+    for (int sp = 0; sp < NSPIN; ++sp)
+        if (chirality(sp) == chi)
+            for (int a = 0; a < NCOL; ++a) acc[sp * NCOL + a] += scale * w[sp * NCOL + a];
+}
+
+/* D_DW at 4d site x for every s.  Row s of the block matrix of Sec. 2.1
+ * (0-based s here):
+ *   out_s = D+ in_s + D- [ P- in_{s+1} + P+ in_{s-1} ],
+ * where the wrapped neighbours carry -m (the corners -m D- P+ at (1,Ls) and
+ * -m D- P- at (Ls,1)).  D+ = b5 D_W + 1, D- = c5 D_W - 1 act on 4d slices, so
+ * D_W is needed on in_s and on the mixed slice w_s at x; they are evaluated
+ * with wilson_site on full slices built on the fly.
+ *
+ * Adjoint: (D^+)_{s,s'} = (D_{s',s})^+.  With y_s = D-^+ in_s:
+ *   out_s = D+^+ in_s + P- y_{s-1} + P+ y_{s+1}   (wraps carry -m). */
+static void dw_site(const orc_params *p, const cplx *U, const cplx *in, int64_t x, cplx *out,
+                    int dag, cplx *slice_buf /* [V][12] scratch */)
+{
+    const int64_t V = vol4(p);
+    const int Ls = p->Ls;
+    cplx t1[SITE_DOF], t2[SITE_DOF];
+    /* the 9 sites D_W at x reads (x and its 8 neighbours) */
+    int64_t nb[9];
+    nb[0] = x;
+    for (int mu = 0; mu < 4; ++mu) {
+        nb[1 + 2 * mu] = neighbour(p, x, mu, +1);
+        nb[2 + 2 * mu] = neighbour(p, x, mu, -1);
+    }
+    for (int s = 0; s < Ls; ++s) {
+        cplx *o = out + (int64_t)s * SITE_DOF;
+        const cplx *ins = in + (int64_t)s * V * SITE_DOF;
+        /* diagonal block D+ (or D+^+) */
+        wilson_site(p, U, ins, x, t1, dag);
+        for (int k = 0; k < SITE_DOF; ++k) o[k] = p->b5 * t1[k] + ins[x * SITE_DOF + k];
+        if (!dag) {
+            /* mixed slice w = P- in_{s+1} + P+ in_{s-1}, needed at the 9 sites */
+            int sp1 = (s + 1) % Ls, sm1 = (s - 1 + Ls) % Ls;
+            double fp1 = (s == Ls - 1) ? -p->mf : 1.0;
+            double fm1 = (s == 0) ? -p->mf : 1.0;
+            for (int j = 0; j < 9; ++j) {
+                cplx *wb = slice_buf + nb[j] * SITE_DOF;
+                memset(wb, 0, sizeof(cplx) * SITE_DOF);
+                chiral_part(in + ((int64_t)sp1 * V + nb[j]) * SITE_DOF, -1, fp1, wb);
+                chiral_part(in + ((int64_t)sm1 * V + nb[j]) * SITE_DOF, +1, fm1, wb);
+            }
+            wilson_site(p, U, slice_buf, x, t2, 0);
+            for (int k = 0; k < SITE_DOF; ++k)
+                o[k] += p->c5 * t2[k] - slice_buf[x * SITE_DOF + k];
+        } else {
+            /* y_{s-1} contributes its P- part, y_{s+1} its P+ part */
+            int sm1 = (s - 1 + Ls) % Ls, sp1 = (s + 1) % Ls;
+            double fm1 = (s == 0) ? -p->mf : 1.0;
+            double fp1 = (s == Ls - 1) ? -p->mf : 1.0;
+            cplx y[SITE_DOF];
+            wilson_site(p, U, in + (int64_t)sm1 * V * SITE_DOF, x, t2, 1);
+            for (int k = 0; k < SITE_DOF; ++k)
+                y[k] = p->c5 * t2[k] - in[((int64_t)sm1 * V + x) * SITE_DOF + k];
+            chiral_part(y, -1, fm1, o);
+            wilson_site(p, U, in + (int64_t)sp1 * V * SITE_DOF, x, t2, 1);
+            for (int k = 0; k < SITE_DOF; ++k)
+                y[k] = p->c5 * t2[k] - in[((int64_t)sp1 * V + x) * SITE_DOF + k];
+            chiral_part(y, +1, fp1, o);
+        }
+    }
+}
+
+/* copy of `in` with the other parity zeroed (in_parity < 0: plain copy) */
+static cplx *masked_copy(const orc_params *p, const cplx *in, int in_parity)
+{
+    const int64_t V = vol4(p);
+    const int64_t n = V * p->Ls * SITE_DOF;
+    cplx *m = (cplx *)malloc(sizeof(cplx) * n);
+    memcpy(m, in, sizeof(cplx) * n);
+    if (in_parity >= 0) {
+        for (int s = 0; s < p->Ls; ++s)
+            for (int64_t x = 0; x < V; ++x)
+                if (site_parity(p, x) != in_parity)
+                    memset(m + ((int64_t)s * V + x) * SITE_DOF, 0, sizeof(cplx) * SITE_DOF);
+    }
+    return m;
+}
+
+void orc_dw_sites(const orc_params *p, const double *Ud, const double *ind, int in_parity,
+                  int64_t nsites, const int64_t *sites, double *outd, int dag)
+{
+    init_gammas();
+    const cplx *U = (const cplx *)Ud;
+    cplx *out = (cplx *)outd;
+    const int64_t V = vol4(p);
+    const int Ls = p->Ls;
+    cplx *in = masked_copy(p, (const cplx *)ind, in_parity);
+#pragma omp parallel
+    {
+        cplx *buf = (cplx *)calloc((size_t)V * SITE_DOF, sizeof(cplx));
+        cplx *tmp = (cplx *)malloc(sizeof(cplx) * Ls * SITE_DOF);
+#pragma omp for schedule(static)
+        for (int64_t k = 0; k < nsites; ++k) {
+            dw_site(p, U, in, sites[k], tmp, dag, buf);
+            memcpy(out + k * Ls * SITE_DOF, tmp, sizeof(cplx) * Ls * SITE_DOF);
+        }
+        free(tmp);
+        free(buf);
+    }
+    free(in);
+}
+
+void orc_dw(const orc_params *p, const double *Ud, const double *ind, double *outd, int dag)
+{
+    init_gammas();
+    const cplx *U = (const cplx *)Ud;
+    const cplx *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+    const int64_t V = vol4(p);
+    const int Ls = p->Ls;
+#pragma omp parallel
+    {
+        cplx *buf = (cplx *)calloc((size_t)V * SITE_DOF, sizeof(cplx));
+        cplx *tmp = (cplx *)malloc(sizeof(cplx) * Ls * SITE_DOF);
+#pragma omp for schedule(static)
+        for (int64_t x = 0; x < V; ++x) {
+            dw_site(p, U, in, x, tmp, dag, buf);
+            for (int s = 0; s < Ls; ++s)
+                memcpy(out + ((int64_t)s * V + x) * SITE_DOF, tmp + s * SITE_DOF,
+                       sizeof(cplx) * SITE_DOF);
+        }
+        free(tmp);
+        free(buf);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* red/black blocks (Sec. 3)                                                 */
+
+static void zero_other_parity(const orc_params *p, cplx *f, int keep_parity)
+{
+    const int64_t V = vol4(p);
+    for (int s = 0; s < p->Ls; ++s)
+        for (int64_t x = 0; x < V; ++x)
+            if (site_parity(p, x) != keep_parity)
+                memset(f + ((int64_t)s * V + x) * SITE_DOF, 0, sizeof(cplx) * SITE_DOF);
+}
+
+static int64_t field_len(const orc_params *p) { return vol4(p) * p->Ls * SITE_DOF; }
+
+/* Off-diagonal block: restrict the input to parity 1-q, apply D (or D^+),
+ * keep parity q of the result.  This is the definition of D_rb / D_br in the
+ * 2x2 block form of Sec. 3. */
+void orc_hop(const orc_params *p, const double *U, int out_parity, const double *ind,
+             double *outd, int dag)
+{
+    cplx *m = masked_copy(p, (const cplx *)ind, 1 - out_parity);
+    orc_dw(p, U, (const double *)m, outd, dag);
+    zero_other_parity(p, (cplx *)outd, out_parity);
+    free(m);
+}
+
+/* Diagonal blocks I_rr = I_bb: the parity-preserving part of D (or D^+). */
+void orc_m5(const orc_params *p, const double *U, const double *ind, double *outd, int dag)
+{
+    const int64_t n = field_len(p);
+    cplx *out = (cplx *)outd;
+    cplx *tmp = (cplx *)malloc(sizeof(cplx) * n);
+    memset(out, 0, sizeof(cplx) * n);
+    for (int q = 0; q < 2; ++q) {
+        cplx *m = masked_copy(p, (const cplx *)ind, q);
+        orc_dw(p, U, (const double *)m, (double *)tmp, dag);
+        zero_other_parity(p, tmp, q);
+        for (int64_t k = 0; k < n; ++k) out[k] += tmp[k];
+        free(m);
+    }
+    free(tmp);
+}
+
+/* Closed-form solves of Sec. 3 with a = M-/M+ and mu = m a (the paper calls
+ * them alpha and M; renamed to avoid clashing with the Moebius alpha and M5).
+ *
+ * A has M+ on the diagonal, M- on the super-diagonal and -m M- at (Ls,1).
+ * A psi = b:  psi_Ls = [b_Ls + mu sum_{s=1}^{Ls-1} (-a)^{s-1} b_s] / (M+ (1 - mu (-a)^{Ls-1})),
+ *             psi_s  = b_s / M+ - a psi_{s+1},   s = Ls-1, ..., 1.
+ * A^T psi = b is the same elimination with rows and columns interchanged
+ * (M- on the sub-diagonal, -m M- at (1,Ls)):
+ *             psi_1  = [b_1 + mu sum_{s=2}^{Ls} (-a)^{Ls-s} b_s] / (M+ (1 - mu (-a)^{Ls-1})),
+ *             psi_s  = b_s / M+ - a psi_{s-1},   s = 2, ..., Ls.
+ * b and psi are strided arrays over s (1-based in the formulas, 0-based here). */
+static void solve_A(const orc_params *p, double Mp, double Mm, const cplx *b, cplx *psi,
+                    int64_t stride, int transpose)
+{
+    const int Ls = p->Ls;
+    const double a = Mm / Mp, mu = p->mf * a;
+    const double denom = Mp * (1.0 - mu * pow(-a, Ls - 1));
+    if (!transpose) {
+        cplx sum = 0;
+        for (int s = 1; s <= Ls - 1; ++s) sum += pow(-a, s - 1) * b[(s - 1) * stride];
+        psi[(Ls - 1) * stride] = (b[(Ls - 1) * stride] + mu * sum) / denom;
+        for (int s = Ls - 1; s >= 1; --s)
+            psi[(s - 1) * stride] = b[(s - 1) * stride] / Mp - a * psi[s * stride];
+    } else {
+        cplx sum = 0;
+        for (int s = 2; s <= Ls; ++s) sum += pow(-a, Ls - s) * b[(s - 1) * stride];
+        psi[0] = (b[0] + mu * sum) / denom;
+        for (int s = 2; s <= Ls; ++s)
+            psi[(s - 1) * stride] = b[(s - 1) * stride] / Mp - a * psi[(s - 2) * stride];
+    }
+}
+
+/* I^{-1} = A^{-1} P- + A^{-T} P+ (Sec. 3), with M+ = b5 (4 - M5) + 1 and
+ * M- = c5 (4 - M5) - 1.  The adjoint I^{-+} = A^{-T} P- + A^{-1} P+ since A is
+ * real.  Applied independently at every 4d site, spin and colour. */
+void orc_m5inv(const orc_params *p, const double *ind, double *outd, int dag)
+{
+    const cplx *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+    const int64_t V = vol4(p);
+    const double Mp = p->b5 * (4.0 - p->M5) + 1.0;
+    const double Mm = p->c5 * (4.0 - p->M5) - 1.0;
+    const int64_t stride = V * SITE_DOF;
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < V; ++x)
+        for (int sp = 0; sp < NSPIN; ++sp)
+            for (int a = 0; a < NCOL; ++a) {
+                int64_t off = x * SITE_DOF + sp * NCOL + a;
+                int minus = chirality(sp) < 0;
+                int transpose = dag ? minus : !minus;
+                solve_A(p, Mp, Mm, in + off, out + off, stride, transpose);
+            }
+}
+
+/* D_pre = 1 - I^{-1} D_oe I^{-1} D_eo on the odd parity (Sec. 3, left
+ * preconditioned Schur complement with red = even, black = odd).
+ * D_pre^+ = 1 - (D_eo)^+ I^{-+} (D_oe)^+ I^{-+}, where (D_eo)^+ is the
+ * odd <- even block of D^+ and (D_oe)^+ its even <- odd block. */
+void orc_schur(const orc_params *p, const double *U, const double *ind, double *outd, int dag)
+{
+    const int64_t n = field_len(p);
+    cplx *t1 = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *t2 = (cplx *)malloc(sizeof(cplx) * n);
+    const cplx *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+    if (!dag) {
+        orc_hop(p, U, 0, ind, (double *)t1, 0);           /* D_eo x      (even) */
+        orc_m5inv(p, (double *)t1, (double *)t2, 0);      /* I^-1        (even) */
+        orc_hop(p, U, 1, (double *)t2, (double *)t1, 0);  /* D_oe        (odd)  */
+        orc_m5inv(p, (double *)t1, (double *)t2, 0);      /* I^-1        (odd)  */
+    } else {
+        cplx *xo = masked_copy(p, in, 1);
+        orc_m5inv(p, (double *)xo, (double *)t1, 1);      /* I^-+        (odd)  */
+        orc_hop(p, U, 0, (double *)t1, (double *)t2, 1);  /* (D_oe)^+    (even) */
+        orc_m5inv(p, (double *)t2, (double *)t1, 1);      /* I^-+        (even) */
+        orc_hop(p, U, 1, (double *)t1, (double *)t2, 1);  /* (D_eo)^+    (odd)  */
+        free(xo);
+    }
+    for (int64_t k = 0; k < n; ++k) out[k] = in[k] - t2[k];
+    zero_other_parity(p, out, 1);
+    free(t1);
+    free(t2);
+}
+
+/* ------------------------------------------------------------------------ */
+/* CGLS                                                                      */
+
+static double norm2(const cplx *v, int64_t n)
+{
+    double s = 0;
+    for (int64_t k = 0; k < n; ++k) s += creal(v[k]) * creal(v[k]) + cimag(v[k]) * cimag(v[k]);
+    return s;
+}
+
+static void apply_op(const orc_params *p, const double *U, int which, const cplx *in, cplx *out,
+                     int dag)
+{
+    if (which == 0)
+        orc_schur(p, U, (const double *)in, (double *)out, dag);
+    else
+        orc_dw(p, U, (const double *)in, (double *)out, dag);
+}
+
+/* Conjugate gradient on the normal equations A^+ A x = A^+ b (CGLS form):
+ *   x = 0, r = b, s = A^+ r, p = s, gamma = |s|^2;
+ *   repeat: q = A p; alpha = gamma/|q|^2; x += alpha p; r -= alpha q;
+ *           s = A^+ r; gamma' = |s|^2; p = s + (gamma'/gamma) p; gamma = gamma'
+ *   until |r| <= tol |b|.  The paper only says "conjugate gradient" (Sec. 4.1). */
+void orc_cgls(const orc_params *p, const double *U, int which, const double *bd, double *xd,
+              double tol, int32_t maxiter, orc_info *info)
+{
+    const int64_t n = field_len(p);
+    const cplx *b = (const cplx *)bd;
+    cplx *x = (cplx *)xd;
+    cplx *r = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *s = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *pv = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *q = (cplx *)malloc(sizeof(cplx) * n);
+    memset(x, 0, sizeof(cplx) * n);
+    memcpy(r, b, sizeof(cplx) * n);
+    apply_op(p, U, which, r, s, 1);
+    memcpy(pv, s, sizeof(cplx) * n);
+    double gamma = norm2(s, n);
+    const double bnorm = sqrt(norm2(b, n));
+    double rnorm = bnorm;
+    int it = 0, conv = 0;
+    if (bnorm == 0.0) conv = 1;
+    while (!conv && it < maxiter) {
+        apply_op(p, U, which, pv, q, 0);
+        const double alpha = gamma / norm2(q, n);
+        for (int64_t k = 0; k < n; ++k) {
+            x[k] += alpha * pv[k];
+            r[k] -= alpha * q[k];
+        }
+        ++it;
+        rnorm = sqrt(norm2(r, n));
+        if (rnorm <= tol * bnorm) {
+            conv = 1;
+            break;
+        }
+        apply_op(p, U, which, r, s, 1);
+        const double gnew = norm2(s, n);
+        const double beta = gnew / gamma;
+        for (int64_t k = 0; k < n; ++k) pv[k] = s[k] + beta * pv[k];
+        gamma = gnew;
+    }
+    if (info) {
+        info->iters = it;
+        info->converged = conv;
+        info->rel_resid = bnorm > 0 ? rnorm / bnorm : 0.0;
+        info->true_resid = -1.0;
+    }
+    free(r);
+    free(s);
+    free(pv);
+    free(q);
+}
+
+/* Red/black solve of D_DW psi = eta through the Schur (LDU) factorisation of
+ * Sec. 3:  b' = I^{-1}(eta_o - D_oe I^{-1} eta_e);  D_pre psi_o = b';
+ *          psi_e = I^{-1}(eta_e - D_eo psi_o). */
+void orc_solve(const orc_params *p, const double *U, const double *etad, double *psid,
+               double tol, int32_t maxiter, orc_info *info)
+{
+    const int64_t n = field_len(p);
+    const cplx *eta = (const cplx *)etad;
+    cplx *psi = (cplx *)psid;
+    cplx *ee = masked_copy(p, eta, 0);
+    cplx *eo = masked_copy(p, eta, 1);
+    cplx *t1 = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *t2 = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *xo = (cplx *)malloc(sizeof(cplx) * n);
+
+    orc_m5inv(p, (double *)ee, (double *)t1, 0);           /* I^-1 eta_e        */
+    orc_hop(p, U, 1, (double *)t1, (double *)t2, 0);       /* D_oe I^-1 eta_e   */
+    for (int64_t k = 0; k < n; ++k) t2[k] = eo[k] - t2[k];
+    orc_m5inv(p, (double *)t2, (double *)t1, 0);           /* b'                */
+    zero_other_parity(p, t1, 1);
+
+    orc_cgls(p, U, 0, (double *)t1, (double *)xo, tol, maxiter, info);
+
+    orc_hop(p, U, 0, (double *)xo, (double *)t2, 0);       /* D_eo psi_o        */
+    for (int64_t k = 0; k < n; ++k) t2[k] = ee[k] - t2[k];
+    orc_m5inv(p, (double *)t2, (double *)t1, 0);           /* psi_e             */
+    zero_other_parity(p, t1, 0);
+    for (int64_t k = 0; k < n; ++k) psi[k] = t1[k] + xo[k];
+
+    /* true residual of the full system */
+    orc_dw(p, U, (double *)psi, (double *)t2, 0);
+    for (int64_t k = 0; k < n; ++k) t2[k] = eta[k] - t2[k];
+    if (info) {
+        double en = sqrt(norm2(eta, n));
+        info->true_resid = en > 0 ? sqrt(norm2(t2, n)) / en : 0.0;
+    }
+    free(ee);
+    free(eo);
+    free(t1);
+    free(t2);
+    free(xo);
+}

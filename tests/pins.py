@@ -1,0 +1,326 @@
+"""Checks that pin the CPU oracle to facts fixed by the paper and by mathematics.
+
+Each pin_* function raises AssertionError on failure.  They are collected as
+tests in test_oracle_pins.py and re-run against deliberately broken builds of
+the oracle in test_oracle_mutants.py (each planted mistake must fail one).
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+import freefield as ff
+from paper_1206_5214_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+def _vdot(a, b):
+    return np.vdot(np.ravel(a), np.ravel(b))
+
+
+def _random_gauge(dims, rng):
+    """Random SU(3) matrix per site, [Lt][Lz][Ly][Lx][3][3]."""
+    Lx, Ly, Lz, Lt = dims
+    A = rng.standard_normal((Lt, Lz, Ly, Lx, 3, 3)) + 1j * rng.standard_normal((Lt, Lz, Ly, Lx, 3, 3))
+    Q, R = np.linalg.qr(A)
+    d = np.diagonal(R, axis1=-2, axis2=-1)
+    Q = Q * (d / np.abs(d))[..., None, :]
+    det = np.linalg.det(Q)
+    return Q / (det ** (1.0 / 3.0))[..., None, None]
+
+
+def _shift(f, mu, dims):
+    """f(x + mu) on the [t][z][y][x] grid (periodic)."""
+    axis = 3 - mu
+    return np.roll(f, -1, axis=axis)
+
+
+def _gauge_transform_links(U, g, dims):
+    """U^g_mu(x) = g(x) U_mu(x) g(x+mu)^+."""
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        gp = _shift(g, mu, dims)
+        Ug[mu] = g @ U[mu] @ np.conj(np.swapaxes(gp, -1, -2))
+    return Ug
+
+
+def _setup(dims, Ls, b5, c5, mf, M5=1.8, eps=0.5, seed=7):
+    from oracle import Params
+    p = Params(tuple(dims), Ls, M5, mf, b5, c5)
+    rng = np.random.default_rng(seed)
+    U = inputs.random_links(dims, eps, rng)
+    return p, U, rng
+
+
+# ---------------------------------------------------------------------------
+# Wilson operator
+
+def pin_wilson_free_symbol(orc):
+    """Unit links: D_W e^{ipx} u = e^{ipx} [(4 - M5 - sum cos p) + i sum g sin p] u (and its adjoint)."""
+    from oracle import Params
+    dims = (4, 2, 6, 8)
+    p = Params(dims, 2, 1.8, 0.1, 1.0, 0.0)
+    U = inputs.unit_links(dims)
+    rng = np.random.default_rng(1)
+    for mom in ff.momenta(dims, rng, 6) + [np.array([np.pi / 2, np.pi, np.pi / 3, np.pi / 4])]:
+        u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+        pw = ff.plane_wave(dims, mom)
+        psi = pw[..., None, None] * u
+        for dag in (False, True):
+            out = orc.wilson(p, U, psi, dag=dag)
+            want = pw[..., None, None] * (ff.wilson_symbol(mom, p.M5, dag) @ u)
+            assert _rel(out, want) < 1e-13, ("wilson free symbol", dag, _rel(out, want))
+
+
+def pin_kernel_bound(orc):
+    """The paper states the Shamir kernel's largest free eigenvalue is (8 - M5)/(10 - M5) ~ 3/4.
+    At p = (pi,pi,pi,pi) the oracle's D_W must be (8 - M5) times the identity."""
+    from oracle import Params
+    with open(os.path.join(GOLDEN, "kernel_bound.json")) as f:
+        g = json.load(f)
+    dims = (4, 4, 4, 4)
+    for M5 in g["M5_values"]:
+        p = Params(dims, 2, M5, 0.1, 1.0, 0.0)
+        U = inputs.unit_links(dims)
+        mom = np.array([np.pi] * 4)
+        pw = ff.plane_wave(dims, mom)
+        rng = np.random.default_rng(2)
+        u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+        out = orc.wilson(p, U, pw[..., None, None] * u)
+        lam = out[0, 0, 0, 0] / u  # site 0 has phase 1
+        assert np.allclose(lam, 8 - M5, rtol=0, atol=1e-12), ("D_W(pi) eigenvalue", M5, lam.ravel()[:3])
+        kernel = (8 - M5) / (10 - M5)
+        assert abs(np.mean(lam).real / (2 + np.mean(lam).real) - kernel) < 1e-12
+        assert abs(kernel - g["lambda_max_approx"]) < g["approx_tol"], (M5, kernel)
+
+
+def pin_gauge_covariance(orc):
+    """D[U^g](g psi) = g D[U] psi for D_W, D_DW and their adjoints."""
+    dims = (4, 2, 2, 4)
+    p, U, rng = _setup(dims, 4, 1.5, 0.5, 0.05)
+    g = _random_gauge(dims, rng)
+    Ug = _gauge_transform_links(U, g, dims)
+    psi5 = inputs.gaussian_spinor(dims, p.Ls, rng)
+    gpsi5 = np.einsum("tzyxab,stzyxkb->stzyxka", g, psi5)
+    for dag in (False, True):
+        a = orc.dw(p, Ug, gpsi5, dag=dag)
+        b = np.einsum("tzyxab,stzyxkb->stzyxka", g, orc.dw(p, U, psi5, dag=dag))
+        assert _rel(a, b) < 1e-13, ("dw gauge covariance", dag, _rel(a, b))
+        a4 = orc.wilson(p, Ug, gpsi5[0], dag=dag)
+        b4 = np.einsum("tzyxab,tzyxkb->tzyxka", g, orc.wilson(p, U, psi5[0], dag=dag))
+        assert _rel(a4, b4) < 1e-13, ("wilson gauge covariance", dag)
+
+
+def pin_wilson_gamma5_hermiticity(orc):
+    """D_W^+ = g5 D_W g5 and <x, D_W y> = <D_W^+ x, y> on random links."""
+    dims = (4, 4, 2, 2)
+    p, U, rng = _setup(dims, 2, 1.0, 0.0, 0.1)
+    x = inputs.gaussian_spinor(dims, 1, rng)[0]
+    y = inputs.gaussian_spinor(dims, 1, rng)[0]
+    g5 = np.diag(ff.G5).real
+    a = orc.wilson(p, U, y, dag=True)
+    b = g5[:, None] * orc.wilson(p, U, g5[:, None] * y)
+    assert _rel(a, b) < 1e-13, ("g5 hermiticity", _rel(a, b))
+    lhs = _vdot(x, orc.wilson(p, U, y))
+    rhs = _vdot(orc.wilson(p, U, x, dag=True), y)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs), ("wilson adjoint", lhs, rhs)
+
+
+# ---------------------------------------------------------------------------
+# 5d operator
+
+def _adjoint_err(orc, A, Adag, x, y):
+    lhs = _vdot(x, A(y))
+    rhs = _vdot(Adag(x), y)
+    return abs(lhs - rhs) / max(abs(lhs), 1e-300)
+
+
+def pin_adjoints(orc):
+    """<x, A y> = <A^+ x, y> for D_DW, the hop blocks, I, I^-1 and D_pre."""
+    dims = (4, 2, 2, 4)
+    p, U, rng = _setup(dims, 5, 1.75, 0.75, 0.07)
+    x = inputs.gaussian_spinor(dims, p.Ls, rng)
+    y = inputs.gaussian_spinor(dims, p.Ls, rng)
+    from oracle import restrict
+    ops = {
+        "dw": (lambda v: orc.dw(p, U, v), lambda v: orc.dw(p, U, v, dag=True), x, y),
+        "m5": (lambda v: orc.m5(p, U, v), lambda v: orc.m5(p, U, v, dag=True), x, y),
+        "m5inv": (lambda v: orc.m5inv(p, v), lambda v: orc.m5inv(p, v, dag=True), x, y),
+        # block (D)_{e,o}: odd -> even; its adjoint is the (D^+)_{o,e} block
+        "hop_eo": (lambda v: orc.hop(p, U, v, 0), lambda v: orc.hop(p, U, v, 1, dag=True),
+                   restrict(p, x, 0), restrict(p, y, 1)),
+        "hop_oe": (lambda v: orc.hop(p, U, v, 1), lambda v: orc.hop(p, U, v, 0, dag=True),
+                   restrict(p, x, 1), restrict(p, y, 0)),
+        "schur": (lambda v: orc.schur(p, U, v), lambda v: orc.schur(p, U, v, dag=True),
+                  restrict(p, x, 1), restrict(p, y, 1)),
+    }
+    for name, (A, Ad, xx, yy) in ops.items():
+        e = _adjoint_err(orc, A, Ad, xx, yy)
+        assert e < 1e-12, ("adjoint", name, e)
+
+
+def _dw_symbol(orc, p, mom):
+    """Extract the 4Ls x 4Ls momentum-space symbol of the oracle's D_DW at unit links."""
+    U = inputs.unit_links(p.dims)
+    pw = ff.plane_wave(p.dims, mom)
+    Ls = p.Ls
+    D = np.zeros((4 * Ls, 4 * Ls), complex)
+    for s0 in range(Ls):
+        for sp0 in range(4):
+            psi = np.zeros(p.shape5(), complex)
+            psi[s0, ..., sp0, 0] = pw
+            out = orc.dw(p, U, psi)
+            D[:, 4 * s0 + sp0] = out[:, 0, 0, 0, 0, :, 0].reshape(-1)
+    return D
+
+
+def _free_cases():
+    from oracle import Params
+    dims = (4, 4, 2, 4)
+    return [Params(dims, 6, 1.8, 0.05, 1.5, 0.5), Params(dims, 5, 1.8, 0.02, 1.0, 0.0),
+            Params(dims, 4, 1.3, 0.1, 1.75, 0.75)]
+
+
+def pin_free_determinant(orc):
+    """det D(m) / det D(1) = det D_ov(m) per momentum (App. A, LDU determinant identity),
+    with D_ov from the polar sign function of the Moebius kernel."""
+    rng = np.random.default_rng(3)
+    for p in _free_cases():
+        from oracle import Params
+        p1 = Params(p.dims, p.Ls, p.M5, 1.0, p.b5, p.c5)
+        for mom in [np.zeros(4)] + ff.momenta(p.dims, rng, 3):
+            Dm = _dw_symbol(orc, p, mom)
+            D1 = _dw_symbol(orc, p1, mom)
+            lhs = np.linalg.det(Dm) / np.linalg.det(D1)
+            rhs = np.linalg.det(ff.overlap_symbol(mom, p.M5, p.b5, p.c5, p.Ls, p.mf))
+            assert abs(lhs - rhs) < 1e-11 * max(1.0, abs(rhs)), ("det identity", p, mom, lhs, rhs)
+
+
+def pin_free_propagator(orc):
+    """[P^+ D(m)^-1 D(1) P]_11 = D_ov(m)^-1 per momentum (Sec. 2.2, propagator matrix)."""
+    rng = np.random.default_rng(4)
+    for p in _free_cases():
+        from oracle import Params
+        p1 = Params(p.dims, p.Ls, p.M5, 1.0, p.b5, p.c5)
+        P = ff.perm_matrix(p.Ls)
+        for mom in [np.zeros(4)] + ff.momenta(p.dims, rng, 2):
+            Dm = _dw_symbol(orc, p, mom)
+            D1 = _dw_symbol(orc, p1, mom)
+            A = np.conj(P.T) @ np.linalg.solve(Dm, D1 @ P)
+            want = np.linalg.inv(ff.overlap_symbol(mom, p.M5, p.b5, p.c5, p.Ls, p.mf))
+            assert _rel(A[:4, :4], want) < 1e-11, ("propagator identity", p, mom)
+            # the rest of the first block row vanishes, the lower-right block is 1
+            assert np.abs(A[:4, 4:]).max() < 1e-11
+            assert np.abs(A[4:, 4:] - np.eye(4 * p.Ls - 4)).max() < 1e-11
+
+
+def _dense(apply, n, shape):
+    M = np.zeros((n, n), complex)
+    for j in range(n):
+        e = np.zeros(n, complex)
+        e[j] = 1
+        M[:, j] = apply(e.reshape(shape)).reshape(-1)
+    return M
+
+
+_DENSE_CACHE = {}
+
+
+def _dense_dw(orc, p, U, key):
+    n = int(np.prod(p.shape5()))
+    k = (key, orc.lib()._name)
+    if k not in _DENSE_CACHE:
+        _DENSE_CACHE.clear()
+        _DENSE_CACHE[k] = _dense(lambda v: orc.dw(p, U, v), n, p.shape5())
+    return _DENSE_CACHE[k]
+
+
+def pin_gamma5_R_hermiticity(orc):
+    """H_DW = g5 R D-^{-1} D_DW is Hermitian (Sec. 2.1, generalised g5-hermiticity)."""
+    dims = (2, 2, 2, 4)
+    p, U, rng = _setup(dims, 4, 1.5, 0.5, 0.05, seed=11)
+    D = _dense_dw(orc, p, U, "g5R")
+    n4 = int(np.prod(p.shape4()))
+    Dw = _dense(lambda v: orc.wilson(p, U, v), n4, p.shape4())
+    Dminus = p.c5 * Dw - np.eye(n4)
+    Ls = p.Ls
+    # 5d index = s * n4 + (site, spin, colour); g5 acts on spin
+    g5 = np.tile(np.repeat(np.diag(ff.G5).real, 3), n4 // 12)
+    Dminv = np.linalg.inv(Dminus)
+    H = np.zeros_like(D)
+    for s in range(Ls):
+        sr = Ls - 1 - s
+        rows = slice(s * n4, (s + 1) * n4)
+        H[rows, :] = g5[:, None] * (Dminv @ D[sr * n4:(sr + 1) * n4, :])
+    err = np.abs(H - np.conj(H.T)).max() / np.abs(H).max()
+    assert err < 1e-12, ("g5 R D-^-1 D hermiticity", err)
+
+
+def pin_m5_block(orc):
+    """The diagonal block of D_DW equals the printed I matrix of Sec. 3 with the
+    corner read as -m M- P+ (Shamir and Moebius), and I I^{-1} = I^{-1} I = 1
+    for the closed-form elimination, with and without dagger."""
+    dims = (2, 2, 2, 2)
+    for (b5, c5, Ls, mf) in [(1.5, 0.5, 6, 0.05), (1.0, 0.0, 5, 0.1), (1.75, 0.75, 8, 0.3)]:
+        p, U, rng = _setup(dims, Ls, b5, c5, mf, seed=5)
+        x = inputs.gaussian_spinor(dims, p.Ls, rng)
+        Mp = b5 * (4 - p.M5) + 1
+        Mm = c5 * (4 - p.M5) - 1
+        # printed matrix, with the corrected (1, Ls) corner
+        Ib = np.zeros((4 * Ls, 4 * Ls))
+        for s in range(Ls):
+            Ib[4 * s:4 * s + 4, 4 * s:4 * s + 4] = Mp * np.eye(4)
+            if s + 1 < Ls:
+                Ib[4 * s:4 * s + 4, 4 * s + 4:4 * s + 8] = Mm * ff.PM.real
+            if s > 0:
+                Ib[4 * s:4 * s + 4, 4 * s - 4:4 * s] = Mm * ff.PP.real
+        Ib[0:4, 4 * Ls - 4:] = -mf * Mm * ff.PP.real
+        Ib[4 * Ls - 4:, 0:4] = -mf * Mm * ff.PM.real
+        want = np.einsum("suSv,Stzyxvc->stzyxuc", Ib.reshape(Ls, 4, Ls, 4), x)
+        got = orc.m5(p, U, x)
+        assert _rel(got, want) < 1e-13, ("I block vs printed matrix", b5, c5, _rel(got, want))
+        for dag in (False, True):
+            y = orc.m5inv(p, orc.m5(p, U, x, dag=dag), dag=dag)
+            assert _rel(y, x) < 1e-13, ("I^-1 I", dag, _rel(y, x))
+            y = orc.m5(p, U, orc.m5inv(p, x, dag=dag), dag=dag)
+            assert _rel(y, x) < 1e-13, ("I I^-1", dag, _rel(y, x))
+
+
+def pin_schur_solve_dense(orc):
+    """Red/black CGLS solution = dense LU solution of D_DW psi = eta (tiny lattice)."""
+    dims = (2, 2, 2, 4)
+    for (b5, c5, Ls, mf, key) in [(1.5, 0.5, 4, 0.05, "g5R"), (1.0, 0.0, 4, 0.01, "shamir")]:
+        p, U, rng = _setup(dims, Ls, b5, c5, mf, seed=11)
+        D = _dense_dw(orc, p, U, key)
+        eta = inputs.gaussian_spinor(dims, Ls, np.random.default_rng(21))
+        want = np.linalg.solve(D, eta.reshape(-1)).reshape(eta.shape)
+        psi, info = orc.solve(p, U, eta, tol=1e-13, maxiter=5000)
+        assert info.converged
+        assert info.true_resid < 1e-11, ("true residual", info)
+        assert _rel(psi, want) < 1e-9, ("schur solve vs dense", key, _rel(psi, want))
+
+
+def pin_rb_equals_unpreconditioned(orc):
+    """Red/black solve equals the unpreconditioned CGLS solution on 4^4 (and the
+    red/black iteration count is lower)."""
+    dims = (4, 4, 4, 4)
+    p, U, rng = _setup(dims, 4, 1.5, 0.5, 0.1, seed=9)
+    eta = inputs.gaussian_spinor(dims, p.Ls, rng)
+    psi_rb, info_rb = orc.solve(p, U, eta, tol=1e-12, maxiter=5000)
+    psi_full, info_full = orc.cgls(p, U, eta, tol=1e-12, maxiter=20000, which="full")
+    assert info_rb.converged and info_full.converged
+    assert _rel(psi_rb, psi_full) < 1e-9, ("rb vs full", _rel(psi_rb, psi_full))
+    assert info_rb.iters < info_full.iters
+
+
+ALL_PINS = [pin_wilson_free_symbol, pin_kernel_bound, pin_gauge_covariance,
+            pin_wilson_gamma5_hermiticity, pin_adjoints, pin_free_determinant,
+            pin_free_propagator, pin_gamma5_R_hermiticity, pin_m5_block, pin_schur_solve_dense,
+            pin_rb_equals_unpreconditioned]

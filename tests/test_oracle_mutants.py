@@ -1,0 +1,62 @@
+"""Plant plausible mistakes in copies of the oracle source and check that the
+pins catch every one (CPU only; the oracle itself is never modified)."""
+import os
+import subprocess
+
+import pytest
+
+import pins
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
+                   "mobius_oracle.c")
+
+# (name, text in the oracle, planted replacement)
+MUTANTS = [
+    ("wilson_mass_sign", "out[k] = (4.0 - p->M5) * in", "out[k] = (4.0 + p->M5) * in"),
+    ("forward_projector", "one_pm_gamma(mu, -sgn, v, w);", "one_pm_gamma(mu, +sgn, v, w);"),
+    ("backward_link_not_daggered", "colour_mul(U + ((int64_t)mu * V + xb) * 9, 1,",
+     "colour_mul(U + ((int64_t)mu * V + xb) * 9, 0,"),
+    ("hop_factor", "out[k] -= 0.5 * w[k];\n        /* backward",
+     "out[k] -= 1.0 * w[k];\n        /* backward"),
+    ("wall_mass_sign", "double fp1 = (s == Ls - 1) ? -p->mf : 1.0;\n            double fm1",
+     "double fp1 = (s == Ls - 1) ? p->mf : 1.0;\n            double fm1"),
+    ("s_coupling_chirality_swapped",
+     "chiral_part(in + ((int64_t)sp1 * V + nb[j]) * SITE_DOF, -1, fp1, wb);\n"
+     "                chiral_part(in + ((int64_t)sm1 * V + nb[j]) * SITE_DOF, +1, fm1, wb);",
+     "chiral_part(in + ((int64_t)sp1 * V + nb[j]) * SITE_DOF, +1, fp1, wb);\n"
+     "                chiral_part(in + ((int64_t)sm1 * V + nb[j]) * SITE_DOF, -1, fm1, wb);"),
+    ("c5_dropped_in_adjoint", "y[k] = p->c5 * t2[k] - in[((int64_t)sm1", "y[k] = 0.0 * t2[k] - in[((int64_t)sm1"),
+    ("m5inv_transpose_swapped", "int transpose = dag ? minus : !minus;",
+     "int transpose = dag ? !minus : minus;"),
+    ("m5inv_corner_mass", "mu = p->mf * a;", "mu = p->mf;"),
+    ("m5inv_power", "sum += pow(-a, s - 1) * b[(s - 1) * stride];",
+     "sum += pow(-a, s) * b[(s - 1) * stride];"),
+    ("Mminus_sign", "const double Mm = p->c5 * (4.0 - p->M5) - 1.0;",
+     "const double Mm = p->c5 * (4.0 - p->M5) + 1.0;"),
+    ("schur_sign", "out[k] = in[k] - t2[k];\n    zero_other_parity(p, out, 1);",
+     "out[k] = in[k] + t2[k];\n    zero_other_parity(p, out, 1);"),
+    ("reconstruct_parity", "orc_hop(p, U, 0, (double *)xo, (double *)t2, 0);       /* D_eo psi_o",
+     "orc_hop(p, U, 1, (double *)xo, (double *)t2, 0);       /* D_eo psi_o"),
+    ("cgls_beta_sign", "pv[k] = s[k] + beta * pv[k];", "pv[k] = s[k] - beta * pv[k];"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(orc, tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not unique/found"
+    mut = tmp_path / "mutant.c"
+    mut.write_text(src.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    hdr_dir = os.path.dirname(SRC)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-I", hdr_dir,
+                    "-o", str(so), str(mut), "-lm"], check=True)
+    caught = None
+    with orc.using(str(so)):
+        for pin in pins.ALL_PINS:
+            try:
+                pin(orc)
+            except AssertionError:
+                caught = pin.__name__
+                break
+    assert caught is not None, f"planted mistake {name} passed every pin"
