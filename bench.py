@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the red/black Moebius CG hot path on one MI355X.
+
+One step = one complete solve of D_DW psi = eta on the 24^3 x 64, Ls = 12
+Moebius workload (b5 = 1.75, c5 = 0.75, M5 = 1.8, mf = 0.005, links
+exp(i 0.6 H), Gaussian source): source preparation, CGLS on the red/black
+Schur operator with an FP16-storage / FP32-arithmetic operator, FP64
+reductions, reliable updates and defect correction, reconstruction and the
+FP64 true-residual check (<= 1e-10).  ms_per_step is the time to solution;
+value is the solve's algorithmic HBM traffic (every field read or written
+once per kernel, links once per hop) divided by that time.
+
+Also reported: the metered hop kernel (D_{p,1-p} = -1/2 H B, Sec. 3) per
+precision against the 8 TB/s HBM roofline, the plain-FP64 and mixed-FP32
+times to solution, and the CPU oracle timed on the host.
+
+Prints exactly one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Möbius Dslash GB/s (% HBM roofline); CG time-to-1e-10: mixed/multi-RHS vs FP64"
+HBM_PEAK_GBS = 8000.0
+PREC_NAMES = {0: "f64", 1: "f32", 2: "f16"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def hop_algo_bytes(op, prec):
+    """In + out half spinors + one parity block of links (8 directions x Vh)."""
+    from paper_1206_5214_amd import mobius
+    link_elem = {mobius.F64: 16, mobius.F32: 8, mobius.F16: 4}[prec]
+    return 2 * op.field_bytes(prec) + 8 * 9 * (op.V // 2) * link_elem
+
+
+def time_hop(torch, op, prec, src_canon, reps):
+    """Average duration of the metered hop kernel, timed with events on the
+    stream the library launches on (torch's current stream)."""
+    from paper_1206_5214_amd import mobius
+    even, odd = op.pack(src_canon, prec)
+    out_e = op.new_field(prec)
+    out_o = op.new_field(prec)
+    for _ in range(5):
+        op.dslash(odd, 0, prec, out=out_e)
+        op.dslash(even, 1, prec, out=out_o)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        op.dslash(odd, 0, prec, out=out_e)
+        op.dslash(even, 1, prec, out=out_o)
+    stop.record()
+    stop.synchronize()
+    ms = start.elapsed_time(stop) / (2 * reps)
+    del even, odd, out_e, out_o
+    return ms
+
+
+def counters_for(kernel_key):
+    """HBM traffic per launch measured with rocprofv3 counters, if they were
+    taken on the current kernel source (profiles/<key>.json records its hash)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_key}.json")
+    src = os.path.join(ROOT, "paper_1206_5214_amd", "csrc", "mobius_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("kernel_source_sha256") != h:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(U, eta, w, sample_frac):
+    """The FP64 oracle's hop block, as it stands, on a bounded sample of the
+    even sites of the same workload; GB/s by the same algorithmic byte count."""
+    import numpy as np
+    import oracle
+    p = oracle.Params(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5)
+    V = w.V
+    Lx, Ly, Lz, Lt = w.dims
+    idx = np.arange(V, dtype=np.int64)
+    x = idx % Lx
+    y = (idx // Lx) % Ly
+    z = (idx // (Lx * Ly)) % Lz
+    t = idx // (Lx * Ly * Lz)
+    even = idx[((x + y + z + t) % 2) == 0]
+    step = max(1, int(round(1.0 / sample_frac)))
+    sites = even[::step]
+    t0 = time.perf_counter()
+    oracle.dw_sites(p, U, eta, sites, in_parity=1)
+    dt = time.perf_counter() - t0
+    # algorithmic bytes of the sampled fraction of one FP64 hop application
+    frac = len(sites) / (V // 2)
+    nbytes = frac * (2 * (V // 2) * w.Ls * 192 + 8 * 9 * (V // 2) * 16)
+    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle hop block D_eo (odd->even) at {len(sites)} of {V // 2} even "
+                      f"4d sites (all Ls={w.Ls} slices) of {Lx}x{Ly}x{Lz}x{Lt}; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mobius_24x24x24x64_ls12")
+    ap.add_argument("--inner", default="f16", choices=["f64", "f32", "f16"])
+    ap.add_argument("--hop-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the FP64 / FP32 comparison solves")
+    ap.add_argument("--cpu-sample", type=float, default=0.5)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the solve of one lattice is not sharded); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1206_5214_amd import inputs, mobius
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = inputs.WORKLOADS[args.workload]
+    inner = mobius.PREC[args.inner]
+    log(f"workload {w.name}: dims {w.dims} Ls {w.Ls}; generating fields (seed {w.seed})")
+    t0 = time.perf_counter()
+    U, eta = inputs.workload_fields(w)
+    log(f"fields ready in {time.perf_counter() - t0:.1f} s")
+    Ud = torch.from_numpy(U).cuda()
+    etad = torch.from_numpy(eta).cuda()
+    op = mobius.Operator(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, Ud)
+    torch.cuda.synchronize()
+
+    # -- metered hop kernel, every precision --------------------------------
+    hop = {}
+    for prec in (mobius.F64, mobius.F32, mobius.F16):
+        ms = time_hop(torch, op, prec, etad, args.hop_reps)
+        nbytes = hop_algo_bytes(op, prec)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        flops = 1416.0 * (op.V // 2) * w.Ls
+        hop[PREC_NAMES[prec]] = {"us": ms * 1e3, "algo_bytes": nbytes, "GBps": gbs,
+                                 "frac_hbm": gbs / HBM_PEAK_GBS,
+                                 "GFLOPps": flops / (ms * 1e-3) / 1e9}
+        log(f"hop {PREC_NAMES[prec]}: {ms * 1e3:.1f} us  {gbs:.0f} GB/s  "
+            f"({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+
+    # -- the step: complete solves to 1e-10 ---------------------------------
+    def solve(prec):
+        sol, info, rc = op.solve(etad, tol=w.tol, maxiter=50000, inner_prec=prec)
+        i = info[0]
+        if rc != mobius.OK or i.true_resid > w.tol:
+            raise RuntimeError(f"solve did not reach {w.tol}: {i}")
+        return sol, i
+
+    for k in range(args.warmup):
+        _, i = solve(inner)
+        log(f"warmup solve {k}: {i.seconds:.3f} s, {i.iters} iters, resid {i.true_resid:.2e}")
+    torch.cuda.synchronize()
+    infos = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        sol, i = solve(inner)
+        infos.append(i)
+        log(f"timed solve {k}: {i.seconds:.3f} s, {i.iters} iters, {i.reliable_updates} reliable "
+            f"updates, true resid {i.true_resid:.2e}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = 1e3 * wall / args.steps
+    algo_bytes = float(np.mean([i.algo_bytes for i in infos]))
+    value = algo_bytes / (ms_per_step * 1e-3) / 1e9
+
+    compare = {}
+    if not args.no_compare:
+        for prec in (mobius.F64, mobius.F32, mobius.F16):
+            if prec == inner:
+                compare[PREC_NAMES[prec]] = {"seconds": ms_per_step * 1e-3,
+                                            "iters": infos[-1].iters,
+                                            "true_resid": infos[-1].true_resid}
+                continue
+            s2, i2 = solve(prec)
+            err = (torch.linalg.vector_norm(s2 - sol) / torch.linalg.vector_norm(s2)).item()
+            compare[PREC_NAMES[prec]] = {"seconds": i2.seconds, "iters": i2.iters,
+                                         "true_resid": i2.true_resid,
+                                         "rel_diff_vs_headline": err}
+            log(f"compare {PREC_NAMES[prec]}: {i2.seconds:.3f} s, {i2.iters} iters, "
+                f"resid {i2.true_resid:.2e}, |diff|/|psi| {err:.2e}")
+            del s2
+        if "f64" in compare:
+            f64s = compare["f64"]["seconds"]
+            for k2, v in compare.items():
+                v["speedup_vs_f64"] = f64s / v["seconds"]
+
+    hname = PREC_NAMES[inner]
+    key = f"hop_{hname}_{args.workload}"
+    traffic = counters_for(key)
+    roofline = {"bound": "hbm", "achieved": hop[hname]["GBps"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": hop[hname]["GBps"] / HBM_PEAK_GBS,
+                "traffic": traffic, "kernel": f"hop_kernel {hname} (D_{{p,1-p}} = -1/2 H B)",
+                "algo_bytes_per_launch": hop[hname]["algo_bytes"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle hop on a sample of the same workload")
+        del op
+        torch.cuda.empty_cache()
+        cpu = cpu_baseline(U, eta, w, args.cpu_sample)
+        log(f"cpu baseline: {cpu['value']:.3f} GB/s on {cpu['cores']} threads ({cpu['sample']})")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if inner != mobius.F64 else "f64",
+        "storage": hname,
+        "data": "synthetic (seeded exp(i eps H) SU(3) links, Gaussian source)",
+        "config": {"workload": w.name, "dims": list(w.dims), "Ls": w.Ls, "M5": w.M5, "mf": w.mf,
+                   "b5": w.b5, "c5": w.c5, "link_eps": w.eps, "seed": w.seed, "tol": w.tol,
+                   "inner_prec": hname, "reductions": "f64"},
+        "solve": {"iters": infos[-1].iters, "reliable_updates": infos[-1].reliable_updates,
+                  "true_resid": infos[-1].true_resid, "algo_bytes": algo_bytes,
+                  "GFLOPps": float(np.mean([i.flops for i in infos])) / (ms_per_step * 1e-3) / 1e9},
+        "hop": hop,
+        "time_to_solution": compare,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

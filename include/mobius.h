@@ -1,0 +1,173 @@
+/*
+ * mobius.h -- C ABI of libmobius.so, the MI355X (gfx950) red/black Moebius
+ * domain-wall operator and its conjugate-gradient solver.
+ *
+ * Operator (Brower, Neff, Orginos, "The Moebius Domain Wall Fermion
+ * Algorithm"): the 5d operator D_DW(m) of Sec. 2.1 (block tridiagonal in s,
+ * diagonal blocks D+ = b5 D_W + 1, off-diagonal D- P-/P+ with D- = c5 D_W - 1,
+ * wall coupling -m D- P+ at (1,Ls) and -m D- P- at (Ls,1)), built on the 4d
+ * Wilson operator of Sec. 2
+ *     D_W psi(x) = (4 - M5) psi(x)
+ *                  - 1/2 sum_mu [(1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^+ psi(x-mu)]
+ * with M5 > 0 the domain-wall height (the paper writes 4 + M5 with M5 = O(-1)).
+ * Gamma matrices are in the chiral basis, g5 = diag(1,1,-1,-1), P+ = spins 0,1.
+ * Periodic boundaries in all four directions.
+ *
+ * Red/black (Sec. 3): 4d parity (x+y+z+t) mod 2, the same for every s.
+ * Parity 0 = even ("red"), parity 1 = odd ("black").  With
+ *     I = M+ + M- C5,  M+ = b5 (4 - M5) + 1,  M- = c5 (4 - M5) - 1,
+ *     (C5 psi)_s = P+ psi_{s-1} + P- psi_{s+1}  (wrapped neighbours carry -m),
+ * the off-diagonal blocks are D_{p,1-p} = -1/2 H_{p,1-p} B with B = b5 + c5 C5
+ * (H the Wilson hopping sum on every s-slice), and the preconditioned operator
+ * on the odd parity is D_pre = 1 - I^{-1} D_oe I^{-1} D_eo.
+ *
+ * Conventions of this ABI
+ *  - All data pointers are DEVICE pointers on the current HIP device; the
+ *    caller owns them.  Nothing here frees caller memory.
+ *  - Canonical layouts (complex128, interleaved re/im):
+ *        links   [mu=x,y,z,t][t][z][y][x][a][b]        U_mu(x), row a, column b
+ *        spinor  [s][t][z][y][x][spin][colour]           s = 0..Ls-1
+ *    Multi-RHS calls add a leading [rhs] index.
+ *  - Packed half-lattice fields ("packed") are private to the library; their
+ *    size in bytes per right-hand side is mobius_field_bytes().  They hold one
+ *    parity of a 5d field in the given storage precision.
+ *  - Every call enqueues its work on `stream` (a hipStream_t, NULL = default
+ *    stream) and returns without synchronising, except mobius_cg_solve which
+ *    synchronises once at the end to fill `info`.
+ *  - Return codes: MOBIUS_OK (0) on success; MOBIUS_NOT_CONVERGED (1) from
+ *    the solver when maxiter is reached (info is still filled); negative codes
+ *    on error, with a message in mobius_last_error().  No call aborts or throws.
+ *  - in == out aliasing is rejected with MOBIUS_EINVAL.
+ */
+#ifndef MOBIUS_H
+#define MOBIUS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MOBIUS_OK 0
+#define MOBIUS_NOT_CONVERGED 1
+#define MOBIUS_EINVAL (-22)
+#define MOBIUS_ENOMEM (-12)
+#define MOBIUS_EHIP (-100)
+
+/* storage precision of packed fields and links */
+typedef enum {
+    MOBIUS_F64 = 0, /* FP64 storage and arithmetic */
+    MOBIUS_F32 = 1, /* FP32 storage and arithmetic */
+    MOBIUS_F16 = 2  /* FP16 storage (spinors scaled by one FP32 max-abs norm per 5d site), FP32 arithmetic */
+} mobius_prec;
+
+/* operator selector for mobius_dslash / mobius_dslash_dag */
+typedef enum {
+    MOBIUS_OP_HOP = 0,   /* off-diagonal block D_{p,1-p} = -1/2 H B: parity 1-p -> p  (Sec. 3) */
+    MOBIUS_OP_M5 = 1,    /* diagonal block I on one half field (parity-independent) (Sec. 3)  */
+    MOBIUS_OP_SCHUR = 2  /* D_pre = 1 - I^-1 D_oe I^-1 D_eo, odd -> odd (out_parity must be 1)  */
+} mobius_op;
+
+typedef struct {
+    int32_t L[4]; /* Lx, Ly, Lz, Lt: each even and >= 2 */
+    int32_t Ls;   /* fifth-dimension extent, 2 <= Ls <= 64 */
+    double M5;    /* domain-wall height (> 0 in this sign convention) */
+    double mf;    /* quark mass m of the wall coupling (0 <= mf <= 1; 1 = Pauli-Villars) */
+    double b5;    /* Moebius b5 (Shamir: 1) */
+    double c5;    /* Moebius c5 (Shamir: 0) */
+} mobius_params;
+
+typedef struct {
+    double tol;            /* target ||eta - D_DW psi|| / ||eta|| (full-system true residual, FP64) */
+    int32_t maxiter;       /* cap on CG iterations (all inner iterations counted) */
+    int32_t inner_prec;    /* mobius_prec of the CG operator: F64 = plain FP64 CGLS; F32/F16 =
+                              low-precision operator with FP64 reductions, reliable updates and
+                              outer defect correction */
+    double reliable_delta; /* reliable update when ||r|| falls below delta * (max ||r|| since the
+                              last update); <= 0 selects 0.1 */
+    int32_t nrhs;          /* number of right-hand sides in src/sol (>= 1) */
+    int32_t check_every;   /* iterations between host convergence checks (<= 0 selects 16) */
+} mobius_solve_opts;
+
+typedef struct {
+    int32_t iters;        /* CGLS iterations */
+    int32_t dirac_apps;   /* hop-kernel applications (4 per CGLS iteration plus source, residual
+                             and reconstruction work) */
+    int32_t reliable_updates;
+    int32_t status;       /* MOBIUS_OK or MOBIUS_NOT_CONVERGED */
+    double true_resid;    /* ||eta - D_DW psi|| / ||eta||, recomputed in FP64 after reconstruction */
+    double schur_resid;   /* ||b' - D_pre psi_o|| / ||b'|| in FP64 */
+    double seconds;       /* wall time of the solve on the stream */
+    double algo_bytes;    /* algorithmic HBM bytes of every kernel the solve launched: each field
+                             read or written once per launch, links once per hop (no neighbour
+                             re-reads, no index tables) */
+    double flops;         /* floating-point operations by the same convention (hop: 1416 per
+                             5d site, I^-1: 96, vector updates: their multiply-adds) */
+} mobius_solve_info;
+
+typedef struct mobius_ctx mobius_ctx;
+
+/* Create a context for one lattice and one set of operator parameters.
+ * links_c128: device pointer to the canonical links (4*V*9 complex128); the
+ * library packs them into context-owned storage (the caller may free its copy
+ * after the stream has run).  Returns MOBIUS_EINVAL for odd or < 2 extents,
+ * Ls outside [2, 64], M+ = 0, or a null pointer. */
+int mobius_create(mobius_ctx **ctx, const mobius_params *params, const void *links_c128,
+                  void *stream);
+
+/* Release every allocation the context owns.  Synchronises the device. */
+int mobius_destroy(mobius_ctx *ctx);
+
+/* Bytes of one packed half-lattice 5d field (one right-hand side) in `prec`. */
+int64_t mobius_field_bytes(const mobius_ctx *ctx, int32_t prec);
+
+/* Split a canonical 5d spinor (complex128, nrhs consecutive fields) into its
+ * even and odd packed halves in precision `prec` (FP16: per-site norm chosen
+ * as the max |component|, round-to-nearest-even). */
+int mobius_pack(mobius_ctx *ctx, int32_t prec, const void *canon_c128, void *even, void *odd,
+                int32_t nrhs, void *stream);
+
+/* Inverse of mobius_pack: packed halves -> canonical complex128. */
+int mobius_unpack(mobius_ctx *ctx, int32_t prec, const void *even, const void *odd,
+                  void *canon_c128, int32_t nrhs, void *stream);
+
+/* Apply one red/black block of D_DW to packed fields (Sec. 3):
+ *   MOBIUS_OP_HOP   out(parity p) = D_{p,1-p} in(parity 1-p), with
+ *                   D_{p,1-p} = -1/2 H_{p,1-p} (b5 + c5 C5): the Wilson hopping
+ *                   term on every s-slice after the b5/c5 mixing in s (Sec. 4.1:
+ *                   gather s-1, s, s+1, then one Dirac application);
+ *   MOBIUS_OP_M5    out = I in (both fields of parity out_parity);
+ *   MOBIUS_OP_SCHUR out = D_pre in on the odd parity (out_parity must be 1).
+ * in and out are packed fields of precision `prec`, nrhs consecutive fields each. */
+int mobius_dslash(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity, const void *in,
+                  void *out, int32_t nrhs, void *stream);
+
+/* The same blocks of the adjoint operator D_DW^+:
+ *   MOBIUS_OP_HOP   out(p) = (D^+)_{p,1-p} in(1-p) = (D_{1-p,p})^+ in
+ *                   = -1/2 B^+ H^+ in, H^+ = H with g_mu -> -g_mu;
+ *   MOBIUS_OP_M5    out = I^+ in;
+ *   MOBIUS_OP_SCHUR out = D_pre^+ in = in - (D_eo)^+ I^-+ (D_oe)^+ I^-+ in. */
+int mobius_dslash_dag(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
+                      const void *in, void *out, int32_t nrhs, void *stream);
+
+/* out = I^{-1} in (dagger = 0) or I^{-+} in (dagger = 1) on a packed half
+ * field, by the closed-form elimination of Sec. 3 (I = A P- + A^T P+, each an
+ * Ls x Ls cyclic bidiagonal solve per site, spin and colour). */
+int mobius_m5inv(mobius_ctx *ctx, int32_t prec, int32_t dagger, const void *in, void *out,
+                 int32_t nrhs, void *stream);
+
+/* Solve D_DW(m) psi = eta (Sec. 3 red/black Schur decomposition, CGLS on
+ * D_pre, reconstruction of the even half, FP64 true residual).
+ * src_c128 / sol_c128: canonical complex128 5d fields, opts->nrhs of them.
+ * info: array of opts->nrhs entries.  Returns MOBIUS_OK when every system
+ * reached opts->tol, MOBIUS_NOT_CONVERGED otherwise. */
+int mobius_cg_solve(mobius_ctx *ctx, const void *src_c128, void *sol_c128,
+                    const mobius_solve_opts *opts, mobius_solve_info *info, void *stream);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *mobius_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,175 @@
+// mobius_internal.h -- private declarations shared by the host side of
+// libmobius.so (context, solver) and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/mobius.h"
+
+namespace mobius {
+
+// ---------------------------------------------------------------------------
+// Geometry and packed layouts
+//
+// A half lattice of parity p holds Vh = V/2 4d sites.  The packed order of
+// the sites of one parity is a bricked traversal: the spatial volume is cut
+// into bricks of Bx x By x Bz sites, each brick extended over all t forms a
+// column, columns are visited in x-fastest order, and inside a column sites
+// run x fastest, then y, z, t.  The t neighbour of a site is then one brick
+// cross-section away in the traversal instead of a whole t-slice, which keeps
+// all eight neighbours of the sites in flight inside one XCD's L2.
+// canon_of[p][i] is the canonical 4d index (x fastest, then y, z, t) of packed
+// site i of parity p.  5d sites are Ls-inner: site5 = i * Ls + s.
+//
+// Spinor field of one parity, storage precision P, is a structure of arrays
+// of 16-byte chunks over site5:
+//   F64: 12 chunks (one complex each)            -> 192 B / site5
+//   F32:  6 chunks (two complex each)            ->  96 B / site5
+//   F16:  3 chunks (four complex each, binary16) + one FP32 norm per site5
+//                                                ->  52 B / site5
+// chunk c of site5 k lives at base + (c * N5 + k) * 16; the F16 norms follow
+// the chunks at base + CH * N5 * 16.  Component order is spin * 3 + colour.
+//
+// Links: for output parity p, 8 directions d: d < 4 is U_d(x), d >= 4 is
+// U_{d-4}(x - d^) (undaggered; the kernel applies the dagger), x the packed
+// site i of parity p.  Layout [p][8][Vh] of link records: 9 complex<prec>
+// (element a*3+b), padded to a multiple of 16 bytes (F64 144 B, F32 80 B,
+// F16 48 B) so that a lane reads its link with 16-byte loads.
+// Neighbour table nbr[p][Vh][8]: packed index (in parity 1-p) of x + d^ for
+// d < 4 and of x - (d-4)^ for d >= 4.
+
+struct Geometry {
+    int L[4];
+    int Ls;
+    int64_t V, Vh, N5;
+    int brick[3];                // Bx, By, Bz of the site order
+    const int32_t *canon_of;     // device [2][Vh]
+};
+
+inline int link_record_bytes(int prec)
+{
+    return prec == MOBIUS_F64 ? 144 : prec == MOBIUS_F32 ? 80 : 48;
+}
+
+inline int64_t field_bytes(const Geometry &g, int prec)
+{
+    switch (prec) {
+    case MOBIUS_F64: return g.N5 * 192;
+    case MOBIUS_F32: return g.N5 * 96;
+    case MOBIUS_F16: return g.N5 * 52;
+    }
+    return -1;
+}
+
+inline int link_elem_bytes(int prec)
+{
+    return prec == MOBIUS_F64 ? 16 : prec == MOBIUS_F32 ? 8 : 4;
+}
+
+// Scalars of the operator, precomputed on the host.
+struct OpCoeffs {
+    double b5, c5, mf;
+    double Mp, Mm;      // M+ = b5 (4 - M5) + 1, M- = c5 (4 - M5) - 1
+    double a;           // M- / M+
+    double mu;          // mf * a
+    double inv_Mp;      // 1 / M+
+    double inv_den;     // 1 / (M+ (1 - mu (-a)^(Ls-1)))
+};
+
+// Epilogue program of the hop kernel, applied in this order to r = -1/2 H (B in):
+enum Epilogue : int {
+    EPI_BDAG = 1,      // r = B^+ r          (always set for the adjoint hop)
+    EPI_M5ADD = 2,     // r = I y + r        (y: same-parity input; full operator)
+    EPI_PRESUB = 4,    // r = x - r
+    EPI_M5INV = 8,     // r = I^-1 r  (I^-+ r for the adjoint)
+    EPI_POSTSUB = 16,  // r = x - r
+    EPI_NORM = 32,     // partial sums of |r|^2 (FP64)
+};
+
+struct HopArgs {
+    int prec;
+    int dag;            // 0: D block, 1: D^+ block
+    int epi;            // Epilogue bit mask
+    int out_parity;
+    const void *in;     // parity 1 - out_parity
+    void *out;          // parity out_parity
+    const void *x;      // same parity as out (PRESUB/POSTSUB), may be null
+    const void *y;      // same parity as out (M5ADD), may be null
+    double *partials;   // per-block |r|^2 (EPI_NORM)
+    int nrhs;
+};
+
+// Launch parameters of the hop kernel chosen at run time (defaults are the
+// tuned values; MOBIUS_XCD_REMAP=0/1 overrides the block order,
+// MOBIUS_PREFETCH=0/1/2 the software pipelining depth of the direction loop).
+struct HopTuning {
+    int xcd_remap = 1;
+    int prefetch = 1;   // 0, 1 (next neighbour spinor), 2 (and its link)
+};
+// Brick of the site order for a lattice: MOBIUS_BRICK="bx,by,bz" overrides.
+void choose_brick(const int L[4], int Ls, int brick[3]);
+HopTuning &hop_tuning();
+
+// Reduction workspace sizing: number of blocks a site kernel launches.
+int64_t site_kernel_blocks(const Geometry &g);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (mobius_kernels.hip)
+
+// nbr from canon_of and its inverse packed_of[V] (index of a canonical site
+// inside its parity)
+hipError_t launch_build_geometry(const Geometry &g, const int32_t *packed_of, int32_t *nbr,
+                                 hipStream_t st);
+hipError_t launch_pack_links(const Geometry &g, int prec, const void *canon, void *packed,
+                             hipStream_t st);
+hipError_t launch_pack_spinor(const Geometry &g, int prec, const void *canon, void *even, void *odd,
+                              int nrhs, hipStream_t st);
+hipError_t launch_unpack_spinor(const Geometry &g, int prec, const void *even, const void *odd,
+                                void *canon, int nrhs, hipStream_t st);
+hipError_t launch_hop(const Geometry &g, const OpCoeffs &c, const void *links, const int32_t *nbr,
+                      const HopArgs &a, hipStream_t st);
+// Per-site s-direction operators on one packed half field:
+//   kind 0: out = I in (dag: I^+ in); kind 1: out = I^-1 in (dag: I^-+ in)
+hipError_t launch_m5(const Geometry &g, const OpCoeffs &c, int prec, int kind, int dag,
+                     const void *in, void *out, int nrhs, hipStream_t st);
+
+// BLAS-1 on packed half fields (storage precision prec), FP64 scalars in
+// device memory, FP64 partial sums per block (deterministic fixed-order
+// reduction in launch_reduce).
+int64_t blas_blocks(const Geometry &g);
+// out = a * x + b * y   (a, b read from device scalars; null scalar = 1)
+hipError_t launch_axpby(const Geometry &g, int prec, const double *a, const void *x,
+                        const double *b, const void *y, void *out, int nrhs, hipStream_t st);
+// |x|^2 partials
+hipError_t launch_norm2(const Geometry &g, int prec, const void *x, double *partials, int nrhs,
+                        hipStream_t st);
+// CG update:  x += alpha p (x in precision prec_x);  r -= alpha q;  partials of |r|^2
+hipError_t launch_cg_xr(const Geometry &g, int prec, int prec_x, const double *alpha, void *x,
+                        const void *p, void *r, const void *q, double *partials, hipStream_t st);
+// precision conversion of a packed half field (also a plain copy when equal)
+hipError_t launch_convert(const Geometry &g, int prec_in, const void *in, int prec_out, void *out,
+                          hipStream_t st);
+// x_hi (F64) += x_lo (prec)
+hipError_t launch_accumulate(const Geometry &g, int prec_lo, const void *x_lo, void *x_hi,
+                             hipStream_t st);
+// fill with zeros (kernel, not hipMemset, so it is safe under graph capture)
+hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t st);
+// sum `n` partials in a fixed order into *out
+hipError_t launch_reduce(const double *partials, int64_t n, double *out, hipStream_t st);
+
+// Scalar updates of CGLS, on device (one thread):
+struct CgScalars {
+    double gamma;      // |s|^2 of the current direction
+    double qq;         // |q|^2
+    double rr;         // |r|^2
+    double gamma_new;
+    double alpha, beta;
+    double scratch[10];
+};
+// op 0: alpha = gamma / qq;  op 1: beta = gamma_new / gamma, gamma = gamma_new
+hipError_t launch_cg_scalar(CgScalars *s, int op, hipStream_t st);
+
+}  // namespace mobius

@@ -1,0 +1,1320 @@
+// mobius_kernels.hip -- HIP kernels for gfx950 (MI355X) of the red/black
+// Moebius domain-wall operator (Brower, Neff, Orginos, Sec. 3 and Sec. 4.1).
+//
+// Thread mapping of the site kernels: one lane per (4d site, s).  A 64-lane
+// wavefront holds floor(64 / Ls) whole 4d sites, their Ls slices in
+// consecutive lanes, so that
+//  * every lane of a site reads the same eight links (one cache line serves
+//    all Ls lanes: the links are read from HBM once per 4d site and reused
+//    across the fifth dimension),
+//  * the b5/c5 coupling between s-1, s, s+1 (the "vector gather" of Sec. 4.1)
+//    is a cross-lane shuffle inside the wavefront,
+//  * the Ls-direction solves I^-1 (closed-form elimination, Sec. 3) run in the
+//    same wavefront through LDS, one lane per colour-spin component.
+// Packed layouts are described in mobius_internal.h.
+#include "mobius_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+
+namespace mobius {
+namespace {
+
+constexpr int WAVES = 4;
+constexpr int BLOCK = 64 * WAVES;
+
+// ---------------------------------------------------------------------------
+// complex helpers
+
+template <typename T>
+struct cx {
+    T r, i;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.r - b.r, a.i - b.i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
+// i * a
+template <typename T>
+__device__ __forceinline__ cx<T> ti(cx<T> a) { return {-a.i, a.r}; }
+// a * b
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
+{
+    return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+// acc + a * b
+template <typename T>
+__device__ __forceinline__ cx<T> cmadd(cx<T> acc, cx<T> a, cx<T> b)
+{
+    return {acc.r + a.r * b.r - a.i * b.i, acc.i + a.r * b.i + a.i * b.r};
+}
+// acc + conj(a) * b
+template <typename T>
+__device__ __forceinline__ cx<T> cjmadd(cx<T> acc, cx<T> a, cx<T> b)
+{
+    return {acc.r + a.r * b.r + a.i * b.i, acc.i + a.r * b.i - a.i * b.r};
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl(T v, int lane)
+{
+    return __shfl(v, lane, 64);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> shfl(cx<T> v, int lane)
+{
+    return {__shfl(v.r, lane, 64), __shfl(v.i, lane, 64)};
+}
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+// Every packed array is accessed through a buffer resource descriptor (four
+// SGPRs: base, size, format) with a 32-bit per-lane byte offset and a
+// wavefront-uniform scalar offset (the chunk or link-element stride).  This
+// keeps 64-bit address arithmetic out of the vector registers, and the
+// hardware range check turns any access past the end of the array into a
+// zero load or a dropped store.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer, CDNA
+
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ Buf(const void *p, int64_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0,
+                                              (int)(uint32_t)(bytes > 0xffffffffll ? 0xffffffffll : bytes),
+                                              RSRC_WORD3))
+    {
+    }
+    __device__ __forceinline__ u32x4 ld16(uint32_t voff, uint32_t soff) const
+    {
+        return __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+    }
+    __device__ __forceinline__ u32x2 ld8(uint32_t voff, uint32_t soff) const
+    {
+        return __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+    }
+    __device__ __forceinline__ uint32_t ld4(uint32_t voff, uint32_t soff) const
+    {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+    }
+    __device__ __forceinline__ void st16(u32x4 v, uint32_t voff, uint32_t soff) const
+    {
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, 0);
+    }
+    __device__ __forceinline__ void st4(uint32_t v, uint32_t voff, uint32_t soff) const
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 0);
+    }
+};
+
+// Materialise a value in VGPRs at this program point (an empty asm with a
+// read-write register operand; no instruction is emitted).  Used to stop the
+// compiler from sinking the per-direction arithmetic of the hop below the
+// last direction, which would keep every loaded operand live.
+template <typename T>
+__device__ __forceinline__ void pin(cx<T> &v)
+{
+    asm volatile("" : "+v"(v.r), "+v"(v.i));
+}
+
+// ---------------------------------------------------------------------------
+// storage policies for packed spinors: 16-byte chunks over site5
+
+template <int P>
+struct Spin;
+
+template <>
+struct Spin<MOBIUS_F64> {
+    using T = double;
+    __host__ __device__ static int64_t bytes(int64_t N5) { return N5 * 192; }
+    __device__ static void load(const Buf &b, uint32_t N5, uint32_t k, cx<T> v[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            double2 t = __builtin_bit_cast(double2, b.ld16(k * 16u, (uint32_t)c * N5 * 16u));
+            v[c] = {t.x, t.y};
+        }
+    }
+    __device__ static void store(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 12; ++c)
+            b.st16(__builtin_bit_cast(u32x4, make_double2(v[c].r, v[c].i)), k * 16u,
+                   (uint32_t)c * N5 * 16u);
+    }
+    __device__ static double store_norm2(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
+    {
+        store(b, N5, k, v);
+        double n = 0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) n += (double)v[c].r * v[c].r + (double)v[c].i * v[c].i;
+        return n;
+    }
+};
+
+template <>
+struct Spin<MOBIUS_F32> {
+    using T = float;
+    __host__ __device__ static int64_t bytes(int64_t N5) { return N5 * 96; }
+    __device__ static void load(const Buf &b, uint32_t N5, uint32_t k, cx<T> v[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            float4 t = __builtin_bit_cast(float4, b.ld16(k * 16u, (uint32_t)c * N5 * 16u));
+            v[2 * c] = {t.x, t.y};
+            v[2 * c + 1] = {t.z, t.w};
+        }
+    }
+    __device__ static void store(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            b.st16(__builtin_bit_cast(u32x4, make_float4(v[2 * c].r, v[2 * c].i, v[2 * c + 1].r,
+                                                         v[2 * c + 1].i)),
+                   k * 16u, (uint32_t)c * N5 * 16u);
+    }
+    __device__ static double store_norm2(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
+    {
+        store(b, N5, k, v);
+        double n = 0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) n += (double)v[c].r * v[c].r + (double)v[c].i * v[c].i;
+        return n;
+    }
+};
+
+template <>
+struct Spin<MOBIUS_F16> {
+    using T = float;
+    __host__ __device__ static int64_t bytes(int64_t N5) { return N5 * 52; }
+    __device__ static void load(const Buf &b, uint32_t N5, uint32_t k, cx<T> v[12])
+    {
+        const float nrm = __builtin_bit_cast(float, b.ld4(k * 4u, 3u * N5 * 16u));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            half8 t = __builtin_bit_cast(half8, b.ld16(k * 16u, (uint32_t)c * N5 * 16u));
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                v[4 * c + j] = {nrm * (float)t[2 * j], nrm * (float)t[2 * j + 1]};
+        }
+    }
+    // Encode a site: FP32 max-abs norm, binary16 components scaled by 1/norm
+    // (round to nearest even).  decode(encode(v)) is what a later load returns.
+    __device__ static float encode(const cx<T> v[12], half8 h[3])
+    {
+        float m = 0.f;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].r), fabsf(v[c].i)));
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                h[c][2 * j] = (_Float16)(v[4 * c + j].r * inv);
+                h[c][2 * j + 1] = (_Float16)(v[4 * c + j].i * inv);
+            }
+        return m;
+    }
+    __device__ static void store(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
+    {
+        half8 h[3];
+        const float m = encode(v, h);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) b.st16(__builtin_bit_cast(u32x4, h[c]), k * 16u, (uint32_t)c * N5 * 16u);
+        b.st4(__builtin_bit_cast(uint32_t, m), k * 4u, 3u * N5 * 16u);
+    }
+    // store, and return |stored value|^2 computed from the encoded registers
+    __device__ static double store_norm2(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
+    {
+        half8 h[3];
+        const float m = encode(v, h);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) b.st16(__builtin_bit_cast(u32x4, h[c]), k * 16u, (uint32_t)c * N5 * 16u);
+        b.st4(__builtin_bit_cast(uint32_t, m), k * 4u, 3u * N5 * 16u);
+        double n = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const double d = (double)(m * (float)h[c][j]);
+                n += d * d;
+            }
+        return n;
+    }
+};
+
+// link records: [8][Vh] of 9 complex<prec> (padded) for one parity
+template <int P>
+struct Link;
+
+template <>
+struct Link<MOBIUS_F64> {
+    using T = double;
+    static constexpr int REC = 144;
+    __device__ static void load(const Buf &b, uint32_t voff, uint32_t soff, cx<T> u[9])
+    {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            double2 t = __builtin_bit_cast(double2, b.ld16(voff + 16u * e, soff));
+            u[e] = {t.x, t.y};
+        }
+    }
+};
+template <>
+struct Link<MOBIUS_F32> {
+    using T = float;
+    static constexpr int REC = 80;
+    __device__ static void load(const Buf &b, uint32_t voff, uint32_t soff, cx<T> u[9])
+    {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            float4 t = __builtin_bit_cast(float4, b.ld16(voff + 16u * q, soff));
+            u[2 * q] = {t.x, t.y};
+            if (2 * q + 1 < 9) u[2 * q + 1] = {t.z, t.w};
+        }
+    }
+};
+template <>
+struct Link<MOBIUS_F16> {
+    using T = float;
+    static constexpr int REC = 48;
+    __device__ static void load(const Buf &b, uint32_t voff, uint32_t soff, cx<T> u[9])
+    {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            half8 t = __builtin_bit_cast(half8, b.ld16(voff + 16u * q, soff));
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (4 * q + j < 9) u[4 * q + j] = {(float)t[2 * j], (float)t[2 * j + 1]};
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// spin algebra in the chiral basis
+//
+// g_mu = [[0, A_mu], [A_mu^+, 0]] with A_k = -i sigma_k, A_4 = 1, so for
+// psi = (u; l) (u = spins 0,1 = P+ part, l = spins 2,3 = P- part) and a sign
+// sigma = +-1:
+//   (1 + sigma g_mu) psi = (h ; sigma A_mu^+ h),   h = u + sigma A_mu l,
+// i.e. the projector keeps two spin components (a half spinor) and the other
+// two are reconstructed after the colour multiply.
+
+// (A_mu l) for the two spin rows, one colour
+template <typename T, int MU>
+__device__ __forceinline__ void A_apply(cx<T> l0, cx<T> l1, cx<T> &o0, cx<T> &o1)
+{
+    if constexpr (MU == 0) {        // -i sigma_1: (-i l1, -i l0)
+        o0 = {l1.i, -l1.r};
+        o1 = {l0.i, -l0.r};
+    } else if constexpr (MU == 1) { // -i sigma_2 = [[0,-1],[1,0]]: (-l1, l0)
+        o0 = {-l1.r, -l1.i};
+        o1 = l0;
+    } else if constexpr (MU == 2) { // -i sigma_3: (-i l0, i l1)
+        o0 = {l0.i, -l0.r};
+        o1 = {-l1.i, l1.r};
+    } else {                        // 1
+        o0 = l0;
+        o1 = l1;
+    }
+}
+
+// (A_mu^+ w) for the two spin rows, one colour
+template <typename T, int MU>
+__device__ __forceinline__ void Adag_apply(cx<T> w0, cx<T> w1, cx<T> &o0, cx<T> &o1)
+{
+    if constexpr (MU == 0) {        // i sigma_1: (i w1, i w0)
+        o0 = ti(w1);
+        o1 = ti(w0);
+    } else if constexpr (MU == 1) { // [[0,1],[-1,0]]: (w1, -w0)
+        o0 = w1;
+        o1 = {-w0.r, -w0.i};
+    } else if constexpr (MU == 2) { // i sigma_3: (i w0, -i w1)
+        o0 = ti(w0);
+        o1 = {w1.i, -w1.r};
+    } else {
+        o0 = w0;
+        o1 = w1;
+    }
+}
+
+// One direction of the hopping sum at one lane: acc += (1 + sigma g_mu) M chi,
+// M = U (forward) or U^+ (backward), chi the (b5/c5-mixed) neighbour spinor.
+template <int P>
+__device__ __forceinline__ void load_link(const Buf &links, uint32_t Vh, int d, uint32_t i,
+                                          cx<typename Spin<P>::T> u[9])
+{
+    Link<P>::load(links, i * (uint32_t)Link<P>::REC, (uint32_t)d * Vh * (uint32_t)Link<P>::REC, u);
+}
+
+// u: the link of this direction as stored (element a*3+b of U_mu(x) or of
+// U_mu(x-mu), whose adjoint the backward term applies)
+template <int P, int MU, bool FWD, int SIGMA>
+__device__ __forceinline__ void hop_dir(const cx<typename Spin<P>::T> chi[12],
+                                        const cx<typename Spin<P>::T> u[9],
+                                        cx<typename Spin<P>::T> acc[12])
+{
+    using T = typename Spin<P>::T;
+    const T sg = (T)SIGMA;
+    // half spinor h = u + sigma A l  (2 spins x 3 colours)
+    cx<T> h0[3], h1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<T> o0, o1;
+        A_apply<T, MU>(chi[6 + a], chi[9 + a], o0, o1);
+        h0[a] = chi[a] + sg * o0;
+        h1[a] = chi[3 + a] + sg * o1;
+    }
+    // colour multiply
+    cx<T> w0[3], w1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        w0[a] = {0, 0};
+        w1[a] = {0, 0};
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if constexpr (FWD) {
+                w0[a] = cmadd(w0[a], u[a * 3 + b], h0[b]);
+                w1[a] = cmadd(w1[a], u[a * 3 + b], h1[b]);
+            } else {  // (U^+)_{ab} = conj(U_ba)
+                w0[a] = cjmadd(w0[a], u[b * 3 + a], h0[b]);
+                w1[a] = cjmadd(w1[a], u[b * 3 + a], h1[b]);
+            }
+        }
+    // reconstruct and accumulate
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        acc[a] = acc[a] + w0[a];
+        acc[3 + a] = acc[3 + a] + w1[a];
+        cx<T> o0, o1;
+        Adag_apply<T, MU>(w0[a], w1[a], o0, o1);
+        acc[6 + a] = acc[6 + a] + sg * o0;
+        acc[9 + a] = acc[9 + a] + sg * o1;
+    }
+}
+
+struct SiteMap {
+    int lane, wave, g, s;
+    bool site_ok;
+    int64_t i;   // packed 4d site (clamped to a valid index)
+    int lm, lp;  // lanes holding s-1 and s+1 of the same site (cyclic)
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b mod 8), each with its own L2.  With remap on, the blocks an XCD receives
+// cover one contiguous range of sites, so the neighbours a block reads were
+// mostly fetched into the same L2 by the blocks just before it.
+constexpr int NUM_XCD = 8;
+
+__device__ __forceinline__ int64_t logical_block(int remap)
+{
+    const int64_t b = blockIdx.x;
+    if (!remap) return b;
+    const int64_t nb = gridDim.x;
+    const int64_t q = nb / NUM_XCD, r = nb % NUM_XCD;
+    const int64_t x = b % NUM_XCD, c = b / NUM_XCD;
+    return x * q + (x < r ? x : r) + c;
+}
+
+__device__ __forceinline__ SiteMap site_map(int Ls, int spw, int64_t Vh, int remap = 0)
+{
+    SiteMap m;
+    m.lane = threadIdx.x & 63;
+    m.wave = threadIdx.x >> 6;
+    m.g = m.lane / Ls;
+    m.s = m.lane - m.g * Ls;
+    int64_t i = (logical_block(remap) * WAVES + m.wave) * spw + m.g;
+    m.site_ok = (m.g < spw) && (i < Vh);
+    m.i = m.site_ok ? i : 0;
+    const int base = m.g * Ls;
+    m.lm = base + (m.s == 0 ? Ls - 1 : m.s - 1);
+    m.lp = base + (m.s == Ls - 1 ? 0 : m.s + 1);
+    return m;
+}
+
+template <typename T>
+struct Coef {
+    T b5, c5, mf, Mp, Mm, a, mu, inv_Mp, inv_den;
+};
+
+template <typename T>
+__device__ __forceinline__ Coef<T> make_coef(const OpCoeffs &c)
+{
+    return {(T)c.b5, (T)c.c5, (T)c.mf, (T)c.Mp, (T)c.Mm, (T)c.a, (T)c.mu, (T)c.inv_Mp,
+            (T)c.inv_den};
+}
+
+// C5 mixing in s from the lanes of the same 4d site.
+//   forward  (C5 v)_s  = P+ v_{s-1} + P- v_{s+1}
+//   adjoint  (C5^+ v)_s = P+ v_{s+1} + P- v_{s-1}
+// wrapped neighbours carry -mf.  Returns alpha * v + beta * C5(^+) v.
+template <typename T>
+__device__ __forceinline__ void mix_s(cx<T> v[12], T alpha, T beta, T mf, const SiteMap &m, int Ls,
+                                      bool adjoint)
+{
+    const int src_up = adjoint ? m.lp : m.lm;  // lane whose P+ part we take
+    const int src_lo = adjoint ? m.lm : m.lp;  // lane whose P- part we take
+    const bool wrap_up = adjoint ? (m.s == Ls - 1) : (m.s == 0);
+    const bool wrap_lo = adjoint ? (m.s == 0) : (m.s == Ls - 1);
+    const T fu = beta * (wrap_up ? -mf : (T)1);
+    const T fl = beta * (wrap_lo ? -mf : (T)1);
+    cx<T> up[6], lo[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        up[c] = shfl(v[c], src_up);
+        lo[c] = shfl(v[6 + c], src_lo);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        v[c] = alpha * v[c] + fu * up[c];
+        v[6 + c] = alpha * v[6 + c] + fl * lo[c];
+    }
+}
+
+// I^-1 (or I^-+) of Sec. 3 on the Ls lanes of each 4d site, through LDS.
+// I^-1 = A^-1 P- + A^-T P+;  I^-+ = A^-T P- + A^-1 P+  (A real).
+// Lane (g, s) of a site solves component c = s, s + Ls, ... by the paper's
+// elimination on the fly:
+//   A^-1 b:  psi_Ls = (b_Ls + mu sum_{s<Ls} (-a)^(s-1) b_s) / (M+ (1 - mu (-a)^(Ls-1)))
+//            psi_s  = b_s / M+ - a psi_{s+1}
+//   A^-T b:  psi_1  = (b_1 + mu sum_{s>1} (-a)^(Ls-s) b_s) / (same)
+//            psi_s  = b_s / M+ - a psi_{s-1}
+template <typename T>
+struct M5Lds {
+    static constexpr int STRIDE = 13;  // complex per lane (12 + 1 pad)
+    cx<T> buf[WAVES][64 * STRIDE];
+};
+
+template <typename T>
+__device__ __forceinline__ void m5inv_lanes(cx<T> r[12], const Coef<T> &k, const SiteMap &m, int Ls,
+                                            bool dag, M5Lds<T> &lds)
+{
+    cx<T> *w = lds.buf[m.wave];
+    constexpr int ST = M5Lds<T>::STRIDE;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) w[m.lane * ST + c] = r[c];
+    __syncthreads();
+    if (m.g * Ls + Ls <= 64) {
+        const int base = m.g * Ls;
+        for (int c = m.s; c < 12; c += Ls) {
+            const bool plus = c < 6;
+            const bool transpose = plus != dag;
+            const T na = -k.a;
+            if (!transpose) {
+                cx<T> sum = {0, 0};
+                for (int t = Ls - 2; t >= 0; --t) sum = w[(base + t) * ST + c] + na * sum;
+                cx<T> psi = k.inv_den * (w[(base + Ls - 1) * ST + c] + k.mu * sum);
+                w[(base + Ls - 1) * ST + c] = psi;
+                for (int t = Ls - 2; t >= 0; --t) {
+                    psi = k.inv_Mp * w[(base + t) * ST + c] - k.a * psi;
+                    w[(base + t) * ST + c] = psi;
+                }
+            } else {
+                cx<T> sum = {0, 0};
+                for (int t = 1; t < Ls; ++t) sum = na * sum + w[(base + t) * ST + c];
+                cx<T> psi = k.inv_den * (w[base * ST + c] + k.mu * sum);
+                w[base * ST + c] = psi;
+                for (int t = 1; t < Ls; ++t) {
+                    psi = k.inv_Mp * w[(base + t) * ST + c] - k.a * psi;
+                    w[(base + t) * ST + c] = psi;
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 12; ++c) r[c] = w[m.lane * ST + c];
+}
+
+// FP64 block reduction of one value per thread -> partials[blockIdx.x]
+__device__ __forceinline__ void block_sum_store(double v, double *partials)
+{
+    __shared__ double red[WAVES];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) t += red[w];
+        partials[blockIdx.x] = t;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ double site_norm2(const cx<T> r[12])
+{
+    double n = 0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) n += (double)r[c].r * r[c].r + (double)r[c].i * r[c].i;
+    return n;
+}
+
+// ---------------------------------------------------------------------------
+// hop kernel: out = epilogue( -1/2 sum_mu [...] )  on every s-slice
+
+struct HopParams {
+    const char *in;
+    char *out;
+    const char *x;
+    const char *y;
+    const char *links;    // parity block of the packed links
+    const int32_t *nbr;   // parity block of the neighbour table
+    double *partials;
+    int64_t Vh, N5;
+    int Ls, spw;
+    int remap;            // XCD-contiguous block order
+    OpCoeffs c;
+};
+
+// PF: software pipelining of the direction loop.  0: operands of direction d
+// are loaded in segment d; 1: the neighbour spinor of direction d+1 is loaded
+// while direction d computes; 2: its link as well.  The eight neighbour
+// indices are always loaded up front.
+template <int P, bool DAG, int EPI, int PF>
+__global__ __launch_bounds__(BLOCK) void hop_kernel(HopParams hp)
+{
+    using S = Spin<P>;
+    using T = typename S::T;
+    const SiteMap m = site_map(hp.Ls, hp.spw, hp.Vh, hp.remap);
+    const Coef<T> k = make_coef<T>(hp.c);
+    const int Ls = hp.Ls;
+    const uint32_t Vh = (uint32_t)hp.Vh, N5 = (uint32_t)hp.N5;
+    const uint32_t i = (uint32_t)m.i;
+    const uint32_t k5 = i * (uint32_t)Ls + (uint32_t)m.s;
+    const int64_t fbytes = S::bytes(hp.N5);
+    const Buf bin(hp.in, fbytes), bout(hp.out, fbytes);
+    const Buf blink(hp.links, (int64_t)8 * hp.Vh * Link<P>::REC);
+    const Buf bnbr(hp.nbr, 8 * hp.Vh * 4);
+
+    uint32_t jn[8];
+    {
+        const u32x4 n0 = bnbr.ld16(i * 32u, 0u), n1 = bnbr.ld16(i * 32u + 16u, 0u);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            jn[d] = n0[d] * (uint32_t)Ls + (uint32_t)m.s;
+            jn[4 + d] = n1[d] * (uint32_t)Ls + (uint32_t)m.s;
+        }
+    }
+
+    cx<T> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+
+    cx<T> nxt[12], unx[9];
+    if constexpr (PF >= 1) S::load(bin, N5, jn[0], nxt);
+    if constexpr (PF >= 2) load_link<P>(blink, Vh, 0, i, unx);
+
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        cx<T> chi[12], u[9];
+        if constexpr (PF >= 1) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) chi[c] = nxt[c];
+            if (d < 7) S::load(bin, N5, jn[d + 1], nxt);
+        } else {
+            S::load(bin, N5, jn[d], chi);
+        }
+        if constexpr (PF >= 2) {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) u[e] = unx[e];
+            if (d < 7) load_link<P>(blink, Vh, d + 1, i, unx);
+        } else {
+            load_link<P>(blink, Vh, d, i, u);
+        }
+        if constexpr (!DAG) {
+            // B = b5 + c5 C5 on the input: gather s-1, s, s+1 of the neighbour
+            mix_s(chi, k.b5, k.c5, k.mf, m, Ls, false);
+        }
+        constexpr int SF = DAG ? +1 : -1;  // forward projector (1 -+ g_mu)
+        switch (d) {
+        case 0: hop_dir<P, 0, true, SF>(chi, u, acc); break;
+        case 1: hop_dir<P, 1, true, SF>(chi, u, acc); break;
+        case 2: hop_dir<P, 2, true, SF>(chi, u, acc); break;
+        case 3: hop_dir<P, 3, true, SF>(chi, u, acc); break;
+        case 4: hop_dir<P, 0, false, -SF>(chi, u, acc); break;
+        case 5: hop_dir<P, 1, false, -SF>(chi, u, acc); break;
+        case 6: hop_dir<P, 2, false, -SF>(chi, u, acc); break;
+        default: hop_dir<P, 3, false, -SF>(chi, u, acc); break;
+        }
+        // the accumulator is complete here; nothing of direction d+1 beyond
+        // its prefetched loads moves above this point
+#pragma unroll
+        for (int c = 0; c < 12; ++c) pin(acc[c]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    const T mhalf = (T)-0.5;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = mhalf * acc[c];
+
+    if constexpr (DAG) mix_s(acc, k.b5, k.c5, k.mf, m, Ls, true);  // B^+ on the output
+    if constexpr ((EPI & EPI_M5ADD) != 0) {
+        cx<T> yv[12];
+        S::load(Buf(hp.y, fbytes), N5, k5, yv);
+        mix_s(yv, k.Mp, k.Mm, k.mf, m, Ls, DAG);  // I y = M+ y + M- C5 y
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = acc[c] + yv[c];
+    }
+    if constexpr ((EPI & EPI_PRESUB) != 0) {
+        cx<T> xv[12];
+        S::load(Buf(hp.x, fbytes), N5, k5, xv);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = xv[c] - acc[c];
+    }
+    if constexpr ((EPI & EPI_M5INV) != 0) {
+        __shared__ M5Lds<T> lds;
+        m5inv_lanes(acc, k, m, Ls, DAG, lds);
+    }
+    if constexpr ((EPI & EPI_POSTSUB) != 0) {
+        cx<T> xv[12];
+        S::load(Buf(hp.x, fbytes), N5, k5, xv);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = xv[c] - acc[c];
+    }
+    if constexpr ((EPI & EPI_NORM) != 0) {
+        // |stored value|^2, from the encoded registers
+        double n = 0;
+        if (m.site_ok) n = S::store_norm2(bout, N5, k5, acc);
+        block_sum_store(n, hp.partials);
+    } else {
+        if (m.site_ok) S::store(bout, N5, k5, acc);
+    }
+}
+
+// per-site s-direction operators: kind 0 -> I (or I^+), kind 1 -> I^-1 (or I^-+)
+template <int P, bool DAG, int KIND>
+__global__ __launch_bounds__(BLOCK) void m5_kernel(const char *in, char *out, int64_t Vh,
+                                                   int64_t N5, int Ls, int spw, OpCoeffs c)
+{
+    using S = Spin<P>;
+    using T = typename S::T;
+    const SiteMap m = site_map(Ls, spw, Vh);
+    const Coef<T> k = make_coef<T>(c);
+    const uint32_t k5 = (uint32_t)m.i * (uint32_t)Ls + (uint32_t)m.s;
+    const int64_t fbytes = S::bytes(N5);
+    cx<T> v[12];
+    S::load(Buf(in, fbytes), (uint32_t)N5, k5, v);
+    if constexpr (KIND == 0) {
+        mix_s(v, k.Mp, k.Mm, k.mf, m, Ls, DAG);
+    } else {
+        __shared__ M5Lds<T> lds;
+        m5inv_lanes(v, k, m, Ls, DAG, lds);
+    }
+    if (m.site_ok) S::store(Buf(out, fbytes), (uint32_t)N5, k5, v);
+}
+
+// ---------------------------------------------------------------------------
+// geometry, packing
+
+__device__ __forceinline__ void coords_of(int64_t c, const int *L, int x[4])
+{
+    for (int mu = 0; mu < 4; ++mu) {
+        x[mu] = (int)(c % L[mu]);
+        c /= L[mu];
+    }
+}
+
+__device__ __forceinline__ int64_t canon_index(const int x[4], const int *L)
+{
+    return (((int64_t)x[3] * L[2] + x[2]) * L[1] + x[1]) * L[0] + x[0];
+}
+
+struct Dims {
+    int L[4];
+};
+
+// nbr[p][i][d] = packed index of the d-th neighbour of packed site i of parity p
+__global__ void build_nbr_kernel(Dims D, int64_t Vh, const int32_t *canon_of,
+                                 const int32_t *packed_of, int32_t *nbr)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * Vh) return;
+    const int64_t c = canon_of[t];
+    int x[4];
+    coords_of(c, D.L, x);
+    for (int d = 0; d < 8; ++d) {
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        const int mu = d & 3;
+        const int dir = d < 4 ? 1 : -1;
+        y[mu] = (y[mu] + dir + D.L[mu]) % D.L[mu];
+        nbr[t * 8 + d] = packed_of[canon_index(y, D.L)];
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void put_link_elem(char *dst, int64_t idx, double re, double im)
+{
+    if constexpr (P == MOBIUS_F64) {
+        reinterpret_cast<double2 *>(dst)[idx] = make_double2(re, im);
+    } else if constexpr (P == MOBIUS_F32) {
+        reinterpret_cast<float2 *>(dst)[idx] = make_float2((float)re, (float)im);
+    } else {
+        half2v h;
+        h.x = (_Float16)re;
+        h.y = (_Float16)im;
+        reinterpret_cast<half2v *>(dst)[idx] = h;
+    }
+}
+
+// record (p, d, i) of the packed links; padding elements are zero
+template <int P>
+__global__ void pack_links_kernel(Dims D, int64_t V, int64_t Vh, const int32_t *canon_of,
+                                  const double2 *canon, char *packed)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * Vh * 8) return;
+    const int64_t i = t % Vh;
+    const int d = (int)((t / Vh) % 8);
+    const int p = (int)(t / (Vh * 8));
+    const int64_t c = canon_of[p * Vh + i];
+    int x[4];
+    coords_of(c, D.L, x);
+    const int mu = d & 3;
+    if (d >= 4) x[mu] = (x[mu] - 1 + D.L[mu]) % D.L[mu];
+    const int64_t src = ((int64_t)mu * V + canon_index(x, D.L)) * 9;
+    constexpr int REC = Link<P>::REC;
+    constexpr int EB = P == MOBIUS_F64 ? 16 : P == MOBIUS_F32 ? 8 : 4;
+    char *rec = packed + (((int64_t)p * 8 + d) * Vh + i) * REC;
+    for (int e = 0; e < REC / EB; ++e) {
+        double2 u = e < 9 ? canon[src + e] : make_double2(0.0, 0.0);
+        put_link_elem<P>(rec, e, u.x, u.y);
+    }
+}
+
+// canonical [s][t][z][y][x][12] complex128 <-> packed halves
+template <int P>
+__global__ __launch_bounds__(256) void pack_spinor_kernel(int64_t Vh, int Ls,
+                                                          const int32_t *canon_of,
+                                                          const double2 *canon, char *even,
+                                                          char *odd)
+{
+    using S = Spin<P>;
+    using T = typename S::T;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N5 = Vh * Ls;
+    if (t >= 2 * N5) return;
+    const int p = (int)(t / N5);
+    const int64_t k5 = t - p * N5;
+    const int64_t i = k5 / Ls;
+    const int s = (int)(k5 - i * Ls);
+    const int64_t V = 2 * Vh;
+    const int64_t c = canon_of[p * Vh + i];
+    const double2 *src = canon + ((int64_t)s * V + c) * 12;
+    cx<T> v[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        double2 z = src[q];
+        v[q] = {(T)z.x, (T)z.y};
+    }
+    S::store(Buf(p == 0 ? even : odd, S::bytes(N5)), (uint32_t)N5, (uint32_t)k5, v);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void unpack_spinor_kernel(int64_t Vh, int Ls,
+                                                            const int32_t *canon_of,
+                                                            const char *even, const char *odd,
+                                                            double2 *canon)
+{
+    using S = Spin<P>;
+    using T = typename S::T;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N5 = Vh * Ls;
+    if (t >= 2 * N5) return;
+    const int p = (int)(t / N5);
+    const int64_t k5 = t - p * N5;
+    const int64_t i = k5 / Ls;
+    const int s = (int)(k5 - i * Ls);
+    const int64_t V = 2 * Vh;
+    const int64_t c = canon_of[p * Vh + i];
+    cx<T> v[12];
+    S::load(Buf(p == 0 ? even : odd, S::bytes(N5)), (uint32_t)N5, (uint32_t)k5, v);
+    double2 *dst = canon + ((int64_t)s * V + c) * 12;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) dst[q] = make_double2((double)v[q].r, (double)v[q].i);
+}
+
+// ---------------------------------------------------------------------------
+// BLAS-1 and reductions (one thread per site5)
+
+constexpr int BLAS_BLOCK = 256;
+
+template <int P>
+__global__ __launch_bounds__(BLAS_BLOCK) void axpby_kernel(int64_t N5, const double *a,
+                                                           const char *x, const double *b,
+                                                           const char *y, char *out)
+{
+    using S = Spin<P>;
+    using T = typename S::T;
+    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (k >= N5) return;
+    const T av = a ? (T)*a : (T)1, bv = b ? (T)*b : (T)1;
+    const int64_t fb = S::bytes(N5);
+    cx<T> xv[12], yv[12];
+    S::load(Buf(x, fb), (uint32_t)N5, (uint32_t)k, xv);
+    S::load(Buf(y, fb), (uint32_t)N5, (uint32_t)k, yv);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) xv[c] = av * xv[c] + bv * yv[c];
+    S::store(Buf(out, fb), (uint32_t)N5, (uint32_t)k, xv);
+}
+
+template <int P>
+__global__ __launch_bounds__(BLAS_BLOCK) void norm2_kernel(int64_t N5, const char *x,
+                                                           double *partials)
+{
+    using S = Spin<P>;
+    using T = typename S::T;
+    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    double n = 0;
+    if (k < N5) {
+        cx<T> v[12];
+        S::load(Buf(x, S::bytes(N5)), (uint32_t)N5, (uint32_t)k, v);
+        n = site_norm2(v);
+    }
+    block_sum_store(n, partials);
+}
+
+// x (precision PX) += alpha p;  r -= alpha q  (precision P);  partials of |r|^2.
+// The solution correction may be kept in a wider format than the Krylov
+// vectors so that small late updates are not lost to its rounding.
+template <int P, int PX>
+__global__ __launch_bounds__(BLAS_BLOCK) void cg_xr_kernel(int64_t N5, const double *alpha,
+                                                           char *x, const char *p, char *r,
+                                                           const char *q, double *partials)
+{
+    using S = Spin<P>;
+    using SX = Spin<PX>;
+    using T = typename S::T;
+    using TX = typename SX::T;
+    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    double n = 0;
+    if (k < N5) {
+        const T al = (T)*alpha;
+        const TX alx = (TX)*alpha;
+        const int64_t fb = S::bytes(N5);
+        const uint32_t n5 = (uint32_t)N5, kk = (uint32_t)k;
+        const Buf bx(x, SX::bytes(N5)), bp(p, fb), br(r, fb), bq(q, fb);
+        cx<TX> xv[12];
+        cx<T> pv[12], rv[12];
+        SX::load(bx, n5, kk, xv);
+        S::load(bp, n5, kk, pv);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) xv[c] = xv[c] + alx * cx<TX>{(TX)pv[c].r, (TX)pv[c].i};
+        SX::store(bx, n5, kk, xv);
+        S::load(br, n5, kk, rv);
+        S::load(bq, n5, kk, pv);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) rv[c] = rv[c] - al * pv[c];
+        n = S::store_norm2(br, n5, kk, rv);
+    }
+    block_sum_store(n, partials);
+}
+
+template <int PI, int PO>
+__global__ __launch_bounds__(BLAS_BLOCK) void convert_kernel(int64_t N5, const char *in, char *out)
+{
+    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (k >= N5) return;
+    cx<typename Spin<PI>::T> v[12];
+    Spin<PI>::load(Buf(in, Spin<PI>::bytes(N5)), (uint32_t)N5, (uint32_t)k, v);
+    cx<typename Spin<PO>::T> w[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c)
+        w[c] = {(typename Spin<PO>::T)v[c].r, (typename Spin<PO>::T)v[c].i};
+    Spin<PO>::store(Buf(out, Spin<PO>::bytes(N5)), (uint32_t)N5, (uint32_t)k, w);
+}
+
+template <int PL>
+__global__ __launch_bounds__(BLAS_BLOCK) void accumulate_kernel(int64_t N5, const char *lo, char *hi)
+{
+    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (k >= N5) return;
+    cx<typename Spin<PL>::T> v[12];
+    Spin<PL>::load(Buf(lo, Spin<PL>::bytes(N5)), (uint32_t)N5, (uint32_t)k, v);
+    cx<double> h[12];
+    const Buf bh(hi, Spin<MOBIUS_F64>::bytes(N5));
+    Spin<MOBIUS_F64>::load(bh, (uint32_t)N5, (uint32_t)k, h);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) h[c] = {h[c].r + (double)v[c].r, h[c].i + (double)v[c].i};
+    Spin<MOBIUS_F64>::store(bh, (uint32_t)N5, (uint32_t)k, h);
+}
+
+__global__ void zero_kernel(uint4 *p, int64_t n16, unsigned char *tail, int64_t ntail)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n16) p[k] = make_uint4(0, 0, 0, 0);
+    if (k < ntail) tail[k] = 0;
+}
+
+constexpr int RED_BLOCK = 1024;
+
+__global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(const double *partials, int64_t n,
+                                                           double *out)
+{
+    __shared__ double sm[RED_BLOCK];
+    double t = 0;
+    for (int64_t k = threadIdx.x; k < n; k += RED_BLOCK) t += partials[k];
+    sm[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = RED_BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sm[0];
+}
+
+__global__ void cg_scalar_kernel(CgScalars *s, int op)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (op == 0) {
+        s->alpha = s->qq > 0 ? s->gamma / s->qq : 0.0;
+    } else {
+        s->beta = s->gamma > 0 ? s->gamma_new / s->gamma : 0.0;
+        s->gamma = s->gamma_new;
+    }
+}
+
+int sites_per_wave(int Ls) { return 64 / Ls; }
+
+}  // namespace
+
+HopTuning &hop_tuning()
+{
+    static HopTuning t = [] {
+        HopTuning d;
+        if (const char *e = std::getenv("MOBIUS_XCD_REMAP")) d.xcd_remap = std::atoi(e);
+        if (const char *e = std::getenv("MOBIUS_PREFETCH")) d.prefetch = std::atoi(e);
+        return d;
+    }();
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+int64_t site_kernel_blocks(const Geometry &g)
+{
+    const int spw = sites_per_wave(g.Ls);
+    const int64_t per_block = (int64_t)spw * WAVES;
+    return (g.Vh + per_block - 1) / per_block;
+}
+
+int64_t blas_blocks(const Geometry &g) { return (g.N5 + BLAS_BLOCK - 1) / BLAS_BLOCK; }
+
+hipError_t launch_build_geometry(const Geometry &g, const int32_t *packed_of, int32_t *nbr,
+                                 hipStream_t st)
+{
+    Dims D{{g.L[0], g.L[1], g.L[2], g.L[3]}};
+    const int64_t n = 2 * g.Vh;
+    hipLaunchKernelGGL(build_nbr_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, D,
+                       g.Vh, g.canon_of, packed_of, nbr);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_links(const Geometry &g, int prec, const void *canon, void *packed,
+                             hipStream_t st)
+{
+    Dims D{{g.L[0], g.L[1], g.L[2], g.L[3]}};
+    const int64_t n = 2 * g.Vh * 8;
+    dim3 grid((unsigned)((n + 255) / 256));
+    const double2 *c = static_cast<const double2 *>(canon);
+    char *o = static_cast<char *>(packed);
+    switch (prec) {
+    case MOBIUS_F64: hipLaunchKernelGGL(pack_links_kernel<MOBIUS_F64>, grid, dim3(256), 0, st, D, g.V, g.Vh, g.canon_of, c, o); break;
+    case MOBIUS_F32: hipLaunchKernelGGL(pack_links_kernel<MOBIUS_F32>, grid, dim3(256), 0, st, D, g.V, g.Vh, g.canon_of, c, o); break;
+    case MOBIUS_F16: hipLaunchKernelGGL(pack_links_kernel<MOBIUS_F16>, grid, dim3(256), 0, st, D, g.V, g.Vh, g.canon_of, c, o); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_spinor(const Geometry &g, int prec, const void *canon, void *even, void *odd,
+                              int nrhs, hipStream_t st)
+{
+    const int64_t n = 2 * g.N5;
+    dim3 grid((unsigned)((n + 255) / 256));
+    const int64_t fb = field_bytes(g, prec);
+    for (int r = 0; r < nrhs; ++r) {
+        const double2 *c = static_cast<const double2 *>(canon) + (int64_t)r * 2 * g.N5 * 12;
+        char *e = static_cast<char *>(even) + r * fb;
+        char *o = static_cast<char *>(odd) + r * fb;
+        switch (prec) {
+        case MOBIUS_F64: hipLaunchKernelGGL(pack_spinor_kernel<MOBIUS_F64>, grid, dim3(256), 0, st, g.Vh, g.Ls, g.canon_of, c, e, o); break;
+        case MOBIUS_F32: hipLaunchKernelGGL(pack_spinor_kernel<MOBIUS_F32>, grid, dim3(256), 0, st, g.Vh, g.Ls, g.canon_of, c, e, o); break;
+        case MOBIUS_F16: hipLaunchKernelGGL(pack_spinor_kernel<MOBIUS_F16>, grid, dim3(256), 0, st, g.Vh, g.Ls, g.canon_of, c, e, o); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_spinor(const Geometry &g, int prec, const void *even, const void *odd,
+                                void *canon, int nrhs, hipStream_t st)
+{
+    const int64_t n = 2 * g.N5;
+    dim3 grid((unsigned)((n + 255) / 256));
+    const int64_t fb = field_bytes(g, prec);
+    for (int r = 0; r < nrhs; ++r) {
+        double2 *c = static_cast<double2 *>(canon) + (int64_t)r * 2 * g.N5 * 12;
+        const char *e = static_cast<const char *>(even) + r * fb;
+        const char *o = static_cast<const char *>(odd) + r * fb;
+        switch (prec) {
+        case MOBIUS_F64: hipLaunchKernelGGL(unpack_spinor_kernel<MOBIUS_F64>, grid, dim3(256), 0, st, g.Vh, g.Ls, g.canon_of, e, o, c); break;
+        case MOBIUS_F32: hipLaunchKernelGGL(unpack_spinor_kernel<MOBIUS_F32>, grid, dim3(256), 0, st, g.Vh, g.Ls, g.canon_of, e, o, c); break;
+        case MOBIUS_F16: hipLaunchKernelGGL(unpack_spinor_kernel<MOBIUS_F16>, grid, dim3(256), 0, st, g.Vh, g.Ls, g.canon_of, e, o, c); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+namespace {
+
+template <int P, bool DAG, int EPI>
+void hop_launch(const HopParams &hp, int64_t blocks, hipStream_t st)
+{
+    switch (hop_tuning().prefetch) {
+    case 0: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 0>), dim3((unsigned)blocks), dim3(BLOCK), 0, st, hp); break;
+    case 1: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 1>), dim3((unsigned)blocks), dim3(BLOCK), 0, st, hp); break;
+    default: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 2>), dim3((unsigned)blocks), dim3(BLOCK), 0, st, hp); break;
+    }
+}
+
+template <int P, bool DAG>
+hipError_t hop_dispatch(const HopParams &hp, int epi, int64_t blocks, hipStream_t st)
+{
+    switch (epi) {
+    case 0: hop_launch<P, DAG, 0>(hp, blocks, st); break;
+    case EPI_M5INV: hop_launch<P, DAG, EPI_M5INV>(hp, blocks, st); break;
+    case EPI_M5INV | EPI_POSTSUB: hop_launch<P, DAG, EPI_M5INV | EPI_POSTSUB>(hp, blocks, st); break;
+    case EPI_POSTSUB: hop_launch<P, DAG, EPI_POSTSUB>(hp, blocks, st); break;
+    case EPI_M5INV | EPI_POSTSUB | EPI_NORM:
+        hop_launch<P, DAG, EPI_M5INV | EPI_POSTSUB | EPI_NORM>(hp, blocks, st);
+        break;
+    case EPI_PRESUB | EPI_M5INV: hop_launch<P, DAG, EPI_PRESUB | EPI_M5INV>(hp, blocks, st); break;
+    case EPI_POSTSUB | EPI_NORM: hop_launch<P, DAG, EPI_POSTSUB | EPI_NORM>(hp, blocks, st); break;
+    case EPI_M5ADD: hop_launch<P, DAG, EPI_M5ADD>(hp, blocks, st); break;
+    case EPI_M5ADD | EPI_PRESUB | EPI_NORM:
+        hop_launch<P, DAG, EPI_M5ADD | EPI_PRESUB | EPI_NORM>(hp, blocks, st);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_hop(const Geometry &g, const OpCoeffs &c, const void *links, const int32_t *nbr,
+                      const HopArgs &a, hipStream_t st)
+{
+    HopParams hp;
+    const int64_t lb = (int64_t)8 * g.Vh * link_record_bytes(a.prec);
+    hp.links = static_cast<const char *>(links) + (int64_t)a.out_parity * lb;
+    hp.nbr = nbr + (int64_t)a.out_parity * 8 * g.Vh;
+    hp.partials = a.partials;
+    hp.Vh = g.Vh;
+    hp.N5 = g.N5;
+    hp.Ls = g.Ls;
+    hp.spw = sites_per_wave(g.Ls);
+    hp.remap = hop_tuning().xcd_remap;
+    hp.c = c;
+    const int64_t blocks = site_kernel_blocks(g);
+    const int64_t fb = field_bytes(g, a.prec);
+    int epi = a.epi & ~EPI_BDAG;
+    for (int r = 0; r < a.nrhs; ++r) {
+        hp.in = static_cast<const char *>(a.in) + r * fb;
+        hp.out = static_cast<char *>(a.out) + r * fb;
+        hp.x = a.x ? static_cast<const char *>(a.x) + r * fb : nullptr;
+        hp.y = a.y ? static_cast<const char *>(a.y) + r * fb : nullptr;
+        if (r > 0 && (epi & EPI_NORM)) hp.partials = a.partials + r * blocks;
+        hipError_t e;
+        if (a.dag) {
+            switch (a.prec) {
+            case MOBIUS_F64: e = hop_dispatch<MOBIUS_F64, true>(hp, epi, blocks, st); break;
+            case MOBIUS_F32: e = hop_dispatch<MOBIUS_F32, true>(hp, epi, blocks, st); break;
+            case MOBIUS_F16: e = hop_dispatch<MOBIUS_F16, true>(hp, epi, blocks, st); break;
+            default: e = hipErrorInvalidValue;
+            }
+        } else {
+            switch (a.prec) {
+            case MOBIUS_F64: e = hop_dispatch<MOBIUS_F64, false>(hp, epi, blocks, st); break;
+            case MOBIUS_F32: e = hop_dispatch<MOBIUS_F32, false>(hp, epi, blocks, st); break;
+            case MOBIUS_F16: e = hop_dispatch<MOBIUS_F16, false>(hp, epi, blocks, st); break;
+            default: e = hipErrorInvalidValue;
+            }
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+namespace {
+template <int P>
+void m5_launch(int kind, int dag, const char *in, char *out, const Geometry &g, const OpCoeffs &c,
+               int64_t blocks, hipStream_t st)
+{
+    const int spw = sites_per_wave(g.Ls);
+    dim3 grid((unsigned)blocks), blk(BLOCK);
+    if (kind == 0 && !dag) hipLaunchKernelGGL((m5_kernel<P, false, 0>), grid, blk, 0, st, in, out, g.Vh, g.N5, g.Ls, spw, c);
+    if (kind == 0 && dag) hipLaunchKernelGGL((m5_kernel<P, true, 0>), grid, blk, 0, st, in, out, g.Vh, g.N5, g.Ls, spw, c);
+    if (kind == 1 && !dag) hipLaunchKernelGGL((m5_kernel<P, false, 1>), grid, blk, 0, st, in, out, g.Vh, g.N5, g.Ls, spw, c);
+    if (kind == 1 && dag) hipLaunchKernelGGL((m5_kernel<P, true, 1>), grid, blk, 0, st, in, out, g.Vh, g.N5, g.Ls, spw, c);
+}
+}  // namespace
+
+hipError_t launch_m5(const Geometry &g, const OpCoeffs &c, int prec, int kind, int dag,
+                     const void *in, void *out, int nrhs, hipStream_t st)
+{
+    const int64_t blocks = site_kernel_blocks(g);
+    const int64_t fb = field_bytes(g, prec);
+    for (int r = 0; r < nrhs; ++r) {
+        const char *i = static_cast<const char *>(in) + r * fb;
+        char *o = static_cast<char *>(out) + r * fb;
+        switch (prec) {
+        case MOBIUS_F64: m5_launch<MOBIUS_F64>(kind, dag, i, o, g, c, blocks, st); break;
+        case MOBIUS_F32: m5_launch<MOBIUS_F32>(kind, dag, i, o, g, c, blocks, st); break;
+        case MOBIUS_F16: m5_launch<MOBIUS_F16>(kind, dag, i, o, g, c, blocks, st); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(const Geometry &g, int prec, const double *a, const void *x,
+                        const double *b, const void *y, void *out, int nrhs, hipStream_t st)
+{
+    dim3 grid((unsigned)blas_blocks(g)), blk(BLAS_BLOCK);
+    const int64_t fb = field_bytes(g, prec);
+    for (int r = 0; r < nrhs; ++r) {
+        const char *xx = static_cast<const char *>(x) + r * fb;
+        const char *yy = static_cast<const char *>(y) + r * fb;
+        char *o = static_cast<char *>(out) + r * fb;
+        switch (prec) {
+        case MOBIUS_F64: hipLaunchKernelGGL(axpby_kernel<MOBIUS_F64>, grid, blk, 0, st, g.N5, a, xx, b, yy, o); break;
+        case MOBIUS_F32: hipLaunchKernelGGL(axpby_kernel<MOBIUS_F32>, grid, blk, 0, st, g.N5, a, xx, b, yy, o); break;
+        case MOBIUS_F16: hipLaunchKernelGGL(axpby_kernel<MOBIUS_F16>, grid, blk, 0, st, g.N5, a, xx, b, yy, o); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_norm2(const Geometry &g, int prec, const void *x, double *partials, int nrhs,
+                        hipStream_t st)
+{
+    const int64_t nb = blas_blocks(g);
+    dim3 grid((unsigned)nb), blk(BLAS_BLOCK);
+    const int64_t fb = field_bytes(g, prec);
+    for (int r = 0; r < nrhs; ++r) {
+        const char *xx = static_cast<const char *>(x) + r * fb;
+        double *pp = partials + r * nb;
+        switch (prec) {
+        case MOBIUS_F64: hipLaunchKernelGGL(norm2_kernel<MOBIUS_F64>, grid, blk, 0, st, g.N5, xx, pp); break;
+        case MOBIUS_F32: hipLaunchKernelGGL(norm2_kernel<MOBIUS_F32>, grid, blk, 0, st, g.N5, xx, pp); break;
+        case MOBIUS_F16: hipLaunchKernelGGL(norm2_kernel<MOBIUS_F16>, grid, blk, 0, st, g.N5, xx, pp); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_xr(const Geometry &g, int prec, int prec_x, const double *alpha, void *x,
+                        const void *p, void *r, const void *q, double *partials, hipStream_t st)
+{
+    dim3 grid((unsigned)blas_blocks(g)), blk(BLAS_BLOCK);
+    char *xx = static_cast<char *>(x);
+    char *rr = static_cast<char *>(r);
+    const char *pp = static_cast<const char *>(p);
+    const char *qq = static_cast<const char *>(q);
+#define MOBIUS_XR(P, PX) hipLaunchKernelGGL((cg_xr_kernel<P, PX>), grid, blk, 0, st, g.N5, alpha, xx, pp, rr, qq, partials)
+    if (prec == MOBIUS_F64 && prec_x == MOBIUS_F64) MOBIUS_XR(MOBIUS_F64, MOBIUS_F64);
+    else if (prec == MOBIUS_F32 && prec_x == MOBIUS_F32) MOBIUS_XR(MOBIUS_F32, MOBIUS_F32);
+    else if (prec == MOBIUS_F32 && prec_x == MOBIUS_F64) MOBIUS_XR(MOBIUS_F32, MOBIUS_F64);
+    else if (prec == MOBIUS_F16 && prec_x == MOBIUS_F32) MOBIUS_XR(MOBIUS_F16, MOBIUS_F32);
+    else if (prec == MOBIUS_F16 && prec_x == MOBIUS_F64) MOBIUS_XR(MOBIUS_F16, MOBIUS_F64);
+    else if (prec == MOBIUS_F16 && prec_x == MOBIUS_F16) MOBIUS_XR(MOBIUS_F16, MOBIUS_F16);
+    else return hipErrorInvalidValue;
+#undef MOBIUS_XR
+    return hipGetLastError();
+}
+
+namespace {
+template <int PI>
+hipError_t convert_from(const Geometry &g, const char *in, int po, char *out, hipStream_t st)
+{
+    dim3 grid((unsigned)blas_blocks(g)), blk(BLAS_BLOCK);
+    switch (po) {
+    case MOBIUS_F64: hipLaunchKernelGGL((convert_kernel<PI, MOBIUS_F64>), grid, blk, 0, st, g.N5, in, out); break;
+    case MOBIUS_F32: hipLaunchKernelGGL((convert_kernel<PI, MOBIUS_F32>), grid, blk, 0, st, g.N5, in, out); break;
+    case MOBIUS_F16: hipLaunchKernelGGL((convert_kernel<PI, MOBIUS_F16>), grid, blk, 0, st, g.N5, in, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_convert(const Geometry &g, int prec_in, const void *in, int prec_out, void *out,
+                          hipStream_t st)
+{
+    const char *i = static_cast<const char *>(in);
+    char *o = static_cast<char *>(out);
+    switch (prec_in) {
+    case MOBIUS_F64: return convert_from<MOBIUS_F64>(g, i, prec_out, o, st);
+    case MOBIUS_F32: return convert_from<MOBIUS_F32>(g, i, prec_out, o, st);
+    case MOBIUS_F16: return convert_from<MOBIUS_F16>(g, i, prec_out, o, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_accumulate(const Geometry &g, int prec_lo, const void *x_lo, void *x_hi,
+                             hipStream_t st)
+{
+    dim3 grid((unsigned)blas_blocks(g)), blk(BLAS_BLOCK);
+    const char *lo = static_cast<const char *>(x_lo);
+    char *hi = static_cast<char *>(x_hi);
+    switch (prec_lo) {
+    case MOBIUS_F64: hipLaunchKernelGGL(accumulate_kernel<MOBIUS_F64>, grid, blk, 0, st, g.N5, lo, hi); break;
+    case MOBIUS_F32: hipLaunchKernelGGL(accumulate_kernel<MOBIUS_F32>, grid, blk, 0, st, g.N5, lo, hi); break;
+    case MOBIUS_F16: hipLaunchKernelGGL(accumulate_kernel<MOBIUS_F16>, grid, blk, 0, st, g.N5, lo, hi); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t st)
+{
+    const int64_t n16 = bytes / 16;
+    const int64_t ntail = bytes - n16 * 16;
+    const int64_t n = n16 > ntail ? n16 : ntail;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       static_cast<uint4 *>(ptr), n16,
+                       static_cast<unsigned char *>(ptr) + n16 * 16, ntail);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double *partials, int64_t n, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(RED_BLOCK), 0, st, partials, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_scalar(CgScalars *s, int op, hipStream_t st)
+{
+    hipLaunchKernelGGL(cg_scalar_kernel, dim3(1), dim3(64), 0, st, s, op);
+    return hipGetLastError();
+}
+
+}  // namespace mobius

@@ -1,0 +1,235 @@
+"""Thin Python binding of libmobius.so (argument marshalling only).
+
+Every operation runs in the HIP library; torch is used for device memory and
+the current stream.  Canonical fields are complex128 CUDA tensors:
+  links   [4][Lt][Lz][Ly][Lx][3][3]
+  spinor  [Ls][Lt][Lz][Ly][Lx][4][3]   (multi-RHS: leading [nrhs])
+Packed half-lattice fields are opaque uint8 tensors of
+``field_bytes(prec) * nrhs`` bytes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmobius.so")
+
+F64, F32, F16 = 0, 1, 2
+PREC = {"f64": F64, "f32": F32, "f16": F16}
+OP_HOP, OP_M5, OP_SCHUR = 0, 1, 2
+OK, NOT_CONVERGED = 0, 1
+
+EXPORTS = ("mobius_create", "mobius_destroy", "mobius_field_bytes", "mobius_pack",
+           "mobius_unpack", "mobius_dslash", "mobius_dslash_dag", "mobius_m5inv",
+           "mobius_cg_solve", "mobius_last_error")
+
+
+class MobiusError(RuntimeError):
+    pass
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32 * 4), ("Ls", ctypes.c_int32), ("M5", ctypes.c_double),
+                ("mf", ctypes.c_double), ("b5", ctypes.c_double), ("c5", ctypes.c_double)]
+
+
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int32),
+                ("inner_prec", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
+                ("nrhs", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("dirac_apps", ctypes.c_int32),
+                ("reliable_updates", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("true_resid", ctypes.c_double), ("schur_resid", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("algo_bytes", ctypes.c_double),
+                ("flops", ctypes.c_double)]
+
+
+@dataclass
+class SolveInfo:
+    iters: int
+    dirac_apps: int
+    reliable_updates: int
+    status: int
+    true_resid: float
+    schur_resid: float
+    seconds: float
+    algo_bytes: float
+    flops: float
+
+
+_lib = None
+
+
+def lib():
+    """Load libmobius.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MobiusError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1206_5214_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.mobius_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Params), vp, vp]
+        L.mobius_destroy.argtypes = [vp]
+        L.mobius_field_bytes.argtypes = [vp, i32]
+        L.mobius_field_bytes.restype = i64
+        L.mobius_pack.argtypes = [vp, i32, vp, vp, vp, i32, vp]
+        L.mobius_unpack.argtypes = [vp, i32, vp, vp, vp, i32, vp]
+        L.mobius_dslash.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp]
+        L.mobius_dslash_dag.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp]
+        L.mobius_m5inv.argtypes = [vp, i32, i32, vp, vp, i32, vp]
+        L.mobius_cg_solve.argtypes = [vp, vp, vp, ctypes.POINTER(_SolveOpts),
+                                      ctypes.POINTER(_SolveInfo), vp]
+        L.mobius_last_error.restype = ctypes.c_char_p
+        for f in EXPORTS:
+            if f not in ("mobius_field_bytes", "mobius_last_error"):
+                getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc < 0:
+        msg = lib().mobius_last_error().decode()
+        raise MobiusError(f"libmobius error {rc}: {msg}")
+    return rc
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _require_cuda(t, dtype=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise MobiusError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise MobiusError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise MobiusError(f"{name} must have dtype {dtype}, got {t.dtype}")
+
+
+class Operator:
+    """A red/black Moebius operator on one lattice (owns the packed links)."""
+
+    def __init__(self, dims, Ls, M5, mf, b5, c5, links):
+        import torch
+        _require_cuda(links, torch.complex128, "links")
+        Lx, Ly, Lz, Lt = dims
+        if tuple(links.shape) != (4, Lt, Lz, Ly, Lx, 3, 3):
+            raise MobiusError(f"links have shape {tuple(links.shape)}")
+        self.dims = tuple(int(d) for d in dims)
+        self.Ls = int(Ls)
+        self.params = dict(M5=M5, mf=mf, b5=b5, c5=c5)
+        p = _Params((ctypes.c_int32 * 4)(*self.dims), self.Ls, M5, mf, b5, c5)
+        h = ctypes.c_void_p()
+        _check(lib().mobius_create(ctypes.byref(h), ctypes.byref(p), _ptr(links), _stream()))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mobius_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- fields ----------------------------------------------------------
+    @property
+    def V(self):
+        Lx, Ly, Lz, Lt = self.dims
+        return Lx * Ly * Lz * Lt
+
+    def canon_shape(self, nrhs=None):
+        Lx, Ly, Lz, Lt = self.dims
+        s = (self.Ls, Lt, Lz, Ly, Lx, 4, 3)
+        return s if nrhs is None else (nrhs,) + s
+
+    def field_bytes(self, prec):
+        return int(lib().mobius_field_bytes(self._h, prec))
+
+    def new_field(self, prec, nrhs=1):
+        import torch
+        return torch.zeros(self.field_bytes(prec) * nrhs, dtype=torch.uint8, device="cuda")
+
+    def _check_canon(self, t, nrhs, name):
+        import torch
+        _require_cuda(t, torch.complex128, name)
+        want = 1
+        for d in self.canon_shape():
+            want *= d
+        if t.numel() != want * nrhs:
+            raise MobiusError(f"{name} has {t.numel()} elements, expected {want * nrhs}")
+
+    def _check_packed(self, t, prec, nrhs, name):
+        import torch
+        _require_cuda(t, torch.uint8, name)
+        need = self.field_bytes(prec)
+        if need < 0:
+            raise MobiusError(f"unknown precision {prec}")
+        if t.numel() < need * nrhs:
+            raise MobiusError(f"{name} holds {t.numel()} bytes, needs {need * nrhs}")
+
+    def pack(self, canon, prec, nrhs=1):
+        self._check_canon(canon, nrhs, "canonical field")
+        even, odd = self.new_field(prec, nrhs), self.new_field(prec, nrhs)
+        _check(lib().mobius_pack(self._h, prec, _ptr(canon), _ptr(even), _ptr(odd), nrhs,
+                                 _stream()))
+        return even, odd
+
+    def unpack(self, even, odd, prec, nrhs=1):
+        import torch
+        self._check_packed(even, prec, nrhs, "even half")
+        self._check_packed(odd, prec, nrhs, "odd half")
+        out = torch.empty(self.canon_shape(nrhs if nrhs > 1 else None), dtype=torch.complex128,
+                          device="cuda")
+        _check(lib().mobius_unpack(self._h, prec, _ptr(even), _ptr(odd), _ptr(out), nrhs,
+                                   _stream()))
+        return out
+
+    # -- operators -------------------------------------------------------
+    def dslash(self, x, out_parity, prec, op=OP_HOP, dag=False, out=None, nrhs=1):
+        """Red/black block of D_DW (or D_DW^+) on packed fields; see mobius.h."""
+        if out is None:
+            out = self.new_field(max(prec, 0) if prec in (F64, F32, F16) else F64, nrhs)
+        self._check_packed(x, prec, nrhs, "input")
+        self._check_packed(out, prec, nrhs, "output")
+        f = lib().mobius_dslash_dag if dag else lib().mobius_dslash
+        _check(f(self._h, prec, op, out_parity, _ptr(x), _ptr(out), nrhs, _stream()))
+        return out
+
+    def m5inv(self, x, prec, dag=False, out=None, nrhs=1):
+        if out is None:
+            out = self.new_field(prec, nrhs)
+        self._check_packed(x, prec, nrhs, "input")
+        self._check_packed(out, prec, nrhs, "output")
+        _check(lib().mobius_m5inv(self._h, prec, int(dag), _ptr(x), _ptr(out), nrhs, _stream()))
+        return out
+
+    def solve(self, src, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.1,
+              check_every=16):
+        """Solve D_DW psi = src (canonical complex128, optional leading nrhs)."""
+        import torch
+        nrhs = 1 if src.dim() == 7 else int(src.shape[0])
+        self._check_canon(src, nrhs, "source")
+        sol = torch.empty_like(src)
+        opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, nrhs, check_every)
+        infos = (_SolveInfo * nrhs)()
+        rc = _check(lib().mobius_cg_solve(self._h, _ptr(src), _ptr(sol), ctypes.byref(opts), infos,
+                                          _stream()))
+        out = [SolveInfo(i.iters, i.dirac_apps, i.reliable_updates, i.status, i.true_resid,
+                         i.schur_resid, i.seconds, i.algo_bytes, i.flops) for i in infos]
+        return sol, out, rc

@@ -1,0 +1,94 @@
+"""Red/black CG solves on the GPU vs the FP64 CPU oracle (through the C ABI).
+
+Targets: full-system true residual ||eta - D_DW psi|| / ||eta|| <= 1e-10
+(recomputed here with the oracle's own D_DW) and solution error vs the
+oracle solution <= 1e-8.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    return torch
+
+
+def _rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+SOLVE_CASES = [
+    # name, dims, Ls, M5, mf, b5, c5, eps, seed
+    ("shamir_4x4x4x4_ls8", (4, 4, 4, 4), 8, 1.8, 0.01, 1.0, 0.0, 0.3, 0),
+    ("mobius_4x4x4x8_ls12", (4, 4, 4, 8), 12, 1.8, 0.005, 1.75, 0.75, 0.6, 1),
+    ("mobius_6x4x4x4_ls16", (6, 4, 4, 4), 16, 1.8, 0.01, 1.5, 0.5, 0.5, 2),
+]
+
+
+@pytest.mark.parametrize("case", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
+@pytest.mark.parametrize("inner", [0, 1, 2], ids=["f64", "mixed_f32", "mixed_f16"])
+def test_solve_vs_oracle(torch_cuda, orc, case, inner):
+    from oracle import Params
+    from paper_1206_5214_amd import inputs, mobius
+    torch = torch_cuda
+    name, dims, Ls, M5, mf, b5, c5, eps, seed = case
+    _flush(f"solve {name} inner={inner}")
+    p = Params(dims, Ls, M5, mf, b5, c5)
+    rng = np.random.default_rng(seed)
+    U = inputs.random_links(dims, eps, rng)
+    eta = inputs.gaussian_spinor(dims, Ls, rng)
+    op = mobius.Operator(dims, Ls, M5, mf, b5, c5, torch.from_numpy(U).cuda())
+    sol, info, rc = op.solve(torch.from_numpy(eta).cuda(), tol=1e-10, maxiter=20000,
+                             inner_prec=inner)
+    _flush(f"  {info[0]}")
+    assert rc == mobius.OK, info
+    psi = sol.cpu().numpy()
+    # true residual with the oracle's operator
+    res = _rel(orc.dw(p, U, psi), eta)
+    assert res <= 1e-10, res
+    assert abs(res - info[0].true_resid) <= 1e-11 + 0.05 * res
+    psi_orc, oinfo = orc.solve(p, U, eta, tol=1e-13, maxiter=20000)
+    assert oinfo.converged
+    err = _rel(psi, psi_orc)
+    _flush(f"  true resid {res:.3e}  error vs oracle {err:.3e}  iters {info[0].iters}")
+    assert err <= 1e-8, err
+    op.close()
+
+
+def test_zero_source(torch_cuda):
+    from paper_1206_5214_amd import inputs, mobius
+    torch = torch_cuda
+    dims, Ls = (4, 4, 4, 4), 8
+    U = inputs.random_links(dims, 0.3, np.random.default_rng(0))
+    op = mobius.Operator(dims, Ls, 1.8, 0.01, 1.5, 0.5, torch.from_numpy(U).cuda())
+    src = torch.zeros(op.canon_shape(), dtype=torch.complex128, device="cuda")
+    sol, info, rc = op.solve(src)
+    assert rc == mobius.OK and info[0].iters == 0
+    assert torch.count_nonzero(sol).item() == 0
+    op.close()
+
+
+def test_maxiter_reports_not_converged(torch_cuda):
+    from paper_1206_5214_amd import inputs, mobius
+    torch = torch_cuda
+    dims, Ls = (4, 4, 4, 4), 8
+    rng = np.random.default_rng(0)
+    U = inputs.random_links(dims, 0.3, rng)
+    eta = inputs.gaussian_spinor(dims, Ls, rng)
+    op = mobius.Operator(dims, Ls, 1.8, 0.01, 1.5, 0.5, torch.from_numpy(U).cuda())
+    sol, info, rc = op.solve(torch.from_numpy(eta).cuda(), maxiter=3)
+    assert rc == mobius.NOT_CONVERGED
+    assert info[0].status == mobius.NOT_CONVERGED and info[0].iters == 3
+    assert info[0].true_resid > 1e-10
+    op.close()
