@@ -12,7 +12,8 @@ once per kernel, links once per hop) divided by that time.
 
 Also reported: the metered hop kernel (D_{p,1-p} = -1/2 H B, Sec. 3) per
 precision against the 8 TB/s HBM roofline, the plain-FP64 and mixed-FP32
-times to solution, and the CPU oracle timed on the host.
+times to solution, and the CPU oracle (one application of the Schur
+operator) timed on the host cores.
 
 Prints exactly one JSON line on stdout; progress goes to stderr.
 """
@@ -82,32 +83,25 @@ def counters_for(kernel_key):
     return rec.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(U, eta, w, sample_frac):
-    """The FP64 oracle's hop block, as it stands, on a bounded sample of the
-    even sites of the same workload; GB/s by the same algorithmic byte count."""
-    import numpy as np
+def cpu_baseline(U, eta, w):
+    """The FP64 oracle, as it stands, applying the red/black Schur operator
+    D_pre once to the odd half of the workload's source; GB/s by the same
+    algorithmic byte count as the GPU's two fused hop launches of D_pre."""
     import oracle
     p = oracle.Params(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5)
-    V = w.V
-    Lx, Ly, Lz, Lt = w.dims
-    idx = np.arange(V, dtype=np.int64)
-    x = idx % Lx
-    y = (idx // Lx) % Ly
-    z = (idx // (Lx * Ly)) % Lz
-    t = idx // (Lx * Ly * Lz)
-    even = idx[((x + y + z + t) % 2) == 0]
-    step = max(1, int(round(1.0 / sample_frac)))
-    sites = even[::step]
+    x_odd = oracle.restrict(p, eta, 1)
     t0 = time.perf_counter()
-    oracle.dw_sites(p, U, eta, sites, in_parity=1)
+    oracle.schur(p, U, x_odd)
     dt = time.perf_counter() - t0
-    # algorithmic bytes of the sampled fraction of one FP64 hop application
-    frac = len(sites) / (V // 2)
-    nbytes = frac * (2 * (V // 2) * w.Ls * 192 + 8 * 9 * (V // 2) * 16)
+    Vh = w.V // 2
+    fb = Vh * w.Ls * 192
+    links = 8 * 9 * Vh * 16
+    nbytes = 2 * (2 * fb + links) + fb
+    Lx, Ly, Lz, Lt = w.dims
     return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"FP64 oracle hop block D_eo (odd->even) at {len(sites)} of {V // 2} even "
-                      f"4d sites (all Ls={w.Ls} slices) of {Lx}x{Ly}x{Lz}x{Lt}; {dt:.1f} s"}
+            "sample": f"one FP64 oracle application of D_pre = 1 - I^-1 D_oe I^-1 D_eo to the odd "
+                      f"half of the {Lx}x{Ly}x{Lz}x{Lt}, Ls={w.Ls} source ({dt:.1f} s)"}
 
 
 def main():
@@ -121,7 +115,6 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 / FP32 comparison solves")
-    ap.add_argument("--cpu-sample", type=float, default=0.5)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -214,10 +207,10 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle hop on a sample of the same workload")
+        log("cpu baseline: one oracle Schur-operator application on the same workload")
         del op
         torch.cuda.empty_cache()
-        cpu = cpu_baseline(U, eta, w, args.cpu_sample)
+        cpu = cpu_baseline(U, eta, w)
         log(f"cpu baseline: {cpu['value']:.3f} GB/s on {cpu['cores']} threads ({cpu['sample']})")
 
     out = {
