@@ -107,8 +107,17 @@ struct HopArgs {
 // MOBIUS_PREFETCH=0/1/2 the software pipelining depth of the direction loop).
 struct HopTuning {
     int xcd_remap = 1;
-    int prefetch = 1;   // 0, 1 (next neighbour spinor), 2 (and its link)
+    int prefetch = -1;     // 0, 1 (next neighbour spinor), 2 (and its link); -1: per precision
+    int stage_links = 1;   // copy each block's links to LDS once
+    int nt_links = 0;      // non-temporal link loads
 };
+// prefetch depth used for a precision (measured at 24^3x64, Ls=12: FP64 is
+// register-limited at depth 2, FP32 and FP16 gain from it)
+inline int prefetch_depth(const HopTuning &t, int prec)
+{
+    if (t.prefetch >= 0) return t.prefetch;
+    return prec == MOBIUS_F64 ? 1 : 2;
+}
 // Brick of the site order for a lattice: MOBIUS_BRICK="bx,by,bz" overrides.
 void choose_brick(const int L[4], int Ls, int brick[3]);
 HopTuning &hop_tuning();

@@ -84,6 +84,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer, CDNA
+constexpr int CPOL_NT = 2;              // cache policy bit: non-temporal
 
 struct Buf {
     __amdgpu_buffer_rsrc_t r;
@@ -108,6 +109,11 @@ struct Buf {
     __device__ __forceinline__ void st16(u32x4 v, uint32_t voff, uint32_t soff) const
     {
         __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, 0);
+    }
+    // non-temporal variants (cache policy NT): data that is not re-read soon
+    __device__ __forceinline__ u32x4 ld16_nt(uint32_t voff, uint32_t soff) const
+    {
+        return __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, CPOL_NT);
     }
     __device__ __forceinline__ void st4(uint32_t v, uint32_t voff, uint32_t soff) const
     {
@@ -259,6 +265,14 @@ template <>
 struct Link<MOBIUS_F64> {
     using T = double;
     static constexpr int REC = 144;
+    __device__ static void from_words(const u32x4 *q, cx<T> u[9])
+    {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            double2 t = __builtin_bit_cast(double2, q[e]);
+            u[e] = {t.x, t.y};
+        }
+    }
     __device__ static void load(const Buf &b, uint32_t voff, uint32_t soff, cx<T> u[9])
     {
 #pragma unroll
@@ -272,6 +286,15 @@ template <>
 struct Link<MOBIUS_F32> {
     using T = float;
     static constexpr int REC = 80;
+    __device__ static void from_words(const u32x4 *q, cx<T> u[9])
+    {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            float4 t = __builtin_bit_cast(float4, q[k]);
+            u[2 * k] = {t.x, t.y};
+            if (2 * k + 1 < 9) u[2 * k + 1] = {t.z, t.w};
+        }
+    }
     __device__ static void load(const Buf &b, uint32_t voff, uint32_t soff, cx<T> u[9])
     {
 #pragma unroll
@@ -286,6 +309,16 @@ template <>
 struct Link<MOBIUS_F16> {
     using T = float;
     static constexpr int REC = 48;
+    __device__ static void from_words(const u32x4 *q, cx<T> u[9])
+    {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            half8 t = __builtin_bit_cast(half8, q[k]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (4 * k + j < 9) u[4 * k + j] = {(float)t[2 * j], (float)t[2 * j + 1]};
+        }
+    }
     __device__ static void load(const Buf &b, uint32_t voff, uint32_t soff, cx<T> u[9])
     {
 #pragma unroll
@@ -355,25 +388,35 @@ __device__ __forceinline__ void load_link(const Buf &links, uint32_t Vh, int d, 
     Link<P>::load(links, i * (uint32_t)Link<P>::REC, (uint32_t)d * Vh * (uint32_t)Link<P>::REC, u);
 }
 
-// u: the link of this direction as stored (element a*3+b of U_mu(x) or of
-// U_mu(x-mu), whose adjoint the backward term applies)
-template <int P, int MU, bool FWD, int SIGMA>
-__device__ __forceinline__ void hop_dir(const cx<typename Spin<P>::T> chi[12],
-                                        const cx<typename Spin<P>::T> u[9],
-                                        cx<typename Spin<P>::T> acc[12])
-{
-    using T = typename Spin<P>::T;
-    const T sg = (T)SIGMA;
-    // half spinor h = u + sigma A l  (2 spins x 3 colours)
-    cx<T> h0[3], h1[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        cx<T> o0, o1;
-        A_apply<T, MU>(chi[6 + a], chi[9 + a], o0, o1);
-        h0[a] = chi[a] + sg * o0;
-        h1[a] = chi[3 + a] + sg * o1;
+// The links of a block's sites, staged in LDS by one cooperative copy so
+// that each record crosses the vector-memory pipeline once instead of once
+// per s-lane.  Layout [d][site in block][record].
+template <int P>
+struct LinkSource {
+    const Buf *glob;
+    const char *lds;   // null: read from global memory
+    uint32_t Vh, i, sib, sites_blk;
+    __device__ __forceinline__ void get(int d, cx<typename Spin<P>::T> u[9]) const
+    {
+        constexpr int REC = Link<P>::REC;
+        if (lds) {
+            const u32x4 *q = reinterpret_cast<const u32x4 *>(lds + ((size_t)d * sites_blk + sib) * REC);
+            Link<P>::from_words(q, u);
+        } else {
+            load_link<P>(*glob, Vh, d, i, u);
+        }
     }
-    // colour multiply
+};
+
+// Colour multiply and reconstruction of one direction: acc += (1 + sigma g_mu) M h
+// given the half spinor h = (h0; h1) = u + sigma A_mu l, with M = U (forward)
+// or U^+ (backward).  u: the link as stored (element a*3+b of U_mu(x) or of
+// U_mu(x-mu), whose adjoint the backward term applies).
+template <typename T, int MU, bool FWD, int SIGMA>
+__device__ __forceinline__ void link_accumulate(const cx<T> h0[3], const cx<T> h1[3],
+                                                const cx<T> u[9], cx<T> acc[12])
+{
+    const T sg = (T)SIGMA;
     cx<T> w0[3], w1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -392,7 +435,6 @@ __device__ __forceinline__ void hop_dir(const cx<typename Spin<P>::T> chi[12],
                 w1[a] = cjmadd(w1[a], u[b * 3 + a], h1[b]);
             }
         }
-    // reconstruct and accumulate
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         acc[a] = acc[a] + w0[a];
@@ -401,6 +443,85 @@ __device__ __forceinline__ void hop_dir(const cx<typename Spin<P>::T> chi[12],
         Adag_apply<T, MU>(w0[a], w1[a], o0, o1);
         acc[6 + a] = acc[6 + a] + sg * o0;
         acc[9 + a] = acc[9 + a] + sg * o1;
+    }
+}
+
+// One direction from a full (already b5/c5-mixed) spinor chi.
+template <int P, int MU, bool FWD, int SIGMA>
+__device__ __forceinline__ void hop_dir(const cx<typename Spin<P>::T> chi[12],
+                                        const cx<typename Spin<P>::T> u[9],
+                                        cx<typename Spin<P>::T> acc[12])
+{
+    using T = typename Spin<P>::T;
+    const T sg = (T)SIGMA;
+    cx<T> h0[3], h1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<T> o0, o1;
+        A_apply<T, MU>(chi[6 + a], chi[9 + a], o0, o1);
+        h0[a] = chi[a] + sg * o0;
+        h1[a] = chi[3 + a] + sg * o1;
+    }
+    link_accumulate<T, MU, FWD, SIGMA>(h0, h1, u, acc);
+}
+
+// ---------------------------------------------------------------------------
+// FP16 direction step without dequantising the spinor: the raw binary16
+// words of the neighbour (and, for the b5/c5 mixing, of its s-1 and s+1
+// slices, fetched from the neighbouring lanes) enter the half spinor through
+// mixed-precision multiply-adds whose scalar factors fold the per-site norms
+// and the mixing weights:
+//   h = al u_s + bu u_{s-1} + sigma A (al l_s + bl l_{s+1}),
+//   al = b5 n_s, bu = c5 f n_{s-1}, bl = c5 f' n_{s+1}  (f, f' = -mf on the wrap).
+
+struct RawH {
+    half2v c[12];  // complex components as (re, im) binary16 pairs
+    float n;       // per-site norm
+};
+
+__device__ __forceinline__ void load_raw_f16(const Buf &b, uint32_t N5, uint32_t k, RawH &r)
+{
+    r.n = __builtin_bit_cast(float, b.ld4(k * 4u, 3u * N5 * 16u));
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const half8 t = __builtin_bit_cast(half8, b.ld16(k * 16u, (uint32_t)q * N5 * 16u));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            half2v h;
+            h.x = t[2 * j];
+            h.y = t[2 * j + 1];
+            r.c[4 * q + j] = h;
+        }
+    }
+}
+
+__device__ __forceinline__ half2v shfl_h2(half2v v, int lane)
+{
+    return __builtin_bit_cast(half2v, __shfl((int)__builtin_bit_cast(uint32_t, v), lane, 64));
+}
+
+__device__ __forceinline__ cx<float> f32(half2v v) { return {(float)v.x, (float)v.y}; }
+
+// h0, h1 for direction MU from raw halves: own spinor o, and (MIX) the P+ part
+// um of slice s-1 and the P- part lp of slice s+1 (6 complex each).
+template <int MU, int SIGMA, bool MIX>
+__device__ __forceinline__ void half_spinor_f16(const RawH &o, const half2v um[6], const half2v lp[6],
+                                                float al, float bu, float bl, cx<float> h0[3],
+                                                cx<float> h1[3])
+{
+    const float sal = (float)SIGMA * al, sbl = (float)SIGMA * bl;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<float> A0, A1;
+        A_apply<float, MU>(f32(o.c[6 + a]), f32(o.c[9 + a]), A0, A1);
+        h0[a] = al * f32(o.c[a]) + sal * A0;
+        h1[a] = al * f32(o.c[3 + a]) + sal * A1;
+        if constexpr (MIX) {
+            cx<float> B0, B1;
+            A_apply<float, MU>(f32(lp[a]), f32(lp[3 + a]), B0, B1);
+            h0[a] = h0[a] + bu * f32(um[a]) + sbl * B0;
+            h1[a] = h1[a] + bu * f32(um[3 + a]) + sbl * B1;
+        }
     }
 }
 
@@ -577,6 +698,8 @@ struct HopParams {
     int64_t Vh, N5;
     int Ls, spw;
     int remap;            // XCD-contiguous block order
+    int stage_links;      // copy the block's links to LDS first
+    int nt;               // non-temporal loads of the links
     OpCoeffs c;
 };
 
@@ -600,6 +723,29 @@ __global__ __launch_bounds__(BLOCK) void hop_kernel(HopParams hp)
     const Buf blink(hp.links, (int64_t)8 * hp.Vh * Link<P>::REC);
     const Buf bnbr(hp.nbr, 8 * hp.Vh * 4);
 
+    extern __shared__ u32x4 dyn_lds[];
+    LinkSource<P> ls;
+    ls.glob = &blink;
+    ls.lds = nullptr;
+    ls.Vh = Vh;
+    ls.i = i;
+    ls.sites_blk = (uint32_t)(WAVES * hp.spw);
+    // lanes without a site (idle tail lanes of a wavefront) read record 0
+    ls.sib = m.site_ok ? (uint32_t)(m.wave * hp.spw + m.g) : 0u;
+    if (hp.stage_links) {
+        constexpr uint32_t REC = Link<P>::REC;
+        const uint32_t i0 = (uint32_t)(logical_block(hp.remap) * WAVES * hp.spw);
+        const uint32_t nsites = min(ls.sites_blk, Vh - i0);
+        const uint32_t cpd = nsites * REC / 16u;  // 16-byte words per direction
+        for (uint32_t c = threadIdx.x; c < 8u * cpd; c += BLOCK) {
+            const uint32_t d = c / cpd, q = c - d * cpd;
+            const u32x4 v = hp.nt ? blink.ld16_nt(i0 * REC + q * 16u, d * Vh * REC)
+                                  : blink.ld16(i0 * REC + q * 16u, d * Vh * REC);
+            dyn_lds[(d * ls.sites_blk * REC) / 16u + q] = v;
+        }
+        ls.lds = reinterpret_cast<const char *>(dyn_lds);
+    }
+
     uint32_t jn[8];
     {
         const u32x4 n0 = bnbr.ld16(i * 32u, 0u), n1 = bnbr.ld16(i * 32u + 16u, 0u);
@@ -610,13 +756,70 @@ __global__ __launch_bounds__(BLOCK) void hop_kernel(HopParams hp)
         }
     }
 
+    if (hp.stage_links) __syncthreads();
+
     cx<T> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
 
+    if constexpr (P == MOBIUS_F16) {
+        // forward block: B mixing weights of this lane (norms folded in per direction)
+        const float wu = DAG ? 0.f : (float)k.c5 * (m.s == 0 ? -(float)k.mf : 1.f);
+        const float wl = DAG ? 0.f : (float)k.c5 * (m.s == Ls - 1 ? -(float)k.mf : 1.f);
+        RawH nx;
+        cx<T> unx[9];
+        load_raw_f16(bin, N5, jn[0], nx);
+        if constexpr (PF >= 2) ls.get(0, unx);
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const RawH o = nx;
+            if (d < 7) load_raw_f16(bin, N5, jn[d + 1], nx);
+            cx<T> u[9];
+            if constexpr (PF >= 2) {
+#pragma unroll
+                for (int e = 0; e < 9; ++e) u[e] = unx[e];
+                if (d < 7) ls.get(d + 1, unx);
+            } else {
+                ls.get(d, u);
+            }
+            constexpr int SF = DAG ? +1 : -1;
+            const int sig = d < 4 ? SF : -SF;
+            cx<float> h0[3], h1[3];
+            half2v um[6], lp[6];
+            float al, bu = 0.f, bl = 0.f;
+            if constexpr (!DAG) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    um[c] = shfl_h2(o.c[c], m.lm);
+                    lp[c] = shfl_h2(o.c[6 + c], m.lp);
+                }
+                al = (float)k.b5 * o.n;
+                bu = wu * __shfl(o.n, m.lm, 64);
+                bl = wl * __shfl(o.n, m.lp, 64);
+            } else {
+                al = o.n;
+            }
+            (void)sig;
+#define MOBIUS_HS(MU, SG) half_spinor_f16<MU, SG, !DAG>(o, um, lp, al, bu, bl, h0, h1)
+            switch (d) {
+            case 0: MOBIUS_HS(0, SF); link_accumulate<float, 0, true, SF>(h0, h1, u, acc); break;
+            case 1: MOBIUS_HS(1, SF); link_accumulate<float, 1, true, SF>(h0, h1, u, acc); break;
+            case 2: MOBIUS_HS(2, SF); link_accumulate<float, 2, true, SF>(h0, h1, u, acc); break;
+            case 3: MOBIUS_HS(3, SF); link_accumulate<float, 3, true, SF>(h0, h1, u, acc); break;
+            case 4: MOBIUS_HS(0, -SF); link_accumulate<float, 0, false, -SF>(h0, h1, u, acc); break;
+            case 5: MOBIUS_HS(1, -SF); link_accumulate<float, 1, false, -SF>(h0, h1, u, acc); break;
+            case 6: MOBIUS_HS(2, -SF); link_accumulate<float, 2, false, -SF>(h0, h1, u, acc); break;
+            default: MOBIUS_HS(3, -SF); link_accumulate<float, 3, false, -SF>(h0, h1, u, acc); break;
+            }
+#undef MOBIUS_HS
+#pragma unroll
+            for (int c = 0; c < 12; ++c) pin(acc[c]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
     cx<T> nxt[12], unx[9];
     if constexpr (PF >= 1) S::load(bin, N5, jn[0], nxt);
-    if constexpr (PF >= 2) load_link<P>(blink, Vh, 0, i, unx);
+    if constexpr (PF >= 2) ls.get(0, unx);
 
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
@@ -631,9 +834,9 @@ __global__ __launch_bounds__(BLOCK) void hop_kernel(HopParams hp)
         if constexpr (PF >= 2) {
 #pragma unroll
             for (int e = 0; e < 9; ++e) u[e] = unx[e];
-            if (d < 7) load_link<P>(blink, Vh, d + 1, i, unx);
+            if (d < 7) ls.get(d + 1, unx);
         } else {
-            load_link<P>(blink, Vh, d, i, u);
+            ls.get(d, u);
         }
         if constexpr (!DAG) {
             // B = b5 + c5 C5 on the input: gather s-1, s, s+1 of the neighbour
@@ -655,6 +858,7 @@ __global__ __launch_bounds__(BLOCK) void hop_kernel(HopParams hp)
 #pragma unroll
         for (int c = 0; c < 12; ++c) pin(acc[c]);
         __builtin_amdgcn_sched_barrier(0);
+    }
     }
     const T mhalf = (T)-0.5;
 #pragma unroll
@@ -996,6 +1200,8 @@ HopTuning &hop_tuning()
         HopTuning d;
         if (const char *e = std::getenv("MOBIUS_XCD_REMAP")) d.xcd_remap = std::atoi(e);
         if (const char *e = std::getenv("MOBIUS_PREFETCH")) d.prefetch = std::atoi(e);
+        if (const char *e = std::getenv("MOBIUS_STAGE_LINKS")) d.stage_links = std::atoi(e);
+        if (const char *e = std::getenv("MOBIUS_NT_LINKS")) d.nt_links = std::atoi(e);
         return d;
     }();
     return t;
@@ -1083,12 +1289,17 @@ hipError_t launch_unpack_spinor(const Geometry &g, int prec, const void *even, c
 namespace {
 
 template <int P, bool DAG, int EPI>
-void hop_launch(const HopParams &hp, int64_t blocks, hipStream_t st)
+void hop_launch(HopParams hp, int64_t blocks, hipStream_t st)
 {
-    switch (hop_tuning().prefetch) {
-    case 0: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 0>), dim3((unsigned)blocks), dim3(BLOCK), 0, st, hp); break;
-    case 1: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 1>), dim3((unsigned)blocks), dim3(BLOCK), 0, st, hp); break;
-    default: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 2>), dim3((unsigned)blocks), dim3(BLOCK), 0, st, hp); break;
+    // links of one block in LDS: [8][sites per block][record]
+    const size_t lds = (size_t)8 * WAVES * hp.spw * Link<P>::REC;
+    hp.stage_links = hop_tuning().stage_links && lds <= 64 * 1024;
+    hp.nt = hop_tuning().nt_links;
+    const size_t dyn = hp.stage_links ? lds : 0;
+    switch (prefetch_depth(hop_tuning(), P)) {
+    case 0: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 0>), dim3((unsigned)blocks), dim3(BLOCK), dyn, st, hp); break;
+    case 1: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 1>), dim3((unsigned)blocks), dim3(BLOCK), dyn, st, hp); break;
+    default: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 2>), dim3((unsigned)blocks), dim3(BLOCK), dyn, st, hp); break;
     }
 }
 
