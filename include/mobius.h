@@ -164,6 +164,17 @@ int mobius_m5inv(mobius_ctx *ctx, int32_t prec, int32_t dagger, const void *in, 
 int mobius_cg_solve(mobius_ctx *ctx, const void *src_c128, void *sol_c128,
                     const mobius_solve_opts *opts, mobius_solve_info *info, void *stream);
 
+/* Solve a batch of independent systems on lattices of possibly different
+ * sizes (one context each, opts->nrhs right-hand sides per context) in
+ * lockstep: every CG step of all systems is one launch (the hop kernels walk
+ * the concatenated block lists of all lattices in one persistent launch), so
+ * small lattices share the GPU.  src[j], sol[j]: canonical fields of context
+ * j; info: n * opts->nrhs entries in context-major order.  The contexts must
+ * be distinct.  Returns as mobius_cg_solve. */
+int mobius_batch_solve(int32_t n, mobius_ctx *const *ctxs, const void *const *src,
+                       void *const *sol, const mobius_solve_opts *opts, mobius_solve_info *info,
+                       void *stream);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *mobius_last_error(void);
 

@@ -98,8 +98,31 @@ struct HopArgs {
     void *out;          // parity out_parity
     const void *x;      // same parity as out (PRESUB/POSTSUB), may be null
     const void *y;      // same parity as out (M5ADD), may be null
-    double *partials;   // per-block |r|^2 (EPI_NORM)
+    double *partials;   // per-block |r|^2 (EPI_NORM), [rhs][pstride]
     int nrhs;
+    const int32_t *active = nullptr;  // per-rhs flags in device memory (null: all)
+    int64_t fstride = 0;  // bytes between rhs fields (0: one field)
+    int64_t pstride = 0;  // partial slots per rhs (0: the number of blocks)
+};
+
+// Kernel arguments of one hop launch over one lattice and nrhs fields (rhs r
+// at base + r * fstride); also the descriptor of one group of a batch.
+struct HopParams {
+    const char *in;
+    char *out;
+    const char *x;
+    const char *y;
+    const char *links;      // parity block of the packed links
+    const int32_t *nbr;     // parity block of the neighbour table
+    double *partials;       // [rhs][pstride], one slot per block
+    const int32_t *active;  // per-rhs flag (null: all); a zero skips that rhs
+    int64_t Vh, N5;
+    int64_t fstride, pstride, nblocks;
+    int Ls, spw, nrhs;
+    int remap;              // XCD-contiguous block order
+    int stage_links;        // copy the block's links to LDS first
+    int nt;                 // non-temporal loads of the links
+    OpCoeffs c;
 };
 
 // Launch parameters of the hop kernel chosen at run time (defaults are the
@@ -140,6 +163,12 @@ hipError_t launch_unpack_spinor(const Geometry &g, int prec, const void *even, c
                                 void *canon, int nrhs, hipStream_t st);
 hipError_t launch_hop(const Geometry &g, const OpCoeffs &c, const void *links, const int32_t *nbr,
                       const HopArgs &a, hipStream_t st);
+HopParams make_hop_params(const Geometry &g, const OpCoeffs &c, const void *links,
+                          const int32_t *nbr, const HopArgs &a);
+size_t hop_link_lds_bytes(int prec, int Ls);
+// persistent launch over groups (device array) with block prefix sums prefix[0..n]
+hipError_t launch_hop_batch(int prec, int dag, int epi, const HopParams *groups_dev, int ngroups,
+                            const int64_t *prefix_dev, size_t lds_bytes, int grid, hipStream_t st);
 // Per-site s-direction operators on one packed half field:
 //   kind 0: out = I in (dag: I^+ in); kind 1: out = I^-1 in (dag: I^-+ in)
 hipError_t launch_m5(const Geometry &g, const OpCoeffs &c, int prec, int kind, int dag,
@@ -181,4 +210,78 @@ struct CgScalars {
 // op 0: alpha = gamma / qq;  op 1: beta = gamma_new / gamma, gamma = gamma_new
 hipError_t launch_cg_scalar(CgScalars *s, int op, hipStream_t st);
 
+// One system (one lattice, one right-hand side) of a batched vector kernel.
+// Field roles per kernel:
+//   VEC_CG_XR       a = x (prec2), b = p, c = r, d = q, s0 = alpha; |r|^2 partials
+//   VEC_AXPBY(_NORM) d = s0 a + s1 b (null scalar = 1) [; |d|^2 partials]
+//   VEC_NORM2       |a|^2 partials
+//   VEC_CONVERT     b (prec2) = a (prec)
+//   VEC_ACCUMULATE  d (FP64) += a (prec); a = 0
+struct VecSys {
+    char *a, *b, *c, *d;
+    const double *s0, *s1;
+    double *partials;      // this system's partial slots
+    int64_t nparts;        // number of valid partial slots (for the reduction)
+    int64_t N5;
+    int32_t flag;          // index into the active flags (-1: always active)
+    int32_t pad;
+};
+enum VecKind { VEC_CG_XR, VEC_AXPBY, VEC_AXPBY_NORM, VEC_NORM2, VEC_CONVERT, VEC_ACCUMULATE };
+hipError_t launch_vec_batch(int kind, int prec, int prec2, const VecSys *sys_dev, int nsys,
+                            int64_t max_n5, const int32_t *active, hipStream_t st);
+// out[sys * out_stride] = sum of partials[0 .. count) of each system (count_override > 0)
+// or of its own nparts
+hipError_t launch_reduce_batch(const VecSys *sys_dev, int nsys, const int32_t *active,
+                               int64_t count_override, double *out, int64_t out_stride,
+                               hipStream_t st);
+hipError_t launch_cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t *active,
+                                  int32_t *restart, hipStream_t st);
+
+// device buffer owned by a context
+struct DevBuf {
+    void *p = nullptr;
+    int64_t bytes = 0;
+    hipError_t ensure(int64_t b)
+    {
+        if (b <= bytes) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) return e;
+            p = nullptr;
+            bytes = 0;
+        }
+        hipError_t e = hipMalloc(&p, b);
+        if (e == hipSuccess) bytes = b;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+// error reporting shared by the host files (message readable through mobius_last_error)
+int set_error(int code, const std::string &msg);
+
+// Batched red/black CG: ngroups lattices (contexts), each with nrhs systems.
+int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *const *sol,
+                const mobius_solve_opts &opts, mobius_solve_info *info, hipStream_t stream);
+
 }  // namespace mobius
+
+struct mobius_ctx {
+    mobius_params P{};
+    mobius::Geometry g{};
+    mobius::OpCoeffs c{};
+    int device = 0;
+    mobius::DevBuf canon_of;  // [2][Vh] canonical index of each packed site
+    mobius::DevBuf nbr;
+    mobius::DevBuf links[3];
+    mobius::DevBuf scratch;   // operator temporaries (SCHUR blocks)
+    mobius::DevBuf work;      // solver fields
+    mobius::DevBuf partials;  // reduction partials
+    mobius::DevBuf scalars;   // solver scalars, flags and descriptor tables
+    hipStream_t solve_stream = nullptr;
+};

@@ -548,20 +548,25 @@ __device__ __forceinline__ int64_t logical_block(int remap)
     return x * q + (x < r ? x : r) + c;
 }
 
-__device__ __forceinline__ SiteMap site_map(int Ls, int spw, int64_t Vh, int remap = 0)
+__device__ __forceinline__ SiteMap site_map_lb(int Ls, int spw, int64_t Vh, int64_t lb)
 {
     SiteMap m;
     m.lane = threadIdx.x & 63;
     m.wave = threadIdx.x >> 6;
     m.g = m.lane / Ls;
     m.s = m.lane - m.g * Ls;
-    int64_t i = (logical_block(remap) * WAVES + m.wave) * spw + m.g;
+    int64_t i = (lb * WAVES + m.wave) * spw + m.g;
     m.site_ok = (m.g < spw) && (i < Vh);
     m.i = m.site_ok ? i : 0;
     const int base = m.g * Ls;
     m.lm = base + (m.s == 0 ? Ls - 1 : m.s - 1);
     m.lp = base + (m.s == Ls - 1 ? 0 : m.s + 1);
     return m;
+}
+
+__device__ __forceinline__ SiteMap site_map(int Ls, int spw, int64_t Vh, int remap = 0)
+{
+    return site_map_lb(Ls, spw, Vh, logical_block(remap));
 }
 
 template <typename T>
@@ -658,8 +663,8 @@ __device__ __forceinline__ void m5inv_lanes(cx<T> r[12], const Coef<T> &k, const
     for (int c = 0; c < 12; ++c) r[c] = w[m.lane * ST + c];
 }
 
-// FP64 block reduction of one value per thread -> partials[blockIdx.x]
-__device__ __forceinline__ void block_sum_store(double v, double *partials)
+// FP64 block reduction of one value per thread -> partials[slot]
+__device__ __forceinline__ void block_sum_store(double v, double *partials, int64_t slot)
 {
     __shared__ double red[WAVES];
 #pragma unroll
@@ -671,8 +676,9 @@ __device__ __forceinline__ void block_sum_store(double v, double *partials)
         double t = 0;
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) t += red[w];
-        partials[blockIdx.x] = t;
+        partials[slot] = t;
     }
+    __syncthreads();  // red[] may be reused by the next call in this block
 }
 
 template <typename T>
@@ -687,39 +693,23 @@ __device__ __forceinline__ double site_norm2(const cx<T> r[12])
 // ---------------------------------------------------------------------------
 // hop kernel: out = epilogue( -1/2 sum_mu [...] )  on every s-slice
 
-struct HopParams {
-    const char *in;
-    char *out;
-    const char *x;
-    const char *y;
-    const char *links;    // parity block of the packed links
-    const int32_t *nbr;   // parity block of the neighbour table
-    double *partials;
-    int64_t Vh, N5;
-    int Ls, spw;
-    int remap;            // XCD-contiguous block order
-    int stage_links;      // copy the block's links to LDS first
-    int nt;               // non-temporal loads of the links
-    OpCoeffs c;
-};
 
 // PF: software pipelining of the direction loop.  0: operands of direction d
 // are loaded in segment d; 1: the neighbour spinor of direction d+1 is loaded
 // while direction d computes; 2: its link as well.  The eight neighbour
 // indices are always loaded up front.
 template <int P, bool DAG, int EPI, int PF>
-__global__ __launch_bounds__(BLOCK) void hop_kernel(HopParams hp)
+__device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
 {
     using S = Spin<P>;
     using T = typename S::T;
-    const SiteMap m = site_map(hp.Ls, hp.spw, hp.Vh, hp.remap);
+    const SiteMap m = site_map_lb(hp.Ls, hp.spw, hp.Vh, lb);
     const Coef<T> k = make_coef<T>(hp.c);
     const int Ls = hp.Ls;
     const uint32_t Vh = (uint32_t)hp.Vh, N5 = (uint32_t)hp.N5;
     const uint32_t i = (uint32_t)m.i;
     const uint32_t k5 = i * (uint32_t)Ls + (uint32_t)m.s;
     const int64_t fbytes = S::bytes(hp.N5);
-    const Buf bin(hp.in, fbytes), bout(hp.out, fbytes);
     const Buf blink(hp.links, (int64_t)8 * hp.Vh * Link<P>::REC);
     const Buf bnbr(hp.nbr, 8 * hp.Vh * 4);
 
@@ -734,7 +724,7 @@ __global__ __launch_bounds__(BLOCK) void hop_kernel(HopParams hp)
     ls.sib = m.site_ok ? (uint32_t)(m.wave * hp.spw + m.g) : 0u;
     if (hp.stage_links) {
         constexpr uint32_t REC = Link<P>::REC;
-        const uint32_t i0 = (uint32_t)(logical_block(hp.remap) * WAVES * hp.spw);
+        const uint32_t i0 = (uint32_t)(lb * WAVES * hp.spw);
         const uint32_t nsites = min(ls.sites_blk, Vh - i0);
         const uint32_t cpd = nsites * REC / 16u;  // 16-byte words per direction
         for (uint32_t c = threadIdx.x; c < 8u * cpd; c += BLOCK) {
@@ -757,6 +747,12 @@ __global__ __launch_bounds__(BLOCK) void hop_kernel(HopParams hp)
     }
 
     if (hp.stage_links) __syncthreads();
+
+    for (int r = 0; r < hp.nrhs; ++r) {
+    if (hp.active && !hp.active[r]) continue;
+    const Buf bin(hp.in + r * hp.fstride, fbytes), bout(hp.out + r * hp.fstride, fbytes);
+    const char *xr = hp.x ? hp.x + r * hp.fstride : nullptr;
+    const char *yr = hp.y ? hp.y + r * hp.fstride : nullptr;
 
     cx<T> acc[12];
 #pragma unroll
@@ -867,14 +863,14 @@ __global__ __launch_bounds__(BLOCK) void hop_kernel(HopParams hp)
     if constexpr (DAG) mix_s(acc, k.b5, k.c5, k.mf, m, Ls, true);  // B^+ on the output
     if constexpr ((EPI & EPI_M5ADD) != 0) {
         cx<T> yv[12];
-        S::load(Buf(hp.y, fbytes), N5, k5, yv);
+        S::load(Buf(yr, fbytes), N5, k5, yv);
         mix_s(yv, k.Mp, k.Mm, k.mf, m, Ls, DAG);  // I y = M+ y + M- C5 y
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] = acc[c] + yv[c];
     }
     if constexpr ((EPI & EPI_PRESUB) != 0) {
         cx<T> xv[12];
-        S::load(Buf(hp.x, fbytes), N5, k5, xv);
+        S::load(Buf(xr, fbytes), N5, k5, xv);
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] = xv[c] - acc[c];
     }
@@ -884,7 +880,7 @@ __global__ __launch_bounds__(BLOCK) void hop_kernel(HopParams hp)
     }
     if constexpr ((EPI & EPI_POSTSUB) != 0) {
         cx<T> xv[12];
-        S::load(Buf(hp.x, fbytes), N5, k5, xv);
+        S::load(Buf(xr, fbytes), N5, k5, xv);
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] = xv[c] - acc[c];
     }
@@ -892,9 +888,32 @@ __global__ __launch_bounds__(BLOCK) void hop_kernel(HopParams hp)
         // |stored value|^2, from the encoded registers
         double n = 0;
         if (m.site_ok) n = S::store_norm2(bout, N5, k5, acc);
-        block_sum_store(n, hp.partials);
+        block_sum_store(n, hp.partials + r * hp.pstride, lb);
     } else {
         if (m.site_ok) S::store(bout, N5, k5, acc);
+    }
+    }  // rhs
+}
+
+template <int P, bool DAG, int EPI, int PF>
+__global__ __launch_bounds__(BLOCK) void hop_kernel(HopParams hp)
+{
+    hop_block<P, DAG, EPI, PF>(hp, logical_block(hp.remap));
+}
+
+// Persistent launch over a batch of lattices of uneven size: a fixed grid
+// walks the concatenated block lists of all groups (group j owns work items
+// [prefix[j], prefix[j+1])); every workgroup exits after its last item.
+template <int P, bool DAG, int EPI, int PF>
+__global__ __launch_bounds__(BLOCK) void hop_batch_kernel(const HopParams *groups, int ngroups,
+                                                          const int64_t *prefix)
+{
+    const int64_t total = prefix[ngroups];
+    int j = 0;
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        while (w >= prefix[j + 1]) ++j;
+        hop_block<P, DAG, EPI, PF>(groups[j], w - prefix[j]);
+        __syncthreads();  // LDS of this item is dead before the next item stages
     }
 }
 
@@ -1087,7 +1106,7 @@ __global__ __launch_bounds__(BLAS_BLOCK) void norm2_kernel(int64_t N5, const cha
         S::load(Buf(x, S::bytes(N5)), (uint32_t)N5, (uint32_t)k, v);
         n = site_norm2(v);
     }
-    block_sum_store(n, partials);
+    block_sum_store(n, partials, blockIdx.x);
 }
 
 // x (precision PX) += alpha p;  r -= alpha q  (precision P);  partials of |r|^2.
@@ -1123,7 +1142,7 @@ __global__ __launch_bounds__(BLAS_BLOCK) void cg_xr_kernel(int64_t N5, const dou
         for (int c = 0; c < 12; ++c) rv[c] = rv[c] - al * pv[c];
         n = S::store_norm2(br, n5, kk, rv);
     }
-    block_sum_store(n, partials);
+    block_sum_store(n, partials, blockIdx.x);
 }
 
 template <int PI, int PO>
@@ -1160,6 +1179,176 @@ __global__ void zero_kernel(uint4 *p, int64_t n16, unsigned char *tail, int64_t 
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n16) p[k] = make_uint4(0, 0, 0, 0);
     if (k < ntail) tail[k] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// batched vector kernels: blockIdx.y selects the system (one lattice and one
+// right-hand side); systems whose active flag is zero return at once.
+
+__device__ __forceinline__ bool sys_inactive(const VecSys &v, const int32_t *active)
+{
+    return v.flag >= 0 && active && active[v.flag] == 0;
+}
+
+// x (PX) += alpha p;  r -= alpha q;  partials of |r|^2.  a = x, b = p, c = r, d = q, s0 = alpha.
+template <int P, int PX>
+__global__ __launch_bounds__(BLAS_BLOCK) void cg_xr_batch(const VecSys *sys, const int32_t *active)
+{
+    const VecSys v = sys[blockIdx.y];
+    if (sys_inactive(v, active)) return;
+    using S = Spin<P>;
+    using SX = Spin<PX>;
+    using T = typename S::T;
+    using TX = typename SX::T;
+    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if ((int64_t)blockIdx.x * BLAS_BLOCK >= v.N5) return;
+    double n = 0;
+    if (k < v.N5) {
+        const T al = (T)*v.s0;
+        const TX alx = (TX)*v.s0;
+        const int64_t fb = S::bytes(v.N5);
+        const uint32_t n5 = (uint32_t)v.N5, kk = (uint32_t)k;
+        const Buf bx(v.a, SX::bytes(v.N5)), bp(v.b, fb), br(v.c, fb), bq(v.d, fb);
+        cx<TX> xv[12];
+        cx<T> pv[12], rv[12];
+        SX::load(bx, n5, kk, xv);
+        S::load(bp, n5, kk, pv);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) xv[c] = xv[c] + alx * cx<TX>{(TX)pv[c].r, (TX)pv[c].i};
+        SX::store(bx, n5, kk, xv);
+        S::load(br, n5, kk, rv);
+        S::load(bq, n5, kk, pv);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) rv[c] = rv[c] - al * pv[c];
+        n = S::store_norm2(br, n5, kk, rv);
+    }
+    block_sum_store(n, v.partials, blockIdx.x);
+}
+
+// d = s0 * a + s1 * b  (null scalar = 1); optional partials of |d|^2
+template <int P, bool NORM>
+__global__ __launch_bounds__(BLAS_BLOCK) void axpby_batch(const VecSys *sys, const int32_t *active)
+{
+    const VecSys v = sys[blockIdx.y];
+    if (sys_inactive(v, active)) return;
+    using S = Spin<P>;
+    using T = typename S::T;
+    if ((int64_t)blockIdx.x * BLAS_BLOCK >= v.N5) return;
+    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    double n = 0;
+    if (k < v.N5) {
+        const T av = v.s0 ? (T)*v.s0 : (T)1, bv = v.s1 ? (T)*v.s1 : (T)1;
+        const int64_t fb = S::bytes(v.N5);
+        const uint32_t n5 = (uint32_t)v.N5, kk = (uint32_t)k;
+        cx<T> xv[12], yv[12];
+        S::load(Buf(v.a, fb), n5, kk, xv);
+        S::load(Buf(v.b, fb), n5, kk, yv);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) xv[c] = av * xv[c] + bv * yv[c];
+        if constexpr (NORM)
+            n = S::store_norm2(Buf(v.d, fb), n5, kk, xv);
+        else
+            S::store(Buf(v.d, fb), n5, kk, xv);
+    }
+    if constexpr (NORM) block_sum_store(n, v.partials, blockIdx.x);
+}
+
+// partials of |a|^2
+template <int P>
+__global__ __launch_bounds__(BLAS_BLOCK) void norm2_batch(const VecSys *sys, const int32_t *active)
+{
+    const VecSys v = sys[blockIdx.y];
+    if (sys_inactive(v, active)) return;
+    using S = Spin<P>;
+    using T = typename S::T;
+    if ((int64_t)blockIdx.x * BLAS_BLOCK >= v.N5) return;
+    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    double n = 0;
+    if (k < v.N5) {
+        cx<T> x[12];
+        S::load(Buf(v.a, S::bytes(v.N5)), (uint32_t)v.N5, (uint32_t)k, x);
+        n = site_norm2(x);
+    }
+    block_sum_store(n, v.partials, blockIdx.x);
+}
+
+// precision conversion b (PO) = a (PI); accumulate: d (F64) += a (PI)
+template <int PI, int PO>
+__global__ __launch_bounds__(BLAS_BLOCK) void convert_batch(const VecSys *sys, const int32_t *active)
+{
+    const VecSys v = sys[blockIdx.y];
+    if (sys_inactive(v, active)) return;
+    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (k >= v.N5) return;
+    cx<typename Spin<PI>::T> x[12];
+    Spin<PI>::load(Buf(v.a, Spin<PI>::bytes(v.N5)), (uint32_t)v.N5, (uint32_t)k, x);
+    cx<typename Spin<PO>::T> w[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) w[c] = {(typename Spin<PO>::T)x[c].r, (typename Spin<PO>::T)x[c].i};
+    Spin<PO>::store(Buf(v.b, Spin<PO>::bytes(v.N5)), (uint32_t)v.N5, (uint32_t)k, w);
+}
+
+template <int PI>
+__global__ __launch_bounds__(BLAS_BLOCK) void accumulate_batch(const VecSys *sys, const int32_t *active)
+{
+    const VecSys v = sys[blockIdx.y];
+    if (sys_inactive(v, active)) return;
+    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (k >= v.N5) return;
+    cx<typename Spin<PI>::T> x[12];
+    Spin<PI>::load(Buf(v.a, Spin<PI>::bytes(v.N5)), (uint32_t)v.N5, (uint32_t)k, x);
+    cx<double> h[12];
+    const Buf bh(v.d, Spin<MOBIUS_F64>::bytes(v.N5));
+    Spin<MOBIUS_F64>::load(bh, (uint32_t)v.N5, (uint32_t)k, h);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) h[c] = {h[c].r + (double)x[c].r, h[c].i + (double)x[c].i};
+    Spin<MOBIUS_F64>::store(bh, (uint32_t)v.N5, (uint32_t)k, h);
+    // the low-precision correction is consumed: clear it
+    cx<typename Spin<PI>::T> z[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) z[c] = {0, 0};
+    Spin<PI>::store(Buf(v.a, Spin<PI>::bytes(v.N5)), (uint32_t)v.N5, (uint32_t)k, z);
+}
+
+// One block per system: out[sys * out_stride] = sum of the system's partials
+// (fixed order).
+__global__ __launch_bounds__(1024) void reduce_batch(const VecSys *sys, const int32_t *active,
+                                                     int64_t count_override, double *out,
+                                                     int64_t out_stride)
+{
+    const VecSys v = sys[blockIdx.x];
+    if (sys_inactive(v, active)) return;
+    __shared__ double sm[1024];
+    const int64_t n = count_override > 0 ? count_override : v.nparts;
+    double t = 0;
+    for (int64_t k = threadIdx.x; k < n; k += 1024) t += v.partials[k];
+    sm[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x * out_stride] = sm[0];
+}
+
+// Per-system CG scalars.  op 0: alpha = gamma / qq;  op 1: beta = gamma_new /
+// gamma (0 when the system restarts), gamma = gamma_new.  Inactive systems get
+// alpha = beta = 0.
+__global__ void cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t *active,
+                                int32_t *restart)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nsys) return;
+    CgScalars &s = sc[j];
+    const bool on = !active || active[j];
+    if (op == 0) {
+        s.alpha = (on && s.qq > 0) ? s.gamma / s.qq : 0.0;
+    } else {
+        const bool rs = restart && restart[j];
+        s.beta = (on && !rs && s.gamma > 0) ? s.gamma_new / s.gamma : 0.0;
+        s.gamma = s.gamma_new;
+        if (restart) restart[j] = 0;
+    }
 }
 
 constexpr int RED_BLOCK = 1024;
@@ -1288,87 +1477,138 @@ hipError_t launch_unpack_spinor(const Geometry &g, int prec, const void *even, c
 
 namespace {
 
-template <int P, bool DAG, int EPI>
-void hop_launch(HopParams hp, int64_t blocks, hipStream_t st)
+// dynamic LDS of one block for the staged links: [8][sites per block][record]
+template <int P>
+size_t link_lds_bytes(int spw)
 {
-    // links of one block in LDS: [8][sites per block][record]
-    const size_t lds = (size_t)8 * WAVES * hp.spw * Link<P>::REC;
-    hp.stage_links = hop_tuning().stage_links && lds <= 64 * 1024;
-    hp.nt = hop_tuning().nt_links;
-    const size_t dyn = hp.stage_links ? lds : 0;
+    return (size_t)8 * WAVES * spw * Link<P>::REC;
+}
+
+template <int P, bool DAG, int EPI>
+void hop_launch(const HopParams &hp, hipStream_t st)
+{
+    const size_t dyn = hp.stage_links ? link_lds_bytes<P>(hp.spw) : 0;
+    const dim3 grid((unsigned)hp.nblocks), blk(BLOCK);
     switch (prefetch_depth(hop_tuning(), P)) {
-    case 0: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 0>), dim3((unsigned)blocks), dim3(BLOCK), dyn, st, hp); break;
-    case 1: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 1>), dim3((unsigned)blocks), dim3(BLOCK), dyn, st, hp); break;
-    default: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 2>), dim3((unsigned)blocks), dim3(BLOCK), dyn, st, hp); break;
+    case 0: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 0>), grid, blk, dyn, st, hp); break;
+    case 1: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 1>), grid, blk, dyn, st, hp); break;
+    default: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 2>), grid, blk, dyn, st, hp); break;
     }
 }
 
-template <int P, bool DAG>
-hipError_t hop_dispatch(const HopParams &hp, int epi, int64_t blocks, hipStream_t st)
+template <int P, bool DAG, int EPI>
+void hop_batch_launch(const HopParams *groups, int n, const int64_t *prefix, size_t dyn, int grid,
+                      hipStream_t st)
 {
-    switch (epi) {
-    case 0: hop_launch<P, DAG, 0>(hp, blocks, st); break;
-    case EPI_M5INV: hop_launch<P, DAG, EPI_M5INV>(hp, blocks, st); break;
-    case EPI_M5INV | EPI_POSTSUB: hop_launch<P, DAG, EPI_M5INV | EPI_POSTSUB>(hp, blocks, st); break;
-    case EPI_POSTSUB: hop_launch<P, DAG, EPI_POSTSUB>(hp, blocks, st); break;
-    case EPI_M5INV | EPI_POSTSUB | EPI_NORM:
-        hop_launch<P, DAG, EPI_M5INV | EPI_POSTSUB | EPI_NORM>(hp, blocks, st);
-        break;
-    case EPI_PRESUB | EPI_M5INV: hop_launch<P, DAG, EPI_PRESUB | EPI_M5INV>(hp, blocks, st); break;
-    case EPI_POSTSUB | EPI_NORM: hop_launch<P, DAG, EPI_POSTSUB | EPI_NORM>(hp, blocks, st); break;
-    case EPI_M5ADD: hop_launch<P, DAG, EPI_M5ADD>(hp, blocks, st); break;
-    case EPI_M5ADD | EPI_PRESUB | EPI_NORM:
-        hop_launch<P, DAG, EPI_M5ADD | EPI_PRESUB | EPI_NORM>(hp, blocks, st);
-        break;
-    default: return hipErrorInvalidValue;
+    switch (prefetch_depth(hop_tuning(), P)) {
+    case 0: hipLaunchKernelGGL((hop_batch_kernel<P, DAG, EPI, 0>), dim3(grid), dim3(BLOCK), dyn, st, groups, n, prefix); break;
+    case 1: hipLaunchKernelGGL((hop_batch_kernel<P, DAG, EPI, 1>), dim3(grid), dim3(BLOCK), dyn, st, groups, n, prefix); break;
+    default: hipLaunchKernelGGL((hop_batch_kernel<P, DAG, EPI, 2>), dim3(grid), dim3(BLOCK), dyn, st, groups, n, prefix); break;
     }
-    return hipGetLastError();
 }
+
+// Calls F<P, DAG, EPI>() for the runtime (prec, dag, epi); false if unsupported.
+template <template <int, bool, int> class F, class... A>
+bool dispatch_hop(int prec, int dag, int epi, A &&...args)
+{
+#define MOBIUS_EPI_CASES(P, D)                                                                     \
+    switch (epi) {                                                                                 \
+    case 0: F<P, D, 0>::run(args...); return true;                                                 \
+    case EPI_M5INV: F<P, D, EPI_M5INV>::run(args...); return true;                                 \
+    case EPI_M5INV | EPI_POSTSUB: F<P, D, EPI_M5INV | EPI_POSTSUB>::run(args...); return true;     \
+    case EPI_POSTSUB: F<P, D, EPI_POSTSUB>::run(args...); return true;                             \
+    case EPI_M5INV | EPI_POSTSUB | EPI_NORM:                                                       \
+        F<P, D, EPI_M5INV | EPI_POSTSUB | EPI_NORM>::run(args...);                                 \
+        return true;                                                                               \
+    case EPI_PRESUB | EPI_M5INV: F<P, D, EPI_PRESUB | EPI_M5INV>::run(args...); return true;       \
+    case EPI_POSTSUB | EPI_NORM: F<P, D, EPI_POSTSUB | EPI_NORM>::run(args...); return true;       \
+    case EPI_M5ADD: F<P, D, EPI_M5ADD>::run(args...); return true;                                 \
+    case EPI_M5ADD | EPI_PRESUB | EPI_NORM:                                                        \
+        F<P, D, EPI_M5ADD | EPI_PRESUB | EPI_NORM>::run(args...);                                  \
+        return true;                                                                               \
+    }                                                                                              \
+    return false;
+    if (dag) {
+        if (prec == MOBIUS_F64) { MOBIUS_EPI_CASES(MOBIUS_F64, true) }
+        if (prec == MOBIUS_F32) { MOBIUS_EPI_CASES(MOBIUS_F32, true) }
+        if (prec == MOBIUS_F16) { MOBIUS_EPI_CASES(MOBIUS_F16, true) }
+    } else {
+        if (prec == MOBIUS_F64) { MOBIUS_EPI_CASES(MOBIUS_F64, false) }
+        if (prec == MOBIUS_F32) { MOBIUS_EPI_CASES(MOBIUS_F32, false) }
+        if (prec == MOBIUS_F16) { MOBIUS_EPI_CASES(MOBIUS_F16, false) }
+    }
+#undef MOBIUS_EPI_CASES
+    return false;
+}
+
+template <int P, bool D, int E>
+struct RunHop {
+    static void run(const HopParams &hp, hipStream_t st) { hop_launch<P, D, E>(hp, st); }
+};
+template <int P, bool D, int E>
+struct RunHopBatch {
+    static void run(const HopParams *g, int n, const int64_t *prefix, size_t dyn, int grid,
+                    hipStream_t st)
+    {
+        hop_batch_launch<P, D, E>(g, n, prefix, dyn, grid, st);
+    }
+};
 
 }  // namespace
+
+size_t hop_link_lds_bytes(int prec, int Ls)
+{
+    const int spw = sites_per_wave(Ls);
+    switch (prec) {
+    case MOBIUS_F64: return link_lds_bytes<MOBIUS_F64>(spw);
+    case MOBIUS_F32: return link_lds_bytes<MOBIUS_F32>(spw);
+    default: return link_lds_bytes<MOBIUS_F16>(spw);
+    }
+}
+
+HopParams make_hop_params(const Geometry &g, const OpCoeffs &c, const void *links,
+                          const int32_t *nbr, const HopArgs &a)
+{
+    HopParams hp{};
+    const int64_t lb = (int64_t)8 * g.Vh * link_record_bytes(a.prec);
+    hp.links = static_cast<const char *>(links) + (int64_t)a.out_parity * lb;
+    hp.nbr = nbr + (int64_t)a.out_parity * 8 * g.Vh;
+    hp.in = static_cast<const char *>(a.in);
+    hp.out = static_cast<char *>(a.out);
+    hp.x = static_cast<const char *>(a.x);
+    hp.y = static_cast<const char *>(a.y);
+    hp.partials = a.partials;
+    hp.active = a.active;
+    hp.Vh = g.Vh;
+    hp.N5 = g.N5;
+    hp.fstride = a.fstride > 0 ? a.fstride : field_bytes(g, a.prec);
+    hp.nblocks = site_kernel_blocks(g);
+    hp.pstride = a.pstride > 0 ? a.pstride : hp.nblocks;
+    hp.Ls = g.Ls;
+    hp.spw = sites_per_wave(g.Ls);
+    hp.nrhs = a.nrhs;
+    hp.remap = hop_tuning().xcd_remap;
+    hp.stage_links = hop_tuning().stage_links && hop_link_lds_bytes(a.prec, g.Ls) <= 64 * 1024;
+    hp.nt = hop_tuning().nt_links;
+    hp.c = c;
+    return hp;
+}
 
 hipError_t launch_hop(const Geometry &g, const OpCoeffs &c, const void *links, const int32_t *nbr,
                       const HopArgs &a, hipStream_t st)
 {
-    HopParams hp;
-    const int64_t lb = (int64_t)8 * g.Vh * link_record_bytes(a.prec);
-    hp.links = static_cast<const char *>(links) + (int64_t)a.out_parity * lb;
-    hp.nbr = nbr + (int64_t)a.out_parity * 8 * g.Vh;
-    hp.partials = a.partials;
-    hp.Vh = g.Vh;
-    hp.N5 = g.N5;
-    hp.Ls = g.Ls;
-    hp.spw = sites_per_wave(g.Ls);
-    hp.remap = hop_tuning().xcd_remap;
-    hp.c = c;
-    const int64_t blocks = site_kernel_blocks(g);
-    const int64_t fb = field_bytes(g, a.prec);
-    int epi = a.epi & ~EPI_BDAG;
-    for (int r = 0; r < a.nrhs; ++r) {
-        hp.in = static_cast<const char *>(a.in) + r * fb;
-        hp.out = static_cast<char *>(a.out) + r * fb;
-        hp.x = a.x ? static_cast<const char *>(a.x) + r * fb : nullptr;
-        hp.y = a.y ? static_cast<const char *>(a.y) + r * fb : nullptr;
-        if (r > 0 && (epi & EPI_NORM)) hp.partials = a.partials + r * blocks;
-        hipError_t e;
-        if (a.dag) {
-            switch (a.prec) {
-            case MOBIUS_F64: e = hop_dispatch<MOBIUS_F64, true>(hp, epi, blocks, st); break;
-            case MOBIUS_F32: e = hop_dispatch<MOBIUS_F32, true>(hp, epi, blocks, st); break;
-            case MOBIUS_F16: e = hop_dispatch<MOBIUS_F16, true>(hp, epi, blocks, st); break;
-            default: e = hipErrorInvalidValue;
-            }
-        } else {
-            switch (a.prec) {
-            case MOBIUS_F64: e = hop_dispatch<MOBIUS_F64, false>(hp, epi, blocks, st); break;
-            case MOBIUS_F32: e = hop_dispatch<MOBIUS_F32, false>(hp, epi, blocks, st); break;
-            case MOBIUS_F16: e = hop_dispatch<MOBIUS_F16, false>(hp, epi, blocks, st); break;
-            default: e = hipErrorInvalidValue;
-            }
-        }
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const HopParams hp = make_hop_params(g, c, links, nbr, a);
+    if (!dispatch_hop<RunHop>(a.prec, a.dag, a.epi & ~EPI_BDAG, hp, st)) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_hop_batch(int prec, int dag, int epi, const HopParams *groups_dev, int ngroups,
+                            const int64_t *prefix_dev, size_t lds_bytes, int grid, hipStream_t st)
+{
+    if (!dispatch_hop<RunHopBatch>(prec, dag, epi & ~EPI_BDAG, groups_dev, ngroups, prefix_dev,
+                                   lds_bytes, grid, st))
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 namespace {
@@ -1513,6 +1753,83 @@ hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t st)
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        static_cast<uint4 *>(ptr), n16,
                        static_cast<unsigned char *>(ptr) + n16 * 16, ntail);
+    return hipGetLastError();
+}
+
+hipError_t launch_vec_batch(int kind, int prec, int prec2, const VecSys *sys_dev, int nsys,
+                            int64_t max_n5, const int32_t *active, hipStream_t st)
+{
+    const dim3 grid((unsigned)((max_n5 + BLAS_BLOCK - 1) / BLAS_BLOCK), (unsigned)nsys), blk(BLAS_BLOCK);
+#define MOBIUS_L(K) hipLaunchKernelGGL(K, grid, blk, 0, st, sys_dev, active)
+#define MOBIUS_P3(KT)                                                                   \
+    switch (prec) {                                                                     \
+    case MOBIUS_F64: MOBIUS_L((KT<MOBIUS_F64>)); break;                                 \
+    case MOBIUS_F32: MOBIUS_L((KT<MOBIUS_F32>)); break;                                 \
+    case MOBIUS_F16: MOBIUS_L((KT<MOBIUS_F16>)); break;                                 \
+    default: return hipErrorInvalidValue;                                               \
+    }
+    switch (kind) {
+    case VEC_CG_XR:
+        if (prec == MOBIUS_F64 && prec2 == MOBIUS_F64) MOBIUS_L((cg_xr_batch<MOBIUS_F64, MOBIUS_F64>));
+        else if (prec == MOBIUS_F32 && prec2 == MOBIUS_F32) MOBIUS_L((cg_xr_batch<MOBIUS_F32, MOBIUS_F32>));
+        else if (prec == MOBIUS_F16 && prec2 == MOBIUS_F32) MOBIUS_L((cg_xr_batch<MOBIUS_F16, MOBIUS_F32>));
+        else return hipErrorInvalidValue;
+        break;
+    case VEC_AXPBY:
+        switch (prec) {
+        case MOBIUS_F64: MOBIUS_L((axpby_batch<MOBIUS_F64, false>)); break;
+        case MOBIUS_F32: MOBIUS_L((axpby_batch<MOBIUS_F32, false>)); break;
+        case MOBIUS_F16: MOBIUS_L((axpby_batch<MOBIUS_F16, false>)); break;
+        default: return hipErrorInvalidValue;
+        }
+        break;
+    case VEC_AXPBY_NORM:
+        switch (prec) {
+        case MOBIUS_F64: MOBIUS_L((axpby_batch<MOBIUS_F64, true>)); break;
+        case MOBIUS_F32: MOBIUS_L((axpby_batch<MOBIUS_F32, true>)); break;
+        case MOBIUS_F16: MOBIUS_L((axpby_batch<MOBIUS_F16, true>)); break;
+        default: return hipErrorInvalidValue;
+        }
+        break;
+    case VEC_NORM2: MOBIUS_P3(norm2_batch) break;
+    case VEC_ACCUMULATE: MOBIUS_P3(accumulate_batch) break;
+    case VEC_CONVERT:
+#define MOBIUS_CV(PI)                                                                   \
+    switch (prec2) {                                                                    \
+    case MOBIUS_F64: MOBIUS_L((convert_batch<PI, MOBIUS_F64>)); break;                  \
+    case MOBIUS_F32: MOBIUS_L((convert_batch<PI, MOBIUS_F32>)); break;                  \
+    case MOBIUS_F16: MOBIUS_L((convert_batch<PI, MOBIUS_F16>)); break;                  \
+    default: return hipErrorInvalidValue;                                               \
+    }
+        switch (prec) {
+        case MOBIUS_F64: MOBIUS_CV(MOBIUS_F64) break;
+        case MOBIUS_F32: MOBIUS_CV(MOBIUS_F32) break;
+        case MOBIUS_F16: MOBIUS_CV(MOBIUS_F16) break;
+        default: return hipErrorInvalidValue;
+        }
+#undef MOBIUS_CV
+        break;
+    default: return hipErrorInvalidValue;
+    }
+#undef MOBIUS_P3
+#undef MOBIUS_L
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_batch(const VecSys *sys_dev, int nsys, const int32_t *active,
+                               int64_t count_override, double *out, int64_t out_stride,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_batch, dim3(nsys), dim3(1024), 0, st, sys_dev, active, count_override,
+                       out, out_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t *active,
+                                  int32_t *restart, hipStream_t st)
+{
+    hipLaunchKernelGGL(cg_scalar_batch, dim3((nsys + 63) / 64), dim3(64), 0, st, sc, nsys, op,
+                       active, restart);
     return hipGetLastError();
 }
 

@@ -1,0 +1,656 @@
+// mobius_solver.cpp -- red/black CGLS for one or many systems at once.
+//
+// A "system" is one right-hand side on one lattice; a "group" is one lattice
+// (context) with its nrhs systems.  All systems of a solve iterate in
+// lockstep: every CG step is a handful of launches that cover every system
+// (the hop kernels stage each block's links in LDS once and reuse them for
+// all right-hand sides of the group; with several groups the hop is one
+// persistent launch over the concatenated block lists of all lattices).
+// Every system has its own CG scalars in device memory and an active flag
+// honoured by every kernel, so converged systems stop costing bandwidth.
+//
+// Algorithm per system (Sec. 3 and Sec. 4.1 of the paper; CGLS on the
+// normal equations of the Schur operator):
+//   b' = I^-1 (eta_o - D_oe I^-1 eta_e)
+//   CGLS on D_pre x = b' with the operator and Krylov vectors in precision lo,
+//     FP64 reductions, x accumulated in a correction x_lo (FP32 for FP16);
+//   reliable update (lo != FP64): when |r| < delta * |r| at the last update,
+//     x_hi += x_lo and r = b' - D_pre x_hi in FP64; if that did not at least
+//     halve the true residual, the next direction restarts (beta = 0:
+//     defect correction);
+//   when |r| reaches the Schur target: psi_e = I^-1 (eta_e - D_eo x_hi) and
+//   the FP64 true residual |eta - D_DW psi| / |eta|; below tol the system is
+//   done, otherwise its Schur target is tightened and it continues.
+// Iterations run in chunks of check_every captured in a hipGraph (the host
+// looks at the residuals only between chunks).
+#include "mobius_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace mobius {
+namespace {
+
+#define CK(expr)                                                                                  \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return set_error(MOBIUS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+int env_int(const char *name, int dflt)
+{
+    const char *e = std::getenv(name);
+    return e ? std::atoi(e) : dflt;
+}
+
+// fields of a group (each holds nrhs consecutive packed fields)
+enum Field { F_ETA_E, F_ETA_O, F_B, F_XH, F_RH, F_T64, F_U64, F_Q64, F_PE,  // FP64
+             F_X,                                                          // correction
+             F_R, F_P, F_Q, F_S, F_T, F_U,                                 // precision lo
+             NFIELDS, F_NONE = -1 };
+
+struct Group {
+    mobius_ctx *ctx;
+    int nrhs, sys0;
+    const char *src;
+    char *sol;
+    int64_t fb[NFIELDS];      // bytes of one field of each kind
+    char *f[NFIELDS];
+    int64_t hop_blocks, blas_blocks;
+};
+
+// extra per-system doubles
+enum Extra { X_BNORM2 = 0, X_RES_E = 2, X_RES_O = 3, X_HR = 4, X_ETA_E2 = 5, X_ETA_O2 = 6,
+             X_MINUS1 = 8, NEXTRA = 16 };
+
+struct HopPattern {
+    int prec, dag, epi, out_parity;
+    Field in, out, x, y;
+    bool norm;
+};
+
+enum HopPid { HP_D0A, HP_D0B, HP_D1B, HP_D1C, HP_H0A, HP_H0B, NHOP };
+enum VecPid { VP_XR, VP_PUPD, VP_CONV_RH_R, VP_ACC, VP_RES, VP_HOPRED, VP_BLASRED, VP_NORM_B,
+              VP_NORM_EE, VP_NORM_EO, VP_CONV_B_RH, NVEC };
+
+struct Batch {
+    std::vector<Group> groups;
+    int nsys = 0;
+    int lo = MOBIUS_F64, px = MOBIUS_F64;
+    hipStream_t st = nullptr;
+    int64_t pstride = 0, max_n5 = 0;
+    // device state (in the first context's buffers)
+    double *part = nullptr;
+    CgScalars *sc = nullptr;
+    double *extra = nullptr;
+    int32_t *active = nullptr, *restart = nullptr;
+    HopParams *hop_tab = nullptr;   // [NHOP][ngroups]
+    VecSys *vec_tab = nullptr;      // [NVEC][nsys]
+    int64_t *prefix = nullptr;      // [NHOP][ngroups + 1]
+    size_t hop_lds[NHOP] = {};
+    int batch_grid = 0;
+    HopPattern hp[NHOP];
+    // host mirrors
+    std::vector<int32_t> h_active, h_restart;
+    std::vector<HopParams> h_hop;
+    std::vector<VecSys> h_vec;
+    std::vector<int64_t> h_prefix;
+    // accounting (count_only: account a graph replay without launching)
+    bool count_only = false;
+    int dirac = 0;
+    double abytes = 0, aflops = 0;
+
+    int ngroups() const { return (int)groups.size(); }
+    int nactive() const
+    {
+        int n = 0;
+        for (int j = 0; j < nsys; ++j) n += h_active[j] != 0;
+        return n;
+    }
+    double sum_fb(int prec, bool active_only) const
+    {
+        double b = 0;
+        for (const Group &g : groups)
+            for (int r = 0; r < g.nrhs; ++r)
+                if (!active_only || h_active[g.sys0 + r]) b += (double)field_bytes(g.ctx->g, prec);
+        return b;
+    }
+    double sum_n5(bool active_only) const
+    {
+        double n = 0;
+        for (const Group &g : groups)
+            for (int r = 0; r < g.nrhs; ++r)
+                if (!active_only || h_active[g.sys0 + r]) n += (double)g.ctx->g.N5;
+        return n;
+    }
+    double sum_links(int prec) const
+    {
+        double b = 0;
+        for (const Group &g : groups) b += 72.0 * g.ctx->g.Vh * link_elem_bytes(prec);
+        return b;
+    }
+
+    int setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *const *sol, int nrhs,
+              int prec);
+    HopArgs hop_args_for(const Group &g, const HopPattern &p) const;
+    hipError_t hop(int pid);
+    hipError_t hop_group(const Group &g, int prec, int dag, int epi, int out_parity, Field in,
+                         Field out, Field x, Field y, bool norm);
+    hipError_t vec(int pid, int kind, int prec, int prec2);
+    hipError_t reduce(int pid, double *out, int64_t stride, bool all = false);
+    hipError_t m5inv_dag_all(Field in, Field out);
+    hipError_t body();                   // one CG iteration
+    hipError_t reliable_update();        // x_hi += x, r = b - D x_hi (FP64), r_lo = r
+    hipError_t finalize_group(const Group &g);
+    int fetch(std::vector<double> &out, int which);
+    void acct_hop(int prec, int epi, double fields, double n5);
+};
+
+int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *const *sol,
+                 int nrhs, int prec)
+{
+    lo = prec;
+    px = prec == MOBIUS_F16 ? MOBIUS_F32 : prec;
+    groups.resize(n);
+    nsys = 0;
+    for (int j = 0; j < n; ++j) {
+        Group &g = groups[j];
+        g.ctx = ctxs[j];
+        g.nrhs = nrhs;
+        g.sys0 = nsys;
+        nsys += nrhs;
+        g.src = static_cast<const char *>(src[j]);
+        g.sol = static_cast<char *>(sol[j]);
+        const Geometry &G = g.ctx->g;
+        for (int k = 0; k < NFIELDS; ++k)
+            g.fb[k] = field_bytes(G, k <= F_PE ? MOBIUS_F64 : k == F_X ? px : lo);
+        int64_t need = 4096;
+        for (int k = 0; k < NFIELDS; ++k) need += g.fb[k] * nrhs;
+        CK(g.ctx->work.ensure(need));
+        char *w = static_cast<char *>(g.ctx->work.p);
+        for (int k = 0; k < NFIELDS; ++k) {
+            g.f[k] = w;
+            w += g.fb[k] * nrhs;
+        }
+        g.hop_blocks = site_kernel_blocks(G);
+        g.blas_blocks = blas_blocks(G);
+        pstride = std::max(pstride, std::max(g.hop_blocks, g.blas_blocks));
+        max_n5 = std::max(max_n5, G.N5);
+    }
+    // hop call patterns of the iteration and of the reliable update
+    hp[HP_D0A] = {lo, 0, EPI_M5INV, 0, F_P, F_T, F_NONE, F_NONE, false};
+    hp[HP_D0B] = {lo, 0, EPI_M5INV | EPI_POSTSUB | EPI_NORM, 1, F_T, F_Q, F_P, F_NONE, true};
+    hp[HP_D1B] = {lo, 1, EPI_M5INV, 0, F_U, F_T, F_NONE, F_NONE, false};
+    hp[HP_D1C] = {lo, 1, EPI_POSTSUB | EPI_NORM, 1, F_T, F_S, F_R, F_NONE, true};
+    hp[HP_H0A] = {MOBIUS_F64, 0, EPI_M5INV, 0, F_XH, F_T64, F_NONE, F_NONE, false};
+    hp[HP_H0B] = {MOBIUS_F64, 0, EPI_M5INV | EPI_POSTSUB, 1, F_T64, F_Q64, F_XH, F_NONE, false};
+
+    // device state in the first context
+    mobius_ctx *c0 = groups[0].ctx;
+    CK(c0->partials.ensure((int64_t)nsys * pstride * (int64_t)sizeof(double)));
+    part = static_cast<double *>(c0->partials.p);
+    const int ng = n;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    };
+    const size_t o_sc = carve(sizeof(CgScalars) * nsys);
+    const size_t o_ex = carve(sizeof(double) * NEXTRA * nsys);
+    const size_t o_ac = carve(sizeof(int32_t) * nsys);
+    const size_t o_rs = carve(sizeof(int32_t) * nsys);
+    const size_t o_hop = carve(sizeof(HopParams) * NHOP * ng);
+    const size_t o_vec = carve(sizeof(VecSys) * NVEC * nsys);
+    const size_t o_pre = carve(sizeof(int64_t) * NHOP * (ng + 1));
+    CK(c0->scalars.ensure((int64_t)off));
+    char *base = static_cast<char *>(c0->scalars.p);
+    sc = reinterpret_cast<CgScalars *>(base + o_sc);
+    extra = reinterpret_cast<double *>(base + o_ex);
+    active = reinterpret_cast<int32_t *>(base + o_ac);
+    restart = reinterpret_cast<int32_t *>(base + o_rs);
+    hop_tab = reinterpret_cast<HopParams *>(base + o_hop);
+    vec_tab = reinterpret_cast<VecSys *>(base + o_vec);
+    prefix = reinterpret_cast<int64_t *>(base + o_pre);
+
+    // descriptor tables
+    h_hop.assign((size_t)NHOP * ng, HopParams{});
+    h_prefix.assign((size_t)NHOP * (ng + 1), 0);
+    for (int pid = 0; pid < NHOP; ++pid) {
+        int64_t acc = 0;
+        hop_lds[pid] = 0;
+        for (int j = 0; j < ng; ++j) {
+            const Group &g = groups[j];
+            const HopParams h = make_hop_params(g.ctx->g, g.ctx->c, g.ctx->links[hp[pid].prec].p,
+                                                static_cast<const int32_t *>(g.ctx->nbr.p),
+                                                hop_args_for(g, hp[pid]));
+            h_hop[(size_t)pid * ng + j] = h;
+            h_prefix[(size_t)pid * (ng + 1) + j] = acc;
+            acc += h.nblocks;
+            if (h.stage_links) hop_lds[pid] = std::max(hop_lds[pid], hop_link_lds_bytes(hp[pid].prec, g.ctx->g.Ls));
+        }
+        h_prefix[(size_t)pid * (ng + 1) + ng] = acc;
+    }
+    // groups of one batch launch must agree on staging (one dynamic LDS size)
+    for (int pid = 0; pid < NHOP; ++pid)
+        for (int j = 0; j < ng; ++j) h_hop[(size_t)pid * ng + j].stage_links = hop_lds[pid] > 0 &&
+            h_hop[(size_t)pid * ng + j].stage_links;
+    h_vec.assign((size_t)NVEC * nsys, VecSys{});
+    for (const Group &g : groups)
+        for (int r = 0; r < g.nrhs; ++r) {
+            const int j = g.sys0 + r;
+            auto F = [&](Field k) { return g.f[k] + r * g.fb[k]; };
+            VecSys v{};
+            v.N5 = g.ctx->g.N5;
+            v.flag = j;
+            v.partials = part + (int64_t)j * pstride;
+            v.nparts = g.blas_blocks;
+            VecSys t = v;
+            t.a = F(F_X); t.b = F(F_P); t.c = F(F_R); t.d = F(F_Q); t.s0 = &sc[j].alpha;
+            h_vec[(size_t)VP_XR * nsys + j] = t;
+            t = v; t.a = F(F_S); t.b = F(F_P); t.d = F(F_P); t.s1 = &sc[j].beta;
+            h_vec[(size_t)VP_PUPD * nsys + j] = t;
+            t = v; t.a = F(F_RH); t.b = F(F_R);
+            h_vec[(size_t)VP_CONV_RH_R * nsys + j] = t;
+            t = v; t.a = F(F_X); t.d = F(F_XH);
+            h_vec[(size_t)VP_ACC * nsys + j] = t;
+            t = v; t.a = F(F_B); t.b = F(F_Q64); t.s1 = &extra[j * NEXTRA + X_MINUS1]; t.d = F(F_RH);
+            h_vec[(size_t)VP_RES * nsys + j] = t;
+            t = v; t.nparts = g.hop_blocks;
+            h_vec[(size_t)VP_HOPRED * nsys + j] = t;
+            h_vec[(size_t)VP_BLASRED * nsys + j] = v;
+            t = v; t.a = F(F_B);
+            h_vec[(size_t)VP_NORM_B * nsys + j] = t;
+            t = v; t.a = F(F_ETA_E);
+            h_vec[(size_t)VP_NORM_EE * nsys + j] = t;
+            t = v; t.a = F(F_ETA_O);
+            h_vec[(size_t)VP_NORM_EO * nsys + j] = t;
+            t = v; t.a = F(F_B); t.b = F(F_RH);
+            h_vec[(size_t)VP_CONV_B_RH * nsys + j] = t;
+        }
+    h_active.assign(nsys, 1);
+    h_restart.assign(nsys, 1);
+    CK(hipMemcpyAsync(hop_tab, h_hop.data(), sizeof(HopParams) * h_hop.size(), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(vec_tab, h_vec.data(), sizeof(VecSys) * h_vec.size(), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(prefix, h_prefix.data(), sizeof(int64_t) * h_prefix.size(), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(active, h_active.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(restart, h_restart.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st));
+    std::vector<double> h_extra((size_t)nsys * NEXTRA, 0.0);
+    for (int j = 0; j < nsys; ++j) h_extra[(size_t)j * NEXTRA + X_MINUS1] = -1.0;
+    CK(hipMemcpyAsync(extra, h_extra.data(), sizeof(double) * h_extra.size(), hipMemcpyHostToDevice, st));
+    CK(hipStreamSynchronize(st));  // the host tables above are pageable and local
+    int dev = 0, ncu = 256;
+    CK(hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 256;
+    batch_grid = ncu * 8;
+    return MOBIUS_OK;
+}
+
+HopArgs Batch::hop_args_for(const Group &g, const HopPattern &p) const
+{
+    HopArgs a;
+    a.prec = p.prec;
+    a.dag = p.dag;
+    a.epi = p.epi;
+    a.out_parity = p.out_parity;
+    a.in = g.f[p.in];
+    a.out = g.f[p.out];
+    a.x = p.x == F_NONE ? nullptr : g.f[p.x];
+    a.y = p.y == F_NONE ? nullptr : g.f[p.y];
+    a.partials = p.norm ? part + (int64_t)g.sys0 * pstride : nullptr;
+    a.nrhs = g.nrhs;
+    a.active = active + g.sys0;
+    a.fstride = g.fb[p.in];
+    a.pstride = pstride;
+    return a;
+}
+
+void Batch::acct_hop(int prec, int epi, double fields, double n5)
+{
+    // per active system: in + out (+ x, + y) spinors; links once per group
+    double nf = 2 + ((epi & (EPI_PRESUB | EPI_POSTSUB)) ? 1 : 0) + ((epi & EPI_M5ADD) ? 1 : 0);
+    abytes += nf * fields + sum_links(prec);
+    aflops += n5 * (1416 + ((epi & EPI_M5INV) ? 96 : 0) + ((epi & (EPI_PRESUB | EPI_POSTSUB)) ? 24 : 0) +
+                    ((epi & EPI_M5ADD) ? 96 : 0) + ((epi & EPI_NORM) ? 48 : 0));
+}
+
+hipError_t Batch::hop(int pid)
+{
+    const HopPattern &p = hp[pid];
+    acct_hop(p.prec, p.epi, sum_fb(p.prec, true), sum_n5(true));
+    if (count_only) return hipSuccess;
+    if (ngroups() == 1) {
+        const Group &g = groups[0];
+        return launch_hop(g.ctx->g, g.ctx->c, g.ctx->links[p.prec].p,
+                          static_cast<const int32_t *>(g.ctx->nbr.p), hop_args_for(g, p), st);
+    }
+    return launch_hop_batch(p.prec, p.dag, p.epi, hop_tab + (size_t)pid * ngroups(), ngroups(),
+                            prefix + (size_t)pid * (ngroups() + 1), hop_lds[pid], batch_grid, st);
+}
+
+hipError_t Batch::hop_group(const Group &g, int prec, int dag, int epi, int out_parity, Field in,
+                            Field out, Field x, Field y, bool norm)
+{
+    HopPattern p{prec, dag, epi, out_parity, in, out, x, y, norm};
+    HopArgs a = hop_args_for(g, p);
+    a.active = nullptr;  // every right-hand side of the group
+    abytes += (2 + (x != F_NONE) + (y != F_NONE)) * (double)g.fb[in] * g.nrhs +
+              72.0 * g.ctx->g.Vh * link_elem_bytes(prec);
+    aflops += (double)g.ctx->g.N5 * g.nrhs * 1416;
+    return launch_hop(g.ctx->g, g.ctx->c, g.ctx->links[prec].p,
+                      static_cast<const int32_t *>(g.ctx->nbr.p), a, st);
+}
+
+hipError_t Batch::vec(int pid, int kind, int prec, int prec2)
+{
+    const double fb = sum_fb(prec, true), fb2 = sum_fb(prec2, true), n5 = sum_n5(true);
+    switch (kind) {
+    case VEC_CG_XR: abytes += 2 * fb2 + 4 * fb; aflops += 144 * n5; break;
+    case VEC_AXPBY: abytes += 3 * fb; aflops += 48 * n5; break;
+    case VEC_AXPBY_NORM: abytes += 3 * fb; aflops += 96 * n5; break;
+    case VEC_NORM2: abytes += fb; aflops += 48 * n5; break;
+    case VEC_CONVERT: abytes += fb + fb2; break;
+    case VEC_ACCUMULATE: abytes += 2 * fb + 2 * sum_fb(MOBIUS_F64, true); aflops += 24 * n5; break;
+    }
+    if (count_only) return hipSuccess;
+    return launch_vec_batch(kind, prec, prec2, vec_tab + (size_t)pid * nsys, nsys, max_n5, active, st);
+}
+
+hipError_t Batch::reduce(int pid, double *out, int64_t stride, bool all)
+{
+    if (count_only) return hipSuccess;
+    return launch_reduce_batch(vec_tab + (size_t)pid * nsys, nsys, all ? nullptr : active, 0, out,
+                               stride, st);
+}
+
+hipError_t Batch::m5inv_dag_all(Field in, Field out)
+{
+    for (const Group &g : groups) {
+        abytes += 2.0 * g.fb[in] * g.nrhs;
+        aflops += 96.0 * g.ctx->g.N5 * g.nrhs;
+        if (count_only) continue;
+        hipError_t e = launch_m5(g.ctx->g, g.ctx->c, lo, 1, 1, g.f[in], g.f[out], g.nrhs, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+constexpr int64_t SC_STRIDE = sizeof(CgScalars) / sizeof(double);
+
+// s = D^+ r (gamma_new); beta; p = s + beta p;  q = D p (qq); alpha;  x += alpha p, r -= alpha q (rr)
+hipError_t Batch::body()
+{
+    hipError_t e;
+    dirac += 4;
+    if ((e = m5inv_dag_all(F_R, F_U)) != hipSuccess) return e;
+    if ((e = hop(HP_D1B)) != hipSuccess) return e;
+    if ((e = hop(HP_D1C)) != hipSuccess) return e;
+    if ((e = reduce(VP_HOPRED, &sc[0].gamma_new, SC_STRIDE)) != hipSuccess) return e;
+    if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 1, active, restart, st)) != hipSuccess) return e;
+    if ((e = vec(VP_PUPD, VEC_AXPBY, lo, lo)) != hipSuccess) return e;
+    if ((e = hop(HP_D0A)) != hipSuccess) return e;
+    if ((e = hop(HP_D0B)) != hipSuccess) return e;
+    if ((e = reduce(VP_HOPRED, &sc[0].qq, SC_STRIDE)) != hipSuccess) return e;
+    if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 0, active, restart, st)) != hipSuccess) return e;
+    if ((e = vec(VP_XR, VEC_CG_XR, lo, px)) != hipSuccess) return e;
+    return reduce(VP_BLASRED, &sc[0].rr, SC_STRIDE);
+}
+
+hipError_t Batch::reliable_update()
+{
+    hipError_t e;
+    dirac += 2;
+    if ((e = vec(VP_ACC, VEC_ACCUMULATE, px, MOBIUS_F64)) != hipSuccess) return e;
+    if ((e = hop(HP_H0A)) != hipSuccess) return e;
+    if ((e = hop(HP_H0B)) != hipSuccess) return e;
+    if ((e = vec(VP_RES, VEC_AXPBY_NORM, MOBIUS_F64, MOBIUS_F64)) != hipSuccess) return e;
+    if ((e = reduce(VP_BLASRED, &extra[X_HR], NEXTRA)) != hipSuccess) return e;
+    return vec(VP_CONV_RH_R, VEC_CONVERT, MOBIUS_F64, lo);
+}
+
+// psi_e = I^-1 (eta_e - D_eo x_hi); |eta - D_DW psi|^2 per parity -> extra
+hipError_t Batch::finalize_group(const Group &g)
+{
+    hipError_t e;
+    dirac += 3;
+    if ((e = hop_group(g, MOBIUS_F64, 0, EPI_PRESUB | EPI_M5INV, 0, F_XH, F_PE, F_ETA_E, F_NONE, false)) != hipSuccess) return e;
+    if ((e = hop_group(g, MOBIUS_F64, 0, EPI_M5ADD | EPI_PRESUB | EPI_NORM, 0, F_XH, F_T64, F_ETA_E, F_PE, true)) != hipSuccess) return e;
+    if ((e = launch_reduce_batch(vec_tab + (size_t)VP_HOPRED * nsys + g.sys0, g.nrhs, nullptr, 0,
+                                 &extra[g.sys0 * NEXTRA + X_RES_E], NEXTRA, st)) != hipSuccess) return e;
+    if ((e = hop_group(g, MOBIUS_F64, 0, EPI_M5ADD | EPI_PRESUB | EPI_NORM, 1, F_PE, F_Q64, F_ETA_O, F_XH, true)) != hipSuccess) return e;
+    return launch_reduce_batch(vec_tab + (size_t)VP_HOPRED * nsys + g.sys0, g.nrhs, nullptr, 0,
+                               &extra[g.sys0 * NEXTRA + X_RES_O], NEXTRA, st);
+}
+
+// which: -1 = rr of every system, otherwise extra[which] of every system
+int Batch::fetch(std::vector<double> &out, int which)
+{
+    out.resize(nsys);
+    if (which < 0) {
+        std::vector<CgScalars> h(nsys);
+        CK(hipMemcpyAsync(h.data(), sc, sizeof(CgScalars) * nsys, hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        for (int j = 0; j < nsys; ++j) out[j] = h[j].rr;
+    } else {
+        std::vector<double> h((size_t)nsys * NEXTRA);
+        CK(hipMemcpyAsync(h.data(), extra, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        for (int j = 0; j < nsys; ++j) out[j] = h[(size_t)j * NEXTRA + which];
+    }
+    return MOBIUS_OK;
+}
+
+}  // namespace
+
+int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *const *sol,
+                const mobius_solve_opts &o, mobius_solve_info *info, hipStream_t user)
+{
+    const int nrhs = o.nrhs > 0 ? o.nrhs : 1;
+    const double tol = o.tol > 0 ? o.tol : 1e-10;
+    const int maxiter = o.maxiter > 0 ? o.maxiter : 10000;
+    const bool mixed = o.inner_prec != MOBIUS_F64;
+    const double delta = mixed ? (o.reliable_delta > 0 ? o.reliable_delta : 0.1) : 0.0;
+    const int check = o.check_every > 0 ? o.check_every : (mixed ? 8 : 16);
+    const bool use_graph = env_int("MOBIUS_GRAPH", 1) != 0;
+
+    Batch B;
+    mobius_ctx *c0 = ctxs[0];
+    if (!c0->solve_stream) CK(hipStreamCreateWithFlags(&c0->solve_stream, hipStreamNonBlocking));
+    B.st = c0->solve_stream;
+    // events and the captured graph are released on every return path
+    struct Owned {
+        hipEvent_t ev_in = nullptr, ev0 = nullptr, ev1 = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t gexec = nullptr;
+        ~Owned()
+        {
+            if (gexec) (void)hipGraphExecDestroy(gexec);
+            if (graph) (void)hipGraphDestroy(graph);
+            for (hipEvent_t e : {ev_in, ev0, ev1})
+                if (e) (void)hipEventDestroy(e);
+        }
+    } own;
+    CK(hipEventCreateWithFlags(&own.ev_in, hipEventDisableTiming));
+    CK(hipEventCreate(&own.ev0));
+    CK(hipEventCreate(&own.ev1));
+    CK(hipEventRecord(own.ev_in, user));
+    CK(hipStreamWaitEvent(B.st, own.ev_in, 0));
+    CK(hipEventRecord(own.ev0, B.st));
+    if (int rc = B.setup(ctxs, ngroups, src, sol, nrhs, o.inner_prec)) return rc;
+    const int nsys = B.nsys;
+    hipStream_t st = B.st;
+
+    // source preparation, per group: b' = I^-1 (eta_o - D_oe I^-1 eta_e)
+    for (const Group &g : B.groups) {
+        const double canon = 2.0 * g.ctx->g.N5 * 12 * 16 * g.nrhs;
+        B.abytes += canon + 2.0 * g.fb[F_ETA_E] * g.nrhs;
+        CK(launch_pack_spinor(g.ctx->g, MOBIUS_F64, g.src, g.f[F_ETA_E], g.f[F_ETA_O], g.nrhs, st));
+        CK(launch_m5(g.ctx->g, g.ctx->c, MOBIUS_F64, 1, 0, g.f[F_ETA_E], g.f[F_T64], g.nrhs, st));
+        CK(B.hop_group(g, MOBIUS_F64, 0, EPI_PRESUB | EPI_M5INV, 1, F_T64, F_B, F_ETA_O, F_NONE, false));
+        CK(launch_zero(g.f[F_XH], g.fb[F_XH] * g.nrhs, st));
+        CK(launch_zero(g.f[F_X], g.fb[F_X] * g.nrhs, st));
+        CK(launch_zero(g.f[F_P], g.fb[F_P] * g.nrhs, st));  // beta = 0 times p must be 0
+    }
+    B.dirac += 1;
+    CK(B.vec(VP_NORM_B, VEC_NORM2, MOBIUS_F64, MOBIUS_F64));
+    CK(B.reduce(VP_BLASRED, &B.extra[X_BNORM2], NEXTRA, true));
+    CK(B.vec(VP_NORM_EE, VEC_NORM2, MOBIUS_F64, MOBIUS_F64));
+    CK(B.reduce(VP_BLASRED, &B.extra[X_ETA_E2], NEXTRA, true));
+    CK(B.vec(VP_NORM_EO, VEC_NORM2, MOBIUS_F64, MOBIUS_F64));
+    CK(B.reduce(VP_BLASRED, &B.extra[X_ETA_O2], NEXTRA, true));
+    CK(B.vec(VP_CONV_B_RH, VEC_CONVERT, MOBIUS_F64, MOBIUS_F64));
+    CK(B.vec(VP_CONV_RH_R, VEC_CONVERT, MOBIUS_F64, B.lo));
+    std::vector<double> bnorm2, eta_e2, eta_o2;
+    if (int rc = B.fetch(bnorm2, X_BNORM2)) return rc;
+    if (int rc = B.fetch(eta_e2, X_ETA_E2)) return rc;
+    if (int rc = B.fetch(eta_o2, X_ETA_O2)) return rc;
+
+    std::vector<double> tol_s(nsys, tol), rmax2(bnorm2), true_res(nsys, INFINITY),
+        schur_res(nsys, INFINITY);
+    std::vector<int> iters(nsys, 0), reliable(nsys, 0), converged(nsys, 0), pending(nsys, 0);
+    for (int j = 0; j < nsys; ++j) {
+        if (bnorm2[j] == 0.0) {  // nothing to iterate: psi_o = 0
+            B.h_active[j] = 0;
+            pending[j] = 1;
+        }
+    }
+
+    hipGraphExec_t &gexec = own.gexec;
+    hipGraph_t &graph = own.graph;
+    int it = 0;
+    auto sync_flags = [&]() -> int {
+        CK(hipMemcpyAsync(B.active, B.h_active.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st));
+        CK(hipMemcpyAsync(B.restart, B.h_restart.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st));
+        CK(hipStreamSynchronize(st));  // host copies are pageable; the device clears restart flags
+        std::fill(B.h_restart.begin(), B.h_restart.end(), 0);
+        return MOBIUS_OK;
+    };
+    if (int rc = sync_flags()) return rc;
+
+    while (true) {
+        // finalize systems whose Schur residual reached the target
+        bool any_pending = false;
+        for (int j = 0; j < nsys; ++j) any_pending |= pending[j] != 0;
+        if (any_pending) {
+            for (const Group &g : B.groups) {
+                bool gp = false;
+                for (int r = 0; r < g.nrhs; ++r) gp |= pending[g.sys0 + r] != 0;
+                if (gp) CK(B.finalize_group(g));
+            }
+            std::vector<double> re, ro, hr;
+            if (int rc = B.fetch(re, X_RES_E)) return rc;
+            if (int rc = B.fetch(ro, X_RES_O)) return rc;
+            if (int rc = B.fetch(hr, X_HR)) return rc;
+            for (int j = 0; j < nsys; ++j) {
+                if (!pending[j]) continue;
+                pending[j] = 0;
+                const double en = std::sqrt(eta_e2[j] + eta_o2[j]);
+                true_res[j] = en > 0 ? std::sqrt(re[j] + ro[j]) / en : 0.0;
+                schur_res[j] = bnorm2[j] > 0 ? std::sqrt(hr[j] / bnorm2[j]) : 0.0;
+                if (true_res[j] <= tol || bnorm2[j] == 0.0) {
+                    converged[j] = 1;
+                    B.h_active[j] = 0;
+                } else {
+                    tol_s[j] *= std::max(0.05, 0.5 * tol / true_res[j]);
+                    B.h_active[j] = 1;
+                    B.h_restart[j] = 1;
+                }
+            }
+            if (int rc = sync_flags()) return rc;
+        }
+        if (B.nactive() == 0 || it >= maxiter) break;
+
+        // a chunk of iterations
+        const int k = std::min(check, maxiter - it);
+        if (use_graph && k == check) {
+            if (!gexec) {
+                CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                hipError_t e = hipSuccess;
+                for (int q = 0; q < k && e == hipSuccess; ++q) e = B.body();
+                hipError_t e2 = hipStreamEndCapture(st, &graph);
+                CK(e);
+                CK(e2);
+                CK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+            } else {
+                // account the replay without launching anything
+                B.count_only = true;
+                for (int q = 0; q < k; ++q) (void)B.body();
+                B.count_only = false;
+            }
+            CK(hipGraphLaunch(gexec, st));
+        } else {
+            for (int q = 0; q < k; ++q) CK(B.body());
+        }
+        it += k;
+        for (int j = 0; j < nsys; ++j)
+            if (B.h_active[j]) iters[j] += k;
+
+        std::vector<double> rr;
+        if (int rc = B.fetch(rr, -1)) return rc;
+        bool need_update = false;
+        for (int j = 0; j < nsys; ++j) {
+            if (!B.h_active[j]) continue;
+            if (!std::isfinite(rr[j])) return set_error(MOBIUS_EHIP, "CG breakdown: non-finite residual");
+            if (rr[j] <= tol_s[j] * tol_s[j] * bnorm2[j] || it >= maxiter ||
+                (mixed && rr[j] < delta * delta * rmax2[j]))
+                need_update = true;
+        }
+        if (!need_update) continue;
+        // reliable update of every active system
+        CK(B.reliable_update());
+        std::vector<double> hr;
+        if (int rc = B.fetch(hr, X_HR)) return rc;
+        for (int j = 0; j < nsys; ++j) {
+            if (!B.h_active[j]) continue;
+            if (mixed) ++reliable[j];
+            const double prev = rmax2[j];
+            rmax2[j] = hr[j];
+            if (hr[j] <= tol_s[j] * tol_s[j] * bnorm2[j] || it >= maxiter) {
+                pending[j] = 1;
+                B.h_active[j] = 0;
+            } else if (!mixed || hr[j] > 0.25 * prev) {
+                B.h_restart[j] = 1;
+            }
+        }
+        if (int rc = sync_flags()) return rc;
+    }
+
+    // solutions: psi_e = I^-1 (eta_e - D_eo x_hi), psi_o = x_hi
+    for (const Group &g : B.groups) {
+        CK(B.hop_group(g, MOBIUS_F64, 0, EPI_PRESUB | EPI_M5INV, 0, F_XH, F_PE, F_ETA_E, F_NONE, false));
+        CK(launch_unpack_spinor(g.ctx->g, MOBIUS_F64, g.f[F_PE], g.f[F_XH], g.sol, g.nrhs, st));
+        B.abytes += 2.0 * g.ctx->g.N5 * 12 * 16 * g.nrhs + 2.0 * g.fb[F_XH] * g.nrhs;
+    }
+    CK(hipEventRecord(own.ev1, st));
+    CK(hipEventSynchronize(own.ev1));
+    float ms = 0;
+    CK(hipEventElapsedTime(&ms, own.ev0, own.ev1));
+    CK(hipEventRecord(own.ev_in, st));
+    CK(hipStreamWaitEvent(user, own.ev_in, 0));
+    int status = MOBIUS_OK;
+    for (int j = 0; j < nsys; ++j) {
+        mobius_solve_info &inf = info[j];
+        std::memset(&inf, 0, sizeof(inf));
+        inf.iters = iters[j];
+        inf.dirac_apps = 1 + 4 * iters[j] + 2 * reliable[j] + 4;
+        inf.reliable_updates = reliable[j];
+        inf.status = converged[j] ? MOBIUS_OK : MOBIUS_NOT_CONVERGED;
+        inf.true_resid = true_res[j];
+        inf.schur_resid = schur_res[j];
+        inf.seconds = ms * 1e-3;
+        inf.algo_bytes = B.abytes;
+        inf.flops = B.aflops;
+        if (!converged[j]) status = MOBIUS_NOT_CONVERGED;
+    }
+    return status;
+}
+
+}  // namespace mobius

@@ -66,6 +66,17 @@ WORKLOADS = {
                                    0.5, 4, notes="fermion-force finite-difference check"),
 }
 
+# Uneven batch solved in lockstep: 8^4, 12^4, 16^4 at Ls = 8 (seeds 1-3), Moebius
+# b5 = 1.5, c5 = 0.5 with the 16^3 x 32 link spread.
+UNEVEN_BATCH = tuple(
+    Workload(f"batch_{L}x{L}x{L}x{L}_ls8", (L, L, L, L), 8, 1.8, 0.01, 1.5, 0.5, 0.5, seed,
+             notes="uneven batch member")
+    for L, seed in ((8, 1), (12, 2), (16, 3)))
+
+# Multi-RHS: the 12 spin-colour point sources of wall_point_sources on the
+# 16^3 x 32, Ls = 16 Moebius lattice.
+MULTI_RHS = WORKLOADS["mobius_16x16x16x32_ls16"]
+
 
 def _reunitarize(U: np.ndarray) -> np.ndarray:
     r0 = U[..., 0, :]

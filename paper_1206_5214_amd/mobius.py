@@ -23,7 +23,7 @@ OK, NOT_CONVERGED = 0, 1
 
 EXPORTS = ("mobius_create", "mobius_destroy", "mobius_field_bytes", "mobius_pack",
            "mobius_unpack", "mobius_dslash", "mobius_dslash_dag", "mobius_m5inv",
-           "mobius_cg_solve", "mobius_last_error")
+           "mobius_cg_solve", "mobius_batch_solve", "mobius_last_error")
 
 
 class MobiusError(RuntimeError):
@@ -85,6 +85,9 @@ def lib():
         L.mobius_m5inv.argtypes = [vp, i32, i32, vp, vp, i32, vp]
         L.mobius_cg_solve.argtypes = [vp, vp, vp, ctypes.POINTER(_SolveOpts),
                                       ctypes.POINTER(_SolveInfo), vp]
+        L.mobius_batch_solve.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.POINTER(vp), ctypes.POINTER(_SolveOpts),
+                                         ctypes.POINTER(_SolveInfo), vp]
         L.mobius_last_error.restype = ctypes.c_char_p
         for f in EXPORTS:
             if f not in ("mobius_field_bytes", "mobius_last_error"):
@@ -220,7 +223,7 @@ class Operator:
         return out
 
     def solve(self, src, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.1,
-              check_every=16):
+              check_every=0):
         """Solve D_DW psi = src (canonical complex128, optional leading nrhs)."""
         import torch
         nrhs = 1 if src.dim() == 7 else int(src.shape[0])
@@ -230,6 +233,36 @@ class Operator:
         infos = (_SolveInfo * nrhs)()
         rc = _check(lib().mobius_cg_solve(self._h, _ptr(src), _ptr(sol), ctypes.byref(opts), infos,
                                           _stream()))
-        out = [SolveInfo(i.iters, i.dirac_apps, i.reliable_updates, i.status, i.true_resid,
-                         i.schur_resid, i.seconds, i.algo_bytes, i.flops) for i in infos]
-        return sol, out, rc
+        return sol, [_info(i) for i in infos], rc
+
+
+def _info(i):
+    return SolveInfo(i.iters, i.dirac_apps, i.reliable_updates, i.status, i.true_resid,
+                     i.schur_resid, i.seconds, i.algo_bytes, i.flops)
+
+
+def batch_solve(ops, srcs, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.1,
+                check_every=0):
+    """Solve D_DW psi_j = src_j for several lattices at once (one Operator per
+    lattice, the same number of right-hand sides each).  Returns the list of
+    solutions, a list (per lattice) of lists of SolveInfo, and the return code."""
+    import torch
+    if len(ops) != len(srcs) or not ops:
+        raise MobiusError("batch_solve needs one source per operator")
+    if len({id(o) for o in ops}) != len(ops):
+        raise MobiusError("batch_solve needs distinct operators")
+    nrhs = 1 if srcs[0].dim() == 7 else int(srcs[0].shape[0])
+    sols = []
+    for op, src in zip(ops, srcs):
+        op._check_canon(src, nrhs, "source")
+        sols.append(torch.empty_like(src))
+    n = len(ops)
+    vp = ctypes.c_void_p
+    hs = (vp * n)(*[o._h for o in ops])
+    ss = (vp * n)(*[s.data_ptr() for s in srcs])
+    xs = (vp * n)(*[s.data_ptr() for s in sols])
+    opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, nrhs, check_every)
+    infos = (_SolveInfo * (n * nrhs))()
+    rc = _check(lib().mobius_batch_solve(n, hs, ss, xs, ctypes.byref(opts), infos, _stream()))
+    out = [[_info(infos[j * nrhs + r]) for r in range(nrhs)] for j in range(n)]
+    return sols, out, rc
