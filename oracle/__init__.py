@@ -60,8 +60,12 @@ def _bind(path):
                            ctypes.POINTER(_Info)]
     L.orc_solve.argtypes = [P, vp, vp, vp, ctypes.c_double, ctypes.c_int32,
                             ctypes.POINTER(_Info)]
+    L.orc_cgne.argtypes = [P, vp, vp, vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_Info)]
+    L.orc_force.argtypes = [P, vp, vp, vp, ctypes.c_int64, vp, vp, ctypes.c_double,
+                            ctypes.c_int32, ctypes.POINTER(_Info)]
+    L.orc_force.restype = ctypes.c_double
     for f in ("orc_wilson", "orc_dw", "orc_dw_sites", "orc_hop", "orc_m5", "orc_m5inv",
-              "orc_schur", "orc_cgls", "orc_solve"):
+              "orc_schur", "orc_cgls", "orc_solve", "orc_cgne"):
         getattr(L, f).restype = None
     return L
 
@@ -208,6 +212,37 @@ def solve(p: Params, U, eta, tol=1e-12, maxiter=10000):
     lib().orc_solve(ctypes.byref(p.c()), _ptr(U), _ptr(eta), _ptr(psi), float(tol), int(maxiter),
                     ctypes.byref(info))
     return psi, Info(info.iters, bool(info.converged), info.rel_resid, info.true_resid)
+
+
+def cgne(p: Params, U, phi, tol=1e-12, maxiter=10000):
+    """X = (D_pre^+ D_pre)^{-1} phi for phi on the odd parity (plain CG)."""
+    U, phi = _c128(U), _c128(phi)
+    x = np.empty_like(phi)
+    info = _Info()
+    lib().orc_cgne(ctypes.byref(p.c()), _ptr(U), _ptr(phi), _ptr(x), float(tol), int(maxiter),
+                   ctypes.byref(info))
+    return x, Info(info.iters, bool(info.converged), info.rel_resid, info.true_resid)
+
+
+def force(p: Params, U, phi, links=None, tol=1e-13, maxiter=20000):
+    """S = phi^+ (D_pre^+ D_pre)^{-1} phi (phi on the odd parity) and its link
+    gradient dS/dRe U + i dS/dIm U.  links: None for every link (gradient in the
+    canonical link layout [4][Lt][Lz][Ly][Lx][3][3]) or a sequence of (mu,
+    canonical 4d index) pairs (gradient [n][3][3]).  Returns (S, X, grad, Info)."""
+    U, phi = _c128(U), _c128(phi)
+    x = np.empty_like(phi)
+    info = _Info()
+    if links is None:
+        grad = np.empty(p.link_shape(), np.complex128)
+        lk, nl = None, 0
+    else:
+        ids = np.ascontiguousarray([mu * p.V + i for mu, i in links], dtype=np.int64)
+        grad = np.empty((len(ids), 3, 3), np.complex128)
+        lk, nl = _ptr(ids), len(ids)
+    S = lib().orc_force(ctypes.byref(p.c()), _ptr(U), _ptr(phi), _ptr(x), nl, lk, _ptr(grad),
+                        float(tol), int(maxiter), ctypes.byref(info))
+    return float(S), x, grad, Info(info.iters, bool(info.converged), info.rel_resid,
+                                   info.true_resid)
 
 
 def parity_mask(p: Params):

@@ -548,3 +548,168 @@ void orc_solve(const orc_params *p, const double *U, const double *etad, double 
     free(t2);
     free(xo);
 }
+
+/* ------------------------------------------------------------------------ */
+/* pseudofermion action and its link derivative                              */
+
+/* Plain conjugate gradient (Hestenes-Stiefel) on the Hermitian positive
+ * operator A = D_pre^+ D_pre of the odd parity:
+ *   x = 0, r = phi, p = r;
+ *   repeat: q = A p; alpha = |r|^2 / <p, q>; x += alpha p; r -= alpha q;
+ *           beta = |r'|^2 / |r|^2; p = r' + beta p
+ *   until |r| <= tol |phi|.  <p, q> = |D_pre p|^2 is evaluated as such. */
+void orc_cgne(const orc_params *p, const double *U, const double *phid, double *xd, double tol,
+              int32_t maxiter, orc_info *info)
+{
+    const int64_t n = field_len(p);
+    cplx *phi = masked_copy(p, (const cplx *)phid, 1);
+    cplx *x = (cplx *)xd;
+    cplx *r = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *pv = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *t = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *q = (cplx *)malloc(sizeof(cplx) * n);
+    memset(x, 0, sizeof(cplx) * n);
+    memcpy(r, phi, sizeof(cplx) * n);
+    memcpy(pv, phi, sizeof(cplx) * n);
+    const double pnorm = sqrt(norm2(phi, n));
+    double rr = norm2(r, n);
+    int it = 0, conv = pnorm == 0.0;
+    while (!conv && it < maxiter) {
+        orc_schur(p, U, (const double *)pv, (double *)t, 0);
+        orc_schur(p, U, (const double *)t, (double *)q, 1);
+        const double alpha = rr / norm2(t, n);
+        for (int64_t k = 0; k < n; ++k) {
+            x[k] += alpha * pv[k];
+            r[k] -= alpha * q[k];
+        }
+        ++it;
+        const double rr_new = norm2(r, n);
+        if (sqrt(rr_new) <= tol * pnorm) {
+            rr = rr_new;
+            conv = 1;
+            break;
+        }
+        const double beta = rr_new / rr;
+        for (int64_t k = 0; k < n; ++k) pv[k] = r[k] + beta * pv[k];
+        rr = rr_new;
+    }
+    if (info) {
+        info->iters = it;
+        info->converged = conv;
+        info->rel_resid = pnorm > 0 ? sqrt(rr) / pnorm : 0.0;
+        info->true_resid = -1.0;
+    }
+    free(phi);
+    free(r);
+    free(pv);
+    free(t);
+    free(q);
+}
+
+/* 2 Re <a, D[E] b> restricted to the 4d sites of the list: D[E] is D_DW
+ * evaluated with the link field E on an input b that vanishes on the parity
+ * of those sites, i.e. the hopping term alone (the site-diagonal parts of D+,
+ * D- and of the s coupling see only b at the site itself, which is zero). */
+static double hop_overlap(const orc_params *p, const cplx *E, const cplx *a, const cplx *b,
+                          const int64_t *sites, int nsites, cplx *tmp, cplx *buf)
+{
+    const int64_t V = vol4(p);
+    double acc = 0.0;
+    for (int j = 0; j < nsites; ++j) {
+        dw_site(p, E, b, sites[j], tmp, 0, buf);
+        for (int s = 0; s < p->Ls; ++s)
+            for (int k = 0; k < SITE_DOF; ++k)
+                acc += 2.0 * creal(conj(a[((int64_t)s * V + sites[j]) * SITE_DOF + k]) *
+                                   tmp[s * SITE_DOF + k]);
+    }
+    return acc;
+}
+
+/* S = phi^+ (D_pre^+ D_pre)^{-1} phi for phi on the odd parity, and its
+ * derivative with respect to the gauge links.
+ *
+ * With X = (D_pre^+ D_pre)^{-1} phi and Y = D_pre X, a change of the links
+ * changes S by dS = -2 Re <Y, dD_pre X>.  I does not depend on the links, so
+ *   dD_pre = -I^-1 dD_oe I^-1 D_eo - I^-1 D_oe I^-1 dD_eo
+ * and  dS = 2 Re <Yt, dD_oe Z> + 2 Re <W, dD_eo X>  with
+ *   Yt = I^-+ Y (odd),  Z = I^-1 D_eo X (even),  W = I^-+ (D_oe)^+ Yt (even).
+ * The off-diagonal blocks are real-linear in the links (they hold the whole
+ * link dependence of D_DW, Sec. 3), so the change of D_oe along a direction
+ * E is the block itself built on the link field E.  For link l = mu*V + y the
+ * directional derivative along E = e_ab (one complex entry set to 1) and
+ * along E = i e_ab gives
+ *   grad[l][a][b] = dS/dRe U + i dS/dIm U
+ * (PyTorch's convention for the gradient of a real function of complex
+ * entries).  Only the sites y and y + mu see link l.
+ *
+ * links: nlinks indices mu*V + y, or NULL for all 4 V links in canonical
+ * order (grad then has the canonical link layout).  X (full-size, zero on the
+ * even parity) receives the CG solution.  Returns S. */
+double orc_force(const orc_params *p, const double *U, const double *phid, double *xd,
+                 int64_t nlinks, const int64_t *links, double *gradd, double tol,
+                 int32_t maxiter, orc_info *info)
+{
+    init_gammas();
+    const int64_t n = field_len(p);
+    const int64_t V = vol4(p);
+    cplx *X = (cplx *)xd;
+    cplx *grad = (cplx *)gradd;
+    orc_cgne(p, U, phid, xd, tol, maxiter, info);
+
+    cplx *Y = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *Yt = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *Z = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *W = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *t = (cplx *)malloc(sizeof(cplx) * n);
+    orc_schur(p, U, xd, (double *)Y, 0);                 /* Y  = D_pre X            */
+    orc_m5inv(p, (double *)Y, (double *)Yt, 1);          /* Yt = I^-+ Y     (odd)   */
+    orc_hop(p, U, 0, xd, (double *)t, 0);                /* D_eo X          (even)  */
+    orc_m5inv(p, (double *)t, (double *)Z, 0);           /* Z  = I^-1 D_eo X        */
+    orc_hop(p, U, 0, (double *)Yt, (double *)t, 1);      /* (D_oe)^+ Yt     (even)  */
+    orc_m5inv(p, (double *)t, (double *)W, 1);           /* W  = I^-+ (D_oe)^+ Yt   */
+
+    const cplx *phi = (const cplx *)phid;
+    double S = 0.0;
+    for (int64_t k = 0; k < n; ++k) S += creal(conj(phi[k]) * X[k]);
+    /* (phi restricted to the odd parity: X vanishes on the even one) */
+
+    const int64_t nl = links ? nlinks : 4 * V;
+#pragma omp parallel
+    {
+        cplx *E = (cplx *)calloc((size_t)4 * V * 9, sizeof(cplx));
+        cplx *buf = (cplx *)calloc((size_t)V * SITE_DOF, sizeof(cplx));
+        cplx *tmp = (cplx *)malloc(sizeof(cplx) * p->Ls * SITE_DOF);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t l = 0; l < nl; ++l) {
+            const int64_t lid = links ? links[l] : l;
+            const int mu = (int)(lid / V);
+            const int64_t y = lid % V;
+            const int64_t sites[2] = {y, neighbour(p, y, mu, +1)};
+            for (int e = 0; e < 9; ++e) {
+                double d[2];
+                for (int part = 0; part < 2; ++part) {
+                    E[lid * 9 + e] = part ? I : 1.0;
+                    double acc = 0.0;
+                    for (int j = 0; j < 2; ++j) {
+                        if (site_parity(p, sites[j]) == 1)  /* odd row: dD_oe on Z */
+                            acc += hop_overlap(p, E, Yt, Z, &sites[j], 1, tmp, buf);
+                        else                                /* even row: dD_eo on X */
+                            acc += hop_overlap(p, E, W, X, &sites[j], 1, tmp, buf);
+                    }
+                    d[part] = acc;
+                    E[lid * 9 + e] = 0.0;
+                }
+                grad[l * 9 + e] = d[0] + I * d[1];
+            }
+        }
+        free(E);
+        free(buf);
+        free(tmp);
+    }
+    free(Y);
+    free(Yt);
+    free(Z);
+    free(W);
+    free(t);
+    return S;
+}

@@ -94,6 +94,20 @@ void orc_cgls(const orc_params *p, const double *U, int which, const double *b, 
 void orc_solve(const orc_params *p, const double *U, const double *eta, double *psi,
                double tol, int32_t maxiter, orc_info *info);
 
+/* Conjugate gradient on D_pre^+ D_pre X = phi (phi on the odd parity; the
+ * even parity of phi is ignored).  info->rel_resid is |phi - A X| / |phi| as
+ * iterated. */
+void orc_cgne(const orc_params *p, const double *U, const double *phi, double *X, double tol,
+              int32_t maxiter, orc_info *info);
+
+/* S = phi^+ (D_pre^+ D_pre)^{-1} phi and dS/dU for the listed links
+ * (mu * V + canonical 4d index; links = NULL: all links, canonical order).
+ * grad[l][a][b] = dS/dRe U_l[a][b] + i dS/dIm U_l[a][b] (complex128).
+ * X receives (D_pre^+ D_pre)^{-1} phi.  Returns S. */
+double orc_force(const orc_params *p, const double *U, const double *phi, double *X,
+                 int64_t nlinks, const int64_t *links, double *grad, double tol,
+                 int32_t maxiter, orc_info *info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -320,7 +320,74 @@ def pin_rb_equals_unpreconditioned(orc):
     assert info_rb.iters < info_full.iters
 
 
+def _normal(orc, p, U, x):
+    """D_pre^+ D_pre x with the oracle's Schur blocks."""
+    return orc.schur(p, U, orc.schur(p, U, x), dag=True)
+
+
+def pin_cgne_dense(orc):
+    """X = (D_pre^+ D_pre)^{-1} phi from the oracle's CG equals the dense solve
+    with D_pre assembled from the parity blocks of the dense D_DW
+    (D_pre = 1 - D_oo^{-1} D_oe D_ee^{-1} D_eo, Sec. 3), and S = phi^+ X."""
+    dims = (2, 2, 2, 4)
+    p, U, rng = _setup(dims, 4, 1.5, 0.5, 0.05, seed=11)
+    D = _dense_dw(orc, p, U, "g5R")
+    odd = np.broadcast_to(orc.parity_mask(p)[None, ..., None, None], p.shape5()).reshape(-1)
+    o, e = np.flatnonzero(odd), np.flatnonzero(~odd)
+    Doo, Dee = D[np.ix_(o, o)], D[np.ix_(e, e)]
+    M = np.eye(len(o)) - np.linalg.solve(Doo, D[np.ix_(o, e)] @ np.linalg.solve(Dee, D[np.ix_(e, o)]))
+    phi = orc.restrict(p, inputs.gaussian_spinor(dims, p.Ls, rng), 1)
+    want = np.linalg.solve(np.conj(M.T) @ M, phi.reshape(-1)[o])
+    X, info = orc.cgne(p, U, phi, tol=1e-14, maxiter=5000)
+    assert info.converged, info
+    assert np.all(X.reshape(-1)[e] == 0)
+    assert _rel(X.reshape(-1)[o], want) < 1e-10, ("cgne vs dense", _rel(X.reshape(-1)[o], want))
+    S, X2, _, _ = orc.force(p, U, phi, links=[(0, 0)], tol=1e-14)
+    S_want = np.vdot(phi.reshape(-1)[o], want).real
+    assert abs(S - S_want) < 1e-11 * abs(S_want), (S, S_want)
+
+
+def pin_force_finite_difference(orc):
+    """dS/dU of S = phi^+ (D_pre^+ D_pre)^{-1} phi against central differences
+    along random complex link directions E (all 18 real components per link):
+    (S(U + hE) - S(U - hE)) / 2h = Re sum conj(G) E + O(h^2).  The difference
+    is formed without cancellation as <X+, (A- - A+) X->, A = D_pre^+ D_pre,
+    X+- = A(U +- hE)^{-1} phi.  Also the source gradient: S is quadratic in
+    phi, so S(phi + t xi) - S(phi - t xi) = 4 t Re <xi, X> exactly."""
+    dims = (2, 2, 2, 4)
+    for (b5, c5, Ls, mf, seed) in [(1.5, 0.5, 4, 0.05, 3), (1.0, 0.0, 4, 0.1, 4)]:
+        p, U, rng = _setup(dims, Ls, b5, c5, mf, seed=seed)
+        phi = orc.restrict(p, inputs.gaussian_spinor(dims, p.Ls, rng), 1)
+        S, X, G, info = orc.force(p, U, phi, tol=1e-14)
+        assert info.converged
+        h = 1e-5
+        V = p.V
+        directions = []
+        E = rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape)
+        directions.append(E)
+        for _ in range(3):  # one link at a time
+            E1 = np.zeros_like(U)
+            mu, i = rng.integers(4), rng.integers(V)
+            E1.reshape(4, V, 3, 3)[mu, i] = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+            directions.append(E1)
+        for E in directions:
+            Up, Um = U + h * E, U - h * E
+            Xp, ip = orc.cgne(p, Up, phi, tol=1e-14, maxiter=5000)
+            Xm, im = orc.cgne(p, Um, phi, tol=1e-14, maxiter=5000)
+            assert ip.converged and im.converged
+            dS = _vdot(Xp, _normal(orc, p, Um, Xm) - _normal(orc, p, Up, Xm)).real / (2 * h)
+            want = np.sum(np.conj(G) * E).real
+            assert abs(dS - want) < 1e-7 * max(abs(dS), 1e-3 * np.abs(G).max()), \
+                ("force vs finite difference", b5, c5, dS, want)
+        xi = orc.restrict(p, inputs.gaussian_spinor(dims, p.Ls, rng), 1)
+        t = 1e-3
+        Sp, _, _, _ = orc.force(p, U, phi + t * xi, links=[(0, 0)], tol=1e-14)
+        Sm, _, _, _ = orc.force(p, U, phi - t * xi, links=[(0, 0)], tol=1e-14)
+        want = 4 * t * _vdot(xi, X).real
+        assert abs((Sp - Sm) - want) < 1e-9 * abs(Sp), ("source gradient 2X", Sp - Sm, want)
+
+
 ALL_PINS = [pin_wilson_free_symbol, pin_kernel_bound, pin_gauge_covariance,
             pin_wilson_gamma5_hermiticity, pin_adjoints, pin_free_determinant,
             pin_free_propagator, pin_gamma5_R_hermiticity, pin_m5_block, pin_schur_solve_dense,
-            pin_rb_equals_unpreconditioned]
+            pin_rb_equals_unpreconditioned, pin_cgne_dense, pin_force_finite_difference]

@@ -38,6 +38,18 @@ MUTANTS = [
     ("reconstruct_parity", "orc_hop(p, U, 0, (double *)xo, (double *)t2, 0);       /* D_eo psi_o",
      "orc_hop(p, U, 1, (double *)xo, (double *)t2, 0);       /* D_eo psi_o"),
     ("cgls_beta_sign", "pv[k] = s[k] + beta * pv[k];", "pv[k] = s[k] - beta * pv[k];"),
+    ("cgne_alpha_uses_r", "const double alpha = rr / norm2(t, n);",
+     "const double alpha = rr / norm2(q, n);"),
+    ("force_imaginary_direction_sign", "E[lid * 9 + e] = part ? I : 1.0;",
+     "E[lid * 9 + e] = part ? -I : 1.0;"),
+    ("force_Yt_without_dagger", "orc_m5inv(p, (double *)Y, (double *)Yt, 1);",
+     "orc_m5inv(p, (double *)Y, (double *)Yt, 0);"),
+    ("force_W_hop_not_adjoint", "orc_hop(p, U, 0, (double *)Yt, (double *)t, 1);",
+     "orc_hop(p, U, 0, (double *)Yt, (double *)t, 0);"),
+    ("force_odd_row_fields_swapped", "acc += hop_overlap(p, E, Yt, Z, &sites[j], 1, tmp, buf);",
+     "acc += hop_overlap(p, E, W, Z, &sites[j], 1, tmp, buf);"),
+    ("force_only_forward_site", "const int64_t sites[2] = {y, neighbour(p, y, mu, +1)};",
+     "const int64_t sites[2] = {y, y};"),
 ]
 
 
