@@ -104,6 +104,111 @@ def cpu_baseline(U, eta, w):
                       f"half of the {Lx}x{Ly}x{Lz}x{Lt}, Ls={w.Ls} source ({dt:.1f} s)"}
 
 
+def point_sources_gpu(torch, dims, Ls):
+    """The 12 spin-colour wall point sources at the origin, built on the device."""
+    Lx, Ly, Lz, Lt = dims
+    src = torch.zeros((12, Ls, Lt, Lz, Ly, Lx, 4, 3), dtype=torch.complex128, device="cuda")
+    for a in range(12):
+        spin, col = divmod(a, 3)
+        src[a, Ls - 1 if spin < 2 else 0, 0, 0, 0, 0, spin, col] = 1.0
+    return src
+
+
+def _rel(torch, a, b):
+    return (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()
+
+
+def multi_rhs_runs(torch, inputs, mobius):
+    """12 point sources on the multi-RHS lattice: one batched solve per inner
+    precision against twelve sequential plain-FP64 solves."""
+    w = inputs.MULTI_RHS
+    U, _ = inputs.workload_fields(w, with_source=False)
+    op = mobius.Operator(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, torch.from_numpy(U).cuda())
+    del U
+    src = point_sources_gpu(torch, w.dims, w.Ls)
+    out = {"workload": f"{w.name} x 12 point sources"}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref, iters = [], []
+    for a in range(12):
+        s1, i1, rc = op.solve(src[a].contiguous(), tol=w.tol, maxiter=50000, inner_prec=mobius.F64)
+        if rc != mobius.OK:
+            raise RuntimeError(f"FP64 solve of source {a} failed: {i1[0]}")
+        ref.append(s1)
+        iters.append(i1[0].iters)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    ref = torch.stack(ref)
+    out["sequential_f64"] = {"seconds": seq, "iters_per_rhs": iters}
+    log(f"multi-rhs: 12 sequential FP64 solves {seq:.3f} s")
+    for prec in (mobius.F64, mobius.F32, mobius.F16):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sol, info, rc = op.solve(src, tol=w.tol, maxiter=50000, inner_prec=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if rc != mobius.OK:
+            raise RuntimeError(f"batched solve failed: {info}")
+        err = max(_rel(torch, sol[a], ref[a]) for a in range(12))
+        out[f"batched_{PREC_NAMES[prec]}"] = {
+            "seconds": dt, "speedup_vs_sequential_f64": seq / dt,
+            "max_iters": max(i.iters for i in info),
+            "max_true_resid": max(i.true_resid for i in info),
+            "max_rel_diff_vs_f64": err,
+            "GBps": info[0].algo_bytes / dt / 1e9}
+        log(f"multi-rhs: batched {PREC_NAMES[prec]} {dt:.3f} s ({seq / dt:.2f}x), "
+            f"max resid {out[f'batched_{PREC_NAMES[prec]}']['max_true_resid']:.2e}, diff {err:.2e}")
+        del sol
+    op.close()
+    return out
+
+
+def uneven_batch_runs(torch, inputs, mobius):
+    """8^4 + 12^4 + 16^4 (Ls = 8) in one lockstep solve against the same
+    lattices solved one after another."""
+    ops, srcs = [], []
+    for w in inputs.UNEVEN_BATCH:
+        U, eta = inputs.workload_fields(w)
+        ops.append(mobius.Operator(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, torch.from_numpy(U).cuda()))
+        srcs.append(torch.from_numpy(eta).cuda())
+    out = {"workload": " + ".join(w.name for w in inputs.UNEVEN_BATCH)}
+    ref = {}
+    for prec in (mobius.F64, mobius.F32):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sols = []
+        for op, src in zip(ops, srcs):
+            s1, i1, rc = op.solve(src, tol=1e-10, maxiter=50000, inner_prec=prec)
+            if rc != mobius.OK:
+                raise RuntimeError(f"solve failed: {i1[0]}")
+            sols.append(s1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ref[prec] = sols
+        out[f"sequential_{PREC_NAMES[prec]}"] = {"seconds": dt}
+        log(f"uneven batch: sequential {PREC_NAMES[prec]} {dt:.3f} s")
+    for prec in (mobius.F64, mobius.F32, mobius.F16):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sols, infos, rc = mobius.batch_solve(ops, srcs, tol=1e-10, maxiter=50000, inner_prec=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if rc != mobius.OK:
+            raise RuntimeError(f"batched solve failed: {infos}")
+        err = max(_rel(torch, a, b) for a, b in zip(sols, ref[mobius.F64]))
+        f64 = out["sequential_f64"]["seconds"]
+        out[f"batched_{PREC_NAMES[prec]}"] = {
+            "seconds": dt, "speedup_vs_sequential_f64": f64 / dt,
+            "iters": [g[0].iters for g in infos],
+            "max_true_resid": max(g[0].true_resid for g in infos),
+            "max_rel_diff_vs_f64": err}
+        log(f"uneven batch: batched {PREC_NAMES[prec]} {dt:.3f} s ({f64 / dt:.2f}x vs sequential "
+            f"FP64), diff {err:.2e}")
+    for op in ops:
+        op.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +220,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 / FP32 comparison solves")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the multi-RHS and uneven-batch time-to-solution runs")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -197,6 +304,14 @@ def main():
             for k2, v in compare.items():
                 v["speedup_vs_f64"] = f64s / v["seconds"]
 
+    batch = None
+    if not args.no_batch:
+        del sol
+        torch.cuda.empty_cache()
+        batch = {"multi_rhs": multi_rhs_runs(torch, inputs, mobius),
+                 "uneven_batch": uneven_batch_runs(torch, inputs, mobius)}
+        torch.cuda.empty_cache()
+
     hname = PREC_NAMES[inner]
     key = f"hop_{hname}_{args.workload}"
     traffic = counters_for(key)
@@ -235,6 +350,7 @@ def main():
                   "GFLOPps": float(np.mean([i.flops for i in infos])) / (ms_per_step * 1e-3) / 1e9},
         "hop": hop,
         "time_to_solution": compare,
+        "batched": batch,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

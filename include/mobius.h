@@ -175,6 +175,28 @@ int mobius_batch_solve(int32_t n, mobius_ctx *const *ctxs, const void *const *sr
                        void *const *sol, const mobius_solve_opts *opts, mobius_solve_info *info,
                        void *stream);
 
+/* Pseudofermion action of the Schur operator and its derivatives:
+ *     S = phi_o^+ (D_pre^+ D_pre)^{-1} phi_o,   X = (D_pre^+ D_pre)^{-1} phi_o,
+ * with phi_o the odd-parity part of phi (D_pre as in Sec. 3).  X comes from
+ * CG on the normal operator (opts: tol on ||phi_o - D_pre^+ D_pre X|| / ||phi_o||,
+ * maxiter, inner_prec with the same FP64 reliable updates as mobius_cg_solve;
+ * opts->nrhs must be 0 or 1).  Outputs:
+ *   grad_links_c128  canonical links layout (4*V*9 complex128), fully written:
+ *                    dS/dRe U + i dS/dIm U for every link entry, treating the
+ *                    entries as independent complex numbers (the gradient
+ *                    convention of PyTorch for a real function of complex
+ *                    inputs; project onto su(3) for a molecular-dynamics force);
+ *   grad_phi_c128    canonical 5d field: dS/dRe phi + i dS/dIm phi = 2 X on
+ *                    the odd sites, 0 on the even sites;
+ *   action           host pointer receiving S.
+ * The link derivative follows dS = -2 Re <D_pre X, dD_pre X>, where only the
+ * hopping blocks D_eo, D_oe depend on the links (Sec. 3).  Synchronises once at
+ * the end.  Returns MOBIUS_OK, MOBIUS_NOT_CONVERGED (outputs still written
+ * from the last iterate) or a negative error code. */
+int mobius_force(mobius_ctx *ctx, const void *phi_c128, void *grad_links_c128, void *grad_phi_c128,
+                 double *action, const mobius_solve_opts *opts, mobius_solve_info *info,
+                 void *stream);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *mobius_last_error(void);
 

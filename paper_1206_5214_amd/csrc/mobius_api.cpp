@@ -412,3 +412,18 @@ extern "C" int mobius_batch_solve(int32_t n, mobius_ctx *const *ctxs, const void
     }
     return batch_solve(ctxs, n, src, sol, *opts, info, S(stream));
 }
+
+extern "C" int mobius_force(mobius_ctx *ctx, const void *phi, void *grad_links, void *grad_phi,
+                            double *action, const mobius_solve_opts *opts, mobius_solve_info *info,
+                            void *stream)
+{
+    g_err.clear();
+    if (int r = check_ctx(ctx)) return r;
+    if (!phi || !grad_links || !grad_phi || !action || !opts || !info)
+        return fail(MOBIUS_EINVAL, "null argument to mobius_force");
+    if (opts->nrhs > 1) return fail(MOBIUS_EINVAL, "mobius_force takes one source (nrhs <= 1)");
+    if (int r = check_prec(opts->inner_prec)) return r;
+    if (phi == grad_phi || phi == grad_links || grad_phi == grad_links)
+        return fail(MOBIUS_EINVAL, "mobius_force arguments alias");
+    return mobius::force(ctx, phi, grad_links, grad_phi, action, *opts, info, S(stream));
+}

@@ -1,0 +1,689 @@
+// mobius_device.h -- device-side building blocks shared by the HIP kernels
+// of libmobius.so: complex arithmetic, buffer-resource loads and stores, the
+// packed spinor and link formats (see mobius_internal.h), the spin algebra of
+// the chiral basis, the lane <-> (4d site, s) map, the s-direction mixing and
+// the I^-1 elimination through LDS, and the FP64 block reduction.
+#pragma once
+
+#include "mobius_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace mobius {
+namespace {
+
+constexpr int WAVES = 4;
+constexpr int BLOCK = 64 * WAVES;
+
+// ---------------------------------------------------------------------------
+// complex helpers
+
+template <typename T>
+struct cx {
+    T r, i;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.r - b.r, a.i - b.i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
+// i * a
+template <typename T>
+__device__ __forceinline__ cx<T> ti(cx<T> a) { return {-a.i, a.r}; }
+// a * b
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
+{
+    return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+// acc + a * b
+template <typename T>
+__device__ __forceinline__ cx<T> cmadd(cx<T> acc, cx<T> a, cx<T> b)
+{
+    return {acc.r + a.r * b.r - a.i * b.i, acc.i + a.r * b.i + a.i * b.r};
+}
+// acc + conj(a) * b
+template <typename T>
+__device__ __forceinline__ cx<T> cjmadd(cx<T> acc, cx<T> a, cx<T> b)
+{
+    return {acc.r + a.r * b.r + a.i * b.i, acc.i + a.r * b.i - a.i * b.r};
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl(T v, int lane)
+{
+    return __shfl(v, lane, 64);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> shfl(cx<T> v, int lane)
+{
+    return {__shfl(v.r, lane, 64), __shfl(v.i, lane, 64)};
+}
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+// Every packed array is accessed through a buffer resource descriptor (four
+// SGPRs: base, size, format) with a 32-bit per-lane byte offset and a
+// wavefront-uniform scalar offset (the chunk or link-element stride).  This
+// keeps 64-bit address arithmetic out of the vector registers, and the
+// hardware range check turns any access past the end of the array into a
+// zero load or a dropped store.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer, CDNA
+constexpr int CPOL_NT = 2;              // cache policy bit: non-temporal
+
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ Buf(const void *p, int64_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0,
+                                              (int)(uint32_t)(bytes > 0xffffffffll ? 0xffffffffll : bytes),
+                                              RSRC_WORD3))
+    {
+    }
+    __device__ __forceinline__ u32x4 ld16(uint32_t voff, uint32_t soff) const
+    {
+        return __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+    }
+    __device__ __forceinline__ u32x2 ld8(uint32_t voff, uint32_t soff) const
+    {
+        return __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+    }
+    __device__ __forceinline__ uint32_t ld4(uint32_t voff, uint32_t soff) const
+    {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+    }
+    __device__ __forceinline__ void st16(u32x4 v, uint32_t voff, uint32_t soff) const
+    {
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, 0);
+    }
+    // non-temporal variants (cache policy NT): data that is not re-read soon
+    __device__ __forceinline__ u32x4 ld16_nt(uint32_t voff, uint32_t soff) const
+    {
+        return __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, CPOL_NT);
+    }
+    __device__ __forceinline__ void st4(uint32_t v, uint32_t voff, uint32_t soff) const
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 0);
+    }
+};
+
+// Materialise a value in VGPRs at this program point (an empty asm with a
+// read-write register operand; no instruction is emitted).  Used to stop the
+// compiler from sinking the per-direction arithmetic of the hop below the
+// last direction, which would keep every loaded operand live.
+template <typename T>
+__device__ __forceinline__ void pin(cx<T> &v)
+{
+    asm volatile("" : "+v"(v.r), "+v"(v.i));
+}
+
+// ---------------------------------------------------------------------------
+// storage policies for packed spinors: 16-byte chunks over site5
+
+template <int P>
+struct Spin;
+
+template <>
+struct Spin<MOBIUS_F64> {
+    using T = double;
+    __host__ __device__ static int64_t bytes(int64_t N5) { return N5 * 192; }
+    __device__ static void load(const Buf &b, uint32_t N5, uint32_t k, cx<T> v[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            double2 t = __builtin_bit_cast(double2, b.ld16(k * 16u, (uint32_t)c * N5 * 16u));
+            v[c] = {t.x, t.y};
+        }
+    }
+    __device__ static void store(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 12; ++c)
+            b.st16(__builtin_bit_cast(u32x4, make_double2(v[c].r, v[c].i)), k * 16u,
+                   (uint32_t)c * N5 * 16u);
+    }
+    __device__ static double store_norm2(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
+    {
+        store(b, N5, k, v);
+        double n = 0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) n += (double)v[c].r * v[c].r + (double)v[c].i * v[c].i;
+        return n;
+    }
+};
+
+template <>
+struct Spin<MOBIUS_F32> {
+    using T = float;
+    __host__ __device__ static int64_t bytes(int64_t N5) { return N5 * 96; }
+    __device__ static void load(const Buf &b, uint32_t N5, uint32_t k, cx<T> v[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            float4 t = __builtin_bit_cast(float4, b.ld16(k * 16u, (uint32_t)c * N5 * 16u));
+            v[2 * c] = {t.x, t.y};
+            v[2 * c + 1] = {t.z, t.w};
+        }
+    }
+    __device__ static void store(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            b.st16(__builtin_bit_cast(u32x4, make_float4(v[2 * c].r, v[2 * c].i, v[2 * c + 1].r,
+                                                         v[2 * c + 1].i)),
+                   k * 16u, (uint32_t)c * N5 * 16u);
+    }
+    __device__ static double store_norm2(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
+    {
+        store(b, N5, k, v);
+        double n = 0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) n += (double)v[c].r * v[c].r + (double)v[c].i * v[c].i;
+        return n;
+    }
+};
+
+template <>
+struct Spin<MOBIUS_F16> {
+    using T = float;
+    __host__ __device__ static int64_t bytes(int64_t N5) { return N5 * 52; }
+    __device__ static void load(const Buf &b, uint32_t N5, uint32_t k, cx<T> v[12])
+    {
+        const float nrm = __builtin_bit_cast(float, b.ld4(k * 4u, 3u * N5 * 16u));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            half8 t = __builtin_bit_cast(half8, b.ld16(k * 16u, (uint32_t)c * N5 * 16u));
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                v[4 * c + j] = {nrm * (float)t[2 * j], nrm * (float)t[2 * j + 1]};
+        }
+    }
+    // Encode a site: FP32 max-abs norm, binary16 components scaled by 1/norm
+    // (round to nearest even).  decode(encode(v)) is what a later load returns.
+    // A site whose largest component is below the smallest normal FP32 value
+    // is stored as zero: 1/norm would overflow (the front of a Krylov vector
+    // grown from a point source reaches such magnitudes).
+    __device__ static float encode(const cx<T> v[12], half8 h[3])
+    {
+        float m = 0.f;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].r), fabsf(v[c].i)));
+        if (!(m >= __FLT_MIN__)) m = 0.f;
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                h[c][2 * j] = (_Float16)(v[4 * c + j].r * inv);
+                h[c][2 * j + 1] = (_Float16)(v[4 * c + j].i * inv);
+            }
+        return m;
+    }
+    __device__ static void store(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
+    {
+        half8 h[3];
+        const float m = encode(v, h);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) b.st16(__builtin_bit_cast(u32x4, h[c]), k * 16u, (uint32_t)c * N5 * 16u);
+        b.st4(__builtin_bit_cast(uint32_t, m), k * 4u, 3u * N5 * 16u);
+    }
+    // store, and return |stored value|^2 computed from the encoded registers
+    __device__ static double store_norm2(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
+    {
+        half8 h[3];
+        const float m = encode(v, h);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) b.st16(__builtin_bit_cast(u32x4, h[c]), k * 16u, (uint32_t)c * N5 * 16u);
+        b.st4(__builtin_bit_cast(uint32_t, m), k * 4u, 3u * N5 * 16u);
+        double n = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const double d = (double)(m * (float)h[c][j]);
+                n += d * d;
+            }
+        return n;
+    }
+};
+
+// link records: [8][Vh] of 9 complex<prec> (padded) for one parity
+template <int P>
+struct Link;
+
+template <>
+struct Link<MOBIUS_F64> {
+    using T = double;
+    static constexpr int REC = 144;
+    __device__ static void from_words(const u32x4 *q, cx<T> u[9])
+    {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            double2 t = __builtin_bit_cast(double2, q[e]);
+            u[e] = {t.x, t.y};
+        }
+    }
+    __device__ static void load(const Buf &b, uint32_t voff, uint32_t soff, cx<T> u[9])
+    {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            double2 t = __builtin_bit_cast(double2, b.ld16(voff + 16u * e, soff));
+            u[e] = {t.x, t.y};
+        }
+    }
+};
+template <>
+struct Link<MOBIUS_F32> {
+    using T = float;
+    static constexpr int REC = 80;
+    __device__ static void from_words(const u32x4 *q, cx<T> u[9])
+    {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            float4 t = __builtin_bit_cast(float4, q[k]);
+            u[2 * k] = {t.x, t.y};
+            if (2 * k + 1 < 9) u[2 * k + 1] = {t.z, t.w};
+        }
+    }
+    __device__ static void load(const Buf &b, uint32_t voff, uint32_t soff, cx<T> u[9])
+    {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            float4 t = __builtin_bit_cast(float4, b.ld16(voff + 16u * q, soff));
+            u[2 * q] = {t.x, t.y};
+            if (2 * q + 1 < 9) u[2 * q + 1] = {t.z, t.w};
+        }
+    }
+};
+template <>
+struct Link<MOBIUS_F16> {
+    using T = float;
+    static constexpr int REC = 48;
+    __device__ static void from_words(const u32x4 *q, cx<T> u[9])
+    {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            half8 t = __builtin_bit_cast(half8, q[k]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (4 * k + j < 9) u[4 * k + j] = {(float)t[2 * j], (float)t[2 * j + 1]};
+        }
+    }
+    __device__ static void load(const Buf &b, uint32_t voff, uint32_t soff, cx<T> u[9])
+    {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            half8 t = __builtin_bit_cast(half8, b.ld16(voff + 16u * q, soff));
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (4 * q + j < 9) u[4 * q + j] = {(float)t[2 * j], (float)t[2 * j + 1]};
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// spin algebra in the chiral basis
+//
+// g_mu = [[0, A_mu], [A_mu^+, 0]] with A_k = -i sigma_k, A_4 = 1, so for
+// psi = (u; l) (u = spins 0,1 = P+ part, l = spins 2,3 = P- part) and a sign
+// sigma = +-1:
+//   (1 + sigma g_mu) psi = (h ; sigma A_mu^+ h),   h = u + sigma A_mu l,
+// i.e. the projector keeps two spin components (a half spinor) and the other
+// two are reconstructed after the colour multiply.
+
+// (A_mu l) for the two spin rows, one colour
+template <typename T, int MU>
+__device__ __forceinline__ void A_apply(cx<T> l0, cx<T> l1, cx<T> &o0, cx<T> &o1)
+{
+    if constexpr (MU == 0) {        // -i sigma_1: (-i l1, -i l0)
+        o0 = {l1.i, -l1.r};
+        o1 = {l0.i, -l0.r};
+    } else if constexpr (MU == 1) { // -i sigma_2 = [[0,-1],[1,0]]: (-l1, l0)
+        o0 = {-l1.r, -l1.i};
+        o1 = l0;
+    } else if constexpr (MU == 2) { // -i sigma_3: (-i l0, i l1)
+        o0 = {l0.i, -l0.r};
+        o1 = {-l1.i, l1.r};
+    } else {                        // 1
+        o0 = l0;
+        o1 = l1;
+    }
+}
+
+// (A_mu^+ w) for the two spin rows, one colour
+template <typename T, int MU>
+__device__ __forceinline__ void Adag_apply(cx<T> w0, cx<T> w1, cx<T> &o0, cx<T> &o1)
+{
+    if constexpr (MU == 0) {        // i sigma_1: (i w1, i w0)
+        o0 = ti(w1);
+        o1 = ti(w0);
+    } else if constexpr (MU == 1) { // [[0,1],[-1,0]]: (w1, -w0)
+        o0 = w1;
+        o1 = {-w0.r, -w0.i};
+    } else if constexpr (MU == 2) { // i sigma_3: (i w0, -i w1)
+        o0 = ti(w0);
+        o1 = {w1.i, -w1.r};
+    } else {
+        o0 = w0;
+        o1 = w1;
+    }
+}
+
+// One direction of the hopping sum at one lane: acc += (1 + sigma g_mu) M chi,
+// M = U (forward) or U^+ (backward), chi the (b5/c5-mixed) neighbour spinor.
+template <int P>
+__device__ __forceinline__ void load_link(const Buf &links, uint32_t Vh, int d, uint32_t i,
+                                          cx<typename Spin<P>::T> u[9])
+{
+    Link<P>::load(links, i * (uint32_t)Link<P>::REC, (uint32_t)d * Vh * (uint32_t)Link<P>::REC, u);
+}
+
+// The links of a block's sites, staged in LDS by one cooperative copy so
+// that each record crosses the vector-memory pipeline once instead of once
+// per s-lane.  Layout [d][site in block][record].
+template <int P>
+struct LinkSource {
+    const Buf *glob;
+    const char *lds;   // null: read from global memory
+    uint32_t Vh, i, sib, sites_blk;
+    __device__ __forceinline__ void get(int d, cx<typename Spin<P>::T> u[9]) const
+    {
+        constexpr int REC = Link<P>::REC;
+        if (lds) {
+            const u32x4 *q = reinterpret_cast<const u32x4 *>(lds + ((size_t)d * sites_blk + sib) * REC);
+            Link<P>::from_words(q, u);
+        } else {
+            load_link<P>(*glob, Vh, d, i, u);
+        }
+    }
+};
+
+// Colour multiply and reconstruction of one direction: acc += (1 + sigma g_mu) M h
+// given the half spinor h = (h0; h1) = u + sigma A_mu l, with M = U (forward)
+// or U^+ (backward).  u: the link as stored (element a*3+b of U_mu(x) or of
+// U_mu(x-mu), whose adjoint the backward term applies).
+template <typename T, int MU, bool FWD, int SIGMA>
+__device__ __forceinline__ void link_accumulate(const cx<T> h0[3], const cx<T> h1[3],
+                                                const cx<T> u[9], cx<T> acc[12])
+{
+    const T sg = (T)SIGMA;
+    cx<T> w0[3], w1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        w0[a] = {0, 0};
+        w1[a] = {0, 0};
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if constexpr (FWD) {
+                w0[a] = cmadd(w0[a], u[a * 3 + b], h0[b]);
+                w1[a] = cmadd(w1[a], u[a * 3 + b], h1[b]);
+            } else {  // (U^+)_{ab} = conj(U_ba)
+                w0[a] = cjmadd(w0[a], u[b * 3 + a], h0[b]);
+                w1[a] = cjmadd(w1[a], u[b * 3 + a], h1[b]);
+            }
+        }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        acc[a] = acc[a] + w0[a];
+        acc[3 + a] = acc[3 + a] + w1[a];
+        cx<T> o0, o1;
+        Adag_apply<T, MU>(w0[a], w1[a], o0, o1);
+        acc[6 + a] = acc[6 + a] + sg * o0;
+        acc[9 + a] = acc[9 + a] + sg * o1;
+    }
+}
+
+// One direction from a full (already b5/c5-mixed) spinor chi.
+template <int P, int MU, bool FWD, int SIGMA>
+__device__ __forceinline__ void hop_dir(const cx<typename Spin<P>::T> chi[12],
+                                        const cx<typename Spin<P>::T> u[9],
+                                        cx<typename Spin<P>::T> acc[12])
+{
+    using T = typename Spin<P>::T;
+    const T sg = (T)SIGMA;
+    cx<T> h0[3], h1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<T> o0, o1;
+        A_apply<T, MU>(chi[6 + a], chi[9 + a], o0, o1);
+        h0[a] = chi[a] + sg * o0;
+        h1[a] = chi[3 + a] + sg * o1;
+    }
+    link_accumulate<T, MU, FWD, SIGMA>(h0, h1, u, acc);
+}
+
+// ---------------------------------------------------------------------------
+// FP16 direction step without dequantising the spinor: the raw binary16
+// words of the neighbour (and, for the b5/c5 mixing, of its s-1 and s+1
+// slices, fetched from the neighbouring lanes) enter the half spinor through
+// mixed-precision multiply-adds whose scalar factors fold the per-site norms
+// and the mixing weights:
+//   h = al u_s + bu u_{s-1} + sigma A (al l_s + bl l_{s+1}),
+//   al = b5 n_s, bu = c5 f n_{s-1}, bl = c5 f' n_{s+1}  (f, f' = -mf on the wrap).
+
+struct RawH {
+    half2v c[12];  // complex components as (re, im) binary16 pairs
+    float n;       // per-site norm
+};
+
+__device__ __forceinline__ void load_raw_f16(const Buf &b, uint32_t N5, uint32_t k, RawH &r)
+{
+    r.n = __builtin_bit_cast(float, b.ld4(k * 4u, 3u * N5 * 16u));
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const half8 t = __builtin_bit_cast(half8, b.ld16(k * 16u, (uint32_t)q * N5 * 16u));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            half2v h;
+            h.x = t[2 * j];
+            h.y = t[2 * j + 1];
+            r.c[4 * q + j] = h;
+        }
+    }
+}
+
+__device__ __forceinline__ half2v shfl_h2(half2v v, int lane)
+{
+    return __builtin_bit_cast(half2v, __shfl((int)__builtin_bit_cast(uint32_t, v), lane, 64));
+}
+
+__device__ __forceinline__ cx<float> f32(half2v v) { return {(float)v.x, (float)v.y}; }
+
+// h0, h1 for direction MU from raw halves: own spinor o, and (MIX) the P+ part
+// um of slice s-1 and the P- part lp of slice s+1 (6 complex each).
+template <int MU, int SIGMA, bool MIX>
+__device__ __forceinline__ void half_spinor_f16(const RawH &o, const half2v um[6], const half2v lp[6],
+                                                float al, float bu, float bl, cx<float> h0[3],
+                                                cx<float> h1[3])
+{
+    const float sal = (float)SIGMA * al, sbl = (float)SIGMA * bl;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<float> A0, A1;
+        A_apply<float, MU>(f32(o.c[6 + a]), f32(o.c[9 + a]), A0, A1);
+        h0[a] = al * f32(o.c[a]) + sal * A0;
+        h1[a] = al * f32(o.c[3 + a]) + sal * A1;
+        if constexpr (MIX) {
+            cx<float> B0, B1;
+            A_apply<float, MU>(f32(lp[a]), f32(lp[3 + a]), B0, B1);
+            h0[a] = h0[a] + bu * f32(um[a]) + sbl * B0;
+            h1[a] = h1[a] + bu * f32(um[3 + a]) + sbl * B1;
+        }
+    }
+}
+
+struct SiteMap {
+    int lane, wave, g, s;
+    bool site_ok;
+    int64_t i;   // packed 4d site (clamped to a valid index)
+    int lm, lp;  // lanes holding s-1 and s+1 of the same site (cyclic)
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b mod 8), each with its own L2.  With remap on, the blocks an XCD receives
+// cover one contiguous range of sites, so the neighbours a block reads were
+// mostly fetched into the same L2 by the blocks just before it.
+constexpr int NUM_XCD = 8;
+
+__device__ __forceinline__ int64_t logical_block(int remap)
+{
+    const int64_t b = blockIdx.x;
+    if (!remap) return b;
+    const int64_t nb = gridDim.x;
+    const int64_t q = nb / NUM_XCD, r = nb % NUM_XCD;
+    const int64_t x = b % NUM_XCD, c = b / NUM_XCD;
+    return x * q + (x < r ? x : r) + c;
+}
+
+__device__ __forceinline__ SiteMap site_map_lb(int Ls, int spw, int64_t Vh, int64_t lb)
+{
+    SiteMap m;
+    m.lane = threadIdx.x & 63;
+    m.wave = threadIdx.x >> 6;
+    m.g = m.lane / Ls;
+    m.s = m.lane - m.g * Ls;
+    int64_t i = (lb * WAVES + m.wave) * spw + m.g;
+    m.site_ok = (m.g < spw) && (i < Vh);
+    m.i = m.site_ok ? i : 0;
+    const int base = m.g * Ls;
+    m.lm = base + (m.s == 0 ? Ls - 1 : m.s - 1);
+    m.lp = base + (m.s == Ls - 1 ? 0 : m.s + 1);
+    return m;
+}
+
+__device__ __forceinline__ SiteMap site_map(int Ls, int spw, int64_t Vh, int remap = 0)
+{
+    return site_map_lb(Ls, spw, Vh, logical_block(remap));
+}
+
+template <typename T>
+struct Coef {
+    T b5, c5, mf, Mp, Mm, a, mu, inv_Mp, inv_den;
+};
+
+template <typename T>
+__device__ __forceinline__ Coef<T> make_coef(const OpCoeffs &c)
+{
+    return {(T)c.b5, (T)c.c5, (T)c.mf, (T)c.Mp, (T)c.Mm, (T)c.a, (T)c.mu, (T)c.inv_Mp,
+            (T)c.inv_den};
+}
+
+// C5 mixing in s from the lanes of the same 4d site.
+//   forward  (C5 v)_s  = P+ v_{s-1} + P- v_{s+1}
+//   adjoint  (C5^+ v)_s = P+ v_{s+1} + P- v_{s-1}
+// wrapped neighbours carry -mf.  Returns alpha * v + beta * C5(^+) v.
+template <typename T>
+__device__ __forceinline__ void mix_s(cx<T> v[12], T alpha, T beta, T mf, const SiteMap &m, int Ls,
+                                      bool adjoint)
+{
+    const int src_up = adjoint ? m.lp : m.lm;  // lane whose P+ part we take
+    const int src_lo = adjoint ? m.lm : m.lp;  // lane whose P- part we take
+    const bool wrap_up = adjoint ? (m.s == Ls - 1) : (m.s == 0);
+    const bool wrap_lo = adjoint ? (m.s == 0) : (m.s == Ls - 1);
+    const T fu = beta * (wrap_up ? -mf : (T)1);
+    const T fl = beta * (wrap_lo ? -mf : (T)1);
+    cx<T> up[6], lo[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        up[c] = shfl(v[c], src_up);
+        lo[c] = shfl(v[6 + c], src_lo);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        v[c] = alpha * v[c] + fu * up[c];
+        v[6 + c] = alpha * v[6 + c] + fl * lo[c];
+    }
+}
+
+// I^-1 (or I^-+) of Sec. 3 on the Ls lanes of each 4d site, through LDS.
+// I^-1 = A^-1 P- + A^-T P+;  I^-+ = A^-T P- + A^-1 P+  (A real).
+// Lane (g, s) of a site solves component c = s, s + Ls, ... by the paper's
+// elimination on the fly:
+//   A^-1 b:  psi_Ls = (b_Ls + mu sum_{s<Ls} (-a)^(s-1) b_s) / (M+ (1 - mu (-a)^(Ls-1)))
+//            psi_s  = b_s / M+ - a psi_{s+1}
+//   A^-T b:  psi_1  = (b_1 + mu sum_{s>1} (-a)^(Ls-s) b_s) / (same)
+//            psi_s  = b_s / M+ - a psi_{s-1}
+template <typename T>
+struct M5Lds {
+    static constexpr int STRIDE = 13;  // complex per lane (12 + 1 pad)
+    cx<T> buf[WAVES][64 * STRIDE];
+};
+
+template <typename T>
+__device__ __forceinline__ void m5inv_lanes(cx<T> r[12], const Coef<T> &k, const SiteMap &m, int Ls,
+                                            bool dag, M5Lds<T> &lds)
+{
+    cx<T> *w = lds.buf[m.wave];
+    constexpr int ST = M5Lds<T>::STRIDE;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) w[m.lane * ST + c] = r[c];
+    __syncthreads();
+    if (m.g * Ls + Ls <= 64) {
+        const int base = m.g * Ls;
+        for (int c = m.s; c < 12; c += Ls) {
+            const bool plus = c < 6;
+            const bool transpose = plus != dag;
+            const T na = -k.a;
+            if (!transpose) {
+                cx<T> sum = {0, 0};
+                for (int t = Ls - 2; t >= 0; --t) sum = w[(base + t) * ST + c] + na * sum;
+                cx<T> psi = k.inv_den * (w[(base + Ls - 1) * ST + c] + k.mu * sum);
+                w[(base + Ls - 1) * ST + c] = psi;
+                for (int t = Ls - 2; t >= 0; --t) {
+                    psi = k.inv_Mp * w[(base + t) * ST + c] - k.a * psi;
+                    w[(base + t) * ST + c] = psi;
+                }
+            } else {
+                cx<T> sum = {0, 0};
+                for (int t = 1; t < Ls; ++t) sum = na * sum + w[(base + t) * ST + c];
+                cx<T> psi = k.inv_den * (w[base * ST + c] + k.mu * sum);
+                w[base * ST + c] = psi;
+                for (int t = 1; t < Ls; ++t) {
+                    psi = k.inv_Mp * w[(base + t) * ST + c] - k.a * psi;
+                    w[(base + t) * ST + c] = psi;
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 12; ++c) r[c] = w[m.lane * ST + c];
+}
+
+// FP64 block reduction of one value per thread -> partials[slot]
+__device__ __forceinline__ void block_sum_store(double v, double *partials, int64_t slot)
+{
+    __shared__ double red[WAVES];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) t += red[w];
+        partials[slot] = t;
+    }
+    __syncthreads();  // red[] may be reused by the next call in this block
+}
+
+template <typename T>
+__device__ __forceinline__ double site_norm2(const cx<T> r[12])
+{
+    double n = 0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) n += (double)r[c].r * r[c].r + (double)r[c].i * r[c].i;
+    return n;
+}
+
+}  // namespace
+}  // namespace mobius

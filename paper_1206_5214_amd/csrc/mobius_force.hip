@@ -1,0 +1,150 @@
+// mobius_force.hip -- link derivative of the pseudofermion action
+//   S = phi^+ (D_pre^+ D_pre)^-1 phi,   D_pre = 1 - I^-1 D_oe I^-1 D_eo  (Sec. 3)
+// for gfx950.
+//
+// With X = (D_pre^+ D_pre)^-1 phi, Y = D_pre X, Yt = I^-+ Y, Z = I^-1 D_eo X and
+// W = I^-+ (D_oe)^+ Yt, a change of the links changes S by
+//   dS = -Re <Yt, dH_oe (B Z)> - Re <W, dH_eo (B X)>
+// (the off-diagonal blocks are D_{p,1-p} = -1/2 H_{p,1-p} B and hold all of the
+// link dependence).  Write L_p for the left field of parity p (L_1 = Yt,
+// L_0 = W) and R_p for the right one (R_1 = X, R_0 = Z).  The link U_mu(y),
+// y of parity p, enters H at the row y (forward hop from y + mu) and at the
+// row y + mu (backward hop from y), so its gradient
+// G = dS/dRe U + i dS/dIm U is
+//   G_ab = - sum_s sum_{spin} [ L_p(y)_a conj(((1 - g_mu) B R_{1-p}(y+mu))_b)
+//                              + ((1 + g_mu) B R_p(y))_a conj(L_{1-p}(y+mu)_b) ].
+// (1 + sigma g_mu)/2 is a rank-2 projector whose image is parametrised by the
+// half spinor h = u + sigma A_mu l (spins 0,1), and A_mu is unitary, so each
+// spin sum collapses onto the two rows of the half spinors:
+//   sum_spin x_a conj(((1 + sigma g_mu) y)_b) = sum_{t=0,1} h^sigma(x)_{t,a} conj(h^sigma(y)_{t,b}).
+//
+// Thread mapping as in the hop kernel: one lane per (site y, s), the Ls lanes
+// of a site in one wavefront, B applied by cross-lane shuffles, and the sum
+// over s through LDS; one launch per parity p covers the four links U_mu(y)
+// of every site y of that parity.
+#include "mobius_device.h"
+
+#include <hip/hip_runtime.h>
+
+namespace mobius {
+namespace {
+
+// half spinor h = u + sigma A_mu l of a full spinor (rows 0, 1; 3 colours each)
+template <int MU, int SIGMA>
+__device__ __forceinline__ void half_of(const cx<double> v[12], cx<double> h[6])
+{
+    const double sg = (double)SIGMA;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<double> o0, o1;
+        A_apply<double, MU>(v[6 + a], v[9 + a], o0, o1);
+        h[a] = v[a] + sg * o0;
+        h[3 + a] = v[3 + a] + sg * o1;
+    }
+}
+
+struct ForceLds {
+    static constexpr int STRIDE = 9;  // complex per lane
+    cx<double> buf[WAVES][64 * STRIDE];
+};
+
+// Contribution of one lane (one s) to G_mu(y), summed over s in LDS and
+// written by lanes s = 0..8 (one matrix element each, or several if Ls < 9).
+template <int MU>
+__device__ __forceinline__ void force_dir(const ForceParams &fp, const SiteMap &m, const Coef<double> &k,
+                                          const cx<double> Lo[12], const cx<double> BRo[12],
+                                          uint32_t jn, ForceLds &lds)
+{
+    using S = Spin<MOBIUS_F64>;
+    const uint32_t N5 = (uint32_t)fp.N5;
+    const int64_t fb = S::bytes(fp.N5);
+    cx<double> Ln[12], Rn[12];
+    S::load(Buf(fp.Ln, fb), N5, jn, Ln);
+    S::load(Buf(fp.Rn, fb), N5, jn, Rn);
+    mix_s(Rn, k.b5, k.c5, k.mf, m, fp.Ls, false);  // B R_{1-p}(y + mu)
+
+    cx<double> hL[6], hR[6], c[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) c[e] = {0, 0};
+    // forward term: L_p(y) against (1 - g_mu) B R_{1-p}(y + mu)
+    half_of<MU, -1>(Lo, hL);
+    half_of<MU, -1>(Rn, hR);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) c[a * 3 + b] = cjmadd(c[a * 3 + b], hR[t * 3 + b], hL[t * 3 + a]);
+    // backward term: (1 + g_mu) B R_p(y) against L_{1-p}(y + mu)
+    half_of<MU, +1>(BRo, hR);
+    half_of<MU, +1>(Ln, hL);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) c[a * 3 + b] = cjmadd(c[a * 3 + b], hL[t * 3 + b], hR[t * 3 + a]);
+
+    cx<double> *w = lds.buf[m.wave];
+    constexpr int ST = ForceLds::STRIDE;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) w[m.lane * ST + e] = c[e];
+    __syncthreads();
+    if (m.site_ok) {
+        const int base = m.g * fp.Ls;
+        const int64_t link = (int64_t)MU * fp.V + fp.canon_of[m.i];
+        for (int e = m.s; e < 9; e += fp.Ls) {
+            cx<double> acc = {0, 0};
+            for (int t = 0; t < fp.Ls; ++t) acc = acc + w[(base + t) * ST + e];
+            fp.grad[link * 9 + e] = make_double2(-acc.r, -acc.i);
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(BLOCK) void force_kernel(ForceParams fp)
+{
+    using S = Spin<MOBIUS_F64>;
+    const SiteMap m = site_map(fp.Ls, fp.spw, fp.Vh);
+    const Coef<double> k = make_coef<double>(fp.c);
+    const uint32_t N5 = (uint32_t)fp.N5;
+    const int64_t fb = S::bytes(fp.N5);
+    const uint32_t k5 = (uint32_t)m.i * (uint32_t)fp.Ls + (uint32_t)m.s;
+    cx<double> Lo[12], BRo[12];
+    S::load(Buf(fp.Lp, fb), N5, k5, Lo);
+    S::load(Buf(fp.Rp, fb), N5, k5, BRo);
+    mix_s(BRo, k.b5, k.c5, k.mf, m, fp.Ls, false);  // B R_p(y)
+    const int32_t *nb = fp.nbr + m.i * 8;
+    __shared__ ForceLds lds;
+    force_dir<0>(fp, m, k, Lo, BRo, (uint32_t)nb[0] * (uint32_t)fp.Ls + (uint32_t)m.s, lds);
+    force_dir<1>(fp, m, k, Lo, BRo, (uint32_t)nb[1] * (uint32_t)fp.Ls + (uint32_t)m.s, lds);
+    force_dir<2>(fp, m, k, Lo, BRo, (uint32_t)nb[2] * (uint32_t)fp.Ls + (uint32_t)m.s, lds);
+    force_dir<3>(fp, m, k, Lo, BRo, (uint32_t)nb[3] * (uint32_t)fp.Ls + (uint32_t)m.s, lds);
+}
+
+}  // namespace
+
+hipError_t launch_force(const Geometry &g, const OpCoeffs &c, int parity, const int32_t *nbr,
+                        const void *Lp, const void *Rp, const void *Ln, const void *Rn,
+                        void *grad, hipStream_t st)
+{
+    ForceParams fp{};
+    fp.Lp = static_cast<const char *>(Lp);
+    fp.Rp = static_cast<const char *>(Rp);
+    fp.Ln = static_cast<const char *>(Ln);
+    fp.Rn = static_cast<const char *>(Rn);
+    fp.nbr = nbr + (int64_t)parity * 8 * g.Vh;
+    fp.canon_of = g.canon_of + (int64_t)parity * g.Vh;
+    fp.grad = static_cast<double2 *>(grad);
+    fp.Vh = g.Vh;
+    fp.N5 = g.N5;
+    fp.V = g.V;
+    fp.Ls = g.Ls;
+    fp.spw = 64 / g.Ls;
+    fp.c = c;
+    const int64_t blocks = site_kernel_blocks(g);
+    hipLaunchKernelGGL(force_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, st, fp);
+    return hipGetLastError();
+}
+
+}  // namespace mobius

@@ -134,12 +134,14 @@ struct HopTuning {
     int stage_links = 1;   // copy each block's links to LDS once
     int nt_links = 0;      // non-temporal link loads
 };
-// prefetch depth used for a precision (measured at 24^3x64, Ls=12: FP64 is
-// register-limited at depth 2, FP32 and FP16 gain from it)
+// prefetch depth used for a precision (measured at 24^3x64, Ls=12: the FP64
+// hop needs more than 256 VGPRs once a neighbour is prefetched, which halves
+// its occupancy -- 967 us at depth 0 against 1262 us at depth 1; FP32 and FP16
+// gain a few percent from depth 2)
 inline int prefetch_depth(const HopTuning &t, int prec)
 {
     if (t.prefetch >= 0) return t.prefetch;
-    return prec == MOBIUS_F64 ? 1 : 2;
+    return prec == MOBIUS_F64 ? 0 : 2;
 }
 // Brick of the site order for a lattice: MOBIUS_BRICK="bx,by,bz" overrides.
 void choose_brick(const int L[4], int Ls, int brick[3]);
@@ -226,7 +228,9 @@ struct VecSys {
     int32_t flag;          // index into the active flags (-1: always active)
     int32_t pad;
 };
-enum VecKind { VEC_CG_XR, VEC_AXPBY, VEC_AXPBY_NORM, VEC_NORM2, VEC_CONVERT, VEC_ACCUMULATE };
+//   VEC_DOT         Re <a, b> partials (a and b in precision prec)
+enum VecKind { VEC_CG_XR, VEC_AXPBY, VEC_AXPBY_NORM, VEC_NORM2, VEC_CONVERT, VEC_ACCUMULATE,
+               VEC_DOT };
 hipError_t launch_vec_batch(int kind, int prec, int prec2, const VecSys *sys_dev, int nsys,
                             int64_t max_n5, const int32_t *active, hipStream_t st);
 // out[sys * out_stride] = sum of partials[0 .. count) of each system (count_override > 0)
@@ -236,6 +240,22 @@ hipError_t launch_reduce_batch(const VecSys *sys_dev, int nsys, const int32_t *a
                                hipStream_t st);
 hipError_t launch_cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t *active,
                                   int32_t *restart, hipStream_t st);
+
+// Link derivative of the pseudofermion action (mobius_force.hip): for the
+// sites y of one parity p, grad[mu][canon(y)] (complex128 3x3, canonical link
+// layout) from FP64 packed fields L_p, R_p (parity p) and L_{1-p}, R_{1-p}.
+struct ForceParams {
+    const char *Lp, *Rp, *Ln, *Rn;
+    const int32_t *nbr;       // parity block of the neighbour table
+    const int32_t *canon_of;  // parity block of the site order
+    double2 *grad;
+    int64_t Vh, N5, V;
+    int Ls, spw;
+    OpCoeffs c;
+};
+hipError_t launch_force(const Geometry &g, const OpCoeffs &c, int parity, const int32_t *nbr,
+                        const void *Lp, const void *Rp, const void *Ln, const void *Rn,
+                        void *grad, hipStream_t st);
 
 // device buffer owned by a context
 struct DevBuf {
@@ -268,6 +288,9 @@ int set_error(int code, const std::string &msg);
 // Batched red/black CG: ngroups lattices (contexts), each with nrhs systems.
 int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *const *sol,
                 const mobius_solve_opts &opts, mobius_solve_info *info, hipStream_t stream);
+// S = phi_o^+ (D_pre^+ D_pre)^-1 phi_o with its link and source gradients.
+int force(mobius_ctx *ctx, const void *phi, void *grad_links, void *grad_phi, double *action,
+          const mobius_solve_opts &opts, mobius_solve_info *info, hipStream_t stream);
 
 }  // namespace mobius
 

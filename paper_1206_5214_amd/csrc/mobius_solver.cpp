@@ -69,7 +69,7 @@ struct Group {
 
 // extra per-system doubles
 enum Extra { X_BNORM2 = 0, X_RES_E = 2, X_RES_O = 3, X_HR = 4, X_ETA_E2 = 5, X_ETA_O2 = 6,
-             X_MINUS1 = 8, NEXTRA = 16 };
+             X_ACTION = 7, X_MINUS1 = 8, NEXTRA = 16 };
 
 struct HopPattern {
     int prec, dag, epi, out_parity;
@@ -77,9 +77,20 @@ struct HopPattern {
     bool norm;
 };
 
-enum HopPid { HP_D0A, HP_D0B, HP_D1B, HP_D1C, HP_H0A, HP_H0B, NHOP };
+// hop call patterns: D0A/D0B = D_pre p (norm), D1B/D1C = D_pre^+ r (norm),
+// H0A/H0B = D_pre x_hi in FP64; normal equations: D1Q = D_pre^+ q (no norm),
+// N64B/N64C = D_pre^+ of an FP64 field
+enum HopPid { HP_D0A, HP_D0B, HP_D1B, HP_D1C, HP_H0A, HP_H0B, HP_D1Q, HP_N64B, HP_N64C, NHOP };
 enum VecPid { VP_XR, VP_PUPD, VP_CONV_RH_R, VP_ACC, VP_RES, VP_HOPRED, VP_BLASRED, VP_NORM_B,
-              VP_NORM_EE, VP_NORM_EO, VP_CONV_B_RH, NVEC };
+              VP_NORM_EE, VP_NORM_EO, VP_CONV_B_RH, VP_XR_N, VP_PUPD_N, VP_RES_N, VP_DOT_B_XH,
+              VP_TWO_XH, NVEC };
+
+// Outputs of a force evaluation (normal-equations mode, one system).
+struct ForceOut {
+    void *grad_links;  // canonical complex128 [4][V][3][3]
+    void *grad_phi;    // canonical complex128 5d field
+    double action;
+};
 
 struct Batch {
     std::vector<Group> groups;
@@ -103,6 +114,9 @@ struct Batch {
     std::vector<HopParams> h_hop;
     std::vector<VecSys> h_vec;
     std::vector<int64_t> h_prefix;
+    // normal: CG on D_pre^+ D_pre x = b (b = the odd half of the source)
+    // instead of CGLS for D_DW psi = eta
+    bool normal = false;
     // accounting (count_only: account a graph replay without launching)
     bool count_only = false;
     int dirac = 0;
@@ -144,10 +158,11 @@ struct Batch {
     hipError_t hop(int pid);
     hipError_t hop_group(const Group &g, int prec, int dag, int epi, int out_parity, Field in,
                          Field out, Field x, Field y, bool norm);
-    hipError_t vec(int pid, int kind, int prec, int prec2);
+    hipError_t vec(int pid, int kind, int prec, int prec2, bool all = false);
     hipError_t reduce(int pid, double *out, int64_t stride, bool all = false);
-    hipError_t m5inv_dag_all(Field in, Field out);
+    hipError_t m5inv_dag_all(int prec, Field in, Field out);
     hipError_t body();                   // one CG iteration
+    hipError_t body_normal();            // one CG iteration on the normal equations
     hipError_t reliable_update();        // x_hi += x, r = b - D x_hi (FP64), r_lo = r
     hipError_t finalize_group(const Group &g);
     int fetch(std::vector<double> &out, int which);
@@ -192,6 +207,9 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
     hp[HP_D1C] = {lo, 1, EPI_POSTSUB | EPI_NORM, 1, F_T, F_S, F_R, F_NONE, true};
     hp[HP_H0A] = {MOBIUS_F64, 0, EPI_M5INV, 0, F_XH, F_T64, F_NONE, F_NONE, false};
     hp[HP_H0B] = {MOBIUS_F64, 0, EPI_M5INV | EPI_POSTSUB, 1, F_T64, F_Q64, F_XH, F_NONE, false};
+    hp[HP_D1Q] = {lo, 1, EPI_POSTSUB, 1, F_T, F_S, F_Q, F_NONE, false};
+    hp[HP_N64B] = {MOBIUS_F64, 1, EPI_M5INV, 0, F_U64, F_T64, F_NONE, F_NONE, false};
+    hp[HP_N64C] = {MOBIUS_F64, 1, EPI_POSTSUB, 1, F_T64, F_PE, F_Q64, F_NONE, false};
 
     // device state in the first context
     mobius_ctx *c0 = groups[0].ctx;
@@ -275,6 +293,16 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
             h_vec[(size_t)VP_NORM_EO * nsys + j] = t;
             t = v; t.a = F(F_B); t.b = F(F_RH);
             h_vec[(size_t)VP_CONV_B_RH * nsys + j] = t;
+            t = v; t.a = F(F_X); t.b = F(F_P); t.c = F(F_R); t.d = F(F_S); t.s0 = &sc[j].alpha;
+            h_vec[(size_t)VP_XR_N * nsys + j] = t;
+            t = v; t.a = F(F_R); t.b = F(F_P); t.d = F(F_P); t.s1 = &sc[j].beta;
+            h_vec[(size_t)VP_PUPD_N * nsys + j] = t;
+            t = v; t.a = F(F_B); t.b = F(F_PE); t.s1 = &extra[j * NEXTRA + X_MINUS1]; t.d = F(F_RH);
+            h_vec[(size_t)VP_RES_N * nsys + j] = t;
+            t = v; t.a = F(F_B); t.b = F(F_XH);
+            h_vec[(size_t)VP_DOT_B_XH * nsys + j] = t;
+            t = v; t.a = F(F_XH); t.b = F(F_XH); t.d = F(F_RH);
+            h_vec[(size_t)VP_TWO_XH * nsys + j] = t;
         }
     h_active.assign(nsys, 1);
     h_restart.assign(nsys, 1);
@@ -349,7 +377,7 @@ hipError_t Batch::hop_group(const Group &g, int prec, int dag, int epi, int out_
                       static_cast<const int32_t *>(g.ctx->nbr.p), a, st);
 }
 
-hipError_t Batch::vec(int pid, int kind, int prec, int prec2)
+hipError_t Batch::vec(int pid, int kind, int prec, int prec2, bool all)
 {
     const double fb = sum_fb(prec, true), fb2 = sum_fb(prec2, true), n5 = sum_n5(true);
     switch (kind) {
@@ -359,9 +387,11 @@ hipError_t Batch::vec(int pid, int kind, int prec, int prec2)
     case VEC_NORM2: abytes += fb; aflops += 48 * n5; break;
     case VEC_CONVERT: abytes += fb + fb2; break;
     case VEC_ACCUMULATE: abytes += 2 * fb + 2 * sum_fb(MOBIUS_F64, true); aflops += 24 * n5; break;
+    case VEC_DOT: abytes += 2 * fb; aflops += 48 * n5; break;
     }
     if (count_only) return hipSuccess;
-    return launch_vec_batch(kind, prec, prec2, vec_tab + (size_t)pid * nsys, nsys, max_n5, active, st);
+    return launch_vec_batch(kind, prec, prec2, vec_tab + (size_t)pid * nsys, nsys, max_n5,
+                            all ? nullptr : active, st);
 }
 
 hipError_t Batch::reduce(int pid, double *out, int64_t stride, bool all)
@@ -371,13 +401,13 @@ hipError_t Batch::reduce(int pid, double *out, int64_t stride, bool all)
                                stride, st);
 }
 
-hipError_t Batch::m5inv_dag_all(Field in, Field out)
+hipError_t Batch::m5inv_dag_all(int prec, Field in, Field out)
 {
     for (const Group &g : groups) {
         abytes += 2.0 * g.fb[in] * g.nrhs;
         aflops += 96.0 * g.ctx->g.N5 * g.nrhs;
         if (count_only) continue;
-        hipError_t e = launch_m5(g.ctx->g, g.ctx->c, lo, 1, 1, g.f[in], g.f[out], g.nrhs, st);
+        hipError_t e = launch_m5(g.ctx->g, g.ctx->c, prec, 1, 1, g.f[in], g.f[out], g.nrhs, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -390,7 +420,7 @@ hipError_t Batch::body()
 {
     hipError_t e;
     dirac += 4;
-    if ((e = m5inv_dag_all(F_R, F_U)) != hipSuccess) return e;
+    if ((e = m5inv_dag_all(lo, F_R, F_U)) != hipSuccess) return e;
     if ((e = hop(HP_D1B)) != hipSuccess) return e;
     if ((e = hop(HP_D1C)) != hipSuccess) return e;
     if ((e = reduce(VP_HOPRED, &sc[0].gamma_new, SC_STRIDE)) != hipSuccess) return e;
@@ -404,15 +434,44 @@ hipError_t Batch::body()
     return reduce(VP_BLASRED, &sc[0].rr, SC_STRIDE);
 }
 
+// Normal equations, p = r + beta p;  q = D p (|q|^2 -> alpha);  s = D^+ q;
+// x += alpha p, r -= alpha s (|r|^2 -> the next gamma).
+hipError_t Batch::body_normal()
+{
+    hipError_t e;
+    dirac += 4;
+    if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 1, active, restart, st)) != hipSuccess) return e;
+    if ((e = vec(VP_PUPD_N, VEC_AXPBY, lo, lo)) != hipSuccess) return e;
+    if ((e = hop(HP_D0A)) != hipSuccess) return e;
+    if ((e = hop(HP_D0B)) != hipSuccess) return e;
+    if ((e = reduce(VP_HOPRED, &sc[0].qq, SC_STRIDE)) != hipSuccess) return e;
+    if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 0, active, restart, st)) != hipSuccess) return e;
+    if ((e = m5inv_dag_all(lo, F_Q, F_U)) != hipSuccess) return e;
+    if ((e = hop(HP_D1B)) != hipSuccess) return e;
+    if ((e = hop(HP_D1Q)) != hipSuccess) return e;
+    if ((e = vec(VP_XR_N, VEC_CG_XR, lo, px)) != hipSuccess) return e;
+    if ((e = reduce(VP_BLASRED, &sc[0].rr, SC_STRIDE)) != hipSuccess) return e;
+    return reduce(VP_BLASRED, &sc[0].gamma_new, SC_STRIDE);
+}
+
 hipError_t Batch::reliable_update()
 {
     hipError_t e;
-    dirac += 2;
+    dirac += normal ? 4 : 2;
     if ((e = vec(VP_ACC, VEC_ACCUMULATE, px, MOBIUS_F64)) != hipSuccess) return e;
     if ((e = hop(HP_H0A)) != hipSuccess) return e;
     if ((e = hop(HP_H0B)) != hipSuccess) return e;
-    if ((e = vec(VP_RES, VEC_AXPBY_NORM, MOBIUS_F64, MOBIUS_F64)) != hipSuccess) return e;
-    if ((e = reduce(VP_BLASRED, &extra[X_HR], NEXTRA)) != hipSuccess) return e;
+    if (normal) {  // r = b - D^+ D x_hi
+        if ((e = m5inv_dag_all(MOBIUS_F64, F_Q64, F_U64)) != hipSuccess) return e;
+        if ((e = hop(HP_N64B)) != hipSuccess) return e;
+        if ((e = hop(HP_N64C)) != hipSuccess) return e;
+        if ((e = vec(VP_RES_N, VEC_AXPBY_NORM, MOBIUS_F64, MOBIUS_F64)) != hipSuccess) return e;
+        if ((e = reduce(VP_BLASRED, &extra[X_HR], NEXTRA)) != hipSuccess) return e;
+        if ((e = reduce(VP_BLASRED, &sc[0].gamma_new, SC_STRIDE)) != hipSuccess) return e;
+    } else {
+        if ((e = vec(VP_RES, VEC_AXPBY_NORM, MOBIUS_F64, MOBIUS_F64)) != hipSuccess) return e;
+        if ((e = reduce(VP_BLASRED, &extra[X_HR], NEXTRA)) != hipSuccess) return e;
+    }
     return vec(VP_CONV_RH_R, VEC_CONVERT, MOBIUS_F64, lo);
 }
 
@@ -448,10 +507,40 @@ int Batch::fetch(std::vector<double> &out, int which)
     return MOBIUS_OK;
 }
 
-}  // namespace
+// The derivative pass of the pseudofermion action after the normal-equations
+// solve (one system, x_hi = X):
+//   Z = I^-1 D_eo X (even), Y = D_pre X, Yt = I^-+ Y, W = I^-+ (D_oe)^+ Yt (even),
+//   link gradient per parity from (L, R) = (Yt, X) on odd and (W, Z) on even sites,
+//   S = Re <phi_o, X>,  dS/dphi = 2 X.
+int force_pass(Batch &B, ForceOut &fo)
+{
+    const Group &g = B.groups[0];
+    const Geometry &G = g.ctx->g;
+    const int32_t *nbr = static_cast<const int32_t *>(g.ctx->nbr.p);
+    hipStream_t st = B.st;
+    B.dirac += 3;
+    CK(B.hop_group(g, MOBIUS_F64, 0, EPI_M5INV, 0, F_XH, F_PE, F_NONE, F_NONE, false));
+    CK(B.hop_group(g, MOBIUS_F64, 0, EPI_M5INV | EPI_POSTSUB, 1, F_PE, F_Q64, F_XH, F_NONE, false));
+    CK(launch_m5(G, g.ctx->c, MOBIUS_F64, 1, 1, g.f[F_Q64], g.f[F_U64], 1, st));
+    CK(B.hop_group(g, MOBIUS_F64, 1, EPI_M5INV, 0, F_U64, F_T64, F_NONE, F_NONE, false));
+    CK(launch_force(G, g.ctx->c, 1, nbr, g.f[F_U64], g.f[F_XH], g.f[F_T64], g.f[F_PE], fo.grad_links, st));
+    CK(launch_force(G, g.ctx->c, 0, nbr, g.f[F_T64], g.f[F_PE], g.f[F_U64], g.f[F_XH], fo.grad_links, st));
+    B.abytes += 2.0 * 4 * g.fb[F_XH] + 4.0 * G.V * 9 * 16;
+    B.aflops += 2.0 * G.N5 * 4 * (2 * 24 + 2 * 2 * 9 * 8 + 96);
+    CK(B.vec(VP_DOT_B_XH, VEC_DOT, MOBIUS_F64, MOBIUS_F64, true));
+    CK(B.reduce(VP_BLASRED, &B.extra[X_ACTION], NEXTRA, true));
+    CK(B.vec(VP_TWO_XH, VEC_AXPBY, MOBIUS_F64, MOBIUS_F64, true));
+    CK(launch_zero(g.f[F_ETA_E], g.fb[F_ETA_E], st));
+    CK(launch_unpack_spinor(G, MOBIUS_F64, g.f[F_ETA_E], g.f[F_RH], fo.grad_phi, 1, st));
+    B.abytes += 2.0 * G.N5 * 12 * 16 + 2.0 * g.fb[F_XH];
+    std::vector<double> S;
+    if (int rc = B.fetch(S, X_ACTION)) return rc;
+    fo.action = S[0];
+    return MOBIUS_OK;
+}
 
-int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *const *sol,
-                const mobius_solve_opts &o, mobius_solve_info *info, hipStream_t user)
+int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *const *sol,
+        const mobius_solve_opts &o, mobius_solve_info *info, hipStream_t user, ForceOut *fo)
 {
     const int nrhs = o.nrhs > 0 ? o.nrhs : 1;
     const double tol = o.tol > 0 ? o.tol : 1e-10;
@@ -484,24 +573,32 @@ int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, vo
     CK(hipEventRecord(own.ev_in, user));
     CK(hipStreamWaitEvent(B.st, own.ev_in, 0));
     CK(hipEventRecord(own.ev0, B.st));
+    B.normal = fo != nullptr;
     if (int rc = B.setup(ctxs, ngroups, src, sol, nrhs, o.inner_prec)) return rc;
     const int nsys = B.nsys;
     hipStream_t st = B.st;
 
-    // source preparation, per group: b' = I^-1 (eta_o - D_oe I^-1 eta_e)
+    // source preparation, per group: b' = I^-1 (eta_o - D_oe I^-1 eta_e), or
+    // for the normal equations b = the odd half of the source
     for (const Group &g : B.groups) {
         const double canon = 2.0 * g.ctx->g.N5 * 12 * 16 * g.nrhs;
         B.abytes += canon + 2.0 * g.fb[F_ETA_E] * g.nrhs;
-        CK(launch_pack_spinor(g.ctx->g, MOBIUS_F64, g.src, g.f[F_ETA_E], g.f[F_ETA_O], g.nrhs, st));
-        CK(launch_m5(g.ctx->g, g.ctx->c, MOBIUS_F64, 1, 0, g.f[F_ETA_E], g.f[F_T64], g.nrhs, st));
-        CK(B.hop_group(g, MOBIUS_F64, 0, EPI_PRESUB | EPI_M5INV, 1, F_T64, F_B, F_ETA_O, F_NONE, false));
+        if (B.normal) {
+            CK(launch_pack_spinor(g.ctx->g, MOBIUS_F64, g.src, g.f[F_ETA_E], g.f[F_B], g.nrhs, st));
+            CK(launch_zero(g.f[F_ETA_O], g.fb[F_ETA_O] * g.nrhs, st));
+        } else {
+            CK(launch_pack_spinor(g.ctx->g, MOBIUS_F64, g.src, g.f[F_ETA_E], g.f[F_ETA_O], g.nrhs, st));
+            CK(launch_m5(g.ctx->g, g.ctx->c, MOBIUS_F64, 1, 0, g.f[F_ETA_E], g.f[F_T64], g.nrhs, st));
+            CK(B.hop_group(g, MOBIUS_F64, 0, EPI_PRESUB | EPI_M5INV, 1, F_T64, F_B, F_ETA_O, F_NONE, false));
+            B.dirac += 1;
+        }
         CK(launch_zero(g.f[F_XH], g.fb[F_XH] * g.nrhs, st));
         CK(launch_zero(g.f[F_X], g.fb[F_X] * g.nrhs, st));
         CK(launch_zero(g.f[F_P], g.fb[F_P] * g.nrhs, st));  // beta = 0 times p must be 0
     }
-    B.dirac += 1;
     CK(B.vec(VP_NORM_B, VEC_NORM2, MOBIUS_F64, MOBIUS_F64));
     CK(B.reduce(VP_BLASRED, &B.extra[X_BNORM2], NEXTRA, true));
+    if (B.normal) CK(B.reduce(VP_BLASRED, &B.sc[0].gamma_new, SC_STRIDE, true));
     CK(B.vec(VP_NORM_EE, VEC_NORM2, MOBIUS_F64, MOBIUS_F64));
     CK(B.reduce(VP_BLASRED, &B.extra[X_ETA_E2], NEXTRA, true));
     CK(B.vec(VP_NORM_EO, VEC_NORM2, MOBIUS_F64, MOBIUS_F64));
@@ -543,7 +640,7 @@ int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, vo
             for (const Group &g : B.groups) {
                 bool gp = false;
                 for (int r = 0; r < g.nrhs; ++r) gp |= pending[g.sys0 + r] != 0;
-                if (gp) CK(B.finalize_group(g));
+                if (gp && !B.normal) CK(B.finalize_group(g));
             }
             std::vector<double> re, ro, hr;
             if (int rc = B.fetch(re, X_RES_E)) return rc;
@@ -553,8 +650,11 @@ int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, vo
                 if (!pending[j]) continue;
                 pending[j] = 0;
                 const double en = std::sqrt(eta_e2[j] + eta_o2[j]);
-                true_res[j] = en > 0 ? std::sqrt(re[j] + ro[j]) / en : 0.0;
                 schur_res[j] = bnorm2[j] > 0 ? std::sqrt(hr[j] / bnorm2[j]) : 0.0;
+                if (B.normal)  // |b - D^+ D x| / |b| is the residual of the system itself
+                    true_res[j] = schur_res[j];
+                else
+                    true_res[j] = en > 0 ? std::sqrt(re[j] + ro[j]) / en : 0.0;
                 if (true_res[j] <= tol || bnorm2[j] == 0.0) {
                     converged[j] = 1;
                     B.h_active[j] = 0;
@@ -574,7 +674,7 @@ int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, vo
             if (!gexec) {
                 CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
                 hipError_t e = hipSuccess;
-                for (int q = 0; q < k && e == hipSuccess; ++q) e = B.body();
+                for (int q = 0; q < k && e == hipSuccess; ++q) e = B.normal ? B.body_normal() : B.body();
                 hipError_t e2 = hipStreamEndCapture(st, &graph);
                 CK(e);
                 CK(e2);
@@ -582,12 +682,12 @@ int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, vo
             } else {
                 // account the replay without launching anything
                 B.count_only = true;
-                for (int q = 0; q < k; ++q) (void)B.body();
+                for (int q = 0; q < k; ++q) (void)(B.normal ? B.body_normal() : B.body());
                 B.count_only = false;
             }
             CK(hipGraphLaunch(gexec, st));
         } else {
-            for (int q = 0; q < k; ++q) CK(B.body());
+            for (int q = 0; q < k; ++q) CK(B.normal ? B.body_normal() : B.body());
         }
         it += k;
         for (int j = 0; j < nsys; ++j)
@@ -623,8 +723,12 @@ int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, vo
         if (int rc = sync_flags()) return rc;
     }
 
+    if (B.normal) {
+        if (int rc = force_pass(B, *fo)) return rc;
+    }
     // solutions: psi_e = I^-1 (eta_e - D_eo x_hi), psi_o = x_hi
     for (const Group &g : B.groups) {
+        if (B.normal) break;
         CK(B.hop_group(g, MOBIUS_F64, 0, EPI_PRESUB | EPI_M5INV, 0, F_XH, F_PE, F_ETA_E, F_NONE, false));
         CK(launch_unpack_spinor(g.ctx->g, MOBIUS_F64, g.f[F_PE], g.f[F_XH], g.sol, g.nrhs, st));
         B.abytes += 2.0 * g.ctx->g.N5 * 12 * 16 * g.nrhs + 2.0 * g.fb[F_XH] * g.nrhs;
@@ -640,7 +744,8 @@ int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, vo
         mobius_solve_info &inf = info[j];
         std::memset(&inf, 0, sizeof(inf));
         inf.iters = iters[j];
-        inf.dirac_apps = 1 + 4 * iters[j] + 2 * reliable[j] + 4;
+        inf.dirac_apps = B.normal ? 4 * iters[j] + 4 * reliable[j] + 3
+                                  : 1 + 4 * iters[j] + 2 * reliable[j] + 4;
         inf.reliable_updates = reliable[j];
         inf.status = converged[j] ? MOBIUS_OK : MOBIUS_NOT_CONVERGED;
         inf.true_resid = true_res[j];
@@ -651,6 +756,26 @@ int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, vo
         if (!converged[j]) status = MOBIUS_NOT_CONVERGED;
     }
     return status;
+}
+
+}  // namespace
+
+int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *const *sol,
+                const mobius_solve_opts &o, mobius_solve_info *info, hipStream_t user)
+{
+    return run(ctxs, ngroups, src, sol, o, info, user, nullptr);
+}
+
+int force(mobius_ctx *ctx, const void *phi, void *grad_links, void *grad_phi, double *action,
+          const mobius_solve_opts &o, mobius_solve_info *info, hipStream_t user)
+{
+    ForceOut fo{grad_links, grad_phi, 0.0};
+    mobius_solve_opts o1 = o;
+    o1.nrhs = 1;
+    void *sol = nullptr;
+    const int rc = run(&ctx, 1, &phi, &sol, o1, info, user, &fo);
+    if (rc >= 0) *action = fo.action;
+    return rc;
 }
 
 }  // namespace mobius

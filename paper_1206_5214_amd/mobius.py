@@ -23,7 +23,7 @@ OK, NOT_CONVERGED = 0, 1
 
 EXPORTS = ("mobius_create", "mobius_destroy", "mobius_field_bytes", "mobius_pack",
            "mobius_unpack", "mobius_dslash", "mobius_dslash_dag", "mobius_m5inv",
-           "mobius_cg_solve", "mobius_batch_solve", "mobius_last_error")
+           "mobius_cg_solve", "mobius_batch_solve", "mobius_force", "mobius_last_error")
 
 
 class MobiusError(RuntimeError):
@@ -88,6 +88,8 @@ def lib():
         L.mobius_batch_solve.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                          ctypes.POINTER(vp), ctypes.POINTER(_SolveOpts),
                                          ctypes.POINTER(_SolveInfo), vp]
+        L.mobius_force.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(_SolveOpts), ctypes.POINTER(_SolveInfo), vp]
         L.mobius_last_error.restype = ctypes.c_char_p
         for f in EXPORTS:
             if f not in ("mobius_field_bytes", "mobius_last_error"):
@@ -160,6 +162,10 @@ class Operator:
         Lx, Ly, Lz, Lt = self.dims
         s = (self.Ls, Lt, Lz, Ly, Lx, 4, 3)
         return s if nrhs is None else (nrhs,) + s
+
+    def link_shape(self):
+        Lx, Ly, Lz, Lt = self.dims
+        return (4, Lt, Lz, Ly, Lx, 3, 3)
 
     def field_bytes(self, prec):
         return int(lib().mobius_field_bytes(self._h, prec))
@@ -234,6 +240,23 @@ class Operator:
         rc = _check(lib().mobius_cg_solve(self._h, _ptr(src), _ptr(sol), ctypes.byref(opts), infos,
                                           _stream()))
         return sol, [_info(i) for i in infos], rc
+
+    def force(self, phi, tol=1e-12, maxiter=20000, inner_prec=F64, reliable_delta=0.1,
+              check_every=0):
+        """S = phi_o^+ (D_pre^+ D_pre)^-1 phi_o (phi canonical complex128, its odd
+        sites used) with dS/dU (canonical links layout) and dS/dphi = 2 X.
+        Returns (S, grad_links, grad_phi, SolveInfo, rc)."""
+        import torch
+        self._check_canon(phi, 1, "phi")
+        grad_links = torch.empty(self.link_shape(), dtype=torch.complex128, device=phi.device)
+        grad_phi = torch.empty_like(phi)
+        action = ctypes.c_double(0.0)
+        opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, 1, check_every)
+        info = _SolveInfo()
+        rc = _check(lib().mobius_force(self._h, _ptr(phi), _ptr(grad_links), _ptr(grad_phi),
+                                       ctypes.byref(action), ctypes.byref(opts), ctypes.byref(info),
+                                       _stream()))
+        return action.value, grad_links, grad_phi, _info(info), rc
 
 
 def _info(i):

@@ -149,6 +149,32 @@ def test_pack_roundtrip_and_adjoint_on_gpu(torch_cuda):
     op.close()
 
 
+def test_f16_pack_tiny_sites(torch_cuda):
+    """FP16 storage of a field whose 5d sites span 1 .. 1e-45 in magnitude (as
+    the front of a Krylov vector grown from a point source does): sites whose
+    largest component is below the smallest normal FP32 number are stored as
+    zero, every other site to binary16 precision relative to its own norm, and
+    nothing decodes to inf or NaN."""
+    torch = torch_cuda
+    p = _params((4, 4, 2, 6), 8)
+    U, psi, op = _setup(torch, p)
+    rng = np.random.default_rng(11)
+    scale = 10.0 ** -rng.uniform(0, 45, size=psi.shape[:-2])
+    x = psi * scale[..., None, None]
+    canon = torch.from_numpy(x).cuda()
+    e, o = op.pack(canon, 2)
+    back = op.unpack(e, o, 2).cpu().numpy()
+    assert np.all(np.isfinite(back))
+    xf = x.astype(np.complex64).astype(np.complex128)  # the pack rounds to FP32 first
+    site_max = np.max(np.maximum(np.abs(xf.real), np.abs(xf.imag)), axis=(-2, -1))
+    tiny = site_max < np.finfo(np.float32).tiny
+    assert np.count_nonzero(tiny) > 0 and np.count_nonzero(~tiny) > 0
+    assert np.all(back[tiny] == 0)
+    err = np.max(np.abs(back - xf), axis=(-2, -1))
+    assert np.all(err[~tiny] <= 2.0 ** -10 * site_max[~tiny])
+    op.close()
+
+
 def test_repeatable_bitwise(torch_cuda):
     """Two applications give bit-identical results (no atomics, fixed reduction order)."""
     from paper_1206_5214_amd import mobius
