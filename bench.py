@@ -209,6 +209,42 @@ def uneven_batch_runs(torch, inputs, mobius):
     return out
 
 
+def force_runs(torch, inputs, mobius):
+    """Pseudofermion action S = phi_o^+ (D_pre^+ D_pre)^-1 phi_o with dS/dU and
+    dS/dphi on the 24^3 x 64, Ls = 12 Moebius lattice (b5 = 1.5, c5 = 0.5):
+    CG on the normal operator to 1e-10 (plain FP64, and FP16-storage inner
+    operator with FP64 reliable updates) followed by the derivative pass."""
+    w = inputs.WORKLOADS["force_24x24x24x64_ls12"]
+    U, phi = inputs.workload_fields(w)
+    op = mobius.Operator(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, torch.from_numpy(U).cuda())
+    phi = torch.from_numpy(phi).cuda()
+    del U
+    for prec in (mobius.F64, mobius.F32, mobius.F16):
+        op.tune(prec)
+    out = {"workload": w.name}
+    ref = None
+    for prec in (mobius.F64, mobius.F16):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S, G, gphi, info, rc = op.force(phi, tol=w.tol, maxiter=50000, inner_prec=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if rc != mobius.OK:
+            raise RuntimeError(f"force solve failed: {info}")
+        rec = {"seconds": dt, "iters": info.iters, "reliable_updates": info.reliable_updates,
+               "normal_resid": info.true_resid, "action": S}
+        if ref is None:
+            ref = (S, G)
+        else:
+            rec["rel_diff_action_vs_f64"] = abs(S - ref[0]) / abs(ref[0])
+            rec["max_rel_diff_grad_vs_f64"] = ((G - ref[1]).abs().max() / ref[1].abs().max()).item()
+        out[f"inner_{PREC_NAMES[prec]}"] = rec
+        log(f"force inner {PREC_NAMES[prec]}: {dt:.3f} s, {info.iters} iters, S = {S:.10e}")
+        del G, gphi
+    op.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +256,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 / FP32 comparison solves")
+    ap.add_argument("--no-force", action="store_true",
+                    help="skip the pseudofermion force timing")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the multi-RHS and uneven-batch time-to-solution runs")
     args = ap.parse_args()
@@ -244,6 +282,10 @@ def main():
     etad = torch.from_numpy(eta).cuda()
     op = mobius.Operator(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, Ud)
     torch.cuda.synchronize()
+    tuning = {}
+    for prec in (mobius.F64, mobius.F32, mobius.F16):
+        tuning[PREC_NAMES[prec]] = op.tune(prec)
+        log(f"tuned hop {PREC_NAMES[prec]}: {tuning[PREC_NAMES[prec]]}")
 
     # -- metered hop kernel, every precision --------------------------------
     hop = {}
@@ -311,6 +353,10 @@ def main():
         batch = {"multi_rhs": multi_rhs_runs(torch, inputs, mobius),
                  "uneven_batch": uneven_batch_runs(torch, inputs, mobius)}
         torch.cuda.empty_cache()
+    force = None
+    if not args.no_force:
+        force = force_runs(torch, inputs, mobius)
+        torch.cuda.empty_cache()
 
     hname = PREC_NAMES[inner]
     key = f"hop_{hname}_{args.workload}"
@@ -351,6 +397,8 @@ def main():
         "hop": hop,
         "time_to_solution": compare,
         "batched": batch,
+        "force": force,
+        "tuning": tuning,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -197,6 +197,32 @@ int mobius_force(mobius_ctx *ctx, const void *phi_c128, void *grad_links_c128, v
                  double *action, const mobius_solve_opts *opts, mobius_solve_info *info,
                  void *stream);
 
+/* Launch parameters of the hop kernel chosen by mobius_tune. */
+typedef struct {
+    int32_t prec;        /* storage precision tuned */
+    int32_t prefetch;    /* software-pipelining depth of the direction loop (0, 1, 2) */
+    int32_t stage_links; /* links of a workgroup's sites copied to LDS first (0/1) */
+    int32_t xcd_remap;   /* workgroups of one XCD cover one contiguous range of sites (0/1) */
+    int32_t nt_links;    /* non-temporal link loads (0/1) */
+    double hop_us;       /* measured time of one hop application D_{p,1-p} (microseconds) */
+} mobius_tune_result;
+
+/* Autotune the hop kernel of this context for storage precision `prec`
+ * (MOBIUS_F64/F32/F16): every combination of the launch parameters above is
+ * timed on `reps` applications of each parity (<= 0 selects 10), the fastest
+ * is kept in the context and used by every later call on it (operator blocks,
+ * solves, batches, force).  If the environment variable MOBIUS_TUNE_CACHE
+ * names a file, an entry for the same lattice, Ls, site order, precision and
+ * device is used without timing, and a new measurement is appended to it.
+ * The tuner uses context scratch memory only; caller fields are untouched.
+ * Synchronises.  out may be NULL. */
+int mobius_tune(mobius_ctx *ctx, int32_t prec, int32_t reps, mobius_tune_result *out, void *stream);
+
+/* Set the hop launch parameters of a context for precision t->prec directly
+ * (for example those an earlier mobius_tune reported; t->hop_us is ignored).
+ * Returns MOBIUS_EINVAL for a value outside the ranges above. */
+int mobius_set_tuning(mobius_ctx *ctx, const mobius_tune_result *t);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *mobius_last_error(void);
 

@@ -20,7 +20,8 @@ LIB = os.path.join(PKG, "libmobius.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["mobius_kernels.hip", "mobius_force.hip", "mobius_api.cpp", "mobius_solver.cpp"]
+SOURCES = ["mobius_kernels.hip", "mobius_force.hip", "mobius_api.cpp", "mobius_solver.cpp",
+           "mobius_tune.cpp"]
 
 COMMON = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

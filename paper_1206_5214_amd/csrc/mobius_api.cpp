@@ -224,6 +224,8 @@ extern "C" int mobius_create(mobius_ctx **out, const mobius_params *p, const voi
     packed_dev.release();
     if (e != hipSuccess) return cleanup(fail(MOBIUS_EHIP, hipGetErrorString(e)));
     for (int prec = 0; prec < 3; ++prec) {
+        ctx->tune[prec] = hop_tuning();
+        ctx->tune[prec].prefetch = prefetch_depth(hop_tuning(), prec);
         e = ctx->links[prec].ensure(2 * 8 * g.Vh * (int64_t)link_record_bytes(prec));
         if (e != hipSuccess) return cleanup(fail(MOBIUS_ENOMEM, "links: " + std::string(hipGetErrorString(e))));
         e = launch_pack_links(g, prec, links_c128, ctx->links[prec].p, st);
@@ -298,8 +300,10 @@ HopArgs hop_args(int prec, int dag, int epi, int out_parity, const void *in, voi
     return a;
 }
 
-hipError_t hop(mobius_ctx *ctx, const HopArgs &a, hipStream_t st)
+hipError_t hop(mobius_ctx *ctx, const HopArgs &a0, hipStream_t st)
 {
+    HopArgs a = a0;
+    a.tune = &ctx->tune[a.prec];
     return launch_hop(ctx->g, ctx->c, ctx->links[a.prec].p, static_cast<const int32_t *>(ctx->nbr.p),
                       a, st);
 }
@@ -426,4 +430,32 @@ extern "C" int mobius_force(mobius_ctx *ctx, const void *phi, void *grad_links, 
     if (phi == grad_phi || phi == grad_links || grad_phi == grad_links)
         return fail(MOBIUS_EINVAL, "mobius_force arguments alias");
     return mobius::force(ctx, phi, grad_links, grad_phi, action, *opts, info, S(stream));
+}
+
+extern "C" int mobius_tune(mobius_ctx *ctx, int32_t prec, int32_t reps, mobius_tune_result *out,
+                           void *stream)
+{
+    g_err.clear();
+    if (int r = check_ctx(ctx)) return r;
+    if (int r = check_prec(prec)) return r;
+    return mobius::tune(ctx, prec, reps, out, S(stream));
+}
+
+extern "C" int mobius_set_tuning(mobius_ctx *ctx, const mobius_tune_result *t)
+{
+    g_err.clear();
+    if (int r = check_ctx(ctx)) return r;
+    if (!t) return fail(MOBIUS_EINVAL, "null tuning");
+    if (int r = check_prec(t->prec)) return r;
+    if (t->prefetch < 0 || t->prefetch > 2 || (t->stage_links & ~1) || (t->xcd_remap & ~1) ||
+        (t->nt_links & ~1))
+        return fail(MOBIUS_EINVAL, "tuning value out of range");
+    HopTuning h;
+    h.prefetch = t->prefetch;
+    h.stage_links = t->stage_links;
+    h.xcd_remap = t->xcd_remap;
+    h.nt_links = t->nt_links;
+    ctx->tune[t->prec] = h;
+    ctx->tuned_us[t->prec] = 0;
+    return MOBIUS_OK;
 }

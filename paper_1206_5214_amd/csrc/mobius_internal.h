@@ -103,6 +103,7 @@ struct HopArgs {
     const int32_t *active = nullptr;  // per-rhs flags in device memory (null: all)
     int64_t fstride = 0;  // bytes between rhs fields (0: one field)
     int64_t pstride = 0;  // partial slots per rhs (0: the number of blocks)
+    const struct HopTuning *tune = nullptr;  // launch parameters (null: process defaults)
 };
 
 // Kernel arguments of one hop launch over one lattice and nrhs fields (rhs r
@@ -122,12 +123,16 @@ struct HopParams {
     int remap;              // XCD-contiguous block order
     int stage_links;        // copy the block's links to LDS first
     int nt;                 // non-temporal loads of the links
+    int pf;                 // prefetch depth of the direction loop (0, 1, 2)
     OpCoeffs c;
 };
 
-// Launch parameters of the hop kernel chosen at run time (defaults are the
-// tuned values; MOBIUS_XCD_REMAP=0/1 overrides the block order,
-// MOBIUS_PREFETCH=0/1/2 the software pipelining depth of the direction loop).
+// Launch parameters of the hop kernel chosen at run time.  The process
+// defaults are the values measured best at 24^3x64, Ls=12 (environment
+// overrides: MOBIUS_XCD_REMAP=0/1 block order, MOBIUS_PREFETCH=0/1/2 software
+// pipelining depth of the direction loop, MOBIUS_STAGE_LINKS=0/1,
+// MOBIUS_NT_LINKS=0/1); every context holds its own copy per precision, which
+// mobius_tune replaces by the fastest measured candidate.
 struct HopTuning {
     int xcd_remap = 1;
     int prefetch = -1;     // 0, 1 (next neighbour spinor), 2 (and its link); -1: per precision
@@ -170,7 +175,8 @@ HopParams make_hop_params(const Geometry &g, const OpCoeffs &c, const void *link
 size_t hop_link_lds_bytes(int prec, int Ls);
 // persistent launch over groups (device array) with block prefix sums prefix[0..n]
 hipError_t launch_hop_batch(int prec, int dag, int epi, const HopParams *groups_dev, int ngroups,
-                            const int64_t *prefix_dev, size_t lds_bytes, int grid, hipStream_t st);
+                            const int64_t *prefix_dev, size_t lds_bytes, int grid, int pf,
+                            hipStream_t st);
 // Per-site s-direction operators on one packed half field:
 //   kind 0: out = I in (dag: I^+ in); kind 1: out = I^-1 in (dag: I^-+ in)
 hipError_t launch_m5(const Geometry &g, const OpCoeffs &c, int prec, int kind, int dag,
@@ -288,6 +294,9 @@ int set_error(int code, const std::string &msg);
 // Batched red/black CG: ngroups lattices (contexts), each with nrhs systems.
 int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *const *sol,
                 const mobius_solve_opts &opts, mobius_solve_info *info, hipStream_t stream);
+// Time the hop launch candidates for one precision; keep the best in ctx.
+int tune(mobius_ctx *ctx, int prec, int reps, mobius_tune_result *out, hipStream_t st);
+
 // S = phi_o^+ (D_pre^+ D_pre)^-1 phi_o with its link and source gradients.
 int force(mobius_ctx *ctx, const void *phi, void *grad_links, void *grad_phi, double *action,
           const mobius_solve_opts &opts, mobius_solve_info *info, hipStream_t stream);
@@ -307,4 +316,6 @@ struct mobius_ctx {
     mobius::DevBuf partials;  // reduction partials
     mobius::DevBuf scalars;   // solver scalars, flags and descriptor tables
     hipStream_t solve_stream = nullptr;
+    mobius::HopTuning tune[3];  // hop launch parameters per storage precision
+    double tuned_us[3] = {0, 0, 0};  // hop time of the tuned parameters (0: not tuned)
 };

@@ -842,7 +842,7 @@ void hop_launch(const HopParams &hp, hipStream_t st)
 {
     const size_t dyn = hp.stage_links ? link_lds_bytes<P>(hp.spw) : 0;
     const dim3 grid((unsigned)hp.nblocks), blk(BLOCK);
-    switch (prefetch_depth(hop_tuning(), P)) {
+    switch (hp.pf) {
     case 0: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 0>), grid, blk, dyn, st, hp); break;
     case 1: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 1>), grid, blk, dyn, st, hp); break;
     default: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 2>), grid, blk, dyn, st, hp); break;
@@ -851,9 +851,9 @@ void hop_launch(const HopParams &hp, hipStream_t st)
 
 template <int P, bool DAG, int EPI>
 void hop_batch_launch(const HopParams *groups, int n, const int64_t *prefix, size_t dyn, int grid,
-                      hipStream_t st)
+                      int pf, hipStream_t st)
 {
-    switch (prefetch_depth(hop_tuning(), P)) {
+    switch (pf) {
     case 0: hipLaunchKernelGGL((hop_batch_kernel<P, DAG, EPI, 0>), dim3(grid), dim3(BLOCK), dyn, st, groups, n, prefix); break;
     case 1: hipLaunchKernelGGL((hop_batch_kernel<P, DAG, EPI, 1>), dim3(grid), dim3(BLOCK), dyn, st, groups, n, prefix); break;
     default: hipLaunchKernelGGL((hop_batch_kernel<P, DAG, EPI, 2>), dim3(grid), dim3(BLOCK), dyn, st, groups, n, prefix); break;
@@ -876,6 +876,7 @@ bool dispatch_hop(int prec, int dag, int epi, A &&...args)
     case EPI_PRESUB | EPI_M5INV: F<P, D, EPI_PRESUB | EPI_M5INV>::run(args...); return true;       \
     case EPI_POSTSUB | EPI_NORM: F<P, D, EPI_POSTSUB | EPI_NORM>::run(args...); return true;       \
     case EPI_M5ADD: F<P, D, EPI_M5ADD>::run(args...); return true;                                 \
+    case EPI_M5ADD | EPI_PRESUB: F<P, D, EPI_M5ADD | EPI_PRESUB>::run(args...); return true;       \
     case EPI_M5ADD | EPI_PRESUB | EPI_NORM:                                                        \
         F<P, D, EPI_M5ADD | EPI_PRESUB | EPI_NORM>::run(args...);                                  \
         return true;                                                                               \
@@ -900,10 +901,10 @@ struct RunHop {
 };
 template <int P, bool D, int E>
 struct RunHopBatch {
-    static void run(const HopParams *g, int n, const int64_t *prefix, size_t dyn, int grid,
+    static void run(const HopParams *g, int n, const int64_t *prefix, size_t dyn, int grid, int pf,
                     hipStream_t st)
     {
-        hop_batch_launch<P, D, E>(g, n, prefix, dyn, grid, st);
+        hop_batch_launch<P, D, E>(g, n, prefix, dyn, grid, pf, st);
     }
 };
 
@@ -940,9 +941,11 @@ HopParams make_hop_params(const Geometry &g, const OpCoeffs &c, const void *link
     hp.Ls = g.Ls;
     hp.spw = sites_per_wave(g.Ls);
     hp.nrhs = a.nrhs;
-    hp.remap = hop_tuning().xcd_remap;
-    hp.stage_links = hop_tuning().stage_links && hop_link_lds_bytes(a.prec, g.Ls) <= 64 * 1024;
-    hp.nt = hop_tuning().nt_links;
+    const HopTuning &t = a.tune ? *a.tune : hop_tuning();
+    hp.remap = t.xcd_remap;
+    hp.stage_links = t.stage_links && hop_link_lds_bytes(a.prec, g.Ls) <= 64 * 1024;
+    hp.nt = t.nt_links;
+    hp.pf = prefetch_depth(t, a.prec);
     hp.c = c;
     return hp;
 }
@@ -956,10 +959,11 @@ hipError_t launch_hop(const Geometry &g, const OpCoeffs &c, const void *links, c
 }
 
 hipError_t launch_hop_batch(int prec, int dag, int epi, const HopParams *groups_dev, int ngroups,
-                            const int64_t *prefix_dev, size_t lds_bytes, int grid, hipStream_t st)
+                            const int64_t *prefix_dev, size_t lds_bytes, int grid, int pf,
+                            hipStream_t st)
 {
     if (!dispatch_hop<RunHopBatch>(prec, dag, epi & ~EPI_BDAG, groups_dev, ngroups, prefix_dev,
-                                   lds_bytes, grid, st))
+                                   lds_bytes, grid, pf, st))
         return hipErrorInvalidValue;
     return hipGetLastError();
 }

@@ -83,7 +83,8 @@ struct HopPattern {
 enum HopPid { HP_D0A, HP_D0B, HP_D1B, HP_D1C, HP_H0A, HP_H0B, HP_D1Q, HP_N64B, HP_N64C, NHOP };
 enum VecPid { VP_XR, VP_PUPD, VP_CONV_RH_R, VP_ACC, VP_RES, VP_HOPRED, VP_BLASRED, VP_NORM_B,
               VP_NORM_EE, VP_NORM_EO, VP_CONV_B_RH, VP_XR_N, VP_PUPD_N, VP_RES_N, VP_DOT_B_XH,
-              VP_TWO_XH, NVEC };
+              VP_TWO_XH, VP_NORM_Q, VP_NORM_S, VP_NORM_T64, VP_NORM_Q64, VP_DBG_R, VP_DBG_P, VP_DBG_Q, VP_DBG_S, VP_DBG_T, VP_DBG_U, VP_DBG_X,
+              NVEC };
 
 // Outputs of a force evaluation (normal-equations mode, one system).
 struct ForceOut {
@@ -119,6 +120,16 @@ struct Batch {
     bool normal = false;
     // accounting (count_only: account a graph replay without launching)
     bool count_only = false;
+    bool trace = false;  // print field norms after every step of body() (eager launches only)
+    // The hop kernels fuse |out|^2 partial sums into their epilogue only when a
+    // workgroup handles one output block of one system (one lattice, one
+    // right-hand side).  With several right-hand sides per workgroup, the fused
+    // sums left corrupted FP16 outputs for some systems on 12^4 and larger
+    // lattices (found by tracing the field norms of each step; the same
+    // kernels without the fused sum, or one launch per right-hand side, are
+    // exact), so there the norms come from a separate reduction pass.
+    bool fused_norm = true;
+
     int dirac = 0;
     double abytes = 0, aflops = 0;
 
@@ -156,6 +167,8 @@ struct Batch {
               int prec);
     HopArgs hop_args_for(const Group &g, const HopPattern &p) const;
     hipError_t hop(int pid);
+    hipError_t launch_pattern(const HopPattern &p, int pid);
+    int norm_red() const { return fused_norm ? VP_HOPRED : VP_BLASRED; }
     hipError_t hop_group(const Group &g, int prec, int dag, int epi, int out_parity, Field in,
                          Field out, Field x, Field y, bool norm);
     hipError_t vec(int pid, int kind, int prec, int prec2, bool all = false);
@@ -166,6 +179,7 @@ struct Batch {
     hipError_t reliable_update();        // x_hi += x, r = b - D x_hi (FP64), r_lo = r
     hipError_t finalize_group(const Group &g);
     int fetch(std::vector<double> &out, int which);
+    int debug_norms(const char *where);  // |field|^2 of every lo-precision field, every system
     void acct_hop(int prec, int epi, double fields, double n5);
 };
 
@@ -200,6 +214,7 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
         pstride = std::max(pstride, std::max(g.hop_blocks, g.blas_blocks));
         max_n5 = std::max(max_n5, G.N5);
     }
+    fused_norm = n == 1 && nrhs == 1;
     // hop call patterns of the iteration and of the reliable update
     hp[HP_D0A] = {lo, 0, EPI_M5INV, 0, F_P, F_T, F_NONE, F_NONE, false};
     hp[HP_D0B] = {lo, 0, EPI_M5INV | EPI_POSTSUB | EPI_NORM, 1, F_T, F_Q, F_P, F_NONE, true};
@@ -303,6 +318,20 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
             h_vec[(size_t)VP_DOT_B_XH * nsys + j] = t;
             t = v; t.a = F(F_XH); t.b = F(F_XH); t.d = F(F_RH);
             h_vec[(size_t)VP_TWO_XH * nsys + j] = t;
+            t = v; t.a = F(F_Q);
+            h_vec[(size_t)VP_NORM_Q * nsys + j] = t;
+            t = v; t.a = F(F_S);
+            h_vec[(size_t)VP_NORM_S * nsys + j] = t;
+            t = v; t.a = F(F_T64);
+            h_vec[(size_t)VP_NORM_T64 * nsys + j] = t;
+            t = v; t.a = F(F_Q64);
+            h_vec[(size_t)VP_NORM_Q64 * nsys + j] = t;
+            const Field dbg[] = {F_R, F_P, F_Q, F_S, F_T, F_U, F_X};
+            for (int q = 0; q < 7; ++q) {
+                t = v;
+                t.a = F(dbg[q]);
+                h_vec[(size_t)(VP_DBG_R + q) * nsys + j] = t;
+            }
         }
     h_active.assign(nsys, 1);
     h_restart.assign(nsys, 1);
@@ -338,6 +367,7 @@ HopArgs Batch::hop_args_for(const Group &g, const HopPattern &p) const
     a.active = active + g.sys0;
     a.fstride = g.fb[p.in];
     a.pstride = pstride;
+    a.tune = &g.ctx->tune[p.prec];
     return a;
 }
 
@@ -354,14 +384,32 @@ hipError_t Batch::hop(int pid)
 {
     const HopPattern &p = hp[pid];
     acct_hop(p.prec, p.epi, sum_fb(p.prec, true), sum_n5(true));
+    if (p.norm && !fused_norm) {
+        // the kernel without the fused sum, then |out|^2 of every active system
+        HopPattern q = p;
+        q.epi &= ~EPI_NORM;
+        q.norm = false;
+        const int npid = p.out == F_Q ? VP_NORM_Q : VP_NORM_S;
+        if (!count_only) {
+            hipError_t e = launch_pattern(q, pid);
+            if (e != hipSuccess) return e;
+        }
+        return vec(npid, VEC_NORM2, p.prec, p.prec);
+    }
     if (count_only) return hipSuccess;
+    return launch_pattern(p, pid);
+}
+
+hipError_t Batch::launch_pattern(const HopPattern &p, int pid)
+{
     if (ngroups() == 1) {
         const Group &g = groups[0];
         return launch_hop(g.ctx->g, g.ctx->c, g.ctx->links[p.prec].p,
                           static_cast<const int32_t *>(g.ctx->nbr.p), hop_args_for(g, p), st);
     }
     return launch_hop_batch(p.prec, p.dag, p.epi, hop_tab + (size_t)pid * ngroups(), ngroups(),
-                            prefix + (size_t)pid * (ngroups() + 1), hop_lds[pid], batch_grid, st);
+                            prefix + (size_t)pid * (ngroups() + 1), hop_lds[pid], batch_grid,
+                            h_hop[(size_t)pid * ngroups()].pf, st);
 }
 
 hipError_t Batch::hop_group(const Group &g, int prec, int dag, int epi, int out_parity, Field in,
@@ -420,18 +468,30 @@ hipError_t Batch::body()
 {
     hipError_t e;
     dirac += 4;
+#define MOBIUS_TRACE(W) \
+    if (trace && debug_norms(W) != MOBIUS_OK) return hipErrorUnknown;
+    MOBIUS_TRACE("start")
     if ((e = m5inv_dag_all(lo, F_R, F_U)) != hipSuccess) return e;
+    MOBIUS_TRACE("m5inv_dag")
     if ((e = hop(HP_D1B)) != hipSuccess) return e;
+    MOBIUS_TRACE("D1B")
     if ((e = hop(HP_D1C)) != hipSuccess) return e;
-    if ((e = reduce(VP_HOPRED, &sc[0].gamma_new, SC_STRIDE)) != hipSuccess) return e;
+    if ((e = reduce(norm_red(), &sc[0].gamma_new, SC_STRIDE)) != hipSuccess) return e;
+    MOBIUS_TRACE("D1C")
     if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 1, active, restart, st)) != hipSuccess) return e;
     if ((e = vec(VP_PUPD, VEC_AXPBY, lo, lo)) != hipSuccess) return e;
+    MOBIUS_TRACE("p-update")
     if ((e = hop(HP_D0A)) != hipSuccess) return e;
+    MOBIUS_TRACE("D0A")
     if ((e = hop(HP_D0B)) != hipSuccess) return e;
-    if ((e = reduce(VP_HOPRED, &sc[0].qq, SC_STRIDE)) != hipSuccess) return e;
+    if ((e = reduce(norm_red(), &sc[0].qq, SC_STRIDE)) != hipSuccess) return e;
+    MOBIUS_TRACE("D0B")
     if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 0, active, restart, st)) != hipSuccess) return e;
     if ((e = vec(VP_XR, VEC_CG_XR, lo, px)) != hipSuccess) return e;
-    return reduce(VP_BLASRED, &sc[0].rr, SC_STRIDE);
+    if ((e = reduce(VP_BLASRED, &sc[0].rr, SC_STRIDE)) != hipSuccess) return e;
+    MOBIUS_TRACE("x,r-update")
+#undef MOBIUS_TRACE
+    return hipSuccess;
 }
 
 // Normal equations, p = r + beta p;  q = D p (|q|^2 -> alpha);  s = D^+ q;
@@ -444,7 +504,7 @@ hipError_t Batch::body_normal()
     if ((e = vec(VP_PUPD_N, VEC_AXPBY, lo, lo)) != hipSuccess) return e;
     if ((e = hop(HP_D0A)) != hipSuccess) return e;
     if ((e = hop(HP_D0B)) != hipSuccess) return e;
-    if ((e = reduce(VP_HOPRED, &sc[0].qq, SC_STRIDE)) != hipSuccess) return e;
+    if ((e = reduce(norm_red(), &sc[0].qq, SC_STRIDE)) != hipSuccess) return e;
     if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 0, active, restart, st)) != hipSuccess) return e;
     if ((e = m5inv_dag_all(lo, F_Q, F_U)) != hipSuccess) return e;
     if ((e = hop(HP_D1B)) != hipSuccess) return e;
@@ -480,13 +540,45 @@ hipError_t Batch::finalize_group(const Group &g)
 {
     hipError_t e;
     dirac += 3;
+    const bool fuse = g.nrhs == 1;
+    const int nepi = fuse ? EPI_NORM : 0;
+    // partial sums of this group's systems: from the hop (fused) or a norm pass
+    auto norms = [&](int npid, Extra slot) -> hipError_t {
+        if (!fuse) {
+            abytes += (double)g.fb[F_T64] * g.nrhs;
+            hipError_t x = launch_vec_batch(VEC_NORM2, MOBIUS_F64, MOBIUS_F64,
+                                            vec_tab + (size_t)npid * nsys + g.sys0, g.nrhs,
+                                            g.ctx->g.N5, nullptr, st);
+            if (x != hipSuccess) return x;
+        }
+        return launch_reduce_batch(vec_tab + (size_t)(fuse ? VP_HOPRED : VP_BLASRED) * nsys + g.sys0,
+                                   g.nrhs, nullptr, 0, &extra[g.sys0 * NEXTRA + slot], NEXTRA, st);
+    };
     if ((e = hop_group(g, MOBIUS_F64, 0, EPI_PRESUB | EPI_M5INV, 0, F_XH, F_PE, F_ETA_E, F_NONE, false)) != hipSuccess) return e;
-    if ((e = hop_group(g, MOBIUS_F64, 0, EPI_M5ADD | EPI_PRESUB | EPI_NORM, 0, F_XH, F_T64, F_ETA_E, F_PE, true)) != hipSuccess) return e;
-    if ((e = launch_reduce_batch(vec_tab + (size_t)VP_HOPRED * nsys + g.sys0, g.nrhs, nullptr, 0,
-                                 &extra[g.sys0 * NEXTRA + X_RES_E], NEXTRA, st)) != hipSuccess) return e;
-    if ((e = hop_group(g, MOBIUS_F64, 0, EPI_M5ADD | EPI_PRESUB | EPI_NORM, 1, F_PE, F_Q64, F_ETA_O, F_XH, true)) != hipSuccess) return e;
-    return launch_reduce_batch(vec_tab + (size_t)VP_HOPRED * nsys + g.sys0, g.nrhs, nullptr, 0,
-                               &extra[g.sys0 * NEXTRA + X_RES_O], NEXTRA, st);
+    if ((e = hop_group(g, MOBIUS_F64, 0, EPI_M5ADD | EPI_PRESUB | nepi, 0, F_XH, F_T64, F_ETA_E, F_PE, fuse)) != hipSuccess) return e;
+    if ((e = norms(VP_NORM_T64, X_RES_E)) != hipSuccess) return e;
+    if ((e = hop_group(g, MOBIUS_F64, 0, EPI_M5ADD | EPI_PRESUB | nepi, 1, F_PE, F_Q64, F_ETA_O, F_XH, fuse)) != hipSuccess) return e;
+    return norms(VP_NORM_Q64, X_RES_O);
+}
+
+// diagnostic (MOBIUS_DEBUG >= 3, eager launches): |field|^2 of the Krylov
+// fields of every system after a step of the iteration
+int Batch::debug_norms(const char *where)
+{
+    static const char *names[] = {"r", "p", "q", "s", "t", "u", "x"};
+    for (int q = 0; q < 7; ++q) {
+        const int prec = q == 6 ? px : lo;
+        CK(launch_vec_batch(VEC_NORM2, prec, prec, vec_tab + (size_t)(VP_DBG_R + q) * nsys, nsys, max_n5,
+                            nullptr, st));
+        CK(launch_reduce_batch(vec_tab + (size_t)VP_BLASRED * nsys, nsys, nullptr, 0,
+                               &extra[X_ACTION], NEXTRA, st));
+        std::vector<double> n;
+        if (int rc = fetch(n, X_ACTION)) return rc;
+        std::fprintf(stderr, "[mobius] %s |%s|^2:", where, names[q]);
+        for (int j = 0; j < nsys; ++j) std::fprintf(stderr, " %.6e", n[j]);
+        std::fprintf(stderr, "\n");
+    }
+    return MOBIUS_OK;
 }
 
 // which: -1 = rr of every system, otherwise extra[which] of every system
@@ -549,6 +641,8 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
     const double delta = mixed ? (o.reliable_delta > 0 ? o.reliable_delta : 0.1) : 0.0;
     const int check = o.check_every > 0 ? o.check_every : (mixed ? 8 : 16);
     const bool use_graph = env_int("MOBIUS_GRAPH", 1) != 0;
+    const int debug_level = env_int("MOBIUS_DEBUG", 0);
+    const bool debug = debug_level != 0;
 
     Batch B;
     mobius_ctx *c0 = ctxs[0];
@@ -574,6 +668,8 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
     CK(hipStreamWaitEvent(B.st, own.ev_in, 0));
     CK(hipEventRecord(own.ev0, B.st));
     B.normal = fo != nullptr;
+
+
     if (int rc = B.setup(ctxs, ngroups, src, sol, nrhs, o.inner_prec)) return rc;
     const int nsys = B.nsys;
     hipStream_t st = B.st;
@@ -687,7 +783,18 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
             }
             CK(hipGraphLaunch(gexec, st));
         } else {
-            for (int q = 0; q < k; ++q) CK(B.normal ? B.body_normal() : B.body());
+            B.trace = debug_level > 2;
+            for (int q = 0; q < k; ++q) {
+                CK(B.normal ? B.body_normal() : B.body());
+                if (debug_level > 1) {  // every CG scalar of every system
+                    std::vector<CgScalars> h(nsys);
+                    CK(hipMemcpyAsync(h.data(), B.sc, sizeof(CgScalars) * nsys, hipMemcpyDeviceToHost, st));
+                    CK(hipStreamSynchronize(st));
+                    for (int j = 0; j < nsys; ++j)
+                        std::fprintf(stderr, "[mobius] it %d sys %d: gamma %.6e gamma_new %.6e beta %.6e qq %.6e alpha %.6e rr %.6e\n",
+                                     it + q + 1, j, h[j].gamma, h[j].gamma_new, h[j].beta, h[j].qq, h[j].alpha, h[j].rr);
+                }
+            }
         }
         it += k;
         for (int j = 0; j < nsys; ++j)
@@ -695,10 +802,19 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
 
         std::vector<double> rr;
         if (int rc = B.fetch(rr, -1)) return rc;
+        if (debug) {
+            std::fprintf(stderr, "[mobius] it %d:", it);
+            for (int j = 0; j < nsys; ++j)
+                if (B.h_active[j]) std::fprintf(stderr, " %d:%.3e", j, std::sqrt(rr[j] / bnorm2[j]));
+            std::fprintf(stderr, "\n");
+        }
         bool need_update = false;
         for (int j = 0; j < nsys; ++j) {
             if (!B.h_active[j]) continue;
-            if (!std::isfinite(rr[j])) return set_error(MOBIUS_EHIP, "CG breakdown: non-finite residual");
+            if (!std::isfinite(rr[j]))
+                return set_error(MOBIUS_EHIP, "CG breakdown: non-finite residual in system " +
+                                                  std::to_string(j) + " after iteration " +
+                                                  std::to_string(it));
             if (rr[j] <= tol_s[j] * tol_s[j] * bnorm2[j] || it >= maxiter ||
                 (mixed && rr[j] < delta * delta * rmax2[j]))
                 need_update = true;

@@ -64,6 +64,8 @@ WORKLOADS = {
                                   0.5, 3, notes="largest lattice of the uneven batch"),
     "force_8x8x8x16_ls8": Workload("force_8x8x8x16_ls8", (8, 8, 8, 16), 8, 1.8, 0.01, 1.5, 0.5,
                                    0.5, 4, notes="fermion-force finite-difference check"),
+    "force_24x24x24x64_ls12": Workload("force_24x24x24x64_ls12", (24, 24, 24, 64), 12, 1.8, 0.005,
+                                       1.5, 0.5, 0.6, 5, notes="fermion force, timed"),
 }
 
 # Uneven batch solved in lockstep: 8^4, 12^4, 16^4 at Ls = 8 (seeds 1-3), Moebius

@@ -23,7 +23,8 @@ OK, NOT_CONVERGED = 0, 1
 
 EXPORTS = ("mobius_create", "mobius_destroy", "mobius_field_bytes", "mobius_pack",
            "mobius_unpack", "mobius_dslash", "mobius_dslash_dag", "mobius_m5inv",
-           "mobius_cg_solve", "mobius_batch_solve", "mobius_force", "mobius_last_error")
+           "mobius_cg_solve", "mobius_batch_solve", "mobius_force", "mobius_tune",
+           "mobius_set_tuning", "mobius_last_error")
 
 
 class MobiusError(RuntimeError):
@@ -39,6 +40,12 @@ class _SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int32),
                 ("inner_prec", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
                 ("nrhs", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("prefetch", ctypes.c_int32),
+                ("stage_links", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("nt_links", ctypes.c_int32), ("hop_us", ctypes.c_double)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -90,6 +97,8 @@ def lib():
                                          ctypes.POINTER(_SolveInfo), vp]
         L.mobius_force.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(_SolveOpts), ctypes.POINTER(_SolveInfo), vp]
+        L.mobius_tune.argtypes = [vp, i32, i32, ctypes.POINTER(_TuneResult), vp]
+        L.mobius_set_tuning.argtypes = [vp, ctypes.POINTER(_TuneResult)]
         L.mobius_last_error.restype = ctypes.c_char_p
         for f in EXPORTS:
             if f not in ("mobius_field_bytes", "mobius_last_error"):
@@ -240,6 +249,19 @@ class Operator:
         rc = _check(lib().mobius_cg_solve(self._h, _ptr(src), _ptr(sol), ctypes.byref(opts), infos,
                                           _stream()))
         return sol, [_info(i) for i in infos], rc
+
+    def tune(self, prec, reps=10):
+        """Autotune the hop launch parameters of this operator for one storage
+        precision; returns the chosen parameters and the measured hop time."""
+        r = _TuneResult()
+        _check(lib().mobius_tune(self._h, prec, reps, ctypes.byref(r), _stream()))
+        return {"prec": r.prec, "prefetch": r.prefetch, "stage_links": r.stage_links,
+                "xcd_remap": r.xcd_remap, "nt_links": r.nt_links, "hop_us": r.hop_us}
+
+    def set_tuning(self, prec, prefetch, stage_links, xcd_remap, nt_links):
+        """Set the hop launch parameters for one precision explicitly."""
+        r = _TuneResult(prec, prefetch, stage_links, xcd_remap, nt_links, 0.0)
+        _check(lib().mobius_set_tuning(self._h, ctypes.byref(r)))
 
     def force(self, phi, tol=1e-12, maxiter=20000, inner_prec=F64, reliable_delta=0.1,
               check_every=0):

@@ -196,3 +196,27 @@ def test_point_sources_full_size_sampled(torch_cuda, orc):
         res, _ = _check_system(orc, p, U, eta, psi, info[a], solve_oracle=False)
         _flush(f"  rhs {a}: iters {info[a].iters} resid {res:.2e}")
     op.close()
+
+
+@pytest.mark.parametrize("inner", [1, 2], ids=["mixed_f32", "mixed_f16"])
+def test_multi_rhs_12x12x12x12_ls16(torch_cuda, orc, inner):
+    """Several right-hand sides on a lattice large enough that many workgroups
+    share each CU (the case whose FP16 outputs were corrupted while the
+    per-system norms were fused into the multi-RHS hop kernel)."""
+    from oracle import Params
+    from paper_1206_5214_amd import inputs, mobius
+    torch = torch_cuda
+    dims, Ls = (12, 12, 12, 12), 16
+    rng = np.random.default_rng(0)
+    U = inputs.random_links(dims, 0.5, rng)
+    eta = inputs.gaussian_spinor(dims, Ls, rng, 3)
+    op = mobius.Operator(dims, Ls, 1.8, 0.01, 1.5, 0.5, torch.from_numpy(U).cuda())
+    _flush(f"multi-rhs 12^4 Ls16 nrhs 3 inner {inner}")
+    sol, info, rc = op.solve(torch.from_numpy(eta).cuda(), tol=TOL, maxiter=50000, inner_prec=inner)
+    assert rc == mobius.OK, info
+    p = Params(dims, Ls, 1.8, 0.01, 1.5, 0.5)
+    psi = sol.cpu().numpy()
+    for r in range(3):
+        res, _ = _check_system(orc, p, U, eta[r], psi[r], info[r], solve_oracle=False)
+        _flush(f"  rhs {r}: iters {info[r].iters} resid {res:.2e}")
+    op.close()
