@@ -1,0 +1,198 @@
+"""Profiling driver for the metered hop kernel (run under rocprofv3).
+
+    python -m paper_1206_5214_amd.profile_hop run --prec f16 --reps 20
+        builds the 24^3 x 64, Ls = 12 workload, tunes the hop for the given
+        storage precision, runs a 1 GiB device copy (the calibration kernel for
+        the memory counters), then `reps` applications of each hop parity.
+
+    python -m paper_1206_5214_amd.profile_hop summarize --prec f16 \\
+            --fetch DIR --write DIR [--stats DIR] --out profiles/NAME
+        reads the rocprofv3 outputs of a FETCH_SIZE pass and a WRITE_SIZE pass
+        (and optionally a --kernel-trace --stats run), scales each counter by
+        what it reads for the calibration copy of known size, and writes
+        NAME.json (the per-launch HBM traffic bench.py reports, keyed to the
+        kernel source it was measured on) and NAME.md (the figures and the
+        commands that produced them).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PREC = {"f64": 0, "f32": 1, "f16": 2}
+COPY_BYTES = 1 << 30      # the calibration copy reads and writes 1 GiB
+HOP_NAME = "hop_kernel"
+
+
+def run(args):
+    import numpy as np
+    import torch
+    from paper_1206_5214_amd import inputs, mobius
+    w = inputs.WORKLOADS[args.workload]
+    prec = PREC[args.prec]
+    U, eta = inputs.workload_fields(w)
+    op = mobius.Operator(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, torch.from_numpy(U).cuda())
+    tuned = op.tune(prec)
+    even, odd = op.pack(torch.from_numpy(eta).cuda(), prec)
+    oe, oo = op.new_field(prec), op.new_field(prec)
+    a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").normal_()
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)                       # calibration: reads and writes COPY_BYTES
+    torch.cuda.synchronize()
+    for _ in range(args.reps):
+        op.dslash(odd, 0, prec, out=oe)
+        op.dslash(even, 1, prec, out=oo)
+    torch.cuda.synchronize()
+    nbytes = 2 * op.field_bytes(prec) + 72 * (op.V // 2) * {0: 16, 1: 8, 2: 4}[prec]
+    print(json.dumps({"workload": w.name, "prec": args.prec, "tuning": tuned,
+                      "algo_bytes_per_launch": nbytes, "reps": args.reps}), flush=True)
+
+
+def _csv_rows(d, pattern):
+    files = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+    if not files:
+        raise SystemExit(f"no {pattern} under {d}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _counter_per_kernel(d, counter):
+    """Counter values (summed over the dimensions rocprofv3 splits a counter
+    into) of the calibration copy and of the hop launches that follow it (the
+    timed launches; the tuner's candidate launches come before the copy)."""
+    rows = _csv_rows(d, "*counter_collection.csv")
+    per = {}
+    names = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter:
+            continue
+        disp = int(r["Dispatch_Id"])
+        per[disp] = per.get(disp, 0.0) + float(r["Counter_Value"])
+        names[disp] = r["Kernel_Name"]
+    copies = [k for k, n in names.items() if "copyBuffer" in n]
+    if not copies:
+        raise SystemExit(f"no calibration copy in {d}")
+    c = max(copies)
+    hops = [per[k] for k, n in sorted(names.items()) if k > c and HOP_NAME in n]
+    return {"copy": [per[c]], HOP_NAME: hops}
+
+
+def summarize(args):
+    src = os.path.join(ROOT, "paper_1206_5214_amd", "csrc", "mobius_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    out = {"kernel": f"{HOP_NAME} ({args.prec}, D_{{p,1-p}} = -1/2 H B, 24^3x64 Ls=12)",
+           "kernel_source_sha256": sha, "calibration_copy_bytes": COPY_BYTES}
+    traffic = {}
+    for counter, d in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
+        per = _counter_per_kernel(d, counter)
+        copy = max(per["copy"])               # KiB the counter reports for the 1 GiB copy
+        scale = COPY_BYTES / (copy * 1024.0)  # true bytes per reported byte
+        hop = per[HOP_NAME]
+        avg_kib = sum(hop) / len(hop)
+        traffic[counter] = {"raw_kib_per_launch": avg_kib, "copy_raw_kib": copy,
+                            "scale": scale, "bytes_per_launch": avg_kib * 1024.0 * scale,
+                            "launches": len(hop)}
+    out["counters"] = traffic
+    out["traffic_bytes_per_launch"] = (traffic["FETCH_SIZE"]["bytes_per_launch"] +
+                                       traffic["WRITE_SIZE"]["bytes_per_launch"])
+    if args.algo_bytes:
+        out["algo_bytes_per_launch"] = args.algo_bytes
+        out["traffic_over_algo"] = out["traffic_bytes_per_launch"] / args.algo_bytes
+    stats = None
+    if args.stats:  # durations of the timed launches (after the calibration copy)
+        rows = _csv_rows(args.stats, "*kernel_trace.csv")
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        c = max(int(r["Dispatch_Id"]) for r in rows if "copyBuffer" in r["Kernel_Name"])
+        durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows
+                if int(r["Dispatch_Id"]) > c and HOP_NAME in r["Kernel_Name"]]
+        name = next(r["Kernel_Name"] for r in rows
+                    if int(r["Dispatch_Id"]) > c and HOP_NAME in r["Kernel_Name"])
+        stats = {"kernel": name.split("(mobius::HopParams")[0].replace("mobius::(anonymous namespace)::", ""),
+                 "launches": len(durs), "avg_us": sum(durs) / len(durs)}
+        out["hop_trace"] = stats
+        if args.algo_bytes:
+            out["achieved_GBps"] = args.algo_bytes / (stats["avg_us"] * 1e-6) / 1e9
+            out["traffic_GBps"] = out["traffic_bytes_per_launch"] / (stats["avg_us"] * 1e-6) / 1e9
+    with open(args.out + ".json", "w") as f:
+        json.dump(out, f, indent=1)
+    lines = [f"# HBM traffic of the hop kernel, {args.prec}, 24^3x64 Ls=12", ""]
+    lines += ["Commands (repository root, one MI355X, `export TMPDIR=/tmp`):", "", "```"]
+    lines += args.command or []
+    lines += ["```", ""]
+    lines += ["| counter | raw KiB / launch | copy raw KiB (1 GiB) | scale | bytes / launch |",
+              "|---|---:|---:|---:|---:|"]
+    for c, t in traffic.items():
+        lines.append(f"| {c} | {t['raw_kib_per_launch']:.0f} | {t['copy_raw_kib']:.0f} | "
+                     f"{t['scale']:.3f} | {t['bytes_per_launch'] / 1e6:.1f} MB |")
+    lines.append("")
+    lines.append(f"Traffic per launch: {out['traffic_bytes_per_launch'] / 1e6:.1f} MB"
+                 + (f" against {args.algo_bytes / 1e6:.1f} MB algorithmic "
+                    f"({out['traffic_over_algo']:.2f}x)" if args.algo_bytes else ""))
+    if stats:
+        lines.append("")
+        lines.append(f"- `{stats['kernel']}`: {stats['launches']} timed launches, average "
+                     f"{stats['avg_us']:.1f} us (kernel-trace run)")
+        if args.algo_bytes:
+            lines.append(f"- algorithmic {out['achieved_GBps']:.0f} GB/s "
+                         f"({100 * out['achieved_GBps'] / 8000:.1f}% of 8 TB/s); counted traffic "
+                         f"{out['traffic_GBps']:.0f} GB/s")
+    lines.append("")
+    lines.append(f"Kernel source sha256: `{sha}`")
+    with open(args.out + ".md", "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(json.dumps(out, indent=1))
+
+
+def stats_md(args):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run."""
+    rows = _csv_rows(args.stats, "*kernel_stats.csv")
+    lines = [f"# {args.title}", "", "Command (repository root, one MI355X, `export TMPDIR=/tmp`):",
+             "", "```"] + (args.command or []) + ["```", "",
+             "| kernel | calls | avg (us) | total (ms) | % |", "|---|---:|---:|---:|---:|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:args.top]:
+        name = r["Name"].replace("mobius::(anonymous namespace)::", "").replace("mobius::", "")
+        name = name.split("(")[0]
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.1f} | {float(r['Percentage']):.1f} |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    r = sub.add_parser("run")
+    r.add_argument("--prec", default="f16", choices=list(PREC))
+    r.add_argument("--reps", type=int, default=20)
+    r.add_argument("--workload", default="mobius_24x24x24x64_ls12")
+    s = sub.add_parser("summarize")
+    s.add_argument("--prec", default="f16", choices=list(PREC))
+    s.add_argument("--fetch", required=True)
+    s.add_argument("--write", required=True)
+    s.add_argument("--stats")
+    s.add_argument("--algo-bytes", type=float)
+    s.add_argument("--out", required=True)
+    s.add_argument("--command", action="append")
+    t = sub.add_parser("stats")
+    t.add_argument("--stats", required=True)
+    t.add_argument("--title", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--top", type=int, default=20)
+    t.add_argument("--command", action="append")
+    args = ap.parse_args()
+    {"run": run, "summarize": summarize, "stats": stats_md}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    main()
