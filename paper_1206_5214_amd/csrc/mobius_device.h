@@ -77,6 +77,15 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer, CDNA
 constexpr int CPOL_NT = 2;              // cache policy bit: non-temporal
 
+// Store-data guard.  Without it, gfx950 code in which a VALU instruction
+// rewrote the data registers of a buffer store issued just before it (store
+// with an SGPR offset) left wrong values in memory: FP16 fields written by the
+// fused CG updates diverged at 12^4 x 16 and larger.  Keeping the data live
+// across two wait states after each store removes the corruption; a full
+// vmcnt(0) drain does too but costs about 3% in the hop.
+#ifndef MOBIUS_STORE_GUARD
+#define MOBIUS_STORE_GUARD(v) asm volatile("s_nop 1" ::"v"(v))
+#endif
 struct Buf {
     __amdgpu_buffer_rsrc_t r;
     __device__ __forceinline__ Buf(const void *p, int64_t bytes)
@@ -100,6 +109,7 @@ struct Buf {
     __device__ __forceinline__ void st16(u32x4 v, uint32_t voff, uint32_t soff) const
     {
         __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, 0);
+        MOBIUS_STORE_GUARD(v);
     }
     // non-temporal variants (cache policy NT): data that is not re-read soon
     __device__ __forceinline__ u32x4 ld16_nt(uint32_t voff, uint32_t soff) const
@@ -109,8 +119,16 @@ struct Buf {
     __device__ __forceinline__ void st4(uint32_t v, uint32_t voff, uint32_t soff) const
     {
         __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 0);
+        MOBIUS_STORE_GUARD(v);
     }
 };
+
+// Wait until every memory instruction this wavefront has issued has completed
+// (stores included).
+__device__ __forceinline__ void vmem_drain()
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
 
 // Materialise a value in VGPRs at this program point (an empty asm with a
 // read-write register operand; no instruction is emitted).  Used to stop the
@@ -147,6 +165,10 @@ struct Spin<MOBIUS_F64> {
             b.st16(__builtin_bit_cast(u32x4, make_double2(v[c].r, v[c].i)), k * 16u,
                    (uint32_t)c * N5 * 16u);
     }
+    __device__ static double store_norm2_q(const Buf &b, uint32_t N5, uint32_t k, cx<T> v[12])
+    {
+        return store_norm2(b, N5, k, v);
+    }
     __device__ static double store_norm2(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
     {
         store(b, N5, k, v);
@@ -177,6 +199,10 @@ struct Spin<MOBIUS_F32> {
             b.st16(__builtin_bit_cast(u32x4, make_float4(v[2 * c].r, v[2 * c].i, v[2 * c + 1].r,
                                                          v[2 * c + 1].i)),
                    k * 16u, (uint32_t)c * N5 * 16u);
+    }
+    __device__ static double store_norm2_q(const Buf &b, uint32_t N5, uint32_t k, cx<T> v[12])
+    {
+        return store_norm2(b, N5, k, v);
     }
     __device__ static double store_norm2(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
     {
@@ -231,6 +257,25 @@ struct Spin<MOBIUS_F16> {
 #pragma unroll
         for (int c = 0; c < 3; ++c) b.st16(__builtin_bit_cast(u32x4, h[c]), k * 16u, (uint32_t)c * N5 * 16u);
         b.st4(__builtin_bit_cast(uint32_t, m), k * 4u, 3u * N5 * 16u);
+    }
+    // store, return |stored value|^2 and replace v by the stored value (what a
+    // later load returns), all from the encoded registers
+    __device__ static double store_norm2_q(const Buf &b, uint32_t N5, uint32_t k, cx<T> v[12])
+    {
+        half8 h[3];
+        const float m = encode(v, h);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) b.st16(__builtin_bit_cast(u32x4, h[c]), k * 16u, (uint32_t)c * N5 * 16u);
+        b.st4(__builtin_bit_cast(uint32_t, m), k * 4u, 3u * N5 * 16u);
+        double n = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                v[4 * c + j] = {m * (float)h[c][2 * j], m * (float)h[c][2 * j + 1]};
+                n += (double)v[4 * c + j].r * v[4 * c + j].r + (double)v[4 * c + j].i * v[4 * c + j].i;
+            }
+        return n;
     }
     // store, and return |stored value|^2 computed from the encoded registers
     __device__ static double store_norm2(const Buf &b, uint32_t N5, uint32_t k, const cx<T> v[12])
@@ -324,6 +369,26 @@ struct Link<MOBIUS_F16> {
                 if (4 * q + j < 9) u[4 * q + j] = {(float)t[2 * j], (float)t[2 * j + 1]};
         }
     }
+    // the record's elements as (re, im) binary16 pairs, unconverted.  (Taken
+    // apart as eight halves: extracting single 32-bit lanes of the 128-bit
+    // buffer load let the compiler shrink the load to its first lane.)
+    __device__ static void raw_from_words(const u32x4 *q, half2v u[9])
+    {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const half8 t = __builtin_bit_cast(half8, q[k]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (4 * k + j < 9) u[4 * k + j] = half2v{t[2 * j], t[2 * j + 1]};
+        }
+    }
+    __device__ static void raw_load(const Buf &b, uint32_t voff, uint32_t soff, half2v u[9])
+    {
+        u32x4 q[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q[k] = b.ld16(voff + 16u * k, soff);
+        raw_from_words(q, u);
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -401,7 +466,131 @@ struct LinkSource {
             load_link<P>(*glob, Vh, d, i, u);
         }
     }
+    // FP16 links as stored (binary16 pairs)
+    __device__ __forceinline__ void get_raw(int d, half2v u[9]) const
+    {
+        constexpr int REC = Link<P>::REC;
+        if (lds) {
+            const u32x4 *q = reinterpret_cast<const u32x4 *>(lds + ((size_t)d * sites_blk + sib) * REC);
+            Link<P>::raw_from_words(q, u);
+        } else {
+            Link<P>::raw_load(*glob, i * (uint32_t)REC, (uint32_t)d * Vh * (uint32_t)REC, u);
+        }
+    }
 };
+
+// FP16 direction step in packed binary16 arithmetic with FP32 accumulation.
+//
+// The half spinor h = al u + bu u_{s-1} + sigma A_mu (al l + bl l_{s+1}) is
+// formed from the stored binary16 words with packed half multiply-adds; the
+// weights al, bu, bl arrive divided by s = max(|al|, |bu|, |bl|) so that every
+// term stays O(1).  The colour multiply M h (M = U or U^+, binary16 pairs as
+// stored) is a chain of packed dot products of two binary16 pairs that
+// accumulate in FP32:
+//   Re(U h)  = Ur hr - Ui hi,  Im(U h)  = Ur hi + Ui hr,
+//   Re(U* h) = Ur hr + Ui hi,  Im(U* h) = Ur hi - Ui hr,
+// with (hi, hr) the half-swapped word and the minus signs as sign-bit flips.
+// Finally acc += s (1 + sigma g_mu) (M h) in FP32.
+__device__ __forceinline__ float dot2(half2v a, half2v b, float c)
+{
+    return __builtin_amdgcn_fdot2(a, b, c, false);
+}
+// the pair with its high half negated (sign bit flip)
+__device__ __forceinline__ half2v neg_hi_h2(half2v b)
+{
+    return __builtin_bit_cast(half2v, __builtin_bit_cast(uint32_t, b) ^ 0x80000000u);
+}
+__device__ __forceinline__ half2v swap_h2(half2v b)
+{
+    const uint32_t w = __builtin_bit_cast(uint32_t, b);
+    return __builtin_bit_cast(half2v, __builtin_amdgcn_alignbit(w, w, 16u));
+}
+__device__ __forceinline__ half2v splat_h2(float x)
+{
+    const _Float16 h = (_Float16)x;
+    return half2v{h, h};
+}
+// multiplication of a binary16 pair (re, im) by -i and by +i
+__device__ __forceinline__ half2v mul_mi(half2v z) { return half2v{z.y, -z.x}; }
+__device__ __forceinline__ half2v mul_pi(half2v z) { return half2v{-z.y, z.x}; }
+
+// h[0..2] = spin row 0, h[3..5] = spin row 1 (colour inner); o holds the 12
+// components (spin * 3 + colour) of the site, um the P+ half of slice s-1 and
+// lp the P- half of slice s+1.
+template <int MU, int SIGMA, bool MIX>
+__device__ __forceinline__ void half_spinor_h2(const half2v o[12], const half2v um[6],
+                                               const half2v lp[6], half2v al, half2v bu,
+                                               half2v bl, half2v h[6])
+{
+    const half2v sg = splat_h2((float)SIGMA);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        half2v t0 = al * o[6 + a], t1 = al * o[9 + a];
+        if constexpr (MIX) {
+            t0 = t0 + bl * lp[a];
+            t1 = t1 + bl * lp[3 + a];
+        }
+        half2v A0, A1;  // A_mu (t0; t1)
+        if constexpr (MU == 0) {        // -i sigma_1
+            A0 = mul_mi(t1);
+            A1 = mul_mi(t0);
+        } else if constexpr (MU == 1) { // [[0,-1],[1,0]]
+            A0 = -t1;
+            A1 = t0;
+        } else if constexpr (MU == 2) { // -i sigma_3
+            A0 = mul_mi(t0);
+            A1 = mul_pi(t1);
+        } else {
+            A0 = t0;
+            A1 = t1;
+        }
+        half2v u0 = al * o[a], u1 = al * o[3 + a];
+        if constexpr (MIX) {
+            u0 = u0 + bu * um[a];
+            u1 = u1 + bu * um[3 + a];
+        }
+        h[a] = u0 + sg * A0;
+        h[3 + a] = u1 + sg * A1;
+    }
+}
+
+template <int MU, bool FWD, int SIGMA>
+__device__ __forceinline__ void link_accumulate_h2(const half2v h[6], float s, const half2v u[9],
+                                                   cx<float> acc[12])
+{
+    // second operands of the real and imaginary dot products
+    half2v hr[6], hi[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        if constexpr (FWD) {
+            hr[c] = neg_hi_h2(h[c]);           // (hr, -hi)
+            hi[c] = swap_h2(h[c]);             // (hi, hr)
+        } else {
+            hr[c] = h[c];                      // (hr, hi)
+            hi[c] = neg_hi_h2(swap_h2(h[c]));  // (hi, -hr)
+        }
+    }
+    const float sg = (float)SIGMA * s;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float w0r = 0.f, w0i = 0.f, w1r = 0.f, w1i = 0.f;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const half2v m = FWD ? u[a * 3 + b] : u[b * 3 + a];  // (U^+)_{ab} = conj(U_ba)
+            w0r = dot2(m, hr[b], w0r);
+            w0i = dot2(m, hi[b], w0i);
+            w1r = dot2(m, hr[3 + b], w1r);
+            w1i = dot2(m, hi[3 + b], w1i);
+        }
+        const cx<float> w0 = {w0r, w0i}, w1 = {w1r, w1i};
+        acc[a] = acc[a] + s * w0;
+        acc[3 + a] = acc[3 + a] + s * w1;
+        cx<float> o0, o1;
+        Adag_apply<float, MU>(w0, w1, o0, o1);
+        acc[6 + a] = acc[6 + a] + sg * o0;
+        acc[9 + a] = acc[9 + a] + sg * o1;
+    }
+}
 
 // Colour multiply and reconstruction of one direction: acc += (1 + sigma g_mu) M h
 // given the half spinor h = (h0; h1) = u + sigma A_mu l, with M = U (forward)
@@ -464,8 +653,8 @@ __device__ __forceinline__ void hop_dir(const cx<typename Spin<P>::T> chi[12],
 // FP16 direction step without dequantising the spinor: the raw binary16
 // words of the neighbour (and, for the b5/c5 mixing, of its s-1 and s+1
 // slices, fetched from the neighbouring lanes) enter the half spinor through
-// mixed-precision multiply-adds whose scalar factors fold the per-site norms
-// and the mixing weights:
+// packed binary16 multiply-adds whose scalar factors fold the per-site norms
+// and the mixing weights (see half_spinor_h2):
 //   h = al u_s + bu u_{s-1} + sigma A (al l_s + bl l_{s+1}),
 //   al = b5 n_s, bu = c5 f n_{s-1}, bl = c5 f' n_{s+1}  (f, f' = -mf on the wrap).
 
@@ -493,31 +682,6 @@ __device__ __forceinline__ void load_raw_f16(const Buf &b, uint32_t N5, uint32_t
 __device__ __forceinline__ half2v shfl_h2(half2v v, int lane)
 {
     return __builtin_bit_cast(half2v, __shfl((int)__builtin_bit_cast(uint32_t, v), lane, 64));
-}
-
-__device__ __forceinline__ cx<float> f32(half2v v) { return {(float)v.x, (float)v.y}; }
-
-// h0, h1 for direction MU from raw halves: own spinor o, and (MIX) the P+ part
-// um of slice s-1 and the P- part lp of slice s+1 (6 complex each).
-template <int MU, int SIGMA, bool MIX>
-__device__ __forceinline__ void half_spinor_f16(const RawH &o, const half2v um[6], const half2v lp[6],
-                                                float al, float bu, float bl, cx<float> h0[3],
-                                                cx<float> h1[3])
-{
-    const float sal = (float)SIGMA * al, sbl = (float)SIGMA * bl;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        cx<float> A0, A1;
-        A_apply<float, MU>(f32(o.c[6 + a]), f32(o.c[9 + a]), A0, A1);
-        h0[a] = al * f32(o.c[a]) + sal * A0;
-        h1[a] = al * f32(o.c[3 + a]) + sal * A1;
-        if constexpr (MIX) {
-            cx<float> B0, B1;
-            A_apply<float, MU>(f32(lp[a]), f32(lp[3 + a]), B0, B1);
-            h0[a] = h0[a] + bu * f32(um[a]) + sbl * B0;
-            h1[a] = h1[a] + bu * f32(um[3 + a]) + sbl * B1;
-        }
-    }
 }
 
 struct SiteMap {

@@ -225,6 +225,9 @@ hipError_t launch_cg_scalar(CgScalars *s, int op, hipStream_t st);
 //   VEC_NORM2       |a|^2 partials
 //   VEC_CONVERT     b (prec2) = a (prec)
 //   VEC_ACCUMULATE  d (FP64) += a (prec); a = 0
+//   VEC_DOT         Re <a, b> partials (a and b in precision prec)
+//   VEC_PUPD_X      c (prec2) += s0 b;  b = a + s1 b          (x += alpha p_old; p = s + beta p_old)
+//   VEC_XFLUSH      c (prec2) += s0 a                          (x += alpha p)
 struct VecSys {
     char *a, *b, *c, *d;
     const double *s0, *s1;
@@ -232,11 +235,11 @@ struct VecSys {
     int64_t nparts;        // number of valid partial slots (for the reduction)
     int64_t N5;
     int32_t flag;          // index into the active flags (-1: always active)
-    int32_t pad;
+    int32_t Ls;            // fifth-dimension extent of the system's lattice
+    const OpCoeffs *coef;  // operator coefficients of the system's lattice (device)
 };
-//   VEC_DOT         Re <a, b> partials (a and b in precision prec)
 enum VecKind { VEC_CG_XR, VEC_AXPBY, VEC_AXPBY_NORM, VEC_NORM2, VEC_CONVERT, VEC_ACCUMULATE,
-               VEC_DOT };
+               VEC_DOT, VEC_PUPD_X, VEC_XFLUSH };
 hipError_t launch_vec_batch(int kind, int prec, int prec2, const VecSys *sys_dev, int nsys,
                             int64_t max_n5, const int32_t *active, hipStream_t st);
 // out[sys * out_stride] = sum of partials[0 .. count) of each system (count_override > 0)
@@ -244,8 +247,14 @@ hipError_t launch_vec_batch(int kind, int prec, int prec2, const VecSys *sys_dev
 hipError_t launch_reduce_batch(const VecSys *sys_dev, int nsys, const int32_t *active,
                                int64_t count_override, double *out, int64_t out_stride,
                                hipStream_t st);
+// op 0: alpha = gamma / qq;  op 1: beta, gamma;  op 2: alpha = 0
 hipError_t launch_cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t *active,
                                   int32_t *restart, hipStream_t st);
+// r = a -= s0 b (|r|^2 partials per site block) and c = I^-+ r, in the site-lane
+// mapping of the hop (one workgroup per site block and system); max_blocks is
+// the largest number of site blocks of any system
+hipError_t launch_rupd_m5inv_batch(int prec, const VecSys *sys_dev, int nsys, int64_t max_blocks,
+                                   const int32_t *active, hipStream_t st);
 
 // Link derivative of the pseudofermion action (mobius_force.hip): for the
 // sites y of one parity p, grad[mu][canon(y)] (complex128 3x3, canonical link

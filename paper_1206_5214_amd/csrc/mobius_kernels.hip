@@ -94,24 +94,23 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
         const float wu = DAG ? 0.f : (float)k.c5 * (m.s == 0 ? -(float)k.mf : 1.f);
         const float wl = DAG ? 0.f : (float)k.c5 * (m.s == Ls - 1 ? -(float)k.mf : 1.f);
         RawH nx;
-        cx<T> unx[9];
+        half2v unx[9];
         load_raw_f16(bin, N5, jn[0], nx);
-        if constexpr (PF >= 2) ls.get(0, unx);
+        if constexpr (PF >= 2) ls.get_raw(0, unx);
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const RawH o = nx;
             if (d < 7) load_raw_f16(bin, N5, jn[d + 1], nx);
-            cx<T> u[9];
+            half2v u[9];
             if constexpr (PF >= 2) {
 #pragma unroll
                 for (int e = 0; e < 9; ++e) u[e] = unx[e];
-                if (d < 7) ls.get(d + 1, unx);
+                if (d < 7) ls.get_raw(d + 1, unx);
             } else {
-                ls.get(d, u);
+                ls.get_raw(d, u);
             }
             constexpr int SF = DAG ? +1 : -1;
             const int sig = d < 4 ? SF : -SF;
-            cx<float> h0[3], h1[3];
             half2v um[6], lp[6];
             float al, bu = 0.f, bl = 0.f;
             if constexpr (!DAG) {
@@ -127,16 +126,24 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
                 al = o.n;
             }
             (void)sig;
-#define MOBIUS_HS(MU, SG) half_spinor_f16<MU, SG, !DAG>(o, um, lp, al, bu, bl, h0, h1)
+            // weights divided by the largest of them (the binary16 step keeps
+            // every term O(1)); the scale is restored in FP32
+            const float sc = fmaxf(fabsf(al), fmaxf(fabsf(bu), fabsf(bl)));
+            // (hardware reciprocal: its last-bit error scales both the
+            // binary16 terms and their restoration, so it cancels)
+            const float inv = sc > 0.f ? __builtin_amdgcn_rcpf(sc) : 0.f;
+            const half2v al2 = splat_h2(al * inv), bu2 = splat_h2(bu * inv), bl2 = splat_h2(bl * inv);
+            half2v hh[6];
+#define MOBIUS_HS(MU, SG) half_spinor_h2<MU, SG, !DAG>(o.c, um, lp, al2, bu2, bl2, hh)
             switch (d) {
-            case 0: MOBIUS_HS(0, SF); link_accumulate<float, 0, true, SF>(h0, h1, u, acc); break;
-            case 1: MOBIUS_HS(1, SF); link_accumulate<float, 1, true, SF>(h0, h1, u, acc); break;
-            case 2: MOBIUS_HS(2, SF); link_accumulate<float, 2, true, SF>(h0, h1, u, acc); break;
-            case 3: MOBIUS_HS(3, SF); link_accumulate<float, 3, true, SF>(h0, h1, u, acc); break;
-            case 4: MOBIUS_HS(0, -SF); link_accumulate<float, 0, false, -SF>(h0, h1, u, acc); break;
-            case 5: MOBIUS_HS(1, -SF); link_accumulate<float, 1, false, -SF>(h0, h1, u, acc); break;
-            case 6: MOBIUS_HS(2, -SF); link_accumulate<float, 2, false, -SF>(h0, h1, u, acc); break;
-            default: MOBIUS_HS(3, -SF); link_accumulate<float, 3, false, -SF>(h0, h1, u, acc); break;
+            case 0: MOBIUS_HS(0, SF); link_accumulate_h2<0, true, SF>(hh, sc, u, acc); break;
+            case 1: MOBIUS_HS(1, SF); link_accumulate_h2<1, true, SF>(hh, sc, u, acc); break;
+            case 2: MOBIUS_HS(2, SF); link_accumulate_h2<2, true, SF>(hh, sc, u, acc); break;
+            case 3: MOBIUS_HS(3, SF); link_accumulate_h2<3, true, SF>(hh, sc, u, acc); break;
+            case 4: MOBIUS_HS(0, -SF); link_accumulate_h2<0, false, -SF>(hh, sc, u, acc); break;
+            case 5: MOBIUS_HS(1, -SF); link_accumulate_h2<1, false, -SF>(hh, sc, u, acc); break;
+            case 6: MOBIUS_HS(2, -SF); link_accumulate_h2<2, false, -SF>(hh, sc, u, acc); break;
+            default: MOBIUS_HS(3, -SF); link_accumulate_h2<3, false, -SF>(hh, sc, u, acc); break;
             }
 #undef MOBIUS_HS
 #pragma unroll
@@ -641,6 +648,94 @@ __global__ __launch_bounds__(BLAS_BLOCK) void accumulate_batch(const VecSys *sys
     Spin<PI>::store(Buf(v.a, Spin<PI>::bytes(v.N5)), (uint32_t)v.N5, (uint32_t)k, z);
 }
 
+// x (PX) += alpha p_old;  p = s + beta p_old.  a = s, b = p, c = x, s0 = alpha, s1 = beta.
+// (The x update of a CG step moved here from the r update: p_old is read anyway.)
+template <int P, int PX>
+__global__ __launch_bounds__(BLAS_BLOCK) void pupd_x_batch(const VecSys *sys, const int32_t *active)
+{
+    const VecSys v = sys[blockIdx.y];
+    if (sys_inactive(v, active)) return;
+    using S = Spin<P>;
+    using SX = Spin<PX>;
+    using T = typename S::T;
+    using TX = typename SX::T;
+    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (k >= v.N5) return;
+    const TX al = (TX)*v.s0;
+    const T be = (T)*v.s1;
+    const int64_t fb = S::bytes(v.N5);
+    const uint32_t n5 = (uint32_t)v.N5, kk = (uint32_t)k;
+    const Buf bs(v.a, fb), bp(v.b, fb), bx(v.c, SX::bytes(v.N5));
+    cx<T> sv[12], pv[12];
+    cx<TX> xv[12];
+    S::load(bp, n5, kk, pv);
+    SX::load(bx, n5, kk, xv);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) xv[c] = xv[c] + al * cx<TX>{(TX)pv[c].r, (TX)pv[c].i};
+    SX::store(bx, n5, kk, xv);
+    S::load(bs, n5, kk, sv);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) pv[c] = sv[c] + be * pv[c];
+    S::store(bp, n5, kk, pv);
+}
+
+// x (PX) += alpha p.  a = p, c = x, s0 = alpha.
+template <int P, int PX>
+__global__ __launch_bounds__(BLAS_BLOCK) void xflush_batch(const VecSys *sys, const int32_t *active)
+{
+    const VecSys v = sys[blockIdx.y];
+    if (sys_inactive(v, active)) return;
+    using S = Spin<P>;
+    using SX = Spin<PX>;
+    using TX = typename SX::T;
+    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (k >= v.N5) return;
+    const TX al = (TX)*v.s0;
+    const uint32_t n5 = (uint32_t)v.N5, kk = (uint32_t)k;
+    const Buf bx(v.c, SX::bytes(v.N5));
+    cx<typename S::T> pv[12];
+    cx<TX> xv[12];
+    S::load(Buf(v.a, S::bytes(v.N5)), n5, kk, pv);
+    SX::load(bx, n5, kk, xv);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) xv[c] = xv[c] + al * cx<TX>{(TX)pv[c].r, (TX)pv[c].i};
+    SX::store(bx, n5, kk, xv);
+}
+
+// r -= alpha q, |r|^2 per site block, and u = I^-+ r of the stored r, in the
+// site-lane mapping of the hop so that the Ls-direction solve stays inside a
+// wavefront.  a = r, b = q, c = u, s0 = alpha; one workgroup per site block.
+template <int P>
+__global__ __launch_bounds__(BLOCK) void rupd_m5inv_batch(const VecSys *sys, const int32_t *active)
+{
+    const VecSys v = sys[blockIdx.y];
+    if (sys_inactive(v, active)) return;
+    const int Ls = v.Ls, spw = 64 / Ls;
+    const int64_t Vh = v.N5 / Ls;
+    const int64_t per_block = (int64_t)spw * WAVES;
+    if ((int64_t)blockIdx.x * per_block >= Vh) return;  // uniform in the workgroup
+    using S = Spin<P>;
+    using T = typename S::T;
+    const SiteMap m = site_map_lb(Ls, spw, Vh, blockIdx.x);
+    const Coef<T> k = make_coef<T>(*v.coef);
+    const uint32_t n5 = (uint32_t)v.N5, k5 = (uint32_t)m.i * (uint32_t)Ls + (uint32_t)m.s;
+    const int64_t fb = S::bytes(v.N5);
+    const Buf br(v.a, fb);
+    cx<T> rv[12], qv[12];
+    S::load(br, n5, k5, rv);
+    S::load(Buf(v.b, fb), n5, k5, qv);
+    const T al = (T)*v.s0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rv[c] = rv[c] - al * qv[c];
+    double n = 0;
+    if (m.site_ok) n = S::store_norm2_q(br, n5, k5, rv);
+    vmem_drain();
+    block_sum_store(n, v.partials, blockIdx.x);
+    __shared__ M5Lds<T> lds;
+    m5inv_lanes(rv, k, m, Ls, true, lds);
+    if (m.site_ok) S::store(Buf(v.c, fb), n5, k5, rv);
+}
+
 // partials of Re <a, b>
 template <int P>
 __global__ __launch_bounds__(BLAS_BLOCK) void dot_batch(const VecSys *sys, const int32_t *active)
@@ -694,7 +789,9 @@ __global__ void cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t *
     if (j >= nsys) return;
     CgScalars &s = sc[j];
     const bool on = !active || active[j];
-    if (op == 0) {
+    if (op == 2) {
+        if (on) s.alpha = 0.0;
+    } else if (op == 0) {
         s.alpha = (on && s.qq > 0) ? s.gamma / s.qq : 0.0;
     } else {
         const bool rs = restart && restart[j];
@@ -1150,6 +1247,18 @@ hipError_t launch_vec_batch(int kind, int prec, int prec2, const VecSys *sys_dev
         break;
     case VEC_NORM2: MOBIUS_P3(norm2_batch) break;
     case VEC_DOT: MOBIUS_P3(dot_batch) break;
+    case VEC_PUPD_X:
+        if (prec == MOBIUS_F64 && prec2 == MOBIUS_F64) MOBIUS_L((pupd_x_batch<MOBIUS_F64, MOBIUS_F64>));
+        else if (prec == MOBIUS_F32 && prec2 == MOBIUS_F32) MOBIUS_L((pupd_x_batch<MOBIUS_F32, MOBIUS_F32>));
+        else if (prec == MOBIUS_F16 && prec2 == MOBIUS_F32) MOBIUS_L((pupd_x_batch<MOBIUS_F16, MOBIUS_F32>));
+        else return hipErrorInvalidValue;
+        break;
+    case VEC_XFLUSH:
+        if (prec == MOBIUS_F64 && prec2 == MOBIUS_F64) MOBIUS_L((xflush_batch<MOBIUS_F64, MOBIUS_F64>));
+        else if (prec == MOBIUS_F32 && prec2 == MOBIUS_F32) MOBIUS_L((xflush_batch<MOBIUS_F32, MOBIUS_F32>));
+        else if (prec == MOBIUS_F16 && prec2 == MOBIUS_F32) MOBIUS_L((xflush_batch<MOBIUS_F16, MOBIUS_F32>));
+        else return hipErrorInvalidValue;
+        break;
     case VEC_ACCUMULATE: MOBIUS_P3(accumulate_batch) break;
     case VEC_CONVERT:
 #define MOBIUS_CV(PI)                                                                   \
@@ -1180,6 +1289,19 @@ hipError_t launch_reduce_batch(const VecSys *sys_dev, int nsys, const int32_t *a
 {
     hipLaunchKernelGGL(reduce_batch, dim3(nsys), dim3(1024), 0, st, sys_dev, active, count_override,
                        out, out_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_rupd_m5inv_batch(int prec, const VecSys *sys_dev, int nsys, int64_t max_blocks,
+                                   const int32_t *active, hipStream_t st)
+{
+    const dim3 grid((unsigned)max_blocks, (unsigned)nsys), blk(BLOCK);
+    switch (prec) {
+    case MOBIUS_F64: hipLaunchKernelGGL(rupd_m5inv_batch<MOBIUS_F64>, grid, blk, 0, st, sys_dev, active); break;
+    case MOBIUS_F32: hipLaunchKernelGGL(rupd_m5inv_batch<MOBIUS_F32>, grid, blk, 0, st, sys_dev, active); break;
+    case MOBIUS_F16: hipLaunchKernelGGL(rupd_m5inv_batch<MOBIUS_F16>, grid, blk, 0, st, sys_dev, active); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

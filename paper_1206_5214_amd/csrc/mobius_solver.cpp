@@ -81,9 +81,9 @@ struct HopPattern {
 // H0A/H0B = D_pre x_hi in FP64; normal equations: D1Q = D_pre^+ q (no norm),
 // N64B/N64C = D_pre^+ of an FP64 field
 enum HopPid { HP_D0A, HP_D0B, HP_D1B, HP_D1C, HP_H0A, HP_H0B, HP_D1Q, HP_N64B, HP_N64C, NHOP };
-enum VecPid { VP_XR, VP_PUPD, VP_CONV_RH_R, VP_ACC, VP_RES, VP_HOPRED, VP_BLASRED, VP_NORM_B,
+enum VecPid { VP_CONV_RH_R, VP_ACC, VP_RES, VP_HOPRED, VP_BLASRED, VP_NORM_B,
               VP_NORM_EE, VP_NORM_EO, VP_CONV_B_RH, VP_XR_N, VP_PUPD_N, VP_RES_N, VP_DOT_B_XH,
-              VP_TWO_XH, VP_NORM_Q, VP_NORM_S, VP_NORM_T64, VP_NORM_Q64, VP_DBG_R, VP_DBG_P, VP_DBG_Q, VP_DBG_S, VP_DBG_T, VP_DBG_U, VP_DBG_X,
+              VP_TWO_XH, VP_PUPD_X, VP_XFLUSH, VP_RUPD, VP_NORM_Q, VP_NORM_S, VP_NORM_T64, VP_NORM_Q64, VP_DBG_R, VP_DBG_P, VP_DBG_Q, VP_DBG_S, VP_DBG_T, VP_DBG_U, VP_DBG_X,
               NVEC };
 
 // Outputs of a force evaluation (normal-equations mode, one system).
@@ -98,7 +98,7 @@ struct Batch {
     int nsys = 0;
     int lo = MOBIUS_F64, px = MOBIUS_F64;
     hipStream_t st = nullptr;
-    int64_t pstride = 0, max_n5 = 0;
+    int64_t pstride = 0, max_n5 = 0, max_site_blocks = 0;
     // device state (in the first context's buffers)
     double *part = nullptr;
     CgScalars *sc = nullptr;
@@ -175,6 +175,7 @@ struct Batch {
     hipError_t reduce(int pid, double *out, int64_t stride, bool all = false);
     hipError_t m5inv_dag_all(int prec, Field in, Field out);
     hipError_t body();                   // one CG iteration
+    hipError_t rupd();                   // r -= alpha q (|r|^2), u = I^-+ r
     hipError_t body_normal();            // one CG iteration on the normal equations
     hipError_t reliable_update();        // x_hi += x, r = b - D x_hi (FP64), r_lo = r
     hipError_t finalize_group(const Group &g);
@@ -210,6 +211,7 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
             w += g.fb[k] * nrhs;
         }
         g.hop_blocks = site_kernel_blocks(G);
+        max_site_blocks = std::max(max_site_blocks, g.hop_blocks);
         g.blas_blocks = blas_blocks(G);
         pstride = std::max(pstride, std::max(g.hop_blocks, g.blas_blocks));
         max_n5 = std::max(max_n5, G.N5);
@@ -244,6 +246,7 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
     const size_t o_hop = carve(sizeof(HopParams) * NHOP * ng);
     const size_t o_vec = carve(sizeof(VecSys) * NVEC * nsys);
     const size_t o_pre = carve(sizeof(int64_t) * NHOP * (ng + 1));
+    const size_t o_coef = carve(sizeof(OpCoeffs) * ng);
     CK(c0->scalars.ensure((int64_t)off));
     char *base = static_cast<char *>(c0->scalars.p);
     sc = reinterpret_cast<CgScalars *>(base + o_sc);
@@ -253,6 +256,9 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
     hop_tab = reinterpret_cast<HopParams *>(base + o_hop);
     vec_tab = reinterpret_cast<VecSys *>(base + o_vec);
     prefix = reinterpret_cast<int64_t *>(base + o_pre);
+    OpCoeffs *coef = reinterpret_cast<OpCoeffs *>(base + o_coef);
+    std::vector<OpCoeffs> h_coef(ng);
+    for (int j = 0; j < ng; ++j) h_coef[j] = groups[j].ctx->c;
 
     // descriptor tables
     h_hop.assign((size_t)NHOP * ng, HopParams{});
@@ -284,13 +290,11 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
             VecSys v{};
             v.N5 = g.ctx->g.N5;
             v.flag = j;
+            v.Ls = g.ctx->g.Ls;
+            v.coef = coef + (&g - groups.data());
             v.partials = part + (int64_t)j * pstride;
             v.nparts = g.blas_blocks;
             VecSys t = v;
-            t.a = F(F_X); t.b = F(F_P); t.c = F(F_R); t.d = F(F_Q); t.s0 = &sc[j].alpha;
-            h_vec[(size_t)VP_XR * nsys + j] = t;
-            t = v; t.a = F(F_S); t.b = F(F_P); t.d = F(F_P); t.s1 = &sc[j].beta;
-            h_vec[(size_t)VP_PUPD * nsys + j] = t;
             t = v; t.a = F(F_RH); t.b = F(F_R);
             h_vec[(size_t)VP_CONV_RH_R * nsys + j] = t;
             t = v; t.a = F(F_X); t.d = F(F_XH);
@@ -318,6 +322,12 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
             h_vec[(size_t)VP_DOT_B_XH * nsys + j] = t;
             t = v; t.a = F(F_XH); t.b = F(F_XH); t.d = F(F_RH);
             h_vec[(size_t)VP_TWO_XH * nsys + j] = t;
+            t = v; t.a = F(F_S); t.b = F(F_P); t.c = F(F_X); t.s0 = &sc[j].alpha; t.s1 = &sc[j].beta;
+            h_vec[(size_t)VP_PUPD_X * nsys + j] = t;
+            t = v; t.a = F(F_P); t.c = F(F_X); t.s0 = &sc[j].alpha;
+            h_vec[(size_t)VP_XFLUSH * nsys + j] = t;
+            t = v; t.a = F(F_R); t.b = F(F_Q); t.c = F(F_U); t.s0 = &sc[j].alpha; t.nparts = g.hop_blocks;
+            h_vec[(size_t)VP_RUPD * nsys + j] = t;
             t = v; t.a = F(F_Q);
             h_vec[(size_t)VP_NORM_Q * nsys + j] = t;
             t = v; t.a = F(F_S);
@@ -338,6 +348,7 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
     CK(hipMemcpyAsync(hop_tab, h_hop.data(), sizeof(HopParams) * h_hop.size(), hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(vec_tab, h_vec.data(), sizeof(VecSys) * h_vec.size(), hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(prefix, h_prefix.data(), sizeof(int64_t) * h_prefix.size(), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(coef, h_coef.data(), sizeof(OpCoeffs) * ng, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(active, h_active.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(restart, h_restart.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st));
     std::vector<double> h_extra((size_t)nsys * NEXTRA, 0.0);
@@ -471,25 +482,23 @@ hipError_t Batch::body()
 #define MOBIUS_TRACE(W) \
     if (trace && debug_norms(W) != MOBIUS_OK) return hipErrorUnknown;
     MOBIUS_TRACE("start")
-    if ((e = m5inv_dag_all(lo, F_R, F_U)) != hipSuccess) return e;
-    MOBIUS_TRACE("m5inv_dag")
     if ((e = hop(HP_D1B)) != hipSuccess) return e;
     MOBIUS_TRACE("D1B")
     if ((e = hop(HP_D1C)) != hipSuccess) return e;
     if ((e = reduce(norm_red(), &sc[0].gamma_new, SC_STRIDE)) != hipSuccess) return e;
     MOBIUS_TRACE("D1C")
     if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 1, active, restart, st)) != hipSuccess) return e;
-    if ((e = vec(VP_PUPD, VEC_AXPBY, lo, lo)) != hipSuccess) return e;
-    MOBIUS_TRACE("p-update")
+    if ((e = vec(VP_PUPD_X, VEC_PUPD_X, lo, px)) != hipSuccess) return e;
+    MOBIUS_TRACE("x,p-update")
     if ((e = hop(HP_D0A)) != hipSuccess) return e;
     MOBIUS_TRACE("D0A")
     if ((e = hop(HP_D0B)) != hipSuccess) return e;
     if ((e = reduce(norm_red(), &sc[0].qq, SC_STRIDE)) != hipSuccess) return e;
     MOBIUS_TRACE("D0B")
     if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 0, active, restart, st)) != hipSuccess) return e;
-    if ((e = vec(VP_XR, VEC_CG_XR, lo, px)) != hipSuccess) return e;
-    if ((e = reduce(VP_BLASRED, &sc[0].rr, SC_STRIDE)) != hipSuccess) return e;
-    MOBIUS_TRACE("x,r-update")
+    if ((e = rupd()) != hipSuccess) return e;
+    if ((e = reduce(VP_RUPD, &sc[0].rr, SC_STRIDE)) != hipSuccess) return e;
+    MOBIUS_TRACE("r-update")
 #undef MOBIUS_TRACE
     return hipSuccess;
 }
@@ -514,10 +523,23 @@ hipError_t Batch::body_normal()
     return reduce(VP_BLASRED, &sc[0].gamma_new, SC_STRIDE);
 }
 
+hipError_t Batch::rupd()
+{
+    const double fb = sum_fb(lo, true), n5 = sum_n5(true);
+    abytes += 4 * fb;
+    aflops += (48 + 96 + 48) * n5;
+    if (count_only) return hipSuccess;
+    return launch_rupd_m5inv_batch(lo, vec_tab + (size_t)VP_RUPD * nsys, nsys, max_site_blocks, active, st);
+}
+
 hipError_t Batch::reliable_update()
 {
     hipError_t e;
     dirac += normal ? 4 : 2;
+    if (!normal) {  // the last alpha p of the iteration, then no pending update
+        if ((e = vec(VP_XFLUSH, VEC_XFLUSH, lo, px)) != hipSuccess) return e;
+        if ((e = launch_cg_scalar_batch(sc, nsys, 2, active, restart, st)) != hipSuccess) return e;
+    }
     if ((e = vec(VP_ACC, VEC_ACCUMULATE, px, MOBIUS_F64)) != hipSuccess) return e;
     if ((e = hop(HP_H0A)) != hipSuccess) return e;
     if ((e = hop(HP_H0B)) != hipSuccess) return e;
@@ -532,7 +554,8 @@ hipError_t Batch::reliable_update()
         if ((e = vec(VP_RES, VEC_AXPBY_NORM, MOBIUS_F64, MOBIUS_F64)) != hipSuccess) return e;
         if ((e = reduce(VP_BLASRED, &extra[X_HR], NEXTRA)) != hipSuccess) return e;
     }
-    return vec(VP_CONV_RH_R, VEC_CONVERT, MOBIUS_F64, lo);
+    if ((e = vec(VP_CONV_RH_R, VEC_CONVERT, MOBIUS_F64, lo)) != hipSuccess) return e;
+    return normal ? hipSuccess : m5inv_dag_all(lo, F_R, F_U);  // u = I^-+ r for the next step
 }
 
 // psi_e = I^-1 (eta_e - D_eo x_hi); |eta - D_DW psi|^2 per parity -> extra
@@ -701,6 +724,10 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
     CK(B.reduce(VP_BLASRED, &B.extra[X_ETA_O2], NEXTRA, true));
     CK(B.vec(VP_CONV_B_RH, VEC_CONVERT, MOBIUS_F64, MOBIUS_F64));
     CK(B.vec(VP_CONV_RH_R, VEC_CONVERT, MOBIUS_F64, B.lo));
+    if (!B.normal) {  // the iteration starts from u = I^-+ r and no pending x update
+        CK(B.m5inv_dag_all(B.lo, F_R, F_U));
+        CK(launch_cg_scalar_batch(B.sc, nsys, 2, nullptr, nullptr, st));
+    }
     std::vector<double> bnorm2, eta_e2, eta_o2;
     if (int rc = B.fetch(bnorm2, X_BNORM2)) return rc;
     if (int rc = B.fetch(eta_e2, X_ETA_E2)) return rc;
