@@ -121,8 +121,10 @@ namespace mobius {
 
 // Site-order brick: among bricks whose sides divide the lattice (bx even),
 // the largest whose one-site-thick slice of an FP64 field (bx by bz / 2 sites
-// x Ls x 192 B) stays within 1 MiB, i.e. a few slices fit one XCD's 4 MiB L2;
-// ties go to the smaller surface.
+// x Ls x 192 B) stays within 2 MiB, half of one XCD's L2, so that the t
+// neighbours one slice away are still cached; ties go to the smaller surface.
+// (At 24^3 x 64, Ls = 12 this is 12^3, one column per XCD, which measured
+// fastest among bricks from 2^3 to 24^3.)
 void choose_brick(const int L[4], int Ls, int brick[3])
 {
     if (const char *e = std::getenv("MOBIUS_BRICK")) {
@@ -132,7 +134,7 @@ void choose_brick(const int L[4], int Ls, int brick[3])
             return;
         }
     }
-    const double budget = 1024.0 * 1024.0;
+    const double budget = 2.0 * 1024.0 * 1024.0;
     const double per_site = 0.5 * Ls * 192.0;
     brick[0] = 2;
     brick[1] = brick[2] = 1;

@@ -448,48 +448,17 @@ __device__ __forceinline__ void load_link(const Buf &links, uint32_t Vh, int d, 
     Link<P>::load(links, i * (uint32_t)Link<P>::REC, (uint32_t)d * Vh * (uint32_t)Link<P>::REC, u);
 }
 
-// The links of a block's sites, staged in LDS by one cooperative copy so
-// that each record crosses the vector-memory pipeline once instead of once
-// per s-lane.  Layout [d][site in block][record].
-template <int P>
-struct LinkSource {
-    const Buf *glob;
-    const char *lds;   // null: read from global memory
-    uint32_t Vh, i, sib, sites_blk;
-    __device__ __forceinline__ void get(int d, cx<typename Spin<P>::T> u[9]) const
-    {
-        constexpr int REC = Link<P>::REC;
-        if (lds) {
-            const u32x4 *q = reinterpret_cast<const u32x4 *>(lds + ((size_t)d * sites_blk + sib) * REC);
-            Link<P>::from_words(q, u);
-        } else {
-            load_link<P>(*glob, Vh, d, i, u);
-        }
-    }
-    // FP16 links as stored (binary16 pairs)
-    __device__ __forceinline__ void get_raw(int d, half2v u[9]) const
-    {
-        constexpr int REC = Link<P>::REC;
-        if (lds) {
-            const u32x4 *q = reinterpret_cast<const u32x4 *>(lds + ((size_t)d * sites_blk + sib) * REC);
-            Link<P>::raw_from_words(q, u);
-        } else {
-            Link<P>::raw_load(*glob, i * (uint32_t)REC, (uint32_t)d * Vh * (uint32_t)REC, u);
-        }
-    }
-};
 
 // FP16 direction step in packed binary16 arithmetic with FP32 accumulation.
 //
 // The half spinor h = al u + bu u_{s-1} + sigma A_mu (al l + bl l_{s+1}) is
 // formed from the stored binary16 words with packed half multiply-adds; the
 // weights al, bu, bl arrive divided by s = max(|al|, |bu|, |bl|) so that every
-// term stays O(1).  The colour multiply M h (M = U or U^+, binary16 pairs as
-// stored) is a chain of packed dot products of two binary16 pairs that
-// accumulate in FP32:
+// term stays O(1).  The colour multiply M h (M = U or U^+) is a chain of
+// packed dot products of two binary16 pairs that accumulate in FP32:
 //   Re(U h)  = Ur hr - Ui hi,  Im(U h)  = Ur hi + Ui hr,
 //   Re(U* h) = Ur hr + Ui hi,  Im(U* h) = Ur hi - Ui hr,
-// with (hi, hr) the half-swapped word and the minus signs as sign-bit flips.
+// whose signs and swaps the link carries (LinkH2), so h enters as formed.
 // Finally acc += s (1 + sigma g_mu) (M h) in FP32.
 __device__ __forceinline__ float dot2(half2v a, half2v b, float c)
 {
@@ -510,6 +479,121 @@ __device__ __forceinline__ half2v splat_h2(float x)
     const _Float16 h = (_Float16)x;
     return half2v{h, h};
 }
+__device__ __forceinline__ half2v neg_lo_h2(half2v b)
+{
+    return __builtin_bit_cast(half2v, __builtin_bit_cast(uint32_t, b) ^ 0x00008000u);
+}
+// chain start: a.lo b.lo + a.hi b.hi with a zero accumulator as an inline
+// constant (the builtin with a literal zero costs an extra register move)
+__device__ __forceinline__ float dot2_0(half2v a, half2v b)
+{
+    float r;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// An FP16 link in the operand form of the dot2 chains.  For M = U (forward
+// hop) or M = U^+ (backward hop) and h_b = (re, im) binary16 pairs,
+//   Re (M h)_a = sum_b dot2(pr[a*3+b], h_b),  Im (M h)_a = sum_b dot2(pi[a*3+b], h_b)
+// with
+//   M = U  : pr_ab = (Re U_ab,  -Im U_ab),  pi_ab = (Im U_ab, Re U_ab)
+//   M = U^+: pr_ab = (Re U_ba,   Im U_ba),  pi_ab = (-Im U_ba, Re U_ba).
+// The block's links are staged in LDS in this form (one expansion per link
+// instead of one sign flip and swap of the half spinor per lane).
+struct LinkH2 {
+    half2v pr[9], pi[9];
+};
+constexpr int LINKH2_REC = 80;  // 72 bytes of pairs, padded to 16-byte words
+
+template <bool FWD>
+__device__ __forceinline__ void expand_link(const half2v u[9], LinkH2 &x)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const half2v e = FWD ? u[a * 3 + b] : u[b * 3 + a];
+            if constexpr (FWD) {
+                x.pr[a * 3 + b] = neg_hi_h2(e);
+                x.pi[a * 3 + b] = swap_h2(e);
+            } else {
+                x.pr[a * 3 + b] = e;
+                x.pi[a * 3 + b] = neg_lo_h2(swap_h2(e));
+            }
+        }
+}
+
+__device__ __forceinline__ void linkh2_from_words(const u32x4 *q, LinkH2 &x)
+{
+    half2v w[20];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const half8 t = __builtin_bit_cast(half8, q[k]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w[4 * k + j] = half2v{t[2 * j], t[2 * j + 1]};
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        x.pr[e] = w[e];
+        x.pi[e] = w[9 + e];
+    }
+}
+
+__device__ __forceinline__ void linkh2_to_words(const LinkH2 &x, u32x4 *q)
+{
+    half2v w[20];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        w[e] = x.pr[e];
+        w[9 + e] = x.pi[e];
+    }
+    w[18] = w[19] = half2v{(_Float16)0, (_Float16)0};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        half8 t;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            t[2 * j] = w[4 * k + j].x;
+            t[2 * j + 1] = w[4 * k + j].y;
+        }
+        q[k] = __builtin_bit_cast(u32x4, t);
+    }
+}
+
+// The links of a block's sites, staged in LDS by one cooperative copy so
+// that each record crosses the vector-memory pipeline once instead of once
+// per s-lane.  Layout [d][site in block][record].
+template <int P>
+struct LinkSource {
+    const Buf *glob;
+    const char *lds;   // null: read from global memory
+    uint32_t Vh, i, sib, sites_blk;
+    __device__ __forceinline__ void get(int d, cx<typename Spin<P>::T> u[9]) const
+    {
+        constexpr int REC = Link<P>::REC;
+        if (lds) {
+            const u32x4 *q = reinterpret_cast<const u32x4 *>(lds + ((size_t)d * sites_blk + sib) * REC);
+            Link<P>::from_words(q, u);
+        } else {
+            load_link<P>(*glob, Vh, d, i, u);
+        }
+    }
+    // FP16 links in the dot2 operand form (staged in that form in LDS)
+    template <bool FWD>
+    __device__ __forceinline__ void get_h2(int d, LinkH2 &x) const
+    {
+        if (lds) {
+            const u32x4 *q = reinterpret_cast<const u32x4 *>(lds + ((size_t)d * sites_blk + sib) * LINKH2_REC);
+            linkh2_from_words(q, x);
+        } else {
+            constexpr int REC = Link<P>::REC;
+            half2v u[9];
+            Link<P>::raw_load(*glob, i * (uint32_t)REC, (uint32_t)d * Vh * (uint32_t)REC, u);
+            expand_link<FWD>(u, x);
+        }
+    }
+};
+
 // multiplication of a binary16 pair (re, im) by -i and by +i
 __device__ __forceinline__ half2v mul_mi(half2v z) { return half2v{z.y, -z.x}; }
 __device__ __forceinline__ half2v mul_pi(half2v z) { return half2v{-z.y, z.x}; }
@@ -554,33 +638,21 @@ __device__ __forceinline__ void half_spinor_h2(const half2v o[12], const half2v 
     }
 }
 
-template <int MU, bool FWD, int SIGMA>
-__device__ __forceinline__ void link_accumulate_h2(const half2v h[6], float s, const half2v u[9],
+template <int MU, int SIGMA>
+__device__ __forceinline__ void link_accumulate_h2(const half2v h[6], float s, const LinkH2 &x,
                                                    cx<float> acc[12])
 {
-    // second operands of the real and imaginary dot products
-    half2v hr[6], hi[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        if constexpr (FWD) {
-            hr[c] = neg_hi_h2(h[c]);           // (hr, -hi)
-            hi[c] = swap_h2(h[c]);             // (hi, hr)
-        } else {
-            hr[c] = h[c];                      // (hr, hi)
-            hi[c] = neg_hi_h2(swap_h2(h[c]));  // (hi, -hr)
-        }
-    }
     const float sg = (float)SIGMA * s;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        float w0r = 0.f, w0i = 0.f, w1r = 0.f, w1i = 0.f;
+        float w0r = dot2_0(x.pr[a * 3], h[0]), w0i = dot2_0(x.pi[a * 3], h[0]);
+        float w1r = dot2_0(x.pr[a * 3], h[3]), w1i = dot2_0(x.pi[a * 3], h[3]);
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const half2v m = FWD ? u[a * 3 + b] : u[b * 3 + a];  // (U^+)_{ab} = conj(U_ba)
-            w0r = dot2(m, hr[b], w0r);
-            w0i = dot2(m, hi[b], w0i);
-            w1r = dot2(m, hr[3 + b], w1r);
-            w1i = dot2(m, hi[3 + b], w1i);
+        for (int b = 1; b < 3; ++b) {
+            w0r = dot2(x.pr[a * 3 + b], h[b], w0r);
+            w0i = dot2(x.pi[a * 3 + b], h[b], w0i);
+            w1r = dot2(x.pr[a * 3 + b], h[3 + b], w1r);
+            w1i = dot2(x.pi[a * 3 + b], h[3 + b], w1i);
         }
         const cx<float> w0 = {w0r, w0i}, w1 = {w1r, w1i};
         acc[a] = acc[a] + s * w0;
@@ -785,14 +857,21 @@ template <typename T>
 __device__ __forceinline__ void m5inv_lanes(cx<T> r[12], const Coef<T> &k, const SiteMap &m, int Ls,
                                             bool dag, M5Lds<T> &lds)
 {
-    cx<T> *w = lds.buf[m.wave];
+    // lane coordinates recomputed here (opaque to common-subexpression
+    // elimination, same mapping as m) so that no address of this step is held
+    // in a register across the caller's main loop
+    (void)m;
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = (int)(tid & 63u), wave = (int)(tid >> 6), g = lane / Ls, s0 = lane - g * Ls;
+    cx<T> *w = lds.buf[wave];
     constexpr int ST = M5Lds<T>::STRIDE;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) w[m.lane * ST + c] = r[c];
+    for (int c = 0; c < 12; ++c) w[lane * ST + c] = r[c];
     __syncthreads();
-    if (m.g * Ls + Ls <= 64) {
-        const int base = m.g * Ls;
-        for (int c = m.s; c < 12; c += Ls) {
+    if (g * Ls + Ls <= 64) {
+        const int base = g * Ls;
+        for (int c = s0; c < 12; c += Ls) {
             const bool plus = c < 6;
             const bool transpose = plus != dag;
             const T na = -k.a;
@@ -819,7 +898,7 @@ __device__ __forceinline__ void m5inv_lanes(cx<T> r[12], const Coef<T> &k, const
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 12; ++c) r[c] = w[m.lane * ST + c];
+    for (int c = 0; c < 12; ++c) r[c] = w[lane * ST + c];
 }
 
 // FP64 block reduction of one value per thread -> partials[slot]

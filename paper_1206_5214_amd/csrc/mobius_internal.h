@@ -87,6 +87,8 @@ enum Epilogue : int {
     EPI_M5INV = 8,     // r = I^-1 r  (I^-+ r for the adjoint)
     EPI_POSTSUB = 16,  // r = x - r
     EPI_NORM = 32,     // partial sums of |r|^2 (FP64)
+    EPI_BMIX = 64,     // r = B r  (after EPI_M5INV; stores the input of a premixed hop)
+    EPI_PREMIXED = 128,  // forward hop whose input already holds B in: r = -1/2 H in
 };
 
 struct HopArgs {

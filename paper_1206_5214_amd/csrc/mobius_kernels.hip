@@ -53,7 +53,29 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
     ls.sites_blk = (uint32_t)(WAVES * hp.spw);
     // lanes without a site (idle tail lanes of a wavefront) read record 0
     ls.sib = m.site_ok ? (uint32_t)(m.wave * hp.spw + m.g) : 0u;
-    if (hp.stage_links) {
+    if (hp.stage_links && P == MOBIUS_F16) {
+        // one thread per (direction, site): the record expanded to the dot2 operand form
+        constexpr uint32_t REC = Link<P>::REC;
+        const uint32_t i0 = (uint32_t)(lb * WAVES * hp.spw);
+        const uint32_t nsites = min(ls.sites_blk, Vh - i0);
+        for (uint32_t c = threadIdx.x; c < 8u * nsites; c += BLOCK) {
+            const uint32_t d = c / nsites, j = c - d * nsites;
+            u32x4 q[3];
+#pragma unroll
+            for (int w = 0; w < 3; ++w)
+                q[w] = hp.nt ? blink.ld16_nt((i0 + j) * REC + 16u * w, d * Vh * REC)
+                             : blink.ld16((i0 + j) * REC + 16u * w, d * Vh * REC);
+            half2v u[9];
+            Link<MOBIUS_F16>::raw_from_words(q, u);
+            LinkH2 x;
+            if (d < 4)
+                expand_link<true>(u, x);
+            else
+                expand_link<false>(u, x);
+            linkh2_to_words(x, dyn_lds + (size_t)(d * ls.sites_blk + j) * (LINKH2_REC / 16));
+        }
+        ls.lds = reinterpret_cast<const char *>(dyn_lds);
+    } else if (hp.stage_links) {
         constexpr uint32_t REC = Link<P>::REC;
         const uint32_t i0 = (uint32_t)(lb * WAVES * hp.spw);
         const uint32_t nsites = min(ls.sites_blk, Vh - i0);
@@ -88,32 +110,40 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
     cx<T> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+    // B = b5 + c5 C5 applied to the neighbours here (forward hop), unless the
+    // input already holds B in (written so by an EPI_BMIX epilogue)
+    constexpr bool MIXIN = !DAG && (EPI & EPI_PREMIXED) == 0;
 
     if constexpr (P == MOBIUS_F16) {
         // forward block: B mixing weights of this lane (norms folded in per direction)
-        const float wu = DAG ? 0.f : (float)k.c5 * (m.s == 0 ? -(float)k.mf : 1.f);
-        const float wl = DAG ? 0.f : (float)k.c5 * (m.s == Ls - 1 ? -(float)k.mf : 1.f);
+        const float wu = MIXIN ? (float)k.c5 * (m.s == 0 ? -(float)k.mf : 1.f) : 0.f;
+        const float wl = MIXIN ? (float)k.c5 * (m.s == Ls - 1 ? -(float)k.mf : 1.f) : 0.f;
         RawH nx;
-        half2v unx[9];
+        LinkH2 unx;
         load_raw_f16(bin, N5, jn[0], nx);
-        if constexpr (PF >= 2) ls.get_raw(0, unx);
+        if constexpr (PF >= 2) ls.template get_h2<true>(0, unx);
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const RawH o = nx;
             if (d < 7) load_raw_f16(bin, N5, jn[d + 1], nx);
-            half2v u[9];
+            LinkH2 u;
             if constexpr (PF >= 2) {
-#pragma unroll
-                for (int e = 0; e < 9; ++e) u[e] = unx[e];
-                if (d < 7) ls.get_raw(d + 1, unx);
+                u = unx;
+                if (d < 3)
+                    ls.template get_h2<true>(d + 1, unx);
+                else if (d < 7)
+                    ls.template get_h2<false>(d + 1, unx);
             } else {
-                ls.get_raw(d, u);
+                if (d < 4)
+                    ls.template get_h2<true>(d, u);
+                else
+                    ls.template get_h2<false>(d, u);
             }
             constexpr int SF = DAG ? +1 : -1;
             const int sig = d < 4 ? SF : -SF;
             half2v um[6], lp[6];
             float al, bu = 0.f, bl = 0.f;
-            if constexpr (!DAG) {
+            if constexpr (MIXIN) {
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
                     um[c] = shfl_h2(o.c[c], m.lm);
@@ -134,16 +164,16 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
             const float inv = sc > 0.f ? __builtin_amdgcn_rcpf(sc) : 0.f;
             const half2v al2 = splat_h2(al * inv), bu2 = splat_h2(bu * inv), bl2 = splat_h2(bl * inv);
             half2v hh[6];
-#define MOBIUS_HS(MU, SG) half_spinor_h2<MU, SG, !DAG>(o.c, um, lp, al2, bu2, bl2, hh)
+#define MOBIUS_HS(MU, SG) half_spinor_h2<MU, SG, MIXIN>(o.c, um, lp, al2, bu2, bl2, hh)
             switch (d) {
-            case 0: MOBIUS_HS(0, SF); link_accumulate_h2<0, true, SF>(hh, sc, u, acc); break;
-            case 1: MOBIUS_HS(1, SF); link_accumulate_h2<1, true, SF>(hh, sc, u, acc); break;
-            case 2: MOBIUS_HS(2, SF); link_accumulate_h2<2, true, SF>(hh, sc, u, acc); break;
-            case 3: MOBIUS_HS(3, SF); link_accumulate_h2<3, true, SF>(hh, sc, u, acc); break;
-            case 4: MOBIUS_HS(0, -SF); link_accumulate_h2<0, false, -SF>(hh, sc, u, acc); break;
-            case 5: MOBIUS_HS(1, -SF); link_accumulate_h2<1, false, -SF>(hh, sc, u, acc); break;
-            case 6: MOBIUS_HS(2, -SF); link_accumulate_h2<2, false, -SF>(hh, sc, u, acc); break;
-            default: MOBIUS_HS(3, -SF); link_accumulate_h2<3, false, -SF>(hh, sc, u, acc); break;
+            case 0: MOBIUS_HS(0, SF); link_accumulate_h2<0, SF>(hh, sc, u, acc); break;
+            case 1: MOBIUS_HS(1, SF); link_accumulate_h2<1, SF>(hh, sc, u, acc); break;
+            case 2: MOBIUS_HS(2, SF); link_accumulate_h2<2, SF>(hh, sc, u, acc); break;
+            case 3: MOBIUS_HS(3, SF); link_accumulate_h2<3, SF>(hh, sc, u, acc); break;
+            case 4: MOBIUS_HS(0, -SF); link_accumulate_h2<0, -SF>(hh, sc, u, acc); break;
+            case 5: MOBIUS_HS(1, -SF); link_accumulate_h2<1, -SF>(hh, sc, u, acc); break;
+            case 6: MOBIUS_HS(2, -SF); link_accumulate_h2<2, -SF>(hh, sc, u, acc); break;
+            default: MOBIUS_HS(3, -SF); link_accumulate_h2<3, -SF>(hh, sc, u, acc); break;
             }
 #undef MOBIUS_HS
 #pragma unroll
@@ -172,7 +202,7 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
         } else {
             ls.get(d, u);
         }
-        if constexpr (!DAG) {
+        if constexpr (MIXIN) {
             // B = b5 + c5 C5 on the input: gather s-1, s, s+1 of the neighbour
             mix_s(chi, k.b5, k.c5, k.mf, m, Ls, false);
         }
@@ -198,6 +228,10 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = mhalf * acc[c];
 
+    {
+    // coefficients of the epilogue, converted here so that none of them is
+    // held in a register across the direction loop
+    const Coef<T> k = make_coef<T>(hp.c);
     if constexpr (DAG) mix_s(acc, k.b5, k.c5, k.mf, m, Ls, true);  // B^+ on the output
     if constexpr ((EPI & EPI_M5ADD) != 0) {
         cx<T> yv[12];
@@ -216,6 +250,7 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
         __shared__ M5Lds<T> lds;
         m5inv_lanes(acc, k, m, Ls, DAG, lds);
     }
+    if constexpr ((EPI & EPI_BMIX) != 0) mix_s(acc, k.b5, k.c5, k.mf, m, Ls, false);  // B r
     if constexpr ((EPI & EPI_POSTSUB) != 0) {
         cx<T> xv[12];
         S::load(Buf(xr, fbytes), N5, k5, xv);
@@ -229,6 +264,7 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
         block_sum_store(n, hp.partials + r * hp.pstride, lb);
     } else {
         if (m.site_ok) S::store(bout, N5, k5, acc);
+    }
     }
     }  // rhs
 }
@@ -931,7 +967,7 @@ namespace {
 template <int P>
 size_t link_lds_bytes(int spw)
 {
-    return (size_t)8 * WAVES * spw * Link<P>::REC;
+    return (size_t)8 * WAVES * spw * (P == MOBIUS_F16 ? LINKH2_REC : Link<P>::REC);
 }
 
 template <int P, bool DAG, int EPI>
@@ -977,6 +1013,15 @@ bool dispatch_hop(int prec, int dag, int epi, A &&...args)
     case EPI_M5ADD | EPI_PRESUB | EPI_NORM:                                                        \
         F<P, D, EPI_M5ADD | EPI_PRESUB | EPI_NORM>::run(args...);                                  \
         return true;                                                                               \
+    case EPI_M5INV | EPI_BMIX:                                                                     \
+        if constexpr (!D) F<P, D, EPI_M5INV | EPI_BMIX>::run(args...);                             \
+        return !D;                                                                                 \
+    case EPI_PREMIXED | EPI_M5INV | EPI_POSTSUB | EPI_NORM:                                        \
+        if constexpr (!D) F<P, D, EPI_PREMIXED | EPI_M5INV | EPI_POSTSUB | EPI_NORM>::run(args...); \
+        return !D;                                                                                 \
+    case EPI_PREMIXED | EPI_M5INV | EPI_POSTSUB:                                                   \
+        if constexpr (!D) F<P, D, EPI_PREMIXED | EPI_M5INV | EPI_POSTSUB>::run(args...);           \
+        return !D;                                                                                 \
     }                                                                                              \
     return false;
     if (dag) {

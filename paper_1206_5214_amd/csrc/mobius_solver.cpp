@@ -218,8 +218,9 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
     }
     fused_norm = n == 1 && nrhs == 1;
     // hop call patterns of the iteration and of the reliable update
-    hp[HP_D0A] = {lo, 0, EPI_M5INV, 0, F_P, F_T, F_NONE, F_NONE, false};
-    hp[HP_D0B] = {lo, 0, EPI_M5INV | EPI_POSTSUB | EPI_NORM, 1, F_T, F_Q, F_P, F_NONE, true};
+    // t = B I^-1 D_eo p, so that the second hop reads its input already mixed in s
+    hp[HP_D0A] = {lo, 0, EPI_M5INV | EPI_BMIX, 0, F_P, F_T, F_NONE, F_NONE, false};
+    hp[HP_D0B] = {lo, 0, EPI_PREMIXED | EPI_M5INV | EPI_POSTSUB | EPI_NORM, 1, F_T, F_Q, F_P, F_NONE, true};
     hp[HP_D1B] = {lo, 1, EPI_M5INV, 0, F_U, F_T, F_NONE, F_NONE, false};
     hp[HP_D1C] = {lo, 1, EPI_POSTSUB | EPI_NORM, 1, F_T, F_S, F_R, F_NONE, true};
     hp[HP_H0A] = {MOBIUS_F64, 0, EPI_M5INV, 0, F_XH, F_T64, F_NONE, F_NONE, false};
