@@ -84,7 +84,8 @@ typedef struct {
                               low-precision operator with FP64 reductions, reliable updates and
                               outer defect correction */
     double reliable_delta; /* reliable update when ||r|| falls below delta * (max ||r|| since the
-                              last update); <= 0 selects 0.1 */
+                              last update); <= 0 selects the default of the inner precision:
+                              0.3 for FP16, 0.1 for FP32 */
     int32_t nrhs;          /* number of right-hand sides in src/sol (>= 1) */
     int32_t check_every;   /* iterations between host convergence checks (<= 0 selects 16) */
 } mobius_solve_opts;

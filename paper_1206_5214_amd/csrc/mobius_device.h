@@ -609,10 +609,12 @@ __device__ __forceinline__ void half_spinor_h2(const half2v o[12], const half2v 
     const half2v sg = splat_h2((float)SIGMA);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        half2v t0 = al * o[6 + a], t1 = al * o[9 + a];
+        // without mixing the only weight is the site norm, restored in FP32
+        // by the caller: h is formed from the stored words as they are
+        half2v t0 = o[6 + a], t1 = o[9 + a];
         if constexpr (MIX) {
-            t0 = t0 + bl * lp[a];
-            t1 = t1 + bl * lp[3 + a];
+            t0 = al * t0 + bl * lp[a];
+            t1 = al * t1 + bl * lp[3 + a];
         }
         half2v A0, A1;  // A_mu (t0; t1)
         if constexpr (MU == 0) {        // -i sigma_1
@@ -628,10 +630,10 @@ __device__ __forceinline__ void half_spinor_h2(const half2v o[12], const half2v 
             A0 = t0;
             A1 = t1;
         }
-        half2v u0 = al * o[a], u1 = al * o[3 + a];
+        half2v u0 = o[a], u1 = o[3 + a];
         if constexpr (MIX) {
-            u0 = u0 + bu * um[a];
-            u1 = u1 + bu * um[3 + a];
+            u0 = al * u0 + bu * um[a];
+            u1 = al * u1 + bu * um[3 + a];
         }
         h[a] = u0 + sg * A0;
         h[3 + a] = u1 + sg * A1;

@@ -237,9 +237,10 @@ class Operator:
         _check(lib().mobius_m5inv(self._h, prec, int(dag), _ptr(x), _ptr(out), nrhs, _stream()))
         return out
 
-    def solve(self, src, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.1,
+    def solve(self, src, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.0,
               check_every=0):
-        """Solve D_DW psi = src (canonical complex128, optional leading nrhs)."""
+        """Solve D_DW psi = src (canonical complex128, optional leading nrhs).
+        reliable_delta <= 0 selects the library's default for inner_prec."""
         import torch
         nrhs = 1 if src.dim() == 7 else int(src.shape[0])
         self._check_canon(src, nrhs, "source")
@@ -263,7 +264,7 @@ class Operator:
         r = _TuneResult(prec, prefetch, stage_links, xcd_remap, nt_links, 0.0)
         _check(lib().mobius_set_tuning(self._h, ctypes.byref(r)))
 
-    def force(self, phi, tol=1e-12, maxiter=20000, inner_prec=F64, reliable_delta=0.1,
+    def force(self, phi, tol=1e-12, maxiter=20000, inner_prec=F64, reliable_delta=0.0,
               check_every=0):
         """S = phi_o^+ (D_pre^+ D_pre)^-1 phi_o (phi canonical complex128, its odd
         sites used) with dS/dU (canonical links layout) and dS/dphi = 2 X.
@@ -286,7 +287,7 @@ def _info(i):
                      i.schur_resid, i.seconds, i.algo_bytes, i.flops)
 
 
-def batch_solve(ops, srcs, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.1,
+def batch_solve(ops, srcs, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.0,
                 check_every=0):
     """Solve D_DW psi_j = src_j for several lattices at once (one Operator per
     lattice, the same number of right-hand sides each).  Returns the list of
