@@ -216,7 +216,11 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
         pstride = std::max(pstride, std::max(g.hop_blocks, g.blas_blocks));
         max_n5 = std::max(max_n5, G.N5);
     }
-    fused_norm = n == 1 && nrhs == 1;
+    // |out|^2 partial sums fused into the hop epilogue for every system (the
+    // FP16 corruption once seen with several right-hand sides came from the
+    // store-data hazard that the buffer-store guard now covers);
+    // MOBIUS_SPLIT_NORM=1 takes them in a separate pass instead
+    fused_norm = env_int("MOBIUS_SPLIT_NORM", 0) == 0;
     // hop call patterns of the iteration and of the reliable update
     // t = B I^-1 D_eo p, so that the second hop reads its input already mixed in s
     hp[HP_D0A] = {lo, 0, EPI_M5INV | EPI_BMIX, 0, F_P, F_T, F_NONE, F_NONE, false};
