@@ -173,7 +173,7 @@ struct Batch {
                          Field out, Field x, Field y, bool norm);
     hipError_t vec(int pid, int kind, int prec, int prec2, bool all = false);
     hipError_t reduce(int pid, double *out, int64_t stride, bool all = false);
-    hipError_t m5inv_dag_all(int prec, Field in, Field out);
+    hipError_t m5inv_dag_all(int prec, Field in, Field out, bool only_active = false);
     hipError_t body();                   // one CG iteration
     hipError_t rupd();                   // r -= alpha q (|r|^2), u = I^-+ r
     hipError_t body_normal();            // one CG iteration on the normal equations
@@ -465,14 +465,20 @@ hipError_t Batch::reduce(int pid, double *out, int64_t stride, bool all)
                                stride, st);
 }
 
-hipError_t Batch::m5inv_dag_all(int prec, Field in, Field out)
+hipError_t Batch::m5inv_dag_all(int prec, Field in, Field out, bool only_active)
 {
     for (const Group &g : groups) {
-        abytes += 2.0 * g.fb[in] * g.nrhs;
-        aflops += 96.0 * g.ctx->g.N5 * g.nrhs;
-        if (count_only) continue;
-        hipError_t e = launch_m5(g.ctx->g, g.ctx->c, prec, 1, 1, g.f[in], g.f[out], g.nrhs, st);
-        if (e != hipSuccess) return e;
+        for (int r = 0; r < g.nrhs; ++r) {
+            // eager callers skip the systems that are off (a reliable update
+            // leaves the Krylov vectors of the systems sitting it out as they are)
+            if (only_active && !h_active[g.sys0 + r]) continue;
+            abytes += 2.0 * g.fb[in];
+            aflops += 96.0 * g.ctx->g.N5;
+            if (count_only) continue;
+            hipError_t e = launch_m5(g.ctx->g, g.ctx->c, prec, 1, 1, g.f[in] + r * g.fb[in],
+                                     g.f[out] + r * g.fb[out], 1, st);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -549,7 +555,7 @@ hipError_t Batch::reliable_update()
     if ((e = hop(HP_H0A)) != hipSuccess) return e;
     if ((e = hop(HP_H0B)) != hipSuccess) return e;
     if (normal) {  // r = b - D^+ D x_hi
-        if ((e = m5inv_dag_all(MOBIUS_F64, F_Q64, F_U64)) != hipSuccess) return e;
+        if ((e = m5inv_dag_all(MOBIUS_F64, F_Q64, F_U64, true)) != hipSuccess) return e;
         if ((e = hop(HP_N64B)) != hipSuccess) return e;
         if ((e = hop(HP_N64C)) != hipSuccess) return e;
         if ((e = vec(VP_RES_N, VEC_AXPBY_NORM, MOBIUS_F64, MOBIUS_F64)) != hipSuccess) return e;
@@ -560,7 +566,7 @@ hipError_t Batch::reliable_update()
         if ((e = reduce(VP_BLASRED, &extra[X_HR], NEXTRA)) != hipSuccess) return e;
     }
     if ((e = vec(VP_CONV_RH_R, VEC_CONVERT, MOBIUS_F64, lo)) != hipSuccess) return e;
-    return normal ? hipSuccess : m5inv_dag_all(lo, F_R, F_U);  // u = I^-+ r for the next step
+    return normal ? hipSuccess : m5inv_dag_all(lo, F_R, F_U, true);  // u = I^-+ r for the next step
 }
 
 // psi_e = I^-1 (eta_e - D_eo x_hi); |eta - D_DW psi|^2 per parity -> extra

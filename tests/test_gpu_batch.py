@@ -220,3 +220,38 @@ def test_multi_rhs_12x12x12x12_ls16(torch_cuda, orc, inner):
         res, _ = _check_system(orc, p, U, eta[r], psi[r], info[r], solve_oracle=False)
         _flush(f"  rhs {r}: iters {info[r].iters} resid {res:.2e}")
     op.close()
+
+
+@pytest.mark.parametrize("inner", [1, 2], ids=["mixed_f32", "mixed_f16"])
+def test_batch_systems_match_single_solves(torch_cuda, orc, inner):
+    """In a batch every system takes its reliable updates at its own threshold
+    (the others sit the update out), so each system runs exactly the
+    iterations of its solo solve and reaches the same solution: a batch of
+    three sources of very different character (Gaussian, point, scaled
+    Gaussian) against three single solves."""
+    from oracle import Params
+    from paper_1206_5214_amd import inputs, mobius
+    torch = torch_cuda
+    dims, Ls = (8, 8, 8, 8), 8
+    _flush(f"batch vs single solves {dims} Ls={Ls} inner={inner}")
+    rng = np.random.default_rng(11)
+    U = inputs.random_links(dims, 0.5, rng)
+    gauss = inputs.gaussian_spinor(dims, Ls, rng, 2)
+    point = inputs.wall_point_sources(dims, Ls)[5]
+    eta = np.stack([gauss[0], point, 1e3 * gauss[1]])
+    op = mobius.Operator(dims, Ls, 1.8, 0.01, 1.5, 0.5, torch.from_numpy(U).cuda())
+    sol_b, info_b, rc = op.solve(torch.from_numpy(eta).cuda(), tol=TOL, maxiter=50000, inner_prec=inner)
+    assert rc == mobius.OK, info_b
+    psi_b = sol_b.cpu().numpy()
+    p = Params(dims, Ls, 1.8, 0.01, 1.5, 0.5)
+    for r in range(3):
+        sol_1, info_1, rc1 = op.solve(torch.from_numpy(eta[r]).cuda(), tol=TOL, maxiter=50000,
+                                      inner_prec=inner)
+        assert rc1 == mobius.OK, info_1
+        _flush(f"  rhs {r}: batch {info_b[r].iters} it / {info_b[r].reliable_updates} ru, "
+               f"single {info_1[0].iters} it / {info_1[0].reliable_updates} ru")
+        assert info_b[r].iters == info_1[0].iters
+        assert info_b[r].reliable_updates == info_1[0].reliable_updates
+        assert _rel(psi_b[r], sol_1.cpu().numpy()) <= 1e-12
+        _check_system(orc, p, U, eta[r], psi_b[r], info_b[r], solve_oracle=False)
+    op.close()
