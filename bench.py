@@ -18,7 +18,6 @@ operator) timed on the host cores.
 Prints exactly one JSON line on stdout; progress goes to stderr.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -71,14 +70,13 @@ def time_hop(torch, op, prec, src_canon, reps):
 def counters_for(kernel_key):
     """HBM traffic per launch measured with rocprofv3 counters, if they were
     taken on the current kernel source (profiles/<key>.json records its hash)."""
+    from paper_1206_5214_amd.profile_hop import hop_sources_sha256
     path = os.path.join(ROOT, "profiles", f"{kernel_key}.json")
-    src = os.path.join(ROOT, "paper_1206_5214_amd", "csrc", "mobius_kernels.hip")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("kernel_source_sha256") != h:
+    if rec.get("kernel_source_sha256") != hop_sources_sha256():
         return None
     return rec.get("traffic_bytes_per_launch")
 

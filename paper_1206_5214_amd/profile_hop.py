@@ -29,6 +29,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PREC = {"f64": 0, "f32": 1, "f16": 2}
+# the files the hop kernel is compiled from; their joint hash keys the counters
+HOP_SOURCES = ("mobius_kernels.hip", "mobius_device.h", "mobius_internal.h")
+
+
+def hop_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for name in HOP_SOURCES:
+        with open(os.path.join(ROOT, "paper_1206_5214_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 COPY_BYTES = 1 << 30      # the calibration copy reads and writes 1 GiB
 HOP_NAME = "hop_kernel"
 
@@ -88,10 +98,10 @@ def _counter_per_kernel(d, counter):
 
 
 def summarize(args):
-    src = os.path.join(ROOT, "paper_1206_5214_amd", "csrc", "mobius_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = hop_sources_sha256()
     out = {"kernel": f"{HOP_NAME} ({args.prec}, D_{{p,1-p}} = -1/2 H B, 24^3x64 Ls=12)",
-           "kernel_source_sha256": sha, "calibration_copy_bytes": COPY_BYTES}
+           "kernel_source_sha256": sha, "kernel_sources": list(HOP_SOURCES),
+           "calibration_copy_bytes": COPY_BYTES}
     traffic = {}
     for counter, d in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
         per = _counter_per_kernel(d, counter)
@@ -147,7 +157,7 @@ def summarize(args):
                          f"({100 * out['achieved_GBps'] / 8000:.1f}% of 8 TB/s); counted traffic "
                          f"{out['traffic_GBps']:.0f} GB/s")
     lines.append("")
-    lines.append(f"Kernel source sha256: `{sha}`")
+    lines.append(f"Kernel sources ({', '.join(HOP_SOURCES)}) sha256: `{sha}`")
     with open(args.out + ".md", "w") as f:
         f.write("\n".join(lines) + "\n")
     print(json.dumps(out, indent=1))
