@@ -83,6 +83,13 @@ constexpr int CPOL_NT = 2;              // cache policy bit: non-temporal
 // fused CG updates diverged at 12^4 x 16 and larger.  Keeping the data live
 // across two wait states after each store removes the corruption; a full
 // vmcnt(0) drain does too but costs about 3% in the hop.
+// Field stores are non-temporal: a field written by one kernel is hundreds of
+// MB and is read back by the next kernel, not from L2, and streaming it past
+// the L2 leaves more room there for the neighbour spinors a hop re-reads
+// (24^3 x 64, Ls = 12: FP32 hop 3 %, FP16 hop and FP16 solve 2 % faster).
+#ifndef MOBIUS_ST_CPOL
+#define MOBIUS_ST_CPOL CPOL_NT
+#endif
 #ifndef MOBIUS_STORE_GUARD
 #define MOBIUS_STORE_GUARD(v) asm volatile("s_nop 1" ::"v"(v))
 #endif
@@ -108,7 +115,7 @@ struct Buf {
     }
     __device__ __forceinline__ void st16(u32x4 v, uint32_t voff, uint32_t soff) const
     {
-        __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, MOBIUS_ST_CPOL);
         MOBIUS_STORE_GUARD(v);
     }
     // non-temporal variants (cache policy NT): data that is not re-read soon
@@ -118,7 +125,7 @@ struct Buf {
     }
     __device__ __forceinline__ void st4(uint32_t v, uint32_t voff, uint32_t soff) const
     {
-        __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, MOBIUS_ST_CPOL);
         MOBIUS_STORE_GUARD(v);
     }
 };
