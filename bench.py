@@ -67,6 +67,46 @@ def time_hop(torch, op, prec, src_canon, reps):
     return ms
 
 
+def time_schur(torch, op, prec, src_canon, reps):
+    """Average duration of one D_pre application (two fused hop launches)."""
+    from paper_1206_5214_amd import mobius
+    _, odd = op.pack(src_canon, prec)
+    out = op.new_field(prec)
+    for _ in range(3):
+        op.dslash(odd, 1, prec, op=mobius.OP_SCHUR, out=out)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        op.dslash(odd, 1, prec, op=mobius.OP_SCHUR, out=out)
+    stop.record()
+    stop.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    del odd, out
+    return ms
+
+
+def copy_peak_gbs(torch, nbytes=1 << 31, reps=10):
+    """Achieved rate of a plain device-to-device copy (read + write bytes)."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        b.copy_(a)
+    stop.record()
+    stop.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def counters_for(kernel_key):
     """HBM traffic per launch measured with rocprofv3 counters, if they were
     taken on the current kernel source (profiles/<key>.json records its hash)."""
@@ -298,6 +338,20 @@ def main():
         log(f"hop {PREC_NAMES[prec]}: {ms * 1e3:.1f} us  {gbs:.0f} GB/s  "
             f"({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
 
+    # -- D_pre = 1 - I^-1 D_oe I^-1 D_eo (two fused hop launches) -----------
+    schur = {}
+    for prec in (mobius.F64, mobius.F32, mobius.F16):
+        ms = time_schur(torch, op, prec, etad, max(10, args.hop_reps // 2))
+        # in, t, t, in (subtracted), out + two link passes
+        nbytes = 5 * op.field_bytes(prec) + 2 * (hop_algo_bytes(op, prec) - 2 * op.field_bytes(prec))
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        schur[PREC_NAMES[prec]] = {"us": ms * 1e3, "algo_bytes": nbytes, "GBps": gbs,
+                                   "frac_hbm": gbs / HBM_PEAK_GBS,
+                                   "GFLOPps": 3048.0 * (op.V // 2) * w.Ls / (ms * 1e-3) / 1e9}
+        log(f"D_pre {PREC_NAMES[prec]}: {ms * 1e3:.1f} us  {gbs:.0f} GB/s")
+    copy_gbs = copy_peak_gbs(torch)
+    log(f"device copy: {copy_gbs:.0f} GB/s")
+
     # -- the step: complete solves to 1e-10 ---------------------------------
     def solve(prec):
         sol, info, rc = op.solve(etad, tol=w.tol, maxiter=50000, inner_prec=prec)
@@ -362,7 +416,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": hop[hname]["GBps"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": hop[hname]["GBps"] / HBM_PEAK_GBS,
                 "traffic": traffic, "kernel": f"hop_kernel {hname} (D_{{p,1-p}} = -1/2 H B)",
-                "algo_bytes_per_launch": hop[hname]["algo_bytes"]}
+                "algo_bytes_per_launch": hop[hname]["algo_bytes"],
+                "copy_GBps": copy_gbs, "frac_of_copy": hop[hname]["GBps"] / copy_gbs}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -393,6 +448,7 @@ def main():
                   "true_resid": infos[-1].true_resid, "algo_bytes": algo_bytes,
                   "GFLOPps": float(np.mean([i.flops for i in infos])) / (ms_per_step * 1e-3) / 1e9},
         "hop": hop,
+        "schur": schur,
         "time_to_solution": compare,
         "batched": batch,
         "force": force,

@@ -318,11 +318,12 @@ hipError_t schur(mobius_ctx *ctx, int prec, int dag, const void *in, void *out, 
     hipError_t e;
     const int norm = partials ? EPI_NORM : 0;
     if (!dag) {
-        // t = I^-1 D_eo in ;  out = in - I^-1 D_oe t
-        e = hop(ctx, hop_args(prec, 0, EPI_M5INV, 0, in, t_even, nullptr, nullptr, nullptr, nrhs), st);
+        // t = B I^-1 D_eo in ;  out = in - I^-1 D_oe (t already mixed in s)
+        e = hop(ctx, hop_args(prec, 0, EPI_M5INV | EPI_BMIX, 0, in, t_even, nullptr, nullptr, nullptr, nrhs),
+                st);
         if (e != hipSuccess) return e;
-        return hop(ctx, hop_args(prec, 0, EPI_M5INV | EPI_POSTSUB | norm, 1, t_even, out, in,
-                                 nullptr, partials, nrhs), st);
+        return hop(ctx, hop_args(prec, 0, EPI_PREMIXED | EPI_M5INV | EPI_POSTSUB | norm, 1, t_even, out,
+                                 in, nullptr, partials, nrhs), st);
     }
     // u = I^-+ in ;  t = I^-+ (D_oe)^+ u ;  out = in - (D_eo)^+ t
     e = launch_m5(ctx->g, ctx->c, prec, 1, 1, in, u_odd, nrhs, st);
