@@ -165,6 +165,21 @@ def multi_rhs_runs(torch, inputs, mobius):
     del U
     src = point_sources_gpu(torch, w.dims, w.Ls)
     out = {"workload": f"{w.name} x 12 point sources"}
+    # the metered hop on this lattice too (its FP32 and FP16 working sets fit
+    # the 256 MB Infinity Cache, so these rates are not HBM-bound figures)
+    gauss = torch.randn(src.shape[1:], dtype=torch.complex128, device="cuda")
+    hop = {}
+    for prec in (mobius.F64, mobius.F32, mobius.F16):
+        op.tune(prec)
+        ms = time_hop(torch, op, prec, gauss, 50)
+        nbytes = hop_algo_bytes(op, prec)
+        hop[PREC_NAMES[prec]] = {"us": ms * 1e3, "algo_bytes": nbytes,
+                                 "GBps": nbytes / (ms * 1e-3) / 1e9,
+                                 "frac_hbm": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log(f"multi-rhs lattice hop {PREC_NAMES[prec]}: {ms * 1e3:.1f} us "
+            f"{hop[PREC_NAMES[prec]]['GBps']:.0f} GB/s")
+    out["hop"] = hop
+    del gauss
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ref, iters = [], []
@@ -209,6 +224,8 @@ def uneven_batch_runs(torch, inputs, mobius):
         U, eta = inputs.workload_fields(w)
         ops.append(mobius.Operator(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, torch.from_numpy(U).cuda()))
         srcs.append(torch.from_numpy(eta).cuda())
+        for prec in (mobius.F64, mobius.F32, mobius.F16):
+            ops[-1].tune(prec)
     out = {"workload": " + ".join(w.name for w in inputs.UNEVEN_BATCH)}
     ref = {}
     for prec in (mobius.F64, mobius.F32):
