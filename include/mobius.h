@@ -165,6 +165,22 @@ int mobius_m5inv(mobius_ctx *ctx, int32_t prec, int32_t dagger, const void *in, 
 int mobius_cg_solve(mobius_ctx *ctx, const void *src_c128, void *sol_c128,
                     const mobius_solve_opts *opts, mobius_solve_info *info, void *stream);
 
+/* 4d propagator of the overlap operator through the 5d solve (Sec. 2.2):
+ *   q = [P^+ D_DW(m)^-1 D_DW(1) P b]_1 = D_ov(m)^-1 b,
+ * with the chiral shift P_{ss'} = delta_{ss'} P- + delta_{s',s+1 mod Ls} P+
+ * (b enters on the walls: P- b on slice 1, P+ b on slice Ls), D_DW(1) the
+ * Pauli-Villars operator (mf = 1, same links and M5, b5, c5) and
+ * D_ov(m) = (1+m)/2 + (1-m)/2 g5 eps_Ls(g5 D_Moebius) (App. A).
+ * src4_c128 / sol4_c128: canonical complex128 4d fields [t][z][y][x][spin][colour],
+ * opts->nrhs of them (device memory, caller-owned).  The 5d solve D_DW(m) psi
+ * = D_DW(1) P b runs as mobius_cg_solve with opts; info (opts->nrhs entries)
+ * describes it (its true residual is that of the 5d system).  The context
+ * keeps three canonical 5d fields and four packed FP64 half fields per
+ * right-hand side as temporaries until mobius_destroy.  Returns as
+ * mobius_cg_solve. */
+int mobius_propagator4d(mobius_ctx *ctx, const void *src4_c128, void *sol4_c128,
+                        const mobius_solve_opts *opts, mobius_solve_info *info, void *stream);
+
 /* Solve a batch of independent systems on lattices of possibly different
  * sizes (one context each, opts->nrhs right-hand sides per context) in
  * lockstep: every CG step of all systems is one launch (the hop kernels walk

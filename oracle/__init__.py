@@ -214,6 +214,31 @@ def solve(p: Params, U, eta, tol=1e-12, maxiter=10000):
     return psi, Info(info.iters, bool(info.converged), info.rel_resid, info.true_resid)
 
 
+def propagator4d(p: Params, U, b4, tol=1e-12, maxiter=20000):
+    """q = [P^+ D_DW(m)^-1 D_DW(1) P b]_1, the overlap propagator D_ov(m)^-1 b
+    obtained from the 5d solve (Sec. 2.2).  The chiral shift P puts b on the
+    walls (P- b on slice 1, P+ b on slice Ls; P+ = spins 0, 1 in the chiral
+    basis), D_DW(1) is the Pauli-Villars operator (mf = 1, same links and
+    M5, b5, c5), and q = (P^+ psi)_1 = P- psi_1 + P+ psi_Ls.  b4: [t][z][y][x][4][3]
+    (leading nrhs allowed).  Returns (q, [Info of each 5d solve])."""
+    b4 = _c128(b4)
+    single = b4.ndim == 6
+    bs = b4[None] if single else b4
+    pv = Params(p.dims, p.Ls, p.M5, 1.0, p.b5, p.c5)
+    qs, infos = [], []
+    for b in bs:
+        wall = np.zeros(p.shape5(), complex)
+        wall[0, ..., 2:, :] = b[..., 2:, :]
+        wall[p.Ls - 1, ..., :2, :] = b[..., :2, :]
+        psi, info = solve(p, U, dw(pv, U, wall), tol=tol, maxiter=maxiter)
+        q = np.empty_like(b)
+        q[..., 2:, :] = psi[0, ..., 2:, :]
+        q[..., :2, :] = psi[p.Ls - 1, ..., :2, :]
+        qs.append(q)
+        infos.append(info)
+    return (qs[0] if single else np.stack(qs)), infos
+
+
 def cgne(p: Params, U, phi, tol=1e-12, maxiter=10000):
     """X = (D_pre^+ D_pre)^{-1} phi for phi on the odd parity (plain CG)."""
     U, phi = _c128(U), _c128(phi)

@@ -248,6 +248,7 @@ extern "C" int mobius_destroy(mobius_ctx *ctx)
     ctx->work.release();
     ctx->partials.release();
     ctx->scalars.release();
+    ctx->prop.release();
     if (ctx->solve_stream) (void)hipStreamDestroy(ctx->solve_stream);
     delete ctx;
     return MOBIUS_OK;
@@ -418,6 +419,51 @@ extern "C" int mobius_batch_solve(int32_t n, mobius_ctx *const *ctxs, const void
             if (ctxs[k] == ctxs[j]) return fail(MOBIUS_EINVAL, "a context appears twice in one batch");
     }
     return batch_solve(ctxs, n, src, sol, *opts, info, S(stream));
+}
+
+extern "C" int mobius_propagator4d(mobius_ctx *ctx, const void *src4, void *sol4,
+                                   const mobius_solve_opts *opts, mobius_solve_info *info, void *stream)
+{
+    g_err.clear();
+    if (int r = check_ctx(ctx)) return r;
+    if (!src4 || !sol4 || !opts || !info) return fail(MOBIUS_EINVAL, "null argument to mobius_propagator4d");
+    if (src4 == sol4) return fail(MOBIUS_EINVAL, "source and solution alias");
+    if (int r = check_prec(opts->inner_prec)) return r;
+    const int nrhs = opts->nrhs > 0 ? opts->nrhs : 1;
+    hipStream_t st = S(stream);
+    const Geometry &g = ctx->g;
+    // temporaries: wall field, 5d source and 5d solution (canonical), and the
+    // packed halves of the wall field and of D(1) applied to it (FP64)
+    const int64_t c5 = g.V * g.Ls * 12 * (int64_t)sizeof(double2) * nrhs;
+    const int64_t fb = field_bytes(g, MOBIUS_F64) * nrhs;
+    HIPCHK(ctx->prop.ensure(3 * c5 + 4 * fb));
+    char *wall = static_cast<char *>(ctx->prop.p), *eta = wall + c5, *psi = eta + c5;
+    char *we = psi + c5, *wo = we + fb, *de = wo + fb, *dod = de + fb;
+    HIPCHK(launch_wall_place(g, src4, wall, nrhs, st));
+    HIPCHK(launch_pack_spinor(g, MOBIUS_F64, wall, we, wo, nrhs, st));
+    // eta = D(1) P b: the Pauli-Villars operator (mf = 1) on the same links,
+    // out_p = D_{p,1-p} in_{1-p} + I in_p for both parities
+    mobius_params pv = ctx->P;
+    pv.mf = 1.0;
+    const OpCoeffs cpv = make_coeffs(pv);
+    const int32_t *nbr = static_cast<const int32_t *>(ctx->nbr.p);
+    HopArgs a = hop_args(MOBIUS_F64, 0, EPI_M5ADD, 0, wo, de, nullptr, we, nullptr, nrhs);
+    a.tune = &ctx->tune[MOBIUS_F64];
+    HIPCHK(launch_hop(g, cpv, ctx->links[MOBIUS_F64].p, nbr, a, st));
+    a = hop_args(MOBIUS_F64, 0, EPI_M5ADD, 1, we, dod, nullptr, wo, nullptr, nrhs);
+    a.tune = &ctx->tune[MOBIUS_F64];
+    HIPCHK(launch_hop(g, cpv, ctx->links[MOBIUS_F64].p, nbr, a, st));
+    HIPCHK(launch_unpack_spinor(g, MOBIUS_F64, de, dod, eta, nrhs, st));
+    // D(m) psi = eta, then q = (P^+ psi)_0
+    mobius_solve_opts o = *opts;
+    o.nrhs = nrhs;
+    mobius_ctx *const ctxs[1] = {ctx};
+    const void *const srcs[1] = {eta};
+    void *const sols[1] = {psi};
+    const int rc = batch_solve(ctxs, 1, srcs, sols, o, info, st);
+    if (rc < 0) return rc;
+    HIPCHK(launch_wall_read(g, psi, sol4, nrhs, st));
+    return rc;
 }
 
 extern "C" int mobius_force(mobius_ctx *ctx, const void *phi, void *grad_links, void *grad_phi,

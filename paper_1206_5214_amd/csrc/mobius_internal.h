@@ -166,6 +166,9 @@ hipError_t launch_build_geometry(const Geometry &g, const int32_t *packed_of, in
                                  hipStream_t st);
 hipError_t launch_pack_links(const Geometry &g, int prec, const void *canon, void *packed,
                              hipStream_t st);
+// 4d field on the walls of the fifth dimension and back (canonical layouts)
+hipError_t launch_wall_place(const Geometry &g, const void *b4, void *eta5, int nrhs, hipStream_t st);
+hipError_t launch_wall_read(const Geometry &g, const void *psi5, void *q4, int nrhs, hipStream_t st);
 hipError_t launch_pack_spinor(const Geometry &g, int prec, const void *canon, void *even, void *odd,
                               int nrhs, hipStream_t st);
 hipError_t launch_unpack_spinor(const Geometry &g, int prec, const void *even, const void *odd,
@@ -326,6 +329,7 @@ struct mobius_ctx {
     mobius::DevBuf work;      // solver fields
     mobius::DevBuf partials;  // reduction partials
     mobius::DevBuf scalars;   // solver scalars, flags and descriptor tables
+    mobius::DevBuf prop;      // 4d propagator temporaries (canonical and packed 5d fields)
     hipStream_t solve_stream = nullptr;
     mobius::HopTuning tune[3];  // hop launch parameters per storage precision
     double tuned_us[3] = {0, 0, 0};  // hop time of the tuned parameters (0: not tuned)

@@ -391,6 +391,40 @@ __global__ void pack_links_kernel(Dims D, int64_t V, int64_t Vh, const int32_t *
     }
 }
 
+// Walls of the fifth dimension (Sec. 2.2): the chiral shift P_{ss'} =
+// delta_{ss'} P- + delta_{s',s+1 mod Ls} P+ puts a 4d field b on slice 0 as
+// P- b and on slice Ls-1 as P+ b, and q = (P^+ psi)_0 = P- psi_0 + P+ psi_{Ls-1}
+// reads one back.  Canonical layouts, P+ = spins 0, 1 (components 0..5).
+__global__ __launch_bounds__(256) void wall_place_kernel(int64_t V, int Ls, int64_t n,
+                                                         const double2 *b4, double2 *eta5)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (rhs, s, x)
+    if (t >= n) return;
+    const int64_t x = t % V, rs = t / V;
+    const int s = (int)(rs % Ls);
+    const int64_t r = rs / Ls;
+    const double2 *src = b4 + (r * V + x) * 12;
+    double2 *dst = eta5 + t * 12;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        const bool take = q < 6 ? s == Ls - 1 : s == 0;
+        dst[q] = take ? src[q] : make_double2(0.0, 0.0);
+    }
+}
+
+__global__ __launch_bounds__(256) void wall_read_kernel(int64_t V, int Ls, int64_t n,
+                                                        const double2 *psi5, double2 *q4)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (rhs, x)
+    if (t >= n) return;
+    const int64_t x = t % V, r = t / V;
+    const double2 *lo = psi5 + ((r * Ls + 0) * V + x) * 12;
+    const double2 *hi = psi5 + ((r * Ls + Ls - 1) * V + x) * 12;
+    double2 *dst = q4 + t * 12;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) dst[q] = q < 6 ? hi[q] : lo[q];
+}
+
 // canonical [s][t][z][y][x][12] complex128 <-> packed halves
 template <int P>
 __global__ __launch_bounds__(256) void pack_spinor_kernel(int64_t Vh, int Ls,
@@ -918,6 +952,22 @@ hipError_t launch_pack_links(const Geometry &g, int prec, const void *canon, voi
     case MOBIUS_F16: hipLaunchKernelGGL(pack_links_kernel<MOBIUS_F16>, grid, dim3(256), 0, st, D, g.V, g.Vh, g.canon_of, c, o); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_place(const Geometry &g, const void *b4, void *eta5, int nrhs, hipStream_t st)
+{
+    const int64_t n = (int64_t)nrhs * g.Ls * g.V;
+    hipLaunchKernelGGL(wall_place_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.V, g.Ls, n,
+                       static_cast<const double2 *>(b4), static_cast<double2 *>(eta5));
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_read(const Geometry &g, const void *psi5, void *q4, int nrhs, hipStream_t st)
+{
+    const int64_t n = (int64_t)nrhs * g.V;
+    hipLaunchKernelGGL(wall_read_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.V, g.Ls, n,
+                       static_cast<const double2 *>(psi5), static_cast<double2 *>(q4));
     return hipGetLastError();
 }
 

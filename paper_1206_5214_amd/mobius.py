@@ -23,8 +23,8 @@ OK, NOT_CONVERGED = 0, 1
 
 EXPORTS = ("mobius_create", "mobius_destroy", "mobius_field_bytes", "mobius_pack",
            "mobius_unpack", "mobius_dslash", "mobius_dslash_dag", "mobius_m5inv",
-           "mobius_cg_solve", "mobius_batch_solve", "mobius_force", "mobius_tune",
-           "mobius_set_tuning", "mobius_last_error")
+           "mobius_cg_solve", "mobius_batch_solve", "mobius_propagator4d", "mobius_force",
+           "mobius_tune", "mobius_set_tuning", "mobius_last_error")
 
 
 class MobiusError(RuntimeError):
@@ -95,6 +95,8 @@ def lib():
         L.mobius_batch_solve.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                          ctypes.POINTER(vp), ctypes.POINTER(_SolveOpts),
                                          ctypes.POINTER(_SolveInfo), vp]
+        L.mobius_propagator4d.argtypes = [vp, vp, vp, ctypes.POINTER(_SolveOpts),
+                                          ctypes.POINTER(_SolveInfo), vp]
         L.mobius_force.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(_SolveOpts), ctypes.POINTER(_SolveInfo), vp]
         L.mobius_tune.argtypes = [vp, i32, i32, ctypes.POINTER(_TuneResult), vp]
@@ -249,6 +251,25 @@ class Operator:
         infos = (_SolveInfo * nrhs)()
         rc = _check(lib().mobius_cg_solve(self._h, _ptr(src), _ptr(sol), ctypes.byref(opts), infos,
                                           _stream()))
+        return sol, [_info(i) for i in infos], rc
+
+    def propagator4d(self, src4, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.0,
+                     check_every=0):
+        """q = D_ov(m)^-1 b through the 5d solve D_DW(m) psi = D_DW(1) P b (see
+        mobius_propagator4d); src4 canonical complex128 [t][z][y][x][4][3], with
+        an optional leading nrhs."""
+        import torch
+        Lx, Ly, Lz, Lt = self.dims
+        shape4 = (Lt, Lz, Ly, Lx, 4, 3)
+        nrhs = 1 if src4.dim() == 6 else int(src4.shape[0])
+        _require_cuda(src4, torch.complex128, "source")
+        if tuple(src4.shape[-6:]) != shape4 or src4.numel() != nrhs * Lt * Lz * Ly * Lx * 12:
+            raise MobiusError(f"source has shape {tuple(src4.shape)}, expected [nrhs,] {shape4}")
+        sol = torch.empty_like(src4)
+        opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, nrhs, check_every)
+        infos = (_SolveInfo * nrhs)()
+        rc = _check(lib().mobius_propagator4d(self._h, _ptr(src4), _ptr(sol), ctypes.byref(opts),
+                                              infos, _stream()))
         return sol, [_info(i) for i in infos], rc
 
     def tune(self, prec, reps=10):

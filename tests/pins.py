@@ -221,6 +221,51 @@ def pin_free_propagator(orc):
             assert np.abs(A[4:, 4:] - np.eye(4 * p.Ls - 4)).max() < 1e-11
 
 
+def pin_propagator4d_free(orc):
+    """The oracle's 4d propagator through the 5d solve equals D_ov(m)^-1 in the
+    free field: a plane wave e^{ipx} u returns e^{ipx} D_ov(p)^-1 u
+    (Sec. 2.2 propagator identity; D_ov from the polar sign, App. A)."""
+    rng = np.random.default_rng(5)
+    for p in _free_cases()[:2]:
+        U = inputs.unit_links(p.dims)
+        for mom in [np.zeros(4)] + ff.momenta(p.dims, rng, 2):
+            wave = ff.plane_wave(p.dims, mom)
+            u = rng.normal(size=(4, 3)) + 1j * rng.normal(size=(4, 3))
+            b = wave[..., None, None] * u
+            q, infos = orc.propagator4d(p, U, b, tol=1e-13)
+            assert all(i.converged for i in infos)
+            want = wave[..., None, None] * (np.linalg.inv(
+                ff.overlap_symbol(mom, p.M5, p.b5, p.c5, p.Ls, p.mf)) @ u)
+            assert _rel(q, want) < 1e-9, ("free 4d propagator", p, mom, _rel(q, want))
+
+
+def pin_propagator4d_dense(orc):
+    """With random links on a 2x2x2x4 lattice: D_ov(m) built densely from the
+    oracle's 4d Wilson operator (Moebius kernel (b5+c5) D_W (2+(b5-c5) D_W)^-1,
+    polar sign of Ls terms, App. A) applied to the oracle's 4d propagator
+    returns the source."""
+    from oracle import Params
+    dims, Ls = (2, 2, 2, 4), 6
+    p = Params(dims, Ls, 1.8, 0.05, 1.5, 0.5)
+    U = inputs.random_links(dims, 0.4, np.random.default_rng(8))
+    shape4 = p.shape4()
+    n = int(np.prod(shape4))
+    Dw = _dense(lambda v: orc.wilson(p, U, v), n, shape4)
+    g5 = np.tile(np.repeat([1.0, 1.0, -1.0, -1.0], 3), n // 12)
+    Dm = np.linalg.solve(2 * np.eye(n) + (p.b5 - p.c5) * Dw, (p.b5 + p.c5) * Dw)
+    H = g5[:, None] * Dm
+    A = np.linalg.matrix_power(np.eye(n) + H, Ls)
+    B = np.linalg.matrix_power(np.eye(n) - H, Ls)
+    eps = np.linalg.solve((A + B).T, (A - B).T).T
+    Dov = 0.5 * (1 + p.mf) * np.eye(n) + 0.5 * (1 - p.mf) * g5[:, None] * eps
+    rng = np.random.default_rng(9)
+    b = rng.normal(size=shape4) + 1j * rng.normal(size=shape4)
+    q, infos = orc.propagator4d(p, U, b, tol=1e-13)
+    assert infos[0].converged
+    got = (Dov @ q.reshape(-1)).reshape(shape4)
+    assert _rel(got, b) < 1e-9, ("D_ov q = b", _rel(got, b))
+
+
 def _dense(apply, n, shape):
     M = np.zeros((n, n), complex)
     for j in range(n):
@@ -390,4 +435,5 @@ def pin_force_finite_difference(orc):
 ALL_PINS = [pin_wilson_free_symbol, pin_kernel_bound, pin_gauge_covariance,
             pin_wilson_gamma5_hermiticity, pin_adjoints, pin_free_determinant,
             pin_free_propagator, pin_gamma5_R_hermiticity, pin_m5_block, pin_schur_solve_dense,
-            pin_rb_equals_unpreconditioned, pin_cgne_dense, pin_force_finite_difference]
+            pin_rb_equals_unpreconditioned, pin_cgne_dense, pin_force_finite_difference,
+            pin_propagator4d_free, pin_propagator4d_dense]
