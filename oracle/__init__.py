@@ -36,7 +36,8 @@ def build(force: bool = True) -> str:
 
 class _Params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32 * 4), ("Ls", ctypes.c_int32), ("M5", ctypes.c_double),
-                ("mf", ctypes.c_double), ("b5", ctypes.c_double), ("c5", ctypes.c_double)]
+                ("mf", ctypes.c_double), ("b5", ctypes.c_double), ("c5", ctypes.c_double),
+                ("mu", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -94,16 +95,19 @@ def using(path):
 
 @dataclass(frozen=True)
 class Params:
-    """Operator parameters: dims (Lx,Ly,Lz,Lt), Ls, M5 (> 0), mf, b5, c5."""
+    """Operator parameters: dims (Lx,Ly,Lz,Lt), Ls, M5 (> 0), mf, b5, c5, and the
+    chemical potential mu (time-like hops carry e^{+-mu})."""
     dims: tuple
     Ls: int
     M5: float
     mf: float
     b5: float
     c5: float
+    mu: float = 0.0
 
     def c(self) -> _Params:
-        return _Params((ctypes.c_int32 * 4)(*self.dims), self.Ls, self.M5, self.mf, self.b5, self.c5)
+        return _Params((ctypes.c_int32 * 4)(*self.dims), self.Ls, self.M5, self.mf, self.b5, self.c5,
+                       self.mu)
 
     @property
     def V(self) -> int:
@@ -224,7 +228,7 @@ def propagator4d(p: Params, U, b4, tol=1e-12, maxiter=20000):
     b4 = _c128(b4)
     single = b4.ndim == 6
     bs = b4[None] if single else b4
-    pv = Params(p.dims, p.Ls, p.M5, 1.0, p.b5, p.c5)
+    pv = Params(p.dims, p.Ls, p.M5, 1.0, p.b5, p.c5, p.mu)
     qs, infos = [], []
     for b in bs:
         wall = np.zeros(p.shape5(), complex)

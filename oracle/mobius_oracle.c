@@ -127,7 +127,10 @@ static void one_pm_gamma(int mu, double sign, const cplx *w, cplx *v)
  * Its adjoint, read off as the conjugate transpose of that matrix (gamma_mu
  * Hermitian), swaps the two projectors:
  *   D_W^+ psi(x) = (4-M5) psi(x) - 1/2 sum_mu [(1+g_mu) U_mu(x) psi(x+mu)
- *                                             + (1-g_mu) U_mu(x-mu)^+ psi(x-mu)]. */
+ *                                             + (1-g_mu) U_mu(x-mu)^+ psi(x-mu)].
+ * A chemical potential multiplies the time-like forward hop of D_W by e^{+mu}
+ * and the backward one by e^{-mu}; the adjoint, being the transpose, carries
+ * e^{-mu} on its forward and e^{+mu} on its backward time-like hop. */
 static void wilson_site(const orc_params *p, const cplx *U, const cplx *in, int64_t x,
                         cplx *out, int dag)
 {
@@ -138,14 +141,16 @@ static void wilson_site(const orc_params *p, const cplx *U, const cplx *in, int6
     for (int mu = 0; mu < 4; ++mu) {
         int64_t xf = neighbour(p, x, mu, +1);
         int64_t xb = neighbour(p, x, mu, -1);
+        const double ef = mu == 3 ? exp(dag ? -p->mu : p->mu) : 1.0;
+        const double eb = mu == 3 ? exp(dag ? p->mu : -p->mu) : 1.0;
         /* forward hop: (1 - sgn g_mu) U_mu(x) psi(x+mu) */
         colour_mul(U + ((int64_t)mu * V + x) * 9, 0, in + xf * SITE_DOF, v);
         one_pm_gamma(mu, -sgn, v, w);
-        for (int k = 0; k < SITE_DOF; ++k) out[k] -= 0.5 * w[k];
+        for (int k = 0; k < SITE_DOF; ++k) out[k] -= 0.5 * ef * w[k];
         /* backward hop: (1 + sgn g_mu) U_mu(x-mu)^+ psi(x-mu) */
         colour_mul(U + ((int64_t)mu * V + xb) * 9, 1, in + xb * SITE_DOF, v);
         one_pm_gamma(mu, +sgn, v, w);
-        for (int k = 0; k < SITE_DOF; ++k) out[k] -= 0.5 * w[k];
+        for (int k = 0; k < SITE_DOF; ++k) out[k] -= 0.5 * eb * w[k];
     }
 }
 

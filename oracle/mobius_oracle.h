@@ -44,6 +44,8 @@ typedef struct {
     double  M5;     /* domain-wall height; D_W diagonal is 4 - M5 */
     double  mf;     /* quark mass m of the wall coupling */
     double  b5, c5; /* Moebius coefficients, constant in s */
+    double  mu;     /* chemical potential: time-like hops carry e^{+mu} (forward) and
+                       e^{-mu} (backward) (Sec. "Baryon current and Chemical Potential") */
 } orc_params;
 
 typedef struct {

@@ -79,6 +79,53 @@ def pin_wilson_free_symbol(orc):
             assert _rel(out, want) < 1e-13, ("wilson free symbol", dag, _rel(out, want))
 
 
+def pin_wilson_free_symbol_mu(orc):
+    """Chemical potential at unit links: the time-like hops carry e^{+-mu}, so
+    D_W e^{ipx} u = e^{ipx} D_W(q) u with q_4 = p_4 - i mu (Sec. "Baryon current
+    and Chemical Potential"), and the adjoint is the symbol at conj(q)."""
+    from oracle import Params
+    dims = (4, 2, 6, 8)
+    U = inputs.unit_links(dims)
+    rng = np.random.default_rng(11)
+    for mu in (0.3, -0.7):
+        p = Params(dims, 2, 1.8, 0.1, 1.0, 0.0, mu)
+        for mom in ff.momenta(dims, rng, 4):
+            u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+            pw = ff.plane_wave(dims, mom)
+            psi = pw[..., None, None] * u
+            q = mom.astype(complex)
+            q[3] -= 1j * mu
+            for dag in (False, True):
+                out = orc.wilson(p, U, psi, dag=dag)
+                want = pw[..., None, None] * (ff.wilson_symbol(np.conj(q) if dag else q, p.M5, dag) @ u)
+                assert _rel(out, want) < 1e-13, ("wilson free symbol, mu", mu, dag, _rel(out, want))
+
+
+def pin_adjoints_mu(orc):
+    """<x, A y> = <A^+ x, y> with a chemical potential (the adjoint carries the
+    opposite factors on the time-like hops): D_DW, the hop blocks, D_pre."""
+    from oracle import Params, restrict
+    dims = (4, 2, 2, 4)
+    rng = np.random.default_rng(12)
+    U = inputs.random_links(dims, 0.5, rng)
+    p = Params(dims, 5, 1.8, 0.07, 1.75, 0.75, 0.4)
+    x = inputs.gaussian_spinor(dims, p.Ls, rng)
+    y = inputs.gaussian_spinor(dims, p.Ls, rng)
+    ops = {
+        "dw": (lambda v: orc.dw(p, U, v), lambda v: orc.dw(p, U, v, dag=True), x, y),
+        "hop_eo": (lambda v: orc.hop(p, U, v, 0), lambda v: orc.hop(p, U, v, 1, dag=True),
+                   restrict(p, x, 0), restrict(p, y, 1)),
+        "schur": (lambda v: orc.schur(p, U, v), lambda v: orc.schur(p, U, v, dag=True),
+                  restrict(p, x, 1), restrict(p, y, 1)),
+    }
+    for name, (A, Ad, xx, yy) in ops.items():
+        e = _adjoint_err(orc, A, Ad, xx, yy)
+        assert e < 1e-12, ("adjoint with mu", name, e)
+    # and the operator does depend on mu
+    p0 = Params(dims, 5, 1.8, 0.07, 1.75, 0.75)
+    assert _rel(orc.dw(p, U, x), orc.dw(p0, U, x)) > 1e-3
+
+
 def pin_kernel_bound(orc):
     """The paper states the Shamir kernel's largest free eigenvalue is (8 - M5)/(10 - M5) ~ 3/4.
     At p = (pi,pi,pi,pi) the oracle's D_W must be (8 - M5) times the identity."""
@@ -436,4 +483,5 @@ ALL_PINS = [pin_wilson_free_symbol, pin_kernel_bound, pin_gauge_covariance,
             pin_wilson_gamma5_hermiticity, pin_adjoints, pin_free_determinant,
             pin_free_propagator, pin_gamma5_R_hermiticity, pin_m5_block, pin_schur_solve_dense,
             pin_rb_equals_unpreconditioned, pin_cgne_dense, pin_force_finite_difference,
-            pin_propagator4d_free, pin_propagator4d_dense]
+            pin_propagator4d_free, pin_propagator4d_dense, pin_wilson_free_symbol_mu,
+            pin_adjoints_mu]

@@ -16,8 +16,18 @@ MUTANTS = [
     ("forward_projector", "one_pm_gamma(mu, -sgn, v, w);", "one_pm_gamma(mu, +sgn, v, w);"),
     ("backward_link_not_daggered", "colour_mul(U + ((int64_t)mu * V + xb) * 9, 1,",
      "colour_mul(U + ((int64_t)mu * V + xb) * 9, 0,"),
-    ("hop_factor", "out[k] -= 0.5 * w[k];\n        /* backward",
-     "out[k] -= 1.0 * w[k];\n        /* backward"),
+    ("hop_factor", "out[k] -= 0.5 * ef * w[k];\n        /* backward",
+     "out[k] -= 1.0 * ef * w[k];\n        /* backward"),
+    ("mu_adjoint_factors_unswapped",
+     "const double ef = mu == 3 ? exp(dag ? -p->mu : p->mu) : 1.0;\n"
+     "        const double eb = mu == 3 ? exp(dag ? p->mu : -p->mu) : 1.0;",
+     "const double ef = mu == 3 ? exp(p->mu) : 1.0;\n"
+     "        const double eb = mu == 3 ? exp(-p->mu) : 1.0;"),
+    ("mu_on_a_spatial_direction",
+     "const double ef = mu == 3 ? exp(dag ? -p->mu : p->mu) : 1.0;\n"
+     "        const double eb = mu == 3 ? exp(dag ? p->mu : -p->mu) : 1.0;",
+     "const double ef = mu == 2 ? exp(dag ? -p->mu : p->mu) : 1.0;\n"
+     "        const double eb = mu == 2 ? exp(dag ? p->mu : -p->mu) : 1.0;"),
     ("wall_mass_sign", "double fp1 = (s == Ls - 1) ? -p->mf : 1.0;\n            double fm1",
      "double fp1 = (s == Ls - 1) ? p->mf : 1.0;\n            double fm1"),
     ("s_coupling_chirality_swapped",
