@@ -75,6 +75,9 @@ typedef struct {
     double mf;    /* quark mass m of the wall coupling (0 <= mf <= 1; 1 = Pauli-Villars) */
     double b5;    /* Moebius b5 (Shamir: 1) */
     double c5;    /* Moebius c5 (Shamir: 0) */
+    double mu;    /* chemical potential (Sec. "Baryon current and Chemical Potential"): the
+                     time-like hops of D_W carry e^{+mu} forward (x -> x + t) and e^{-mu}
+                     backward; 0 = none; |mu| <= 10.  mobius_force requires mu = 0. */
 } mobius_params;
 
 typedef struct {

@@ -180,10 +180,13 @@ extern "C" int mobius_create(mobius_ctx **out, const mobius_params *p, const voi
     if (Mp == 0.0) return fail(MOBIUS_EINVAL, "M+ = b5 (4 - M5) + 1 is zero");
     const OpCoeffs c = make_coeffs(*p);
     if (!std::isfinite(c.inv_den)) return fail(MOBIUS_EINVAL, "the Ls-direction block I is singular");
+    if (!std::isfinite(p->mu) || std::fabs(p->mu) > 10.0)
+        return fail(MOBIUS_EINVAL, "the chemical potential must be finite with |mu| <= 10");
 
     mobius_ctx *ctx = new mobius_ctx();
     ctx->P = *p;
     ctx->c = c;
+    ctx->has_mu = p->mu != 0.0;
     Geometry &g = ctx->g;
     for (int mu = 0; mu < 4; ++mu) g.L[mu] = p->L[mu];
     g.Ls = p->Ls;
@@ -228,10 +231,20 @@ extern "C" int mobius_create(mobius_ctx **out, const mobius_params *p, const voi
     for (int prec = 0; prec < 3; ++prec) {
         ctx->tune[prec] = hop_tuning();
         ctx->tune[prec].prefetch = prefetch_depth(hop_tuning(), prec);
+        // a chemical potential enters the time-like records: e^{+mu} forward,
+        // e^{-mu} backward, and the opposite in the adjoint's own records
+        const double ef = std::exp(p->mu), eb = std::exp(-p->mu);
         e = ctx->links[prec].ensure(2 * 8 * g.Vh * (int64_t)link_record_bytes(prec));
         if (e != hipSuccess) return cleanup(fail(MOBIUS_ENOMEM, "links: " + std::string(hipGetErrorString(e))));
-        e = launch_pack_links(g, prec, links_c128, ctx->links[prec].p, st);
+        e = launch_pack_links(g, prec, links_c128, ctx->links[prec].p, st, ef, eb);
         if (e != hipSuccess) return cleanup(fail(MOBIUS_EHIP, hipGetErrorString(e)));
+        if (ctx->has_mu) {
+            e = ctx->links_dag[prec].ensure(2 * 8 * g.Vh * (int64_t)link_record_bytes(prec));
+            if (e != hipSuccess)
+                return cleanup(fail(MOBIUS_ENOMEM, "links: " + std::string(hipGetErrorString(e))));
+            e = launch_pack_links(g, prec, links_c128, ctx->links_dag[prec].p, st, eb, ef);
+            if (e != hipSuccess) return cleanup(fail(MOBIUS_EHIP, hipGetErrorString(e)));
+        }
     }
     *out = ctx;
     return MOBIUS_OK;
@@ -244,6 +257,7 @@ extern "C" int mobius_destroy(mobius_ctx *ctx)
     ctx->nbr.release();
     ctx->canon_of.release();
     for (auto &l : ctx->links) l.release();
+    for (auto &l : ctx->links_dag) l.release();
     ctx->scratch.release();
     ctx->work.release();
     ctx->partials.release();
@@ -307,7 +321,7 @@ hipError_t hop(mobius_ctx *ctx, const HopArgs &a0, hipStream_t st)
 {
     HopArgs a = a0;
     a.tune = &ctx->tune[a.prec];
-    return launch_hop(ctx->g, ctx->c, ctx->links[a.prec].p, static_cast<const int32_t *>(ctx->nbr.p),
+    return launch_hop(ctx->g, ctx->c, hop_links(ctx, a.prec, a.dag), static_cast<const int32_t *>(ctx->nbr.p),
                       a, st);
 }
 
@@ -449,10 +463,10 @@ extern "C" int mobius_propagator4d(mobius_ctx *ctx, const void *src4, void *sol4
     const int32_t *nbr = static_cast<const int32_t *>(ctx->nbr.p);
     HopArgs a = hop_args(MOBIUS_F64, 0, EPI_M5ADD, 0, wo, de, nullptr, we, nullptr, nrhs);
     a.tune = &ctx->tune[MOBIUS_F64];
-    HIPCHK(launch_hop(g, cpv, ctx->links[MOBIUS_F64].p, nbr, a, st));
+    HIPCHK(launch_hop(g, cpv, hop_links(ctx, MOBIUS_F64, 0), nbr, a, st));
     a = hop_args(MOBIUS_F64, 0, EPI_M5ADD, 1, we, dod, nullptr, wo, nullptr, nrhs);
     a.tune = &ctx->tune[MOBIUS_F64];
-    HIPCHK(launch_hop(g, cpv, ctx->links[MOBIUS_F64].p, nbr, a, st));
+    HIPCHK(launch_hop(g, cpv, hop_links(ctx, MOBIUS_F64, 0), nbr, a, st));
     HIPCHK(launch_unpack_spinor(g, MOBIUS_F64, de, dod, eta, nrhs, st));
     // D(m) psi = eta, then q = (P^+ psi)_0
     mobius_solve_opts o = *opts;
@@ -475,6 +489,7 @@ extern "C" int mobius_force(mobius_ctx *ctx, const void *phi, void *grad_links, 
     if (!phi || !grad_links || !grad_phi || !action || !opts || !info)
         return fail(MOBIUS_EINVAL, "null argument to mobius_force");
     if (opts->nrhs > 1) return fail(MOBIUS_EINVAL, "mobius_force takes one source (nrhs <= 1)");
+    if (ctx->has_mu) return fail(MOBIUS_EINVAL, "mobius_force: no chemical potential (mu must be 0)");
     if (int r = check_prec(opts->inner_prec)) return r;
     if (phi == grad_phi || phi == grad_links || grad_phi == grad_links)
         return fail(MOBIUS_EINVAL, "mobius_force arguments alias");

@@ -165,7 +165,8 @@ int64_t site_kernel_blocks(const Geometry &g);
 hipError_t launch_build_geometry(const Geometry &g, const int32_t *packed_of, int32_t *nbr,
                                  hipStream_t st);
 hipError_t launch_pack_links(const Geometry &g, int prec, const void *canon, void *packed,
-                             hipStream_t st);
+                             hipStream_t st,
+                             double sf = 1.0, double sb = 1.0);
 // 4d field on the walls of the fifth dimension and back (canonical layouts)
 hipError_t launch_wall_place(const Geometry &g, const void *b4, void *eta5, int nrhs, hipStream_t st);
 hipError_t launch_wall_read(const Geometry &g, const void *psi5, void *q4, int nrhs, hipStream_t st);
@@ -325,6 +326,8 @@ struct mobius_ctx {
     mobius::DevBuf canon_of;  // [2][Vh] canonical index of each packed site
     mobius::DevBuf nbr;
     mobius::DevBuf links[3];
+    mobius::DevBuf links_dag[3];  // adjoint's records when a chemical potential is set
+    bool has_mu = false;
     mobius::DevBuf scratch;   // operator temporaries (SCHUR blocks)
     mobius::DevBuf work;      // solver fields
     mobius::DevBuf partials;  // reduction partials
@@ -334,3 +337,10 @@ struct mobius_ctx {
     mobius::HopTuning tune[3];  // hop launch parameters per storage precision
     double tuned_us[3] = {0, 0, 0};  // hop time of the tuned parameters (0: not tuned)
 };
+
+// Link records a hop reads: with a chemical potential the adjoint hops use
+// their own records (factors e^{-+mu} instead of e^{+-mu} on the time-like ones).
+inline const void *hop_links(const mobius_ctx *ctx, int prec, int dag)
+{
+    return (dag && ctx->has_mu) ? ctx->links_dag[prec].p : ctx->links[prec].p;
+}

@@ -368,8 +368,10 @@ __device__ __forceinline__ void put_link_elem(char *dst, int64_t idx, double re,
 
 // record (p, d, i) of the packed links; padding elements are zero
 template <int P>
+// sf, sb: factors of the time-like forward (d = 3) and backward (d = 7)
+// records (e^{+-mu} of a chemical potential; 1 without one)
 __global__ void pack_links_kernel(Dims D, int64_t V, int64_t Vh, const int32_t *canon_of,
-                                  const double2 *canon, char *packed)
+                                  const double2 *canon, char *packed, double sf, double sb)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * Vh * 8) return;
@@ -385,9 +387,10 @@ __global__ void pack_links_kernel(Dims D, int64_t V, int64_t Vh, const int32_t *
     constexpr int REC = Link<P>::REC;
     constexpr int EB = P == MOBIUS_F64 ? 16 : P == MOBIUS_F32 ? 8 : 4;
     char *rec = packed + (((int64_t)p * 8 + d) * Vh + i) * REC;
+    const double f = d == 3 ? sf : d == 7 ? sb : 1.0;
     for (int e = 0; e < REC / EB; ++e) {
         double2 u = e < 9 ? canon[src + e] : make_double2(0.0, 0.0);
-        put_link_elem<P>(rec, e, u.x, u.y);
+        put_link_elem<P>(rec, e, f * u.x, f * u.y);
     }
 }
 
@@ -939,7 +942,7 @@ hipError_t launch_build_geometry(const Geometry &g, const int32_t *packed_of, in
 }
 
 hipError_t launch_pack_links(const Geometry &g, int prec, const void *canon, void *packed,
-                             hipStream_t st)
+                             hipStream_t st, double sf, double sb)
 {
     Dims D{{g.L[0], g.L[1], g.L[2], g.L[3]}};
     const int64_t n = 2 * g.Vh * 8;
@@ -947,9 +950,9 @@ hipError_t launch_pack_links(const Geometry &g, int prec, const void *canon, voi
     const double2 *c = static_cast<const double2 *>(canon);
     char *o = static_cast<char *>(packed);
     switch (prec) {
-    case MOBIUS_F64: hipLaunchKernelGGL(pack_links_kernel<MOBIUS_F64>, grid, dim3(256), 0, st, D, g.V, g.Vh, g.canon_of, c, o); break;
-    case MOBIUS_F32: hipLaunchKernelGGL(pack_links_kernel<MOBIUS_F32>, grid, dim3(256), 0, st, D, g.V, g.Vh, g.canon_of, c, o); break;
-    case MOBIUS_F16: hipLaunchKernelGGL(pack_links_kernel<MOBIUS_F16>, grid, dim3(256), 0, st, D, g.V, g.Vh, g.canon_of, c, o); break;
+    case MOBIUS_F64: hipLaunchKernelGGL(pack_links_kernel<MOBIUS_F64>, grid, dim3(256), 0, st, D, g.V, g.Vh, g.canon_of, c, o, sf, sb); break;
+    case MOBIUS_F32: hipLaunchKernelGGL(pack_links_kernel<MOBIUS_F32>, grid, dim3(256), 0, st, D, g.V, g.Vh, g.canon_of, c, o, sf, sb); break;
+    case MOBIUS_F16: hipLaunchKernelGGL(pack_links_kernel<MOBIUS_F16>, grid, dim3(256), 0, st, D, g.V, g.Vh, g.canon_of, c, o, sf, sb); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

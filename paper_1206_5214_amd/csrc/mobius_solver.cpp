@@ -273,7 +273,7 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
         hop_lds[pid] = 0;
         for (int j = 0; j < ng; ++j) {
             const Group &g = groups[j];
-            const HopParams h = make_hop_params(g.ctx->g, g.ctx->c, g.ctx->links[hp[pid].prec].p,
+            const HopParams h = make_hop_params(g.ctx->g, g.ctx->c, hop_links(g.ctx, hp[pid].prec, hp[pid].dag),
                                                 static_cast<const int32_t *>(g.ctx->nbr.p),
                                                 hop_args_for(g, hp[pid]));
             h_hop[(size_t)pid * ng + j] = h;
@@ -420,7 +420,7 @@ hipError_t Batch::launch_pattern(const HopPattern &p, int pid)
 {
     if (ngroups() == 1) {
         const Group &g = groups[0];
-        return launch_hop(g.ctx->g, g.ctx->c, g.ctx->links[p.prec].p,
+        return launch_hop(g.ctx->g, g.ctx->c, hop_links(g.ctx, p.prec, p.dag),
                           static_cast<const int32_t *>(g.ctx->nbr.p), hop_args_for(g, p), st);
     }
     return launch_hop_batch(p.prec, p.dag, p.epi, hop_tab + (size_t)pid * ngroups(), ngroups(),
@@ -437,7 +437,7 @@ hipError_t Batch::hop_group(const Group &g, int prec, int dag, int epi, int out_
     abytes += (2 + (x != F_NONE) + (y != F_NONE)) * (double)g.fb[in] * g.nrhs +
               72.0 * g.ctx->g.Vh * link_elem_bytes(prec);
     aflops += (double)g.ctx->g.N5 * g.nrhs * 1416;
-    return launch_hop(g.ctx->g, g.ctx->c, g.ctx->links[prec].p,
+    return launch_hop(g.ctx->g, g.ctx->c, hop_links(g.ctx, prec, dag),
                       static_cast<const int32_t *>(g.ctx->nbr.p), a, st);
 }
 

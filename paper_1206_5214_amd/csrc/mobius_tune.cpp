@@ -113,7 +113,7 @@ int tune(mobius_ctx *ctx, int prec, int reps, mobius_tune_result *out, hipStream
                             for (int r = 0; r < n; ++r)
                                 for (int par = 0; par < 2; ++par) {
                                     a.out_parity = par;
-                                    hipError_t x = launch_hop(g, ctx->c, ctx->links[prec].p,
+                                    hipError_t x = launch_hop(g, ctx->c, hop_links(ctx, prec, a.dag),
                                                               static_cast<const int32_t *>(ctx->nbr.p), a, st);
                                     if (x != hipSuccess) return x;
                                 }

@@ -33,7 +33,8 @@ class MobiusError(RuntimeError):
 
 class _Params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32 * 4), ("Ls", ctypes.c_int32), ("M5", ctypes.c_double),
-                ("mf", ctypes.c_double), ("b5", ctypes.c_double), ("c5", ctypes.c_double)]
+                ("mf", ctypes.c_double), ("b5", ctypes.c_double), ("c5", ctypes.c_double),
+                ("mu", ctypes.c_double)]
 
 
 class _SolveOpts(ctypes.Structure):
@@ -138,7 +139,7 @@ def _require_cuda(t, dtype=None, name="tensor"):
 class Operator:
     """A red/black Moebius operator on one lattice (owns the packed links)."""
 
-    def __init__(self, dims, Ls, M5, mf, b5, c5, links):
+    def __init__(self, dims, Ls, M5, mf, b5, c5, links, mu=0.0):
         import torch
         _require_cuda(links, torch.complex128, "links")
         Lx, Ly, Lz, Lt = dims
@@ -146,8 +147,8 @@ class Operator:
             raise MobiusError(f"links have shape {tuple(links.shape)}")
         self.dims = tuple(int(d) for d in dims)
         self.Ls = int(Ls)
-        self.params = dict(M5=M5, mf=mf, b5=b5, c5=c5)
-        p = _Params((ctypes.c_int32 * 4)(*self.dims), self.Ls, M5, mf, b5, c5)
+        self.params = dict(M5=M5, mf=mf, b5=b5, c5=c5, mu=mu)
+        p = _Params((ctypes.c_int32 * 4)(*self.dims), self.Ls, M5, mf, b5, c5, mu)
         h = ctypes.c_void_p()
         _check(lib().mobius_create(ctypes.byref(h), ctypes.byref(p), _ptr(links), _stream()))
         self._h = h

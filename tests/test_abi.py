@@ -52,6 +52,10 @@ def test_error_paths_without_gpu():
     # Ls out of range
     p = mobius._Params((ctypes.c_int32 * 4)(4, 4, 4, 4), 65, 1.8, 0.01, 1.0, 0.0)
     assert L.mobius_create(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(1), None) == -22
+    # non-finite chemical potential
+    p = mobius._Params((ctypes.c_int32 * 4)(4, 4, 4, 4), 8, 1.8, 0.01, 1.0, 0.0, float("nan"))
+    assert L.mobius_create(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(1), None) == -22
+    assert b"chemical" in L.mobius_last_error()
     # null links
     p = mobius._Params((ctypes.c_int32 * 4)(4, 4, 4, 4), 8, 1.8, 0.01, 1.0, 0.0)
     assert L.mobius_create(ctypes.byref(h), ctypes.byref(p), None, None) == -22
