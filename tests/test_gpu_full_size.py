@@ -1,0 +1,97 @@
+"""The 24^3 x 64, Ls = 12 workload at full size, in the launch configuration
+the benchmark times (tuned per precision), against the FP64 CPU oracle:
+
+* the hop blocks (both parities, D and D^+) at sampled output sites, each
+  recomputed one by one with the oracle's D_DW restricted to those sites;
+* the FP16-operator solve to 1e-10, whose full-system true residual the
+  oracle recomputes over the whole lattice (one matrix-free D_DW on the host).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 2e-5, 2: 4e-3}  # as the operator parity tests
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def workload(torch_cuda):
+    from oracle import Params
+    from paper_1206_5214_amd import inputs, mobius
+    w = inputs.WORKLOADS["mobius_24x24x24x64_ls12"]
+    _flush(f"generating {w.name}")
+    U, eta = inputs.workload_fields(w)
+    op = mobius.Operator(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, torch_cuda.from_numpy(U).cuda())
+    p = Params(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5)
+    yield w, p, U, eta, op
+    op.close()
+
+
+def _sites(p, parity, n, seed):
+    """n canonical 4d site indices of the given parity (first, last and random ones)."""
+    Lx, Ly, Lz, Lt = p.dims
+    idx = np.arange(p.V)
+    x = idx % Lx
+    y = (idx // Lx) % Ly
+    z = (idx // (Lx * Ly)) % Lz
+    t = idx // (Lx * Ly * Lz)
+    of = idx[((x + y + z + t) & 1) == parity]
+    rng = np.random.default_rng(seed)
+    pick = np.concatenate([of[:2], of[-2:], rng.choice(of, n - 4, replace=False)])
+    return np.sort(pick)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "f16"])
+def test_hop_full_size_sampled(torch_cuda, orc, workload, prec):
+    torch = torch_cuda
+    w, p, U, eta, op = workload
+    op.tune(prec)
+    _flush(f"full-size hop {w.name} prec={prec}")
+    even, odd = op.pack(torch.from_numpy(eta).cuda(), prec)
+    halves = {0: even, 1: odd}
+    zero = op.new_field(prec)
+    for outp in (0, 1):
+        sites = _sites(p, outp, 48, 40 + outp)
+        for dag in (False, True):
+            out = op.dslash(halves[1 - outp], outp, prec, dag=dag)
+            got = op.unpack(out if outp == 0 else zero, zero if outp == 0 else out, prec).cpu().numpy()
+            # canonical [s][t][z][y][x][4][3] -> rows of the sampled sites: [n][Ls][4][3]
+            got_s = got.reshape(p.Ls, p.V, 4, 3)[:, sites].transpose(1, 0, 2, 3)
+            # D_DW at those sites with the input zero on their own parity = the hop block
+            want = orc.dw_sites(p, U, eta, sites, in_parity=1 - outp, dag=dag)
+            err = float(np.abs(got_s - want).max() / np.abs(want).max())
+            _flush(f"  out parity {outp} dag {dag}: {len(sites)} sites, err {err:.2e}")
+            assert err < TOL[prec], (outp, dag, err)
+            del got, out
+
+
+def test_solve_full_size_true_residual(torch_cuda, orc, workload):
+    from paper_1206_5214_amd import mobius
+    torch = torch_cuda
+    w, p, U, eta, op = workload
+    op.tune(mobius.F16)
+    _flush(f"full-size solve {w.name}, FP16 operator")
+    sol, info, rc = op.solve(torch.from_numpy(eta).cuda(), tol=w.tol, maxiter=50000,
+                             inner_prec=mobius.F16)
+    assert rc == mobius.OK, info
+    psi = sol.cpu().numpy()
+    del sol
+    r = orc.dw(p, U, psi) - eta
+    res = float(np.linalg.norm(r.ravel()) / np.linalg.norm(eta.ravel()))
+    _flush(f"  iters {info[0].iters}, oracle true residual {res:.3e} (solver {info[0].true_resid:.3e})")
+    assert res <= w.tol
+    assert abs(res - info[0].true_resid) <= 0.05 * res
