@@ -11,7 +11,9 @@
  *                  - 1/2 sum_mu [(1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^+ psi(x-mu)]
  * with M5 > 0 the domain-wall height (the paper writes 4 + M5 with M5 = O(-1)).
  * Gamma matrices are in the chiral basis, g5 = diag(1,1,-1,-1), P+ = spins 0,1.
- * Periodic boundaries in all four directions.
+ * Periodic boundaries in all four directions.  An optional chemical potential
+ * mu (mobius_params.mu) multiplies the time-like forward hop by e^{+mu} and the
+ * backward one by e^{-mu} (Sec. "Baryon current and Chemical Potential").
  *
  * Red/black (Sec. 3): 4d parity (x+y+z+t) mod 2, the same for every s.
  * Parity 0 = even ("red"), parity 1 = odd ("black").  With
@@ -32,8 +34,9 @@
  *    size in bytes per right-hand side is mobius_field_bytes().  They hold one
  *    parity of a 5d field in the given storage precision.
  *  - Every call enqueues its work on `stream` (a hipStream_t, NULL = default
- *    stream) and returns without synchronising, except mobius_cg_solve which
- *    synchronises once at the end to fill `info`.
+ *    stream) and returns without synchronising, except mobius_cg_solve,
+ *    mobius_batch_solve, mobius_propagator4d, mobius_force and mobius_tune,
+ *    which synchronise once at the end to fill their outputs.
  *  - Return codes: MOBIUS_OK (0) on success; MOBIUS_NOT_CONVERGED (1) from
  *    the solver when maxiter is reached (info is still filled); negative codes
  *    on error, with a message in mobius_last_error().  No call aborts or throws.
