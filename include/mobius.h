@@ -220,6 +220,16 @@ int mobius_force(mobius_ctx *ctx, const void *phi_c128, void *grad_links_c128, v
                  double *action, const mobius_solve_opts *opts, mobius_solve_info *info,
                  void *stream);
 
+/* Lie-algebra form of a link gradient, for molecular-dynamics updates:
+ *   F_mu(x) = TA(U_mu(x) G_mu(x)^+),  TA(M) = (M - M^+)/2 - tr(M - M^+)/6,
+ * traceless anti-Hermitian, so that for U -> e^{eps X} U (X in su(3)) the
+ * action changes at the rate dS/deps = Re tr(F X).  links_c128, grad_links_c128
+ * (G as mobius_force returns it) and lie_c128: canonical [mu][t][z][y][x][a][b]
+ * complex128 device arrays of 4 V 3x3 entries; lie_c128 must not alias either
+ * input.  Enqueued on stream. */
+int mobius_force_lie(mobius_ctx *ctx, const void *links_c128, const void *grad_links_c128,
+                     void *lie_c128, void *stream);
+
 /* Launch parameters of the hop kernel chosen by mobius_tune. */
 typedef struct {
     int32_t prec;        /* storage precision tuned */

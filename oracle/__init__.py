@@ -274,6 +274,16 @@ def force(p: Params, U, phi, links=None, tol=1e-13, maxiter=20000):
                                    info.true_resid)
 
 
+def force_lie(U, G):
+    """F = TA(U G^+) per link, TA(M) = (M - M^+)/2 - tr(M - M^+)/6: the su(3)
+    form of the link gradient G (dS/dRe U + i dS/dIm U), with dS/deps =
+    Re tr(F X) for U -> e^{eps X} U.  U, G: [..., 3, 3]."""
+    M = _c128(U) @ np.conj(np.swapaxes(_c128(G), -1, -2))
+    A = 0.5 * (M - np.conj(np.swapaxes(M, -1, -2)))
+    tr = np.trace(A, axis1=-2, axis2=-1) / 3.0
+    return A - tr[..., None, None] * np.eye(3)
+
+
 def parity_mask(p: Params):
     """Boolean [Lt][Lz][Ly][Lx] mask of odd sites ((x+y+z+t) mod 2 == 1)."""
     Lx, Ly, Lz, Lt = p.dims

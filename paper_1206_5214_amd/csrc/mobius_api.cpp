@@ -480,6 +480,18 @@ extern "C" int mobius_propagator4d(mobius_ctx *ctx, const void *src4, void *sol4
     return rc;
 }
 
+extern "C" int mobius_force_lie(mobius_ctx *ctx, const void *links_c128, const void *grad_links_c128,
+                                void *lie_c128, void *stream)
+{
+    g_err.clear();
+    if (int r = check_ctx(ctx)) return r;
+    if (!links_c128 || !grad_links_c128 || !lie_c128) return fail(MOBIUS_EINVAL, "null argument to mobius_force_lie");
+    if (lie_c128 == links_c128 || lie_c128 == grad_links_c128)
+        return fail(MOBIUS_EINVAL, "the output aliases an input");
+    HIPCHK(launch_lie_force(4 * ctx->g.V, links_c128, grad_links_c128, lie_c128, S(stream)));
+    return MOBIUS_OK;
+}
+
 extern "C" int mobius_force(mobius_ctx *ctx, const void *phi, void *grad_links, void *grad_phi,
                             double *action, const mobius_solve_opts *opts, mobius_solve_info *info,
                             void *stream)

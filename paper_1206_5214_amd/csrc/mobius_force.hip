@@ -122,7 +122,51 @@ __global__ __launch_bounds__(BLOCK) void force_kernel(ForceParams fp)
     force_dir<3>(fp, m, k, Lo, BRo, (uint32_t)nb[3] * (uint32_t)fp.Ls + (uint32_t)m.s, lds);
 }
 
+// Lie-algebra force per link: F = TA(U G^+), TA(M) = (M - M^+)/2 - tr(M - M^+)/6,
+// so that for U -> e^{eps X} U (X in su(3)) dS/deps = Re tr(F X).
+__global__ __launch_bounds__(256) void lie_force_kernel(int64_t nlinks, const double2 *U,
+                                                        const double2 *G, double2 *F)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nlinks) return;
+    cx<double> u[9], g[9], m[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        u[e] = {U[l * 9 + e].x, U[l * 9 + e].y};
+        g[e] = {G[l * 9 + e].x, G[l * 9 + e].y};
+    }
+    // M = U G^+: M_ab = sum_c U_ac conj(G_bc)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            cx<double> acc = {0, 0};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc = cjmadd(acc, g[b * 3 + c], u[a * 3 + c]);
+            m[a * 3 + b] = acc;
+        }
+    // anti-Hermitian part, then its trace removed (the trace is imaginary)
+    const double tr = (m[0].i + m[4].i + m[8].i) / 3.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const cx<double> x = m[a * 3 + b], y = m[b * 3 + a];
+            double re = 0.5 * (x.r - y.r), im = 0.5 * (x.i + y.i);
+            if (a == b) im -= tr;
+            F[l * 9 + a * 3 + b] = make_double2(re, im);
+        }
+}
+
 }  // namespace
+
+hipError_t launch_lie_force(int64_t nlinks, const void *U, const void *G, void *F, hipStream_t st)
+{
+    hipLaunchKernelGGL(lie_force_kernel, dim3((unsigned)((nlinks + 255) / 256)), dim3(256), 0, st, nlinks,
+                       static_cast<const double2 *>(U), static_cast<const double2 *>(G),
+                       static_cast<double2 *>(F));
+    return hipGetLastError();
+}
 
 hipError_t launch_force(const Geometry &g, const OpCoeffs &c, int parity, const int32_t *nbr,
                         const void *Lp, const void *Rp, const void *Ln, const void *Rn,

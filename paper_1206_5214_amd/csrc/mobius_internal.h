@@ -167,6 +167,8 @@ hipError_t launch_build_geometry(const Geometry &g, const int32_t *packed_of, in
 hipError_t launch_pack_links(const Geometry &g, int prec, const void *canon, void *packed,
                              hipStream_t st,
                              double sf = 1.0, double sb = 1.0);
+// F = TA(U G^+) per link (canonical complex128 3x3 records, nlinks of them)
+hipError_t launch_lie_force(int64_t nlinks, const void *U, const void *G, void *F, hipStream_t st);
 // 4d field on the walls of the fifth dimension and back (canonical layouts)
 hipError_t launch_wall_place(const Geometry &g, const void *b4, void *eta5, int nrhs, hipStream_t st);
 hipError_t launch_wall_read(const Geometry &g, const void *psi5, void *q4, int nrhs, hipStream_t st);

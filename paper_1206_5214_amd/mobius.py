@@ -23,7 +23,7 @@ OK, NOT_CONVERGED = 0, 1
 
 EXPORTS = ("mobius_create", "mobius_destroy", "mobius_field_bytes", "mobius_pack",
            "mobius_unpack", "mobius_dslash", "mobius_dslash_dag", "mobius_m5inv",
-           "mobius_cg_solve", "mobius_batch_solve", "mobius_propagator4d", "mobius_force",
+           "mobius_cg_solve", "mobius_batch_solve", "mobius_propagator4d", "mobius_force", "mobius_force_lie",
            "mobius_tune", "mobius_set_tuning", "mobius_last_error")
 
 
@@ -100,6 +100,7 @@ def lib():
                                           ctypes.POINTER(_SolveInfo), vp]
         L.mobius_force.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(_SolveOpts), ctypes.POINTER(_SolveInfo), vp]
+        L.mobius_force_lie.argtypes = [vp, vp, vp, vp, vp]
         L.mobius_tune.argtypes = [vp, i32, i32, ctypes.POINTER(_TuneResult), vp]
         L.mobius_set_tuning.argtypes = [vp, ctypes.POINTER(_TuneResult)]
         L.mobius_last_error.restype = ctypes.c_char_p
@@ -272,6 +273,18 @@ class Operator:
         rc = _check(lib().mobius_propagator4d(self._h, _ptr(src4), _ptr(sol), ctypes.byref(opts),
                                               infos, _stream()))
         return sol, [_info(i) for i in infos], rc
+
+    def force_lie(self, links, grad):
+        """F = TA(U G^+) per link (see mobius_force_lie): the su(3) form of a
+        link gradient G, with dS/deps = Re tr(F X) for U -> e^{eps X} U."""
+        import torch
+        _require_cuda(links, torch.complex128, "links")
+        _require_cuda(grad, torch.complex128, "gradient")
+        if tuple(links.shape) != self.link_shape() or tuple(grad.shape) != self.link_shape():
+            raise MobiusError(f"links and gradient must have shape {self.link_shape()}")
+        out = torch.empty_like(links)
+        _check(lib().mobius_force_lie(self._h, _ptr(links), _ptr(grad), _ptr(out), _stream()))
+        return out
 
     def tune(self, prec, reps=10):
         """Autotune the hop launch parameters of this operator for one storage

@@ -313,6 +313,38 @@ def pin_propagator4d_dense(orc):
     assert _rel(got, b) < 1e-9, ("D_ov q = b", _rel(got, b))
 
 
+def pin_force_lie(orc):
+    """The su(3) form F = TA(U G^+) of the oracle's link gradient: at every link
+    Re tr(F X) = Re tr(G^+ X U) for random X in su(3) (the first-order change of
+    S under U -> e^{eps X} U), F is traceless anti-Hermitian, and a central
+    difference of S along e^{+-eps X} at one link matches Re tr(F X)."""
+    from scipy.linalg import expm
+    p, U, rng = _setup((2, 2, 2, 4), 4, 1.5, 0.5, 0.1, seed=13)
+    from oracle import restrict
+    phi = restrict(p, inputs.gaussian_spinor(p.dims, p.Ls, rng), 1)
+    S, _, G, _ = orc.force(p, U, phi, tol=1e-14)
+    F = orc.force_lie(U, G)
+    assert np.abs(F + np.conj(np.swapaxes(F, -1, -2))).max() < 1e-12 * np.abs(F).max()
+    assert np.abs(np.trace(F, axis1=-2, axis2=-1)).max() < 1e-12 * np.abs(F).max()
+    X = rng.normal(size=U.shape) + 1j * rng.normal(size=U.shape)
+    X = 0.5 * (X - np.conj(np.swapaxes(X, -1, -2)))
+    X -= (np.trace(X, axis1=-2, axis2=-1) / 3.0)[..., None, None] * np.eye(3)
+    lhs = np.einsum("...ab,...ba->...", F, X).real
+    rhs = np.einsum("...ba,...bc,...ca->...", np.conj(G), X, U).real
+    assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(rhs).max(), "Re tr(F X) = Re tr(G^+ X U)"
+    # one link, central difference of S (loose: the action is O(|phi|^2))
+    mu, site, eps = 3, 5, 1e-4
+    Xl = X[(mu,) + np.unravel_index(site, U.shape[1:5])]
+    def S_at(e):
+        Up = U.copy()
+        idx = (mu,) + np.unravel_index(site, U.shape[1:5])
+        Up[idx] = expm(e * Xl) @ U[idx]
+        return orc.force(p, Up, phi, links=[(0, 0)], tol=1e-14)[0]
+    fd = (S_at(eps) - S_at(-eps)) / (2 * eps)
+    want = lhs[(mu,) + np.unravel_index(site, U.shape[1:5])]
+    assert abs(fd - want) < 1e-5 * max(abs(want), 1e-3 * abs(S)), ("dS/deps", fd, want)
+
+
 def _dense(apply, n, shape):
     M = np.zeros((n, n), complex)
     for j in range(n):
@@ -484,4 +516,4 @@ ALL_PINS = [pin_wilson_free_symbol, pin_kernel_bound, pin_gauge_covariance,
             pin_free_propagator, pin_gamma5_R_hermiticity, pin_m5_block, pin_schur_solve_dense,
             pin_rb_equals_unpreconditioned, pin_cgne_dense, pin_force_finite_difference,
             pin_propagator4d_free, pin_propagator4d_dense, pin_wilson_free_symbol_mu,
-            pin_adjoints_mu]
+            pin_adjoints_mu, pin_force_lie]

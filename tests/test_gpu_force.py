@@ -173,3 +173,24 @@ def test_force_rejects_bad_arguments(torch_cuda):
     with pytest.raises(mobius.MobiusError):
         op.force(phi[:2].contiguous())
     op.close()
+
+
+def test_force_lie_vs_oracle(torch_cuda, orc):
+    """F = TA(U G^+) per link on the GPU (mobius_force_lie) against the oracle's
+    projection, for the force of the 4^4, Ls=8 lattice and for random G."""
+    from paper_1206_5214_amd import inputs, mobius
+    torch = torch_cuda
+    dims, Ls = (4, 4, 4, 4), 8
+    rng = np.random.default_rng(51)
+    U = inputs.random_links(dims, 0.5, rng)
+    op = mobius.Operator(dims, Ls, 1.8, 0.05, 1.5, 0.5, torch.from_numpy(U).cuda())
+    G = rng.normal(size=U.shape) + 1j * rng.normal(size=U.shape)
+    F = op.force_lie(torch.from_numpy(U).cuda(), torch.from_numpy(G).cuda()).cpu().numpy()
+    want = orc.force_lie(U, G)
+    err = float(np.abs(F - want).max() / np.abs(want).max())
+    assert err < 1e-14, err
+    import ctypes
+    u = torch.from_numpy(U).cuda()
+    assert mobius.lib().mobius_force_lie(op._h, mobius._ptr(u), mobius._ptr(u), mobius._ptr(u),
+                                         None) == -22  # output aliases an input
+    op.close()
