@@ -181,7 +181,7 @@ int mobius_cg_solve(mobius_ctx *ctx, const void *src_c128, void *sol_c128,
  * opts->nrhs of them (device memory, caller-owned).  The 5d solve D_DW(m) psi
  * = D_DW(1) P b runs as mobius_cg_solve with opts; info (opts->nrhs entries)
  * describes it (its true residual is that of the 5d system).  The context
- * keeps three canonical 5d fields and four packed FP64 half fields per
+ * keeps two canonical 5d fields and four packed FP64 half fields per
  * right-hand side as temporaries until mobius_destroy.  Returns as
  * mobius_cg_solve. */
 int mobius_propagator4d(mobius_ctx *ctx, const void *src4_c128, void *sol4_c128,

@@ -446,12 +446,13 @@ extern "C" int mobius_propagator4d(mobius_ctx *ctx, const void *src4, void *sol4
     const int nrhs = opts->nrhs > 0 ? opts->nrhs : 1;
     hipStream_t st = S(stream);
     const Geometry &g = ctx->g;
-    // temporaries: wall field, 5d source and 5d solution (canonical), and the
-    // packed halves of the wall field and of D(1) applied to it (FP64)
+    // temporaries: 5d source and 5d solution (canonical; the wall field lives
+    // in the solution's buffer until it is packed), and the packed halves of
+    // the wall field and of D(1) applied to it (FP64)
     const int64_t c5 = g.V * g.Ls * 12 * (int64_t)sizeof(double2) * nrhs;
     const int64_t fb = field_bytes(g, MOBIUS_F64) * nrhs;
-    HIPCHK(ctx->prop.ensure(3 * c5 + 4 * fb));
-    char *wall = static_cast<char *>(ctx->prop.p), *eta = wall + c5, *psi = eta + c5;
+    HIPCHK(ctx->prop.ensure(2 * c5 + 4 * fb));
+    char *eta = static_cast<char *>(ctx->prop.p), *psi = eta + c5, *wall = psi;
     char *we = psi + c5, *wo = we + fb, *de = wo + fb, *dod = de + fb;
     HIPCHK(launch_wall_place(g, src4, wall, nrhs, st));
     HIPCHK(launch_pack_spinor(g, MOBIUS_F64, wall, we, wo, nrhs, st));
