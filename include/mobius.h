@@ -68,7 +68,8 @@ typedef enum {
 typedef enum {
     MOBIUS_OP_HOP = 0,   /* off-diagonal block D_{p,1-p} = -1/2 H B: parity 1-p -> p  (Sec. 3) */
     MOBIUS_OP_M5 = 1,    /* diagonal block I on one half field (parity-independent) (Sec. 3)  */
-    MOBIUS_OP_SCHUR = 2  /* D_pre = 1 - I^-1 D_oe I^-1 D_eo, odd -> odd (out_parity must be 1)  */
+    MOBIUS_OP_SCHUR = 2, /* D_pre = 1 - I^-1 D_oe I^-1 D_eo, odd -> odd (out_parity must be 1)  */
+    MOBIUS_OP_FULL = 3   /* the unpreconditioned D_DW(m) on both halves (Sec. 2.1)            */
 } mobius_op;
 
 typedef struct {
@@ -144,8 +145,15 @@ int mobius_unpack(mobius_ctx *ctx, int32_t prec, const void *even, const void *o
  *                   term on every s-slice after the b5/c5 mixing in s (Sec. 4.1:
  *                   gather s-1, s, s+1, then one Dirac application);
  *   MOBIUS_OP_M5    out = I in (both fields of parity out_parity);
- *   MOBIUS_OP_SCHUR out = D_pre in on the odd parity (out_parity must be 1).
- * in and out are packed fields of precision `prec`, nrhs consecutive fields each. */
+ *   MOBIUS_OP_SCHUR out = D_pre in on the odd parity (out_parity must be 1);
+ *   MOBIUS_OP_FULL  out = D_DW(m) in, the whole 5d operator of Sec. 2.1 (the
+ *                   block tridiagonal matrix in s with D+ = b5 D_W + 1 on the
+ *                   diagonal), applied on both parities as
+ *                   out_p = D_{p,1-p} in_{1-p} + I in_p; out_parity is ignored.
+ * in and out are packed fields of precision `prec`, nrhs consecutive fields
+ * each; for MOBIUS_OP_FULL each holds 2 nrhs fields: the nrhs even halves, then
+ * the nrhs odd halves (the two outputs of mobius_pack placed back to back), and
+ * in and out must not overlap. */
 int mobius_dslash(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity, const void *in,
                   void *out, int32_t nrhs, void *stream);
 
@@ -153,7 +161,8 @@ int mobius_dslash(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
  *   MOBIUS_OP_HOP   out(p) = (D^+)_{p,1-p} in(1-p) = (D_{1-p,p})^+ in
  *                   = -1/2 B^+ H^+ in, H^+ = H with g_mu -> -g_mu;
  *   MOBIUS_OP_M5    out = I^+ in;
- *   MOBIUS_OP_SCHUR out = D_pre^+ in = in - (D_eo)^+ I^-+ (D_oe)^+ I^-+ in. */
+ *   MOBIUS_OP_SCHUR out = D_pre^+ in = in - (D_eo)^+ I^-+ (D_oe)^+ I^-+ in;
+ *   MOBIUS_OP_FULL  out = D_DW(m)^+ in, out_p = (D^+)_{p,1-p} in_{1-p} + I^+ in_p. */
 int mobius_dslash_dag(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
                       const void *in, void *out, int32_t nrhs, void *stream);
 
@@ -209,6 +218,7 @@ int mobius_batch_solve(int32_t n, mobius_ctx *const *ctxs, const void *const *sr
  *                    entries as independent complex numbers (the gradient
  *                    convention of PyTorch for a real function of complex
  *                    inputs; project onto su(3) for a molecular-dynamics force);
+ *                    NULL skips the link-derivative pass (S and grad_phi only);
  *   grad_phi_c128    canonical 5d field: dS/dRe phi + i dS/dIm phi = 2 X on
  *                    the odd sites, 0 on the even sites;
  *   action           host pointer receiving S.

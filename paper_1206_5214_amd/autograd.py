@@ -19,19 +19,25 @@ from . import mobius
 
 class MobiusAction(torch.autograd.Function):
     """S = phi_o^+ (D_pre^+ D_pre)^-1 phi_o as a differentiable function of the
-    links and of phi (both complex128 CUDA tensors in the canonical layouts)."""
+    links and of phi (both complex128 CUDA tensors in the canonical layouts).
+    The link-derivative pass runs only when the links need a gradient."""
 
     @staticmethod
-    def forward(ctx, links, phi, dims, Ls, M5, mf, b5, c5, tol, maxiter, inner_prec):
-        op = mobius.Operator(dims, Ls, M5, mf, b5, c5, links.detach().contiguous())
+    def forward(ctx, links, phi, dims, Ls, M5, mf, b5, c5, tol, maxiter, inner_prec, op):
+        want_links = ctx.needs_input_grad[0]
+        own = op is None
+        if own:
+            op = mobius.Operator(dims, Ls, M5, mf, b5, c5, links.detach().contiguous())
         try:
             S, g_links, g_phi, info, rc = op.force(phi.detach().contiguous(), tol=tol,
-                                                   maxiter=maxiter, inner_prec=inner_prec)
+                                                   maxiter=maxiter, inner_prec=inner_prec,
+                                                   link_grad=want_links)
         finally:
-            op.close()
+            if own:
+                op.close()
         if rc != mobius.OK:
             raise mobius.MobiusError(f"force solve did not converge: {info}")
-        ctx.save_for_backward(g_links, g_phi)
+        ctx.save_for_backward(g_links if want_links else None, g_phi)
         ctx.info = info
         return torch.tensor(S, dtype=torch.float64, device=links.device)
 
@@ -40,10 +46,13 @@ class MobiusAction(torch.autograd.Function):
         g_links, g_phi = ctx.saved_tensors
         gl = grad_out * g_links if ctx.needs_input_grad[0] else None
         gp = grad_out * g_phi if ctx.needs_input_grad[1] else None
-        return gl, gp, None, None, None, None, None, None, None, None, None
+        return gl, gp, None, None, None, None, None, None, None, None, None, None
 
 
-def action(links, phi, dims, Ls, M5, mf, b5, c5, tol=1e-12, maxiter=20000, inner_prec=mobius.F64):
-    """Differentiable S(U, phi) (a float64 scalar tensor on the links' device)."""
+def action(links, phi, dims, Ls, M5, mf, b5, c5, tol=1e-12, maxiter=20000, inner_prec=mobius.F64,
+           op=None):
+    """Differentiable S(U, phi) (a float64 scalar tensor on the links' device).
+    op: an existing mobius.Operator built on these same links and parameters
+    (saves packing the links again); None builds one for the call."""
     return MobiusAction.apply(links, phi, tuple(dims), int(Ls), float(M5), float(mf), float(b5),
-                              float(c5), float(tol), int(maxiter), int(inner_prec))
+                              float(c5), float(tol), int(maxiter), int(inner_prec), op)

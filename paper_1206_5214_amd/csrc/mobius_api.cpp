@@ -72,25 +72,6 @@ int check_prec(int prec)
 
 hipStream_t S(void *stream) { return static_cast<hipStream_t>(stream); }
 
-// MOBIUS_DEBUG=1 prints the CG scalars of every iteration to stderr.
-int debug_level()
-{
-    static const int lvl = [] {
-        const char *e = std::getenv("MOBIUS_DEBUG");
-        return e ? std::atoi(e) : 0;
-    }();
-    return lvl;
-}
-
-// Reduction workspace large enough for a hop-kernel norm and a BLAS norm.
-int ensure_partials(mobius_ctx *ctx, int nrhs)
-{
-    int64_t n = std::max(site_kernel_blocks(ctx->g), blas_blocks(ctx->g)) * std::max(nrhs, 1);
-    HIPCHK(ctx->partials.ensure(n * (int64_t)sizeof(double)));
-    HIPCHK(ctx->scalars.ensure(64 * (int64_t)sizeof(double) * std::max(nrhs, 1)));
-    return MOBIUS_OK;
-}
-
 // Bricked site order (see mobius_internal.h): columns of bx x by x bz sites
 // over all t, columns x fastest, inside a column x, y, z, then t.
 void site_order(const Geometry &g, std::vector<int32_t> &canon_of, std::vector<int32_t> &packed_of)
@@ -366,6 +347,17 @@ int dslash_common(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
     case MOBIUS_OP_M5:
         HIPCHK(launch_m5(ctx->g, ctx->c, prec, 0, dag, in, out, nrhs, st));
         return MOBIUS_OK;
+    case MOBIUS_OP_FULL: {
+        // in, out: the nrhs even fields followed by the nrhs odd fields;
+        // out_p = D_{p,1-p} in_{1-p} + I in_p (daggered blocks for the adjoint)
+        const int64_t fb = field_bytes(ctx->g, prec) * nrhs;
+        const char *ie = static_cast<const char *>(in), *io = ie + fb;
+        char *oe = static_cast<char *>(out), *oo = oe + fb;
+        if (oe < io + fb && ie < oo + fb) return fail(MOBIUS_EINVAL, "in and out overlap");
+        HIPCHK(hop(ctx, hop_args(prec, dag, EPI_M5ADD, 0, io, oe, nullptr, ie, nullptr, nrhs), st));
+        HIPCHK(hop(ctx, hop_args(prec, dag, EPI_M5ADD, 1, ie, oo, nullptr, io, nullptr, nrhs), st));
+        return MOBIUS_OK;
+    }
     case MOBIUS_OP_SCHUR: {
         if (out_parity != 1) return fail(MOBIUS_EINVAL, "SCHUR acts on the odd parity (out_parity = 1)");
         const int64_t fb = field_bytes(ctx->g, prec) * nrhs;
@@ -499,7 +491,7 @@ extern "C" int mobius_force(mobius_ctx *ctx, const void *phi, void *grad_links, 
 {
     g_err.clear();
     if (int r = check_ctx(ctx)) return r;
-    if (!phi || !grad_links || !grad_phi || !action || !opts || !info)
+    if (!phi || !grad_phi || !action || !opts || !info)
         return fail(MOBIUS_EINVAL, "null argument to mobius_force");
     if (opts->nrhs > 1) return fail(MOBIUS_EINVAL, "mobius_force takes one source (nrhs <= 1)");
     if (ctx->has_mu) return fail(MOBIUS_EINVAL, "mobius_force: no chemical potential (mu must be 0)");

@@ -83,7 +83,7 @@ struct HopPattern {
 enum HopPid { HP_D0A, HP_D0B, HP_D1B, HP_D1C, HP_H0A, HP_H0B, HP_D1Q, HP_N64B, HP_N64C, NHOP };
 enum VecPid { VP_CONV_RH_R, VP_ACC, VP_RES, VP_HOPRED, VP_BLASRED, VP_NORM_B,
               VP_NORM_EE, VP_NORM_EO, VP_CONV_B_RH, VP_XR_N, VP_PUPD_N, VP_RES_N, VP_DOT_B_XH,
-              VP_TWO_XH, VP_PUPD_X, VP_XFLUSH, VP_RUPD, VP_NORM_Q, VP_NORM_S, VP_NORM_T64, VP_NORM_Q64, VP_DBG_R, VP_DBG_P, VP_DBG_Q, VP_DBG_S, VP_DBG_T, VP_DBG_U, VP_DBG_X,
+              VP_TWO_XH, VP_PUPD_X, VP_XFLUSH, VP_RUPD, VP_NORM_Q, VP_NORM_S, VP_NORM_T64, VP_NORM_Q64,
               NVEC };
 
 // Outputs of a force evaluation (normal-equations mode, one system).
@@ -120,14 +120,8 @@ struct Batch {
     bool normal = false;
     // accounting (count_only: account a graph replay without launching)
     bool count_only = false;
-    bool trace = false;  // print field norms after every step of body() (eager launches only)
-    // The hop kernels fuse |out|^2 partial sums into their epilogue only when a
-    // workgroup handles one output block of one system (one lattice, one
-    // right-hand side).  With several right-hand sides per workgroup, the fused
-    // sums left corrupted FP16 outputs for some systems on 12^4 and larger
-    // lattices (found by tracing the field norms of each step; the same
-    // kernels without the fused sum, or one launch per right-hand side, are
-    // exact), so there the norms come from a separate reduction pass.
+    // |out|^2 partial sums fused into the epilogue of the hops that produce q
+    // and s (false: the hop without them, then a separate norm pass)
     bool fused_norm = true;
 
     int dirac = 0;
@@ -180,7 +174,6 @@ struct Batch {
     hipError_t reliable_update();        // x_hi += x, r = b - D x_hi (FP64), r_lo = r
     hipError_t finalize_group(const Group &g);
     int fetch(std::vector<double> &out, int which);
-    int debug_norms(const char *where);  // |field|^2 of every lo-precision field, every system
     void acct_hop(int prec, int epi, double fields, double n5);
 };
 
@@ -341,12 +334,6 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
             h_vec[(size_t)VP_NORM_T64 * nsys + j] = t;
             t = v; t.a = F(F_Q64);
             h_vec[(size_t)VP_NORM_Q64 * nsys + j] = t;
-            const Field dbg[] = {F_R, F_P, F_Q, F_S, F_T, F_U, F_X};
-            for (int q = 0; q < 7; ++q) {
-                t = v;
-                t.a = F(dbg[q]);
-                h_vec[(size_t)(VP_DBG_R + q) * nsys + j] = t;
-            }
         }
     h_active.assign(nsys, 1);
     h_restart.assign(nsys, 1);
@@ -452,6 +439,10 @@ hipError_t Batch::vec(int pid, int kind, int prec, int prec2, bool all)
     case VEC_CONVERT: abytes += fb + fb2; break;
     case VEC_ACCUMULATE: abytes += 2 * fb + 2 * sum_fb(MOBIUS_F64, true); aflops += 24 * n5; break;
     case VEC_DOT: abytes += 2 * fb; aflops += 48 * n5; break;
+    // x (prec2) += alpha p, p = s + beta p: reads s, p, x; writes p, x
+    case VEC_PUPD_X: abytes += 3 * fb + 2 * fb2; aflops += 96 * n5; break;
+    // x (prec2) += alpha p: reads p, x; writes x
+    case VEC_XFLUSH: abytes += fb + 2 * fb2; aflops += 48 * n5; break;
     }
     if (count_only) return hipSuccess;
     return launch_vec_batch(kind, prec, prec2, vec_tab + (size_t)pid * nsys, nsys, max_n5,
@@ -490,28 +481,17 @@ hipError_t Batch::body()
 {
     hipError_t e;
     dirac += 4;
-#define MOBIUS_TRACE(W) \
-    if (trace && debug_norms(W) != MOBIUS_OK) return hipErrorUnknown;
-    MOBIUS_TRACE("start")
     if ((e = hop(HP_D1B)) != hipSuccess) return e;
-    MOBIUS_TRACE("D1B")
     if ((e = hop(HP_D1C)) != hipSuccess) return e;
     if ((e = reduce(norm_red(), &sc[0].gamma_new, SC_STRIDE)) != hipSuccess) return e;
-    MOBIUS_TRACE("D1C")
     if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 1, active, restart, st)) != hipSuccess) return e;
     if ((e = vec(VP_PUPD_X, VEC_PUPD_X, lo, px)) != hipSuccess) return e;
-    MOBIUS_TRACE("x,p-update")
     if ((e = hop(HP_D0A)) != hipSuccess) return e;
-    MOBIUS_TRACE("D0A")
     if ((e = hop(HP_D0B)) != hipSuccess) return e;
     if ((e = reduce(norm_red(), &sc[0].qq, SC_STRIDE)) != hipSuccess) return e;
-    MOBIUS_TRACE("D0B")
     if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 0, active, restart, st)) != hipSuccess) return e;
     if ((e = rupd()) != hipSuccess) return e;
-    if ((e = reduce(VP_RUPD, &sc[0].rr, SC_STRIDE)) != hipSuccess) return e;
-    MOBIUS_TRACE("r-update")
-#undef MOBIUS_TRACE
-    return hipSuccess;
+    return reduce(VP_RUPD, &sc[0].rr, SC_STRIDE);
 }
 
 // Normal equations, p = r + beta p;  q = D p (|q|^2 -> alpha);  s = D^+ q;
@@ -595,26 +575,6 @@ hipError_t Batch::finalize_group(const Group &g)
     return norms(VP_NORM_Q64, X_RES_O);
 }
 
-// diagnostic (MOBIUS_DEBUG >= 3, eager launches): |field|^2 of the Krylov
-// fields of every system after a step of the iteration
-int Batch::debug_norms(const char *where)
-{
-    static const char *names[] = {"r", "p", "q", "s", "t", "u", "x"};
-    for (int q = 0; q < 7; ++q) {
-        const int prec = q == 6 ? px : lo;
-        CK(launch_vec_batch(VEC_NORM2, prec, prec, vec_tab + (size_t)(VP_DBG_R + q) * nsys, nsys, max_n5,
-                            nullptr, st));
-        CK(launch_reduce_batch(vec_tab + (size_t)VP_BLASRED * nsys, nsys, nullptr, 0,
-                               &extra[X_ACTION], NEXTRA, st));
-        std::vector<double> n;
-        if (int rc = fetch(n, X_ACTION)) return rc;
-        std::fprintf(stderr, "[mobius] %s |%s|^2:", where, names[q]);
-        for (int j = 0; j < nsys; ++j) std::fprintf(stderr, " %.6e", n[j]);
-        std::fprintf(stderr, "\n");
-    }
-    return MOBIUS_OK;
-}
-
 // which: -1 = rr of every system, otherwise extra[which] of every system
 int Batch::fetch(std::vector<double> &out, int which)
 {
@@ -644,15 +604,17 @@ int force_pass(Batch &B, ForceOut &fo)
     const Geometry &G = g.ctx->g;
     const int32_t *nbr = static_cast<const int32_t *>(g.ctx->nbr.p);
     hipStream_t st = B.st;
-    B.dirac += 3;
-    CK(B.hop_group(g, MOBIUS_F64, 0, EPI_M5INV, 0, F_XH, F_PE, F_NONE, F_NONE, false));
-    CK(B.hop_group(g, MOBIUS_F64, 0, EPI_M5INV | EPI_POSTSUB, 1, F_PE, F_Q64, F_XH, F_NONE, false));
-    CK(launch_m5(G, g.ctx->c, MOBIUS_F64, 1, 1, g.f[F_Q64], g.f[F_U64], 1, st));
-    CK(B.hop_group(g, MOBIUS_F64, 1, EPI_M5INV, 0, F_U64, F_T64, F_NONE, F_NONE, false));
-    CK(launch_force(G, g.ctx->c, 1, nbr, g.f[F_U64], g.f[F_XH], g.f[F_T64], g.f[F_PE], fo.grad_links, st));
-    CK(launch_force(G, g.ctx->c, 0, nbr, g.f[F_T64], g.f[F_PE], g.f[F_U64], g.f[F_XH], fo.grad_links, st));
-    B.abytes += 2.0 * 4 * g.fb[F_XH] + 4.0 * G.V * 9 * 16;
-    B.aflops += 2.0 * G.N5 * 4 * (2 * 24 + 2 * 2 * 9 * 8 + 96);
+    if (fo.grad_links) {  // the link derivative (skipped when no link gradient is asked for)
+        B.dirac += 3;
+        CK(B.hop_group(g, MOBIUS_F64, 0, EPI_M5INV, 0, F_XH, F_PE, F_NONE, F_NONE, false));
+        CK(B.hop_group(g, MOBIUS_F64, 0, EPI_M5INV | EPI_POSTSUB, 1, F_PE, F_Q64, F_XH, F_NONE, false));
+        CK(launch_m5(G, g.ctx->c, MOBIUS_F64, 1, 1, g.f[F_Q64], g.f[F_U64], 1, st));
+        CK(B.hop_group(g, MOBIUS_F64, 1, EPI_M5INV, 0, F_U64, F_T64, F_NONE, F_NONE, false));
+        CK(launch_force(G, g.ctx->c, 1, nbr, g.f[F_U64], g.f[F_XH], g.f[F_T64], g.f[F_PE], fo.grad_links, st));
+        CK(launch_force(G, g.ctx->c, 0, nbr, g.f[F_T64], g.f[F_PE], g.f[F_U64], g.f[F_XH], fo.grad_links, st));
+        B.abytes += 2.0 * 4 * g.fb[F_XH] + 4.0 * G.V * 9 * 16;
+        B.aflops += 2.0 * G.N5 * 4 * (2 * 24 + 2 * 2 * 9 * 8 + 96);
+    }
     CK(B.vec(VP_DOT_B_XH, VEC_DOT, MOBIUS_F64, MOBIUS_F64, true));
     CK(B.reduce(VP_BLASRED, &B.extra[X_ACTION], NEXTRA, true));
     CK(B.vec(VP_TWO_XH, VEC_AXPBY, MOBIUS_F64, MOBIUS_F64, true));
@@ -682,8 +644,6 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
     const double delta = mixed ? (o.reliable_delta > 0 ? o.reliable_delta : delta_default) : 0.0;
     const int check = o.check_every > 0 ? o.check_every : (mixed ? 8 : 16);
     const bool use_graph = env_int("MOBIUS_GRAPH", 1) != 0;
-    const int debug_level = env_int("MOBIUS_DEBUG", 0);
-    const bool debug = debug_level != 0;
 
     Batch B;
     mobius_ctx *c0 = ctxs[0];
@@ -828,18 +788,7 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
             }
             CK(hipGraphLaunch(gexec, st));
         } else {
-            B.trace = debug_level > 2;
-            for (int q = 0; q < k; ++q) {
-                CK(B.normal ? B.body_normal() : B.body());
-                if (debug_level > 1) {  // every CG scalar of every system
-                    std::vector<CgScalars> h(nsys);
-                    CK(hipMemcpyAsync(h.data(), B.sc, sizeof(CgScalars) * nsys, hipMemcpyDeviceToHost, st));
-                    CK(hipStreamSynchronize(st));
-                    for (int j = 0; j < nsys; ++j)
-                        std::fprintf(stderr, "[mobius] it %d sys %d: gamma %.6e gamma_new %.6e beta %.6e qq %.6e alpha %.6e rr %.6e\n",
-                                     it + q + 1, j, h[j].gamma, h[j].gamma_new, h[j].beta, h[j].qq, h[j].alpha, h[j].rr);
-                }
-            }
+            for (int q = 0; q < k; ++q) CK(B.normal ? B.body_normal() : B.body());
         }
         it += k;
         for (int j = 0; j < nsys; ++j)
@@ -847,12 +796,6 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
 
         std::vector<double> rr;
         if (int rc = B.fetch(rr, -1)) return rc;
-        if (debug) {
-            std::fprintf(stderr, "[mobius] it %d:", it);
-            for (int j = 0; j < nsys; ++j)
-                if (B.h_active[j]) std::fprintf(stderr, " %d:%.3e", j, std::sqrt(rr[j] / bnorm2[j]));
-            std::fprintf(stderr, "\n");
-        }
         bool need_update = false;
         std::vector<int> upd(nsys, 0);
         for (int j = 0; j < nsys; ++j) {
@@ -924,7 +867,7 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
         mobius_solve_info &inf = info[j];
         std::memset(&inf, 0, sizeof(inf));
         inf.iters = iters[j];
-        inf.dirac_apps = B.normal ? 4 * iters[j] + 4 * reliable[j] + 3
+        inf.dirac_apps = B.normal ? 4 * iters[j] + 4 * reliable[j] + (fo->grad_links ? 3 : 0)
                                   : 1 + 4 * iters[j] + 2 * reliable[j] + 4;
         inf.reliable_updates = reliable[j];
         inf.status = converged[j] ? MOBIUS_OK : MOBIUS_NOT_CONVERGED;

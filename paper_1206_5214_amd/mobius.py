@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmobius.so")
 
 F64, F32, F16 = 0, 1, 2
 PREC = {"f64": F64, "f32": F32, "f16": F16}
-OP_HOP, OP_M5, OP_SCHUR = 0, 1, 2
+OP_HOP, OP_M5, OP_SCHUR, OP_FULL = 0, 1, 2, 3
 OK, NOT_CONVERGED = 0, 1
 
 EXPORTS = ("mobius_create", "mobius_destroy", "mobius_field_bytes", "mobius_pack",
@@ -212,6 +212,22 @@ class Operator:
                                  _stream()))
         return even, odd
 
+    def pack_full(self, canon, prec, nrhs=1):
+        """Pack a canonical field into one buffer holding its nrhs even halves
+        followed by its nrhs odd halves (the operand form of OP_FULL)."""
+        self._check_canon(canon, nrhs, "canonical field")
+        fb = self.field_bytes(prec) * nrhs
+        buf = self.new_field(prec, 2 * nrhs)
+        _check(lib().mobius_pack(self._h, prec, _ptr(canon), _ptr(buf), _ptr(buf[fb:]), nrhs,
+                                 _stream()))
+        return buf
+
+    def unpack_full(self, buf, prec, nrhs=1):
+        """Inverse of pack_full."""
+        fb = self.field_bytes(prec) * nrhs
+        self._check_packed(buf, prec, 2 * nrhs, "full field")
+        return self.unpack(buf[:fb], buf[fb:2 * fb], prec, nrhs)
+
     def unpack(self, even, odd, prec, nrhs=1):
         import torch
         self._check_packed(even, prec, nrhs, "even half")
@@ -224,11 +240,13 @@ class Operator:
 
     # -- operators -------------------------------------------------------
     def dslash(self, x, out_parity, prec, op=OP_HOP, dag=False, out=None, nrhs=1):
-        """Red/black block of D_DW (or D_DW^+) on packed fields; see mobius.h."""
+        """Red/black block of D_DW (or D_DW^+) on packed fields; see mobius.h.
+        For op=OP_FULL, x and out hold both halves (see pack_full)."""
+        nf = 2 * nrhs if op == OP_FULL else nrhs
         if out is None:
-            out = self.new_field(max(prec, 0) if prec in (F64, F32, F16) else F64, nrhs)
-        self._check_packed(x, prec, nrhs, "input")
-        self._check_packed(out, prec, nrhs, "output")
+            out = self.new_field(max(prec, 0) if prec in (F64, F32, F16) else F64, nf)
+        self._check_packed(x, prec, nf, "input")
+        self._check_packed(out, prec, nf, "output")
         f = lib().mobius_dslash_dag if dag else lib().mobius_dslash
         _check(f(self._h, prec, op, out_parity, _ptr(x), _ptr(out), nrhs, _stream()))
         return out
@@ -300,18 +318,21 @@ class Operator:
         _check(lib().mobius_set_tuning(self._h, ctypes.byref(r)))
 
     def force(self, phi, tol=1e-12, maxiter=20000, inner_prec=F64, reliable_delta=0.0,
-              check_every=0):
+              check_every=0, link_grad=True):
         """S = phi_o^+ (D_pre^+ D_pre)^-1 phi_o (phi canonical complex128, its odd
-        sites used) with dS/dU (canonical links layout) and dS/dphi = 2 X.
+        sites used) with dS/dU (canonical links layout; None when link_grad is
+        false, which skips the link-derivative pass) and dS/dphi = 2 X.
         Returns (S, grad_links, grad_phi, SolveInfo, rc)."""
         import torch
         self._check_canon(phi, 1, "phi")
-        grad_links = torch.empty(self.link_shape(), dtype=torch.complex128, device=phi.device)
+        grad_links = (torch.empty(self.link_shape(), dtype=torch.complex128, device=phi.device)
+                      if link_grad else None)
         grad_phi = torch.empty_like(phi)
         action = ctypes.c_double(0.0)
         opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, 1, check_every)
         info = _SolveInfo()
-        rc = _check(lib().mobius_force(self._h, _ptr(phi), _ptr(grad_links), _ptr(grad_phi),
+        gl = _ptr(grad_links) if grad_links is not None else ctypes.c_void_p(None)
+        rc = _check(lib().mobius_force(self._h, _ptr(phi), gl, _ptr(grad_phi),
                                        ctypes.byref(action), ctypes.byref(opts), ctypes.byref(info),
                                        _stream()))
         return action.value, grad_links, grad_phi, _info(info), rc

@@ -511,9 +511,30 @@ def pin_force_finite_difference(orc):
         assert abs((Sp - Sm) - want) < 1e-9 * abs(Sp), ("source gradient 2X", Sp - Sm, want)
 
 
+def pin_dw_sites(orc):
+    """D_DW (and D_DW^+) evaluated at a list of 4d sites equals the whole-lattice
+    D_DW at those sites, with the input taken as is or restricted to one parity
+    first (the restriction that turns D_DW into a hop block at sites of the other
+    parity): the site-sampled form used for checks at sizes where the whole
+    operator is too slow."""
+    from oracle import restrict
+    for dims, Ls, seed in [((4, 4, 4, 4), 6, 31), ((2, 2, 2, 4), 5, 32)]:
+        p, U, rng = _setup(dims, Ls, 1.75, 0.75, 0.03, seed=seed)
+        psi = inputs.gaussian_spinor(dims, Ls, rng)
+        V = p.V
+        sites = np.concatenate([[0, V - 1], rng.choice(V, 9, replace=False)])
+        for in_parity in (-1, 0, 1):
+            src = psi if in_parity < 0 else restrict(p, psi, in_parity)
+            for dag in (False, True):
+                full = orc.dw(p, U, src, dag=dag).reshape(Ls, V, 4, 3)
+                want = full[:, sites].transpose(1, 0, 2, 3)
+                got = orc.dw_sites(p, U, psi, sites, in_parity=in_parity, dag=dag)
+                assert _rel(got, want) < 1e-15, ("dw_sites", dims, in_parity, dag, _rel(got, want))
+
+
 ALL_PINS = [pin_wilson_free_symbol, pin_kernel_bound, pin_gauge_covariance,
             pin_wilson_gamma5_hermiticity, pin_adjoints, pin_free_determinant,
             pin_free_propagator, pin_gamma5_R_hermiticity, pin_m5_block, pin_schur_solve_dense,
             pin_rb_equals_unpreconditioned, pin_cgne_dense, pin_force_finite_difference,
             pin_propagator4d_free, pin_propagator4d_dense, pin_wilson_free_symbol_mu,
-            pin_adjoints_mu, pin_force_lie]
+            pin_adjoints_mu, pin_force_lie, pin_dw_sites]

@@ -134,10 +134,19 @@ def test_autograd_action(torch_cuda):
     assert abs(S.item() - S2) <= 1e-12 * abs(S2)
     assert torch.allclose(Ul.grad, 3.0 * G, rtol=0, atol=1e-12 * G.abs().max().item())
     assert torch.allclose(ph.grad, 3.0 * gphi, rtol=0, atol=1e-12 * gphi.abs().max().item())
-    # phi only: the links need no gradient
+    # phi only: the links need no gradient, so the link-derivative pass is
+    # skipped (an existing operator on the same links is reused)
+    op = mobius.Operator(dims, Ls, 1.8, 0.05, 1.5, 0.5, U)
     ph2 = phi.clone().requires_grad_(True)
-    autograd.action(U, ph2, dims, Ls, 1.8, 0.05, 1.5, 0.5).backward()
+    S3 = autograd.action(U, ph2, dims, Ls, 1.8, 0.05, 1.5, 0.5, op=op)
+    S3.backward()
     assert torch.allclose(ph2.grad, gphi, rtol=0, atol=1e-10 * gphi.abs().max().item())
+    assert abs(S3.item() - S2) <= 1e-10 * abs(S2)
+    S4, G4, gphi4, info4, rc = op.force(phi, tol=1e-12, link_grad=False)
+    assert rc == mobius.OK and G4 is None
+    assert S4 == S2 and torch.equal(gphi4, gphi)
+    assert info4.dirac_apps == info.dirac_apps - 3
+    op.close()
 
 
 @pytest.mark.parametrize("inner", [1, 2], ids=["mixed_f32", "mixed_f16"])

@@ -11,6 +11,8 @@ import sys
 import numpy as np
 import pytest
 
+from parity import check
+
 pytestmark = pytest.mark.gpu
 
 TOL = {0: 1e-12, 1: 2e-5, 2: 4e-3}  # as the operator parity tests
@@ -73,9 +75,8 @@ def test_hop_full_size_sampled(torch_cuda, orc, workload, prec):
             got_s = got.reshape(p.Ls, p.V, 4, 3)[:, sites].transpose(1, 0, 2, 3)
             # D_DW at those sites with the input zero on their own parity = the hop block
             want = orc.dw_sites(p, U, eta, sites, in_parity=1 - outp, dag=dag)
-            err = float(np.abs(got_s - want).max() / np.abs(want).max())
-            _flush(f"  out parity {outp} dag {dag}: {len(sites)} sites, err {err:.2e}")
-            assert err < TOL[prec], (outp, dag, err)
+            g, s = check(got_s, want, TOL[prec], (outp, dag))
+            _flush(f"  out parity {outp} dag {dag}: {len(sites)} sites, err {g:.2e} (per site {s:.2e})")
             del got, out
 
 

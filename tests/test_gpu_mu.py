@@ -7,6 +7,8 @@ import sys
 import numpy as np
 import pytest
 
+from parity import check
+
 pytestmark = pytest.mark.gpu
 
 TOL = {0: 1e-12, 1: 2e-5, 2: 4e-3}  # as the operator parity tests
@@ -22,10 +24,6 @@ def torch_cuda():
     import torch
     assert torch.cuda.is_available(), "GPU tests need an MI355X"
     return torch
-
-
-def _relmax(a, b):
-    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
 def _rel(a, b):
@@ -59,14 +57,13 @@ def test_hop_and_schur_with_mu(torch_cuda, orc, mu, prec):
         for outp in (0, 1):
             out = op.dslash(halves[1 - outp], outp, prec, dag=dag)
             got = op.unpack(out if outp == 0 else zero, zero if outp == 0 else out, prec).cpu().numpy()
-            err = _relmax(got, orc.hop(p, U, psi, outp, dag=dag))
-            assert err < TOL[prec], ("hop", dag, outp, err)
+            check(got, orc.hop(p, U, psi, outp, dag=dag), TOL[prec], ("hop", dag, outp))
     psi_o = restrict(p, psi, 1)
     e, o = op.pack(torch.from_numpy(psi_o).cuda(), prec)
     for dag in (False, True):
         got = op.unpack(zero, op.dslash(o, 1, prec, op=mobius.OP_SCHUR, dag=dag), prec).cpu().numpy()
-        err = _relmax(got, orc.schur(p, U, psi_o, dag=dag))
-        assert err < TOL[prec] * (3 if prec == 2 else 1), ("schur", dag, err)
+        check(got, orc.schur(p, U, psi_o, dag=dag), TOL[prec] * (3 if prec == 2 else 1),
+              ("schur", dag))
     op.close()
 
 

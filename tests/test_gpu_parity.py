@@ -1,16 +1,22 @@
 """HIP path vs the FP64 CPU oracle, element by element, through the C ABI.
 
-Tolerances (max-abs difference relative to max |oracle|), derived from the
-arithmetic of one hop (a sum of ~100 products of O(1) numbers per output):
+Tolerances, derived from the arithmetic of one hop (a sum of ~100 products
+of O(1) numbers per output), each applied both to the max-abs difference over
+the field relative to max |oracle| and per 5d site relative to that site's own
+max |oracle| (tests/parity.py):
   FP64: 1e-12     (unit roundoff 1.1e-16 times the ~1e2 terms, with margin)
   FP32: 2e-5      (unit roundoff 6e-8 times ~1e2 terms, with margin)
   FP16 storage:   4e-3 of the site norm per stored value (binary16 unit roundoff
                   4.9e-4 on spinor and link storage, a few roundings deep)
+Besides Gaussian fields, the hop blocks and D_pre are checked on graded
+fields whose 5d site norms span six decades.
 """
 import sys
 
 import numpy as np
 import pytest
+
+from parity import check, graded
 
 pytestmark = pytest.mark.gpu
 
@@ -43,10 +49,6 @@ def _setup(torch, p, seed=3, eps=0.5):
     return U, psi, op
 
 
-def _relmax(a, b):
-    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
-
-
 CASES = [
     # dims, Ls, b5, c5, mf : several tiles, ragged tails, Ls not dividing 64
     ((4, 4, 4, 4), 8, 1.0, 0.0, 0.01),        # Shamir
@@ -76,8 +78,7 @@ def test_hop_blocks_vs_oracle(torch_cuda, orc, case, prec):
             out = op.dslash(halves[1 - outp], outp, prec, dag=dag)
             got = op.unpack(out if outp == 0 else zero, zero if outp == 0 else out, prec).cpu().numpy()
             want = orc.hop(p, U, psi, outp, dag=dag)
-            err = _relmax(got, want)
-            assert err < TOL[prec], (case, prec, dag, outp, err)
+            check(got, want, TOL[prec], (case, prec, dag, outp))
     op.close()
 
 
@@ -96,11 +97,11 @@ def test_m5_and_m5inv_vs_oracle(torch_cuda, orc, case, prec):
         me = op.dslash(even, 0, prec, op=mobius.OP_M5, dag=dag)
         mo = op.dslash(odd, 1, prec, op=mobius.OP_M5, dag=dag)
         got = op.unpack(me, mo, prec).cpu().numpy()
-        assert _relmax(got, orc.m5(p, U, psi, dag=dag)) < TOL[prec], ("m5", dag)
+        check(got, orc.m5(p, U, psi, dag=dag), TOL[prec], ("m5", dag))
         ie = op.m5inv(even, prec, dag=dag)
         io = op.m5inv(odd, prec, dag=dag)
         got = op.unpack(ie, io, prec).cpu().numpy()
-        assert _relmax(got, orc.m5inv(p, psi, dag=dag)) < TOL[prec], ("m5inv", dag)
+        check(got, orc.m5inv(p, psi, dag=dag), TOL[prec], ("m5inv", dag))
     op.close()
 
 
@@ -122,7 +123,65 @@ def test_schur_vs_oracle(torch_cuda, orc, case, prec):
         got = op.unpack(zero, out, prec).cpu().numpy()
         want = orc.schur(p, U, psi_o, dag=dag)
         tol = TOL[prec] * (3 if prec == 2 else 1)
-        assert _relmax(got, want) < tol, ("schur", dag, _relmax(got, want))
+        check(got, want, tol, ("schur", dag))
+    op.close()
+
+
+@pytest.mark.parametrize("case", CASES[:5], ids=[f"{c[0]}-Ls{c[1]}" for c in CASES[:5]])
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "f16"])
+def test_full_operator_vs_oracle(torch_cuda, orc, case, prec):
+    """MOBIUS_OP_FULL: the unpreconditioned D_DW(m) and D_DW(m)^+ on both packed
+    halves against the oracle's whole-lattice D_DW, one and two right-hand sides."""
+    from paper_1206_5214_amd import mobius
+    torch = torch_cuda
+    dims, Ls, b5, c5, mf = case
+    p = _params(dims, Ls, b5=b5, c5=c5, mf=mf)
+    _flush(f"full operator parity {case} prec={prec}")
+    U, psi, op = _setup(torch, p)
+    psi2 = np.stack([psi, graded(psi, np.random.default_rng(5))])
+    for nrhs, field in ((1, psi), (2, psi2)):
+        x = op.pack_full(torch.from_numpy(np.ascontiguousarray(field)).cuda(), prec, nrhs)
+        for dag in (False, True):
+            out = op.dslash(x, 0, prec, op=mobius.OP_FULL, dag=dag, nrhs=nrhs)
+            got = op.unpack_full(out, prec, nrhs).cpu().numpy()
+            want = np.stack([orc.dw(p, U, f, dag=dag) for f in (field if nrhs > 1 else [field])])
+            check(got.reshape(want.shape), want, TOL[prec], ("full", nrhs, dag))
+    # in and out overlap by one half: rejected before anything is launched
+    x = op.pack_full(torch.from_numpy(psi).cuda(), prec)
+    fb = op.field_bytes(prec)
+    assert mobius.lib().mobius_dslash(op._h, prec, mobius.OP_FULL, 0, mobius._ptr(x),
+                                      mobius._ptr(x[fb:]), 1, None) == -22
+    op.close()
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[4]], ids=["4^4-Ls8", "6x4x2x4-Ls12", "4x2x6x2-Ls16"])
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "f16"])
+def test_graded_field_vs_oracle(torch_cuda, orc, case, prec):
+    """Hop blocks (D and D^+, both parities) and D_pre (and D_pre^+) on a field
+    whose 5d site norms span six decades, per site against the oracle."""
+    from paper_1206_5214_amd import mobius
+    from oracle import restrict
+    torch = torch_cuda
+    dims, Ls, b5, c5, mf = case
+    p = _params(dims, Ls, b5=b5, c5=c5, mf=mf)
+    _flush(f"graded-field parity {case} prec={prec}")
+    U, psi, op = _setup(torch, p)
+    psi = graded(psi, np.random.default_rng(77))
+    even, odd = op.pack(torch.from_numpy(psi).cuda(), prec)
+    zero = op.new_field(prec)
+    halves = {0: even, 1: odd}
+    for dag in (False, True):
+        for outp in (0, 1):
+            out = op.dslash(halves[1 - outp], outp, prec, dag=dag)
+            got = op.unpack(out if outp == 0 else zero, zero if outp == 0 else out, prec).cpu().numpy()
+            check(got, orc.hop(p, U, psi, outp, dag=dag), TOL[prec], ("graded hop", dag, outp))
+    psi_o = restrict(p, psi, 1)
+    _, odd = op.pack(torch.from_numpy(psi_o).cuda(), prec)
+    for dag in (False, True):
+        out = op.dslash(odd, 1, prec, op=mobius.OP_SCHUR, dag=dag)
+        got = op.unpack(zero, out, prec).cpu().numpy()
+        check(got, orc.schur(p, U, psi_o, dag=dag), TOL[prec] * (3 if prec == 2 else 1),
+              ("graded schur", dag))
     op.close()
 
 
@@ -225,13 +284,13 @@ def test_site_orders_vs_oracle(torch_cuda, orc, brick, monkeypatch):
         assert torch.equal(op.unpack(even, odd, 0), canon) if prec == 0 else True
         zero = op.new_field(prec)
         got = op.unpack(op.dslash(odd, 0, prec), zero, prec).cpu().numpy()
-        assert _relmax(got, orc.hop(p, U, psi, 0)) < TOL[prec]
+        check(got, orc.hop(p, U, psi, 0), TOL[prec], ("hop", brick, prec))
         got = op.unpack(zero, op.dslash(even, 1, prec, dag=True), prec).cpu().numpy()
-        assert _relmax(got, orc.hop(p, U, psi, 1, dag=True)) < TOL[prec]
+        check(got, orc.hop(p, U, psi, 1, dag=True), TOL[prec], ("hop dag", brick, prec))
     psi_o = restrict(p, psi, 1)
     e, o = op.pack(torch.from_numpy(psi_o).cuda(), 0)
     got = op.unpack(op.new_field(0), op.dslash(o, 1, 0, op=mobius.OP_SCHUR), 0).cpu().numpy()
-    assert _relmax(got, orc.schur(p, U, psi_o)) < TOL[0]
+    check(got, orc.schur(p, U, psi_o), TOL[0], ("schur", brick))
     sol, info, rc = op.solve(canon, tol=1e-10)
     assert rc == mobius.OK
     res = np.linalg.norm(orc.dw(p, U, sol.cpu().numpy()) - psi) / np.linalg.norm(psi)

@@ -58,6 +58,10 @@ MUTANTS = [
      "orc_hop(p, U, 0, (double *)Yt, (double *)t, 0);"),
     ("force_odd_row_fields_swapped", "acc += hop_overlap(p, E, Yt, Z, &sites[j], 1, tmp, buf);",
      "acc += hop_overlap(p, E, W, Z, &sites[j], 1, tmp, buf);"),
+    ("dw_sites_mask_other_parity", "masked_copy(p, (const cplx *)ind, in_parity);",
+     "masked_copy(p, (const cplx *)ind, in_parity < 0 ? in_parity : 1 - in_parity);"),
+    ("dw_sites_adjoint_dropped", "dw_site(p, U, in, sites[k], tmp, dag, buf);",
+     "dw_site(p, U, in, sites[k], tmp, 0, buf);"),
     ("force_only_forward_site", "const int64_t sites[2] = {y, neighbour(p, y, mu, +1)};",
      "const int64_t sites[2] = {y, y};"),
 ]
