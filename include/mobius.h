@@ -82,6 +82,11 @@ typedef struct {
     double mu;    /* chemical potential (Sec. "Baryon current and Chemical Potential"): the
                      time-like hops of D_W carry e^{+mu} forward (x -> x + t) and e^{-mu}
                      backward; 0 = none; |mu| <= 10.  mobius_force requires mu = 0. */
+    const double *b5s, *c5s; /* optional HOST arrays of Ls per-slice coefficients b5(s), c5(s),
+                     s = 1..Ls, of the general operator of Sec. 2.1 (row s of D_DW holds
+                     D+(s) = b5(s) D_W + 1 and D-(s) = c5(s) D_W - 1; e.g. Zolotarev
+                     coefficients, Sec. 4.3); read by mobius_create only.  NULL: the
+                     constant b5 (c5) above; one NULL and one not: the NULL one constant. */
 } mobius_params;
 
 typedef struct {
@@ -95,6 +100,8 @@ typedef struct {
                               0.3 for FP16, 0.1 for FP32 */
     int32_t nrhs;          /* number of right-hand sides in src/sol (>= 1) */
     int32_t check_every;   /* iterations between host convergence checks (<= 0 selects 16) */
+    double err_tol;        /* > 0: also iterate until err_bound (below) <= err_tol, tightening
+                              the Schur target as needed; <= 0: the residual test alone */
 } mobius_solve_opts;
 
 typedef struct {
@@ -111,6 +118,12 @@ typedef struct {
                              re-reads, no index tables) */
     double flops;         /* floating-point operations by the same convention (hop: 1416 per
                              5d site, I^-1: 96, vector updates: their multiply-adds) */
+    double kappa;         /* estimate of the condition number of D_pre: sqrt(lambda_max /
+                             lambda_min) of the Lanczos tridiagonal of D_pre^+ D_pre that the CG
+                             coefficients define (extreme Ritz values; 0 if no iteration ran) */
+    double err_bound;     /* kappa * schur_resid: bound on ||psi_o - psi_o*|| / ||psi_o*|| of the
+                             odd half the CG iterates on (kappa^2 times the residual of the
+                             normal equations for mobius_force) */
 } mobius_solve_info;
 
 typedef struct mobius_ctx mobius_ctx;
@@ -119,7 +132,9 @@ typedef struct mobius_ctx mobius_ctx;
  * links_c128: device pointer to the canonical links (4*V*9 complex128); the
  * library packs them into context-owned storage (the caller may free its copy
  * after the stream has run).  Returns MOBIUS_EINVAL for odd or < 2 extents,
- * Ls outside [2, 64], M+ = 0, or a null pointer. */
+ * Ls outside [2, 64], a singular Ls-direction block I (M+(s) = 0 for some s,
+ * or a vanishing pivot of its cyclic elimination), a non-finite coefficient,
+ * or a null pointer. */
 int mobius_create(mobius_ctx **ctx, const mobius_params *params, const void *links_c128,
                   void *stream);
 

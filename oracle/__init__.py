@@ -37,7 +37,8 @@ def build(force: bool = True) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32 * 4), ("Ls", ctypes.c_int32), ("M5", ctypes.c_double),
                 ("mf", ctypes.c_double), ("b5", ctypes.c_double), ("c5", ctypes.c_double),
-                ("mu", ctypes.c_double)]
+                ("mu", ctypes.c_double), ("b5s", ctypes.POINTER(ctypes.c_double)),
+                ("c5s", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Info(ctypes.Structure):
@@ -95,8 +96,10 @@ def using(path):
 
 @dataclass(frozen=True)
 class Params:
-    """Operator parameters: dims (Lx,Ly,Lz,Lt), Ls, M5 (> 0), mf, b5, c5, and the
-    chemical potential mu (time-like hops carry e^{+-mu})."""
+    """Operator parameters: dims (Lx,Ly,Lz,Lt), Ls, M5 (> 0), mf, b5, c5, the
+    chemical potential mu (time-like hops carry e^{+-mu}), and optional
+    per-slice coefficients b5s, c5s (Ls values each, s = 1..Ls; they replace
+    b5, c5: the general operator of Sec. 2.1)."""
     dims: tuple
     Ls: int
     M5: float
@@ -104,10 +107,28 @@ class Params:
     b5: float
     c5: float
     mu: float = 0.0
+    b5s: tuple = None
+    c5s: tuple = None
 
     def c(self) -> _Params:
-        return _Params((ctypes.c_int32 * 4)(*self.dims), self.Ls, self.M5, self.mf, self.b5, self.c5,
-                       self.mu)
+        P = _Params((ctypes.c_int32 * 4)(*self.dims), self.Ls, self.M5, self.mf, self.b5, self.c5,
+                    self.mu)
+        if self.b5s is not None or self.c5s is not None:
+            b = self.b5s if self.b5s is not None else (self.b5,) * self.Ls
+            c = self.c5s if self.c5s is not None else (self.c5,) * self.Ls
+            assert len(b) == self.Ls and len(c) == self.Ls
+            P._keep = ((ctypes.c_double * self.Ls)(*b), (ctypes.c_double * self.Ls)(*c))
+            P.b5s = ctypes.cast(P._keep[0], ctypes.POINTER(ctypes.c_double))
+            P.c5s = ctypes.cast(P._keep[1], ctypes.POINTER(ctypes.c_double))
+        return P
+
+    def b5_at(self, s):
+        """b5 of slice s (0-based)."""
+        return self.b5s[s] if self.b5s is not None else self.b5
+
+    def c5_at(self, s):
+        """c5 of slice s (0-based)."""
+        return self.c5s[s] if self.c5s is not None else self.c5
 
     @property
     def V(self) -> int:
@@ -228,7 +249,7 @@ def propagator4d(p: Params, U, b4, tol=1e-12, maxiter=20000):
     b4 = _c128(b4)
     single = b4.ndim == 6
     bs = b4[None] if single else b4
-    pv = Params(p.dims, p.Ls, p.M5, 1.0, p.b5, p.c5, p.mu)
+    pv = Params(p.dims, p.Ls, p.M5, 1.0, p.b5, p.c5, p.mu, p.b5s, p.c5s)
     qs, infos = [], []
     for b in bs:
         wall = np.zeros(p.shape5(), complex)

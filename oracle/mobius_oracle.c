@@ -177,6 +177,11 @@ void orc_wilson(const orc_params *p, const double *Ud, const double *ind, double
 /* ------------------------------------------------------------------------ */
 /* 5d Moebius operator                                                       */
 
+/* Coefficients of row s (0-based) of D_DW: b5(s), c5(s) of the general operator
+ * of Sec. 2.1 when per-slice values are given, else the constant ones. */
+static double b5_of(const orc_params *p, int s) { return p->b5s ? p->b5s[s] : p->b5; }
+static double c5_of(const orc_params *p, int s) { return p->c5s ? p->c5s[s] : p->c5; }
+
 /* chiral projection of a 4d site vector: keep components of chirality `chi` */
 static void chiral_part(const cplx *w, int chi, double scale, cplx *acc)
 {
@@ -193,8 +198,9 @@ static void chiral_part(const cplx *w, int chi, double scale, cplx *acc)
  * D_W is needed on in_s and on the mixed slice w_s at x; they are evaluated
  * with wilson_site on full slices built on the fly.
  *
- * Adjoint: (D^+)_{s,s'} = (D_{s',s})^+.  With y_s = D-^+ in_s:
- *   out_s = D+^+ in_s + P- y_{s-1} + P+ y_{s+1}   (wraps carry -m). */
+ * Adjoint: (D^+)_{s,s'} = (D_{s',s})^+.  With y_s = D-(s)^+ in_s (the
+ * coefficient of the row the coupling came from):
+ *   out_s = D+(s)^+ in_s + P- y_{s-1} + P+ y_{s+1}   (wraps carry -m). */
 static void dw_site(const orc_params *p, const cplx *U, const cplx *in, int64_t x, cplx *out,
                     int dag, cplx *slice_buf /* [V][12] scratch */)
 {
@@ -213,7 +219,7 @@ static void dw_site(const orc_params *p, const cplx *U, const cplx *in, int64_t 
         const cplx *ins = in + (int64_t)s * V * SITE_DOF;
         /* diagonal block D+ (or D+^+) */
         wilson_site(p, U, ins, x, t1, dag);
-        for (int k = 0; k < SITE_DOF; ++k) o[k] = p->b5 * t1[k] + ins[x * SITE_DOF + k];
+        for (int k = 0; k < SITE_DOF; ++k) o[k] = b5_of(p, s) * t1[k] + ins[x * SITE_DOF + k];
         if (!dag) {
             /* mixed slice w = P- in_{s+1} + P+ in_{s-1}, needed at the 9 sites */
             int sp1 = (s + 1) % Ls, sm1 = (s - 1 + Ls) % Ls;
@@ -227,7 +233,7 @@ static void dw_site(const orc_params *p, const cplx *U, const cplx *in, int64_t 
             }
             wilson_site(p, U, slice_buf, x, t2, 0);
             for (int k = 0; k < SITE_DOF; ++k)
-                o[k] += p->c5 * t2[k] - slice_buf[x * SITE_DOF + k];
+                o[k] += c5_of(p, s) * t2[k] - slice_buf[x * SITE_DOF + k];
         } else {
             /* y_{s-1} contributes its P- part, y_{s+1} its P+ part */
             int sm1 = (s - 1 + Ls) % Ls, sp1 = (s + 1) % Ls;
@@ -236,11 +242,11 @@ static void dw_site(const orc_params *p, const cplx *U, const cplx *in, int64_t 
             cplx y[SITE_DOF];
             wilson_site(p, U, in + (int64_t)sm1 * V * SITE_DOF, x, t2, 1);
             for (int k = 0; k < SITE_DOF; ++k)
-                y[k] = p->c5 * t2[k] - in[((int64_t)sm1 * V + x) * SITE_DOF + k];
+                y[k] = c5_of(p, sm1) * t2[k] - in[((int64_t)sm1 * V + x) * SITE_DOF + k];
             chiral_part(y, -1, fm1, o);
             wilson_site(p, U, in + (int64_t)sp1 * V * SITE_DOF, x, t2, 1);
             for (int k = 0; k < SITE_DOF; ++k)
-                y[k] = p->c5 * t2[k] - in[((int64_t)sp1 * V + x) * SITE_DOF + k];
+                y[k] = c5_of(p, sp1) * t2[k] - in[((int64_t)sp1 * V + x) * SITE_DOF + k];
             chiral_part(y, +1, fp1, o);
         }
     }
@@ -385,6 +391,89 @@ static void solve_A(const orc_params *p, double Mp, double Mm, const cplx *b, cp
     }
 }
 
+/* s-dependent coefficients (Sec. 2.1 with the red/black blocks of Sec. 3):
+ * the diagonal block of D_DW restricted to one chirality is an Ls x Ls cyclic
+ * bidiagonal matrix with d_s = M+(s) = b5(s) (4 - M5) + 1 on the diagonal and
+ * M-(s) = c5(s) (4 - M5) - 1 off it:
+ *   P-:  "upper" form, M-(s) at (s, s+1), -m M-(Ls) at (Ls, 1);
+ *   P+:  "lower" form, M-(s) at (s, s-1), -m M-(1) at (1, Ls);
+ * and the adjoint I^+ holds their transposes.  The elimination of Sec. 3
+ * carries over with the ratios taken row by row: for the upper form,
+ *   psi_1 = S + Q psi_Ls,  S = sum_{s<Ls} g_s b_s / d_s,  g_1 = 1,
+ *   g_{s+1} = -g_s e_s / d_s,  Q = g_Ls  (forward elimination),
+ *   psi_Ls = (b_Ls - k S) / (d_Ls + k Q)  (k the corner),
+ *   psi_s = (b_s - e_s psi_{s+1}) / d_s,  s = Ls-1, ..., 1  (back substitution);
+ * the lower form is its mirror image in s.  e[s] holds the off-diagonal
+ * element of row s (unused where the row has none). */
+static void solve_upper(int Ls, const double *d, const double *e, double k, const cplx *b, cplx *psi,
+                        int64_t st)
+{
+    cplx S = 0;
+    double g = 1.0;
+    for (int s = 0; s < Ls - 1; ++s) {
+        S += g * b[s * st] / d[s];
+        g *= -e[s] / d[s];
+    }
+    psi[(Ls - 1) * st] = (b[(Ls - 1) * st] - k * S) / (d[Ls - 1] + k * g);
+    for (int s = Ls - 2; s >= 0; --s) psi[s * st] = (b[s * st] - e[s] * psi[(s + 1) * st]) / d[s];
+}
+
+static void solve_lower(int Ls, const double *d, const double *e, double k, const cplx *b, cplx *psi,
+                        int64_t st)
+{
+    cplx S = 0;
+    double g = 1.0;
+    for (int s = Ls - 1; s > 0; --s) {
+        S += g * b[s * st] / d[s];
+        g *= -e[s] / d[s];
+    }
+    psi[0] = (b[0] - k * S) / (d[0] + k * g);
+    for (int s = 1; s < Ls; ++s) psi[s * st] = (b[s * st] - e[s] * psi[(s - 1) * st]) / d[s];
+}
+
+static void m5inv_general(const orc_params *p, const cplx *in, cplx *out, int dag)
+{
+    const int64_t V = vol4(p);
+    const int Ls = p->Ls;
+    double *Mp = (double *)malloc(sizeof(double) * Ls), *Mm = (double *)malloc(sizeof(double) * Ls);
+    double *em = (double *)malloc(sizeof(double) * Ls), *ep = (double *)malloc(sizeof(double) * Ls);
+    for (int s = 0; s < Ls; ++s) {
+        Mp[s] = b5_of(p, s) * (4.0 - p->M5) + 1.0;
+        Mm[s] = c5_of(p, s) * (4.0 - p->M5) - 1.0;
+    }
+    /* off-diagonal element of each row and the corner, per chirality */
+    double km, kp;
+    if (!dag) {  /* I:   P- upper (row s: M-(s)),   P+ lower (row s: M-(s)) */
+        for (int s = 0; s < Ls; ++s) em[s] = ep[s] = Mm[s];
+        km = -p->mf * Mm[Ls - 1];
+        kp = -p->mf * Mm[0];
+    } else {     /* I^+: P- lower (row s: M-(s-1)), P+ upper (row s: M-(s+1)) */
+        for (int s = 0; s < Ls; ++s) {
+            em[s] = s > 0 ? Mm[s - 1] : 0.0;
+            ep[s] = s < Ls - 1 ? Mm[s + 1] : 0.0;
+        }
+        km = -p->mf * Mm[Ls - 1];
+        kp = -p->mf * Mm[0];
+    }
+    const int64_t stride = V * SITE_DOF;
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < V; ++x)
+        for (int sp = 0; sp < NSPIN; ++sp)
+            for (int a = 0; a < NCOL; ++a) {
+                const int64_t off = x * SITE_DOF + sp * NCOL + a;
+                const int minus = chirality(sp) < 0;
+                const int upper = minus != dag;
+                if (upper)
+                    solve_upper(Ls, Mp, minus ? em : ep, minus ? km : kp, in + off, out + off, stride);
+                else
+                    solve_lower(Ls, Mp, minus ? em : ep, minus ? km : kp, in + off, out + off, stride);
+            }
+    free(Mp);
+    free(Mm);
+    free(em);
+    free(ep);
+}
+
 /* I^{-1} = A^{-1} P- + A^{-T} P+ (Sec. 3), with M+ = b5 (4 - M5) + 1 and
  * M- = c5 (4 - M5) - 1.  The adjoint I^{-+} = A^{-T} P- + A^{-1} P+ since A is
  * real.  Applied independently at every 4d site, spin and colour. */
@@ -392,6 +481,10 @@ void orc_m5inv(const orc_params *p, const double *ind, double *outd, int dag)
 {
     const cplx *in = (const cplx *)ind;
     cplx *out = (cplx *)outd;
+    if (p->b5s || p->c5s) {
+        m5inv_general(p, in, out, dag);
+        return;
+    }
     const int64_t V = vol4(p);
     const double Mp = p->b5 * (4.0 - p->M5) + 1.0;
     const double Mm = p->c5 * (4.0 - p->M5) - 1.0;

@@ -24,10 +24,10 @@
  *    the sign).  Periodic in all four directions.
  *  - Chiral gamma basis: g_k = [[0,-i s_k],[i s_k,0]], g_4 = [[0,1],[1,0]],
  *    g5 = g1 g2 g3 g4 = diag(1,1,-1,-1); P+ = spins {0,1}, P- = spins {2,3}.
- *  - D_DW(m): the Ls x Ls tridiagonal block matrix of Sec. 2.1 (eq. MoebiusOp)
- *    with constant b5, c5: D+ = b5 D_W + 1 on the diagonal, D- P- on the
- *    super-diagonal, D- P+ on the sub-diagonal, -m D- P+ at (1,Ls) and
- *    -m D- P- at (Ls,1), D- = c5 D_W - 1.
+ *  - D_DW(m): the Ls x Ls tridiagonal block matrix of Sec. 2.1 (eq. MoebiusOp):
+ *    row s holds D+(s) = b5(s) D_W + 1 on the diagonal, D-(s) P- at (s,s+1),
+ *    D-(s) P+ at (s,s-1), -m D-(1) P+ at (1,Ls) and -m D-(Ls) P- at (Ls,1),
+ *    D-(s) = c5(s) D_W - 1 (constant b5, c5 unless per-slice values are given).
  */
 #ifndef MOBIUS_ORACLE_H
 #define MOBIUS_ORACLE_H
@@ -46,6 +46,10 @@ typedef struct {
     double  b5, c5; /* Moebius coefficients, constant in s */
     double  mu;     /* chemical potential: time-like hops carry e^{+mu} (forward) and
                        e^{-mu} (backward) (Sec. "Baryon current and Chemical Potential") */
+    const double *b5s, *c5s; /* optional per-slice coefficients b5(s), c5(s), s = 1..Ls
+                       (Ls values each; the general operator of Sec. 2.1 with
+                       D+(s) = b5(s) D_W + 1, D-(s) = c5(s) D_W - 1); NULL: the
+                       constant b5, c5 above */
 } orc_params;
 
 typedef struct {
@@ -78,7 +82,8 @@ void orc_hop(const orc_params *p, const double *U, int out_parity, const double 
 /* Diagonal block I (= I_rr = I_bb), applied on both parities. */
 void orc_m5(const orc_params *p, const double *U, const double *in, double *out, int dag);
 
-/* I^{-1} (dag = 0) or I^{-+} (dag = 1) by the closed-form elimination of Sec. 3. */
+/* I^{-1} (dag = 0) or I^{-+} (dag = 1) by the closed-form elimination of Sec. 3
+ * (constant coefficients) or its O(Ls) generalisation to s-dependent ones. */
 void orc_m5inv(const orc_params *p, const double *in, double *out, int dag);
 
 /* Schur complement D_pre = 1 - I^{-1} D_oe I^{-1} D_eo on the odd parity

@@ -54,7 +54,40 @@ OpCoeffs make_coeffs(const mobius_params &p)
     c.mu = p.mf * c.a;
     c.inv_Mp = 1.0 / c.Mp;
     c.inv_den = 1.0 / (c.Mp * (1.0 - c.mu * std::pow(-c.a, p.Ls - 1)));
+    c.ls = nullptr;
     return c;
+}
+
+// Per-slice table of the general operator (Sec. 2.1) from the caller's
+// b5(s), c5(s); false if the Ls-direction block is singular: some M+(s) = 0,
+// or a vanishing pivot d + k g of the cyclic elimination of either chirality
+// (the product g of the row ratios -M-(t)/M+(t) over the Ls-1 rows, the same
+// for I and its transpose), for the quark mass and for the Pauli-Villars mass 1.
+bool ls_table(const mobius_params &p, std::vector<double> &tab)
+{
+    const int Ls = p.Ls;
+    tab.assign((size_t)Ls * LSC, 0.0);
+    for (int s = 0; s < Ls; ++s) {
+        const double b = p.b5s ? p.b5s[s] : p.b5, c = p.c5s ? p.c5s[s] : p.c5;
+        const double Mp = b * (4.0 - p.M5) + 1.0, Mm = c * (4.0 - p.M5) - 1.0;
+        if (!std::isfinite(b) || !std::isfinite(c) || Mp == 0.0) return false;
+        double *r = &tab[(size_t)s * LSC];
+        r[LS_B5] = b;
+        r[LS_C5] = c;
+        r[LS_MP] = Mp;
+        r[LS_MM] = Mm;
+        r[LS_INV_MP] = 1.0 / Mp;
+    }
+    for (double mf : {p.mf, 1.0}) {
+        double gu = 1.0, gl = 1.0;  // upper form: rows 0..Ls-2; lower form: rows Ls-1..1
+        for (int t = 0; t < Ls - 1; ++t) gu *= -tab[t * LSC + LS_MM] / tab[t * LSC + LS_MP];
+        for (int t = Ls - 1; t > 0; --t) gl *= -tab[t * LSC + LS_MM] / tab[t * LSC + LS_MP];
+        const double km = -mf * tab[(Ls - 1) * LSC + LS_MM], kp = -mf * tab[LS_MM];
+        const double pu = tab[(Ls - 1) * LSC + LS_MP] + km * gu;  // P- of I
+        const double pl = tab[LS_MP] + kp * gl;                   // P+ of I
+        if (!(std::isfinite(pu) && std::isfinite(pl)) || pu == 0.0 || pl == 0.0) return false;
+    }
+    return true;
 }
 
 int check_ctx(const mobius_ctx *ctx)
@@ -157,15 +190,24 @@ extern "C" int mobius_create(mobius_ctx **out, const mobius_params *p, const voi
         if (p->L[mu] < 2 || (p->L[mu] & 1))
             return fail(MOBIUS_EINVAL, "every lattice extent must be even and >= 2");
     if (p->Ls < 2 || p->Ls > 64) return fail(MOBIUS_EINVAL, "Ls must be in [2, 64]");
-    const double Mp = p->b5 * (4.0 - p->M5) + 1.0;
-    if (Mp == 0.0) return fail(MOBIUS_EINVAL, "M+ = b5 (4 - M5) + 1 is zero");
-    const OpCoeffs c = make_coeffs(*p);
-    if (!std::isfinite(c.inv_den)) return fail(MOBIUS_EINVAL, "the Ls-direction block I is singular");
+    const bool sdep = p->b5s || p->c5s;
+    std::vector<double> tab;
+    if (sdep) {
+        if (!ls_table(*p, tab)) return fail(MOBIUS_EINVAL, "the Ls-direction block I is singular "
+                                                           "or a per-slice coefficient is not finite");
+    } else {
+        const double Mp = p->b5 * (4.0 - p->M5) + 1.0;
+        if (Mp == 0.0) return fail(MOBIUS_EINVAL, "M+ = b5 (4 - M5) + 1 is zero");
+    }
+    OpCoeffs c = make_coeffs(*p);
+    if (!sdep && !std::isfinite(c.inv_den)) return fail(MOBIUS_EINVAL, "the Ls-direction block I is singular");
     if (!std::isfinite(p->mu) || std::fabs(p->mu) > 10.0)
         return fail(MOBIUS_EINVAL, "the chemical potential must be finite with |mu| <= 10");
 
     mobius_ctx *ctx = new mobius_ctx();
     ctx->P = *p;
+    ctx->P.b5s = ctx->P.c5s = nullptr;  // the caller's arrays are not kept
+    ctx->sdep = sdep;
     ctx->c = c;
     ctx->has_mu = p->mu != 0.0;
     Geometry &g = ctx->g;
@@ -188,6 +230,13 @@ extern "C" int mobius_create(mobius_ctx **out, const mobius_params *p, const voi
     };
     hipError_t e = hipGetDevice(&ctx->device);
     if (e != hipSuccess) return cleanup(fail(MOBIUS_EHIP, hipGetErrorString(e)));
+    if (sdep) {
+        e = ctx->ls_coef.ensure((int64_t)(tab.size() * sizeof(double)));
+        if (e == hipSuccess)
+            e = hipMemcpy(ctx->ls_coef.p, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return cleanup(fail(MOBIUS_EHIP, hipGetErrorString(e)));
+        ctx->c.ls = static_cast<const double *>(ctx->ls_coef.p);
+    }
     // site order and neighbour table
     choose_brick(g.L, g.Ls, g.brick);
     std::vector<int32_t> canon_of, packed_of;
@@ -244,6 +293,7 @@ extern "C" int mobius_destroy(mobius_ctx *ctx)
     ctx->partials.release();
     ctx->scalars.release();
     ctx->prop.release();
+    ctx->ls_coef.release();
     if (ctx->solve_stream) (void)hipStreamDestroy(ctx->solve_stream);
     delete ctx;
     return MOBIUS_OK;
@@ -452,7 +502,8 @@ extern "C" int mobius_propagator4d(mobius_ctx *ctx, const void *src4, void *sol4
     // out_p = D_{p,1-p} in_{1-p} + I in_p for both parities
     mobius_params pv = ctx->P;
     pv.mf = 1.0;
-    const OpCoeffs cpv = make_coeffs(pv);
+    OpCoeffs cpv = make_coeffs(pv);
+    cpv.ls = ctx->c.ls;  // per-slice coefficients do not depend on the mass
     const int32_t *nbr = static_cast<const int32_t *>(ctx->nbr.p);
     HopArgs a = hop_args(MOBIUS_F64, 0, EPI_M5ADD, 0, wo, de, nullptr, we, nullptr, nrhs);
     a.tune = &ctx->tune[MOBIUS_F64];

@@ -812,29 +812,59 @@ __device__ __forceinline__ SiteMap site_map(int Ls, int spw, int64_t Vh, int rem
 template <typename T>
 struct Coef {
     T b5, c5, mf, Mp, Mm, a, mu, inv_Mp, inv_den;
+    const double *ls;  // per-slice table (null: constant coefficients)
 };
 
 template <typename T>
 __device__ __forceinline__ Coef<T> make_coef(const OpCoeffs &c)
 {
     return {(T)c.b5, (T)c.c5, (T)c.mf, (T)c.Mp, (T)c.Mm, (T)c.a, (T)c.mu, (T)c.inv_Mp,
-            (T)c.inv_den};
+            (T)c.inv_den, c.ls};
+}
+
+// Weights of one lane of X + Y C5 (forward) or X + C5^+ Y (adjoint), with
+// (X, Y) = (b5, c5) for B or (M+, M-) for I: a is the lane's own X, bu and bl
+// the Y of the rows the P+ and P- parts belong to -- the lane's own row in
+// the forward form, the source rows s+1 and s-1 in the adjoint (Y is a
+// coefficient of the row of D_DW, so the adjoint carries it to the column).
+template <typename T>
+struct MixW {
+    T a, bu, bl;
+};
+
+template <typename T>
+__device__ __forceinline__ MixW<T> mix_w(const Coef<T> &k, bool minv, const SiteMap &m, int Ls,
+                                         bool adjoint)
+{
+    const T X = minv ? k.Mp : k.b5, Y = minv ? k.Mm : k.c5;
+    if (!k.ls) return {X, Y, Y};
+    const int ox = minv ? LS_MP : LS_B5;
+    const double *t = k.ls;
+    const T a = (T)t[m.s * LSC + ox];
+    if (!adjoint) {
+        const T y = (T)t[m.s * LSC + ox + 1];
+        return {a, y, y};
+    }
+    const int su = m.s == Ls - 1 ? 0 : m.s + 1, sl = m.s == 0 ? Ls - 1 : m.s - 1;
+    return {a, (T)t[su * LSC + ox + 1], (T)t[sl * LSC + ox + 1]};
 }
 
 // C5 mixing in s from the lanes of the same 4d site.
 //   forward  (C5 v)_s  = P+ v_{s-1} + P- v_{s+1}
 //   adjoint  (C5^+ v)_s = P+ v_{s+1} + P- v_{s-1}
-// wrapped neighbours carry -mf.  Returns alpha * v + beta * C5(^+) v.
+// wrapped neighbours carry -mf.  Returns w.a v + (w.bu P+ + w.bl P-) C5(^+) v
+// (alpha v + beta C5(^+) v for constant coefficients).
 template <typename T>
-__device__ __forceinline__ void mix_s(cx<T> v[12], T alpha, T beta, T mf, const SiteMap &m, int Ls,
+__device__ __forceinline__ void mix_s(cx<T> v[12], MixW<T> w, T mf, const SiteMap &m, int Ls,
                                       bool adjoint)
 {
     const int src_up = adjoint ? m.lp : m.lm;  // lane whose P+ part we take
     const int src_lo = adjoint ? m.lm : m.lp;  // lane whose P- part we take
     const bool wrap_up = adjoint ? (m.s == Ls - 1) : (m.s == 0);
     const bool wrap_lo = adjoint ? (m.s == 0) : (m.s == Ls - 1);
-    const T fu = beta * (wrap_up ? -mf : (T)1);
-    const T fl = beta * (wrap_lo ? -mf : (T)1);
+    const T alpha = w.a;
+    const T fu = w.bu * (wrap_up ? -mf : (T)1);
+    const T fl = w.bl * (wrap_lo ? -mf : (T)1);
     cx<T> up[6], lo[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -878,7 +908,56 @@ __device__ __forceinline__ void m5inv_lanes(cx<T> r[12], const Coef<T> &k, const
 #pragma unroll
     for (int c = 0; c < 12; ++c) w[lane * ST + c] = r[c];
     __syncthreads();
-    if (g * Ls + Ls <= 64) {
+    if (k.ls && g * Ls + Ls <= 64) {
+        // s-dependent coefficients: the cyclic bidiagonal form of each
+        // chirality (P-: M-(t) at (t, t+1) and -m M-(Ls) at (Ls, 1); P+: M-(t)
+        // at (t, t-1) and -m M-(1) at (1, Ls); transposed for I^+), solved by
+        // the same elimination with per-row ratios: the unknown at the far end
+        // from the running sum S and product g, then back-substitution.
+        const int base = g * Ls;
+        const double *tb = k.ls;
+        const T corner_m = -k.mf * (T)tb[(Ls - 1) * LSC + LS_MM];
+        const T corner_p = -k.mf * (T)tb[LS_MM];
+        for (int c = s0; c < 12; c += Ls) {
+            const bool minus = c >= 6;
+            const bool upper = minus != dag;
+            const T kc = minus ? corner_m : corner_p;
+            // off-diagonal element of row t: forward M-(t); adjoint M-(t-1)
+            // (P-) or M-(t+1) (P+)
+            const int sh = !dag ? 0 : (minus ? -1 : 1);
+            cx<T> S = {0, 0};
+            T gg = (T)1;
+            if (upper) {
+                for (int t = 0; t < Ls - 1; ++t) {
+                    const T id = (T)tb[t * LSC + LS_INV_MP], e = (T)tb[(t + sh) * LSC + LS_MM];
+                    S = S + (gg * id) * w[(base + t) * ST + c];
+                    gg = -gg * e * id;
+                }
+                const T dl = (T)tb[(Ls - 1) * LSC + LS_MP];
+                cx<T> psi = ((T)1 / (dl + kc * gg)) * (w[(base + Ls - 1) * ST + c] - kc * S);
+                w[(base + Ls - 1) * ST + c] = psi;
+                for (int t = Ls - 2; t >= 0; --t) {
+                    const T id = (T)tb[t * LSC + LS_INV_MP], e = (T)tb[(t + sh) * LSC + LS_MM];
+                    psi = id * (w[(base + t) * ST + c] - e * psi);
+                    w[(base + t) * ST + c] = psi;
+                }
+            } else {
+                for (int t = Ls - 1; t > 0; --t) {
+                    const T id = (T)tb[t * LSC + LS_INV_MP], e = (T)tb[(t + sh) * LSC + LS_MM];
+                    S = S + (gg * id) * w[(base + t) * ST + c];
+                    gg = -gg * e * id;
+                }
+                const T d0 = (T)tb[LS_MP];
+                cx<T> psi = ((T)1 / (d0 + kc * gg)) * (w[base * ST + c] - kc * S);
+                w[base * ST + c] = psi;
+                for (int t = 1; t < Ls; ++t) {
+                    const T id = (T)tb[t * LSC + LS_INV_MP], e = (T)tb[(t + sh) * LSC + LS_MM];
+                    psi = id * (w[(base + t) * ST + c] - e * psi);
+                    w[(base + t) * ST + c] = psi;
+                }
+            }
+        }
+    } else if (g * Ls + Ls <= 64) {
         const int base = g * Ls;
         for (int c = s0; c < 12; c += Ls) {
             const bool plus = c < 6;

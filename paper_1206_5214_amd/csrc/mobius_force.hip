@@ -61,7 +61,7 @@ __device__ __forceinline__ void force_dir(const ForceParams &fp, const SiteMap &
     cx<double> Ln[12], Rn[12];
     S::load(Buf(fp.Ln, fb), N5, jn, Ln);
     S::load(Buf(fp.Rn, fb), N5, jn, Rn);
-    mix_s(Rn, k.b5, k.c5, k.mf, m, fp.Ls, false);  // B R_{1-p}(y + mu)
+    mix_s(Rn, mix_w(k, false, m, fp.Ls, false), k.mf, m, fp.Ls, false);  // B R_{1-p}(y + mu)
 
     cx<double> hL[6], hR[6], c[9];
 #pragma unroll
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(BLOCK) void force_kernel(ForceParams fp)
     cx<double> Lo[12], BRo[12];
     S::load(Buf(fp.Lp, fb), N5, k5, Lo);
     S::load(Buf(fp.Rp, fb), N5, k5, BRo);
-    mix_s(BRo, k.b5, k.c5, k.mf, m, fp.Ls, false);  // B R_p(y)
+    mix_s(BRo, mix_w(k, false, m, fp.Ls, false), k.mf, m, fp.Ls, false);  // B R_p(y)
     const int32_t *nb = fp.nbr + m.i * 8;
     __shared__ ForceLds lds;
     force_dir<0>(fp, m, k, Lo, BRo, (uint32_t)nb[0] * (uint32_t)fp.Ls + (uint32_t)m.s, lds);

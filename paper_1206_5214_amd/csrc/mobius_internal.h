@@ -69,6 +69,10 @@ inline int link_elem_bytes(int prec)
     return prec == MOBIUS_F64 ? 16 : prec == MOBIUS_F32 ? 8 : 4;
 }
 
+// Per-slice coefficients of the general operator (Sec. 2.1): row s of the
+// device table holds LS_B5 .. LS_INV_MP.
+enum LsCoef { LS_B5 = 0, LS_C5 = 1, LS_MP = 2, LS_MM = 3, LS_INV_MP = 4, LSC = 5 };
+
 // Scalars of the operator, precomputed on the host.
 struct OpCoeffs {
     double b5, c5, mf;
@@ -77,6 +81,8 @@ struct OpCoeffs {
     double mu;          // mf * a
     double inv_Mp;      // 1 / M+
     double inv_den;     // 1 / (M+ (1 - mu (-a)^(Ls-1)))
+    const double *ls;   // device [Ls][LSC] per-slice b5(s), c5(s), M+(s), M-(s), 1/M+(s);
+                        // null: the constant coefficients above
 };
 
 // Epilogue program of the hop kernel, applied in this order to r = -1/2 H (B in):
@@ -192,39 +198,23 @@ hipError_t launch_m5(const Geometry &g, const OpCoeffs &c, int prec, int kind, i
 
 // BLAS-1 on packed half fields (storage precision prec), FP64 scalars in
 // device memory, FP64 partial sums per block (deterministic fixed-order
-// reduction in launch_reduce).
+// reduction in launch_reduce_batch).
 int64_t blas_blocks(const Geometry &g);
-// out = a * x + b * y   (a, b read from device scalars; null scalar = 1)
-hipError_t launch_axpby(const Geometry &g, int prec, const double *a, const void *x,
-                        const double *b, const void *y, void *out, int nrhs, hipStream_t st);
-// |x|^2 partials
-hipError_t launch_norm2(const Geometry &g, int prec, const void *x, double *partials, int nrhs,
-                        hipStream_t st);
-// CG update:  x += alpha p (x in precision prec_x);  r -= alpha q;  partials of |r|^2
-hipError_t launch_cg_xr(const Geometry &g, int prec, int prec_x, const double *alpha, void *x,
-                        const void *p, void *r, const void *q, double *partials, hipStream_t st);
-// precision conversion of a packed half field (also a plain copy when equal)
-hipError_t launch_convert(const Geometry &g, int prec_in, const void *in, int prec_out, void *out,
-                          hipStream_t st);
-// x_hi (F64) += x_lo (prec)
-hipError_t launch_accumulate(const Geometry &g, int prec_lo, const void *x_lo, void *x_hi,
-                             hipStream_t st);
 // fill with zeros (kernel, not hipMemset, so it is safe under graph capture)
 hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t st);
-// sum `n` partials in a fixed order into *out
-hipError_t launch_reduce(const double *partials, int64_t n, double *out, hipStream_t st);
-
-// Scalar updates of CGLS, on device (one thread):
+// Scalar updates of CGLS, on device (one thread per system):
 struct CgScalars {
     double gamma;      // |s|^2 of the current direction
     double qq;         // |q|^2
     double rr;         // |r|^2
     double gamma_new;
     double alpha, beta;
-    double scratch[10];
+    // Coefficient history for the Lanczos estimate of the condition number:
+    // hist[k] = (beta_{k-1}, alpha_k) of iteration k (beta_{k-1} = 0 at the
+    // first step of a Krylov segment), kept for the first hmax iterations.
+    double *hist;
+    int64_t nhist, hmax;
 };
-// op 0: alpha = gamma / qq;  op 1: beta = gamma_new / gamma, gamma = gamma_new
-hipError_t launch_cg_scalar(CgScalars *s, int op, hipStream_t st);
 
 // One system (one lattice, one right-hand side) of a batched vector kernel.
 // Field roles per kernel:
@@ -335,6 +325,8 @@ struct mobius_ctx {
     mobius::DevBuf partials;  // reduction partials
     mobius::DevBuf scalars;   // solver scalars, flags and descriptor tables
     mobius::DevBuf prop;      // 4d propagator temporaries (canonical and packed 5d fields)
+    mobius::DevBuf ls_coef;   // per-slice coefficient table [Ls][LSC] (s-dependent b5, c5)
+    bool sdep = false;        // the operator has per-slice coefficients
     hipStream_t solve_stream = nullptr;
     mobius::HopTuning tune[3];  // hop launch parameters per storage precision
     double tuned_us[3] = {0, 0, 0};  // hop time of the tuned parameters (0: not tuned)

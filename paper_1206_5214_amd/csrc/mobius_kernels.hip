@@ -114,10 +114,12 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
     // input already holds B in (written so by an EPI_BMIX epilogue)
     constexpr bool MIXIN = !DAG && (EPI & EPI_PREMIXED) == 0;
 
+    // B weights of this lane (per-slice b5(s), c5(s) when the operator has them)
+    const MixW<T> wB = mix_w(k, false, m, Ls, false);
     if constexpr (P == MOBIUS_F16) {
         // forward block: B mixing weights of this lane (norms folded in per direction)
-        const float wu = MIXIN ? (float)k.c5 * (m.s == 0 ? -(float)k.mf : 1.f) : 0.f;
-        const float wl = MIXIN ? (float)k.c5 * (m.s == Ls - 1 ? -(float)k.mf : 1.f) : 0.f;
+        const float wu = MIXIN ? (float)wB.bu * (m.s == 0 ? -(float)k.mf : 1.f) : 0.f;
+        const float wl = MIXIN ? (float)wB.bl * (m.s == Ls - 1 ? -(float)k.mf : 1.f) : 0.f;
         RawH nx;
         LinkH2 unx;
         load_raw_f16(bin, N5, jn[0], nx);
@@ -149,7 +151,7 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
                     um[c] = shfl_h2(o.c[c], m.lm);
                     lp[c] = shfl_h2(o.c[6 + c], m.lp);
                 }
-                al = (float)k.b5 * o.n;
+                al = (float)wB.a * o.n;
                 bu = wu * __shfl(o.n, m.lm, 64);
                 bl = wl * __shfl(o.n, m.lp, 64);
             } else {
@@ -204,7 +206,7 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
         }
         if constexpr (MIXIN) {
             // B = b5 + c5 C5 on the input: gather s-1, s, s+1 of the neighbour
-            mix_s(chi, k.b5, k.c5, k.mf, m, Ls, false);
+            mix_s(chi, wB, k.mf, m, Ls, false);
         }
         constexpr int SF = DAG ? +1 : -1;  // forward projector (1 -+ g_mu)
         switch (d) {
@@ -232,11 +234,11 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
     // coefficients of the epilogue, converted here so that none of them is
     // held in a register across the direction loop
     const Coef<T> k = make_coef<T>(hp.c);
-    if constexpr (DAG) mix_s(acc, k.b5, k.c5, k.mf, m, Ls, true);  // B^+ on the output
+    if constexpr (DAG) mix_s(acc, mix_w(k, false, m, Ls, true), k.mf, m, Ls, true);  // B^+ on the output
     if constexpr ((EPI & EPI_M5ADD) != 0) {
         cx<T> yv[12];
         S::load(Buf(yr, fbytes), N5, k5, yv);
-        mix_s(yv, k.Mp, k.Mm, k.mf, m, Ls, DAG);  // I y = M+ y + M- C5 y
+        mix_s(yv, mix_w(k, true, m, Ls, DAG), k.mf, m, Ls, DAG);  // I y = M+ y + M- C5 y
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] = acc[c] + yv[c];
     }
@@ -250,7 +252,7 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
         __shared__ M5Lds<T> lds;
         m5inv_lanes(acc, k, m, Ls, DAG, lds);
     }
-    if constexpr ((EPI & EPI_BMIX) != 0) mix_s(acc, k.b5, k.c5, k.mf, m, Ls, false);  // B r
+    if constexpr ((EPI & EPI_BMIX) != 0) mix_s(acc, mix_w(k, false, m, Ls, false), k.mf, m, Ls, false);  // B r
     if constexpr ((EPI & EPI_POSTSUB) != 0) {
         cx<T> xv[12];
         S::load(Buf(xr, fbytes), N5, k5, xv);
@@ -305,7 +307,7 @@ __global__ __launch_bounds__(BLOCK) void m5_kernel(const char *in, char *out, in
     cx<T> v[12];
     S::load(Buf(in, fbytes), (uint32_t)N5, k5, v);
     if constexpr (KIND == 0) {
-        mix_s(v, k.Mp, k.Mm, k.mf, m, Ls, DAG);
+        mix_s(v, mix_w(k, true, m, Ls, DAG), k.mf, m, Ls, DAG);
     } else {
         __shared__ M5Lds<T> lds;
         m5inv_lanes(v, k, m, Ls, DAG, lds);
@@ -484,106 +486,6 @@ __global__ __launch_bounds__(256) void unpack_spinor_kernel(int64_t Vh, int Ls,
 // BLAS-1 and reductions (one thread per site5)
 
 constexpr int BLAS_BLOCK = 256;
-
-template <int P>
-__global__ __launch_bounds__(BLAS_BLOCK) void axpby_kernel(int64_t N5, const double *a,
-                                                           const char *x, const double *b,
-                                                           const char *y, char *out)
-{
-    using S = Spin<P>;
-    using T = typename S::T;
-    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
-    if (k >= N5) return;
-    const T av = a ? (T)*a : (T)1, bv = b ? (T)*b : (T)1;
-    const int64_t fb = S::bytes(N5);
-    cx<T> xv[12], yv[12];
-    S::load(Buf(x, fb), (uint32_t)N5, (uint32_t)k, xv);
-    S::load(Buf(y, fb), (uint32_t)N5, (uint32_t)k, yv);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) xv[c] = av * xv[c] + bv * yv[c];
-    S::store(Buf(out, fb), (uint32_t)N5, (uint32_t)k, xv);
-}
-
-template <int P>
-__global__ __launch_bounds__(BLAS_BLOCK) void norm2_kernel(int64_t N5, const char *x,
-                                                           double *partials)
-{
-    using S = Spin<P>;
-    using T = typename S::T;
-    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
-    double n = 0;
-    if (k < N5) {
-        cx<T> v[12];
-        S::load(Buf(x, S::bytes(N5)), (uint32_t)N5, (uint32_t)k, v);
-        n = site_norm2(v);
-    }
-    block_sum_store(n, partials, blockIdx.x);
-}
-
-// x (precision PX) += alpha p;  r -= alpha q  (precision P);  partials of |r|^2.
-// The solution correction may be kept in a wider format than the Krylov
-// vectors so that small late updates are not lost to its rounding.
-template <int P, int PX>
-__global__ __launch_bounds__(BLAS_BLOCK) void cg_xr_kernel(int64_t N5, const double *alpha,
-                                                           char *x, const char *p, char *r,
-                                                           const char *q, double *partials)
-{
-    using S = Spin<P>;
-    using SX = Spin<PX>;
-    using T = typename S::T;
-    using TX = typename SX::T;
-    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
-    double n = 0;
-    if (k < N5) {
-        const T al = (T)*alpha;
-        const TX alx = (TX)*alpha;
-        const int64_t fb = S::bytes(N5);
-        const uint32_t n5 = (uint32_t)N5, kk = (uint32_t)k;
-        const Buf bx(x, SX::bytes(N5)), bp(p, fb), br(r, fb), bq(q, fb);
-        cx<TX> xv[12];
-        cx<T> pv[12], rv[12];
-        SX::load(bx, n5, kk, xv);
-        S::load(bp, n5, kk, pv);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) xv[c] = xv[c] + alx * cx<TX>{(TX)pv[c].r, (TX)pv[c].i};
-        SX::store(bx, n5, kk, xv);
-        S::load(br, n5, kk, rv);
-        S::load(bq, n5, kk, pv);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) rv[c] = rv[c] - al * pv[c];
-        n = S::store_norm2(br, n5, kk, rv);
-    }
-    block_sum_store(n, partials, blockIdx.x);
-}
-
-template <int PI, int PO>
-__global__ __launch_bounds__(BLAS_BLOCK) void convert_kernel(int64_t N5, const char *in, char *out)
-{
-    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
-    if (k >= N5) return;
-    cx<typename Spin<PI>::T> v[12];
-    Spin<PI>::load(Buf(in, Spin<PI>::bytes(N5)), (uint32_t)N5, (uint32_t)k, v);
-    cx<typename Spin<PO>::T> w[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c)
-        w[c] = {(typename Spin<PO>::T)v[c].r, (typename Spin<PO>::T)v[c].i};
-    Spin<PO>::store(Buf(out, Spin<PO>::bytes(N5)), (uint32_t)N5, (uint32_t)k, w);
-}
-
-template <int PL>
-__global__ __launch_bounds__(BLAS_BLOCK) void accumulate_kernel(int64_t N5, const char *lo, char *hi)
-{
-    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
-    if (k >= N5) return;
-    cx<typename Spin<PL>::T> v[12];
-    Spin<PL>::load(Buf(lo, Spin<PL>::bytes(N5)), (uint32_t)N5, (uint32_t)k, v);
-    cx<double> h[12];
-    const Buf bh(hi, Spin<MOBIUS_F64>::bytes(N5));
-    Spin<MOBIUS_F64>::load(bh, (uint32_t)N5, (uint32_t)k, h);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) h[c] = {h[c].r + (double)v[c].r, h[c].i + (double)v[c].i};
-    Spin<MOBIUS_F64>::store(bh, (uint32_t)N5, (uint32_t)k, h);
-}
 
 __global__ void zero_kernel(uint4 *p, int64_t n16, unsigned char *tail, int64_t ntail)
 {
@@ -862,43 +764,18 @@ __global__ void cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t *
     if (j >= nsys) return;
     CgScalars &s = sc[j];
     const bool on = !active || active[j];
+    const bool rec = on && s.hist && s.nhist < s.hmax;
     if (op == 2) {
         if (on) s.alpha = 0.0;
     } else if (op == 0) {
         s.alpha = (on && s.qq > 0) ? s.gamma / s.qq : 0.0;
+        if (rec) s.hist[2 * s.nhist++ + 1] = s.alpha;
     } else {
         const bool rs = restart && restart[j];
         s.beta = (on && !rs && s.gamma > 0) ? s.gamma_new / s.gamma : 0.0;
         s.gamma = s.gamma_new;
         if (restart) restart[j] = 0;
-    }
-}
-
-constexpr int RED_BLOCK = 1024;
-
-__global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(const double *partials, int64_t n,
-                                                           double *out)
-{
-    __shared__ double sm[RED_BLOCK];
-    double t = 0;
-    for (int64_t k = threadIdx.x; k < n; k += RED_BLOCK) t += partials[k];
-    sm[threadIdx.x] = t;
-    __syncthreads();
-    for (int w = RED_BLOCK / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = sm[0];
-}
-
-__global__ void cg_scalar_kernel(CgScalars *s, int op)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (op == 0) {
-        s->alpha = s->qq > 0 ? s->gamma / s->qq : 0.0;
-    } else {
-        s->beta = s->gamma > 0 ? s->gamma_new / s->gamma : 0.0;
-        s->gamma = s->gamma_new;
+        if (rec) s.hist[2 * s.nhist] = s.beta;
     }
 }
 
@@ -1195,107 +1072,6 @@ hipError_t launch_m5(const Geometry &g, const OpCoeffs &c, int prec, int kind, i
     return hipGetLastError();
 }
 
-hipError_t launch_axpby(const Geometry &g, int prec, const double *a, const void *x,
-                        const double *b, const void *y, void *out, int nrhs, hipStream_t st)
-{
-    dim3 grid((unsigned)blas_blocks(g)), blk(BLAS_BLOCK);
-    const int64_t fb = field_bytes(g, prec);
-    for (int r = 0; r < nrhs; ++r) {
-        const char *xx = static_cast<const char *>(x) + r * fb;
-        const char *yy = static_cast<const char *>(y) + r * fb;
-        char *o = static_cast<char *>(out) + r * fb;
-        switch (prec) {
-        case MOBIUS_F64: hipLaunchKernelGGL(axpby_kernel<MOBIUS_F64>, grid, blk, 0, st, g.N5, a, xx, b, yy, o); break;
-        case MOBIUS_F32: hipLaunchKernelGGL(axpby_kernel<MOBIUS_F32>, grid, blk, 0, st, g.N5, a, xx, b, yy, o); break;
-        case MOBIUS_F16: hipLaunchKernelGGL(axpby_kernel<MOBIUS_F16>, grid, blk, 0, st, g.N5, a, xx, b, yy, o); break;
-        default: return hipErrorInvalidValue;
-        }
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_norm2(const Geometry &g, int prec, const void *x, double *partials, int nrhs,
-                        hipStream_t st)
-{
-    const int64_t nb = blas_blocks(g);
-    dim3 grid((unsigned)nb), blk(BLAS_BLOCK);
-    const int64_t fb = field_bytes(g, prec);
-    for (int r = 0; r < nrhs; ++r) {
-        const char *xx = static_cast<const char *>(x) + r * fb;
-        double *pp = partials + r * nb;
-        switch (prec) {
-        case MOBIUS_F64: hipLaunchKernelGGL(norm2_kernel<MOBIUS_F64>, grid, blk, 0, st, g.N5, xx, pp); break;
-        case MOBIUS_F32: hipLaunchKernelGGL(norm2_kernel<MOBIUS_F32>, grid, blk, 0, st, g.N5, xx, pp); break;
-        case MOBIUS_F16: hipLaunchKernelGGL(norm2_kernel<MOBIUS_F16>, grid, blk, 0, st, g.N5, xx, pp); break;
-        default: return hipErrorInvalidValue;
-        }
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_xr(const Geometry &g, int prec, int prec_x, const double *alpha, void *x,
-                        const void *p, void *r, const void *q, double *partials, hipStream_t st)
-{
-    dim3 grid((unsigned)blas_blocks(g)), blk(BLAS_BLOCK);
-    char *xx = static_cast<char *>(x);
-    char *rr = static_cast<char *>(r);
-    const char *pp = static_cast<const char *>(p);
-    const char *qq = static_cast<const char *>(q);
-#define MOBIUS_XR(P, PX) hipLaunchKernelGGL((cg_xr_kernel<P, PX>), grid, blk, 0, st, g.N5, alpha, xx, pp, rr, qq, partials)
-    if (prec == MOBIUS_F64 && prec_x == MOBIUS_F64) MOBIUS_XR(MOBIUS_F64, MOBIUS_F64);
-    else if (prec == MOBIUS_F32 && prec_x == MOBIUS_F32) MOBIUS_XR(MOBIUS_F32, MOBIUS_F32);
-    else if (prec == MOBIUS_F32 && prec_x == MOBIUS_F64) MOBIUS_XR(MOBIUS_F32, MOBIUS_F64);
-    else if (prec == MOBIUS_F16 && prec_x == MOBIUS_F32) MOBIUS_XR(MOBIUS_F16, MOBIUS_F32);
-    else if (prec == MOBIUS_F16 && prec_x == MOBIUS_F64) MOBIUS_XR(MOBIUS_F16, MOBIUS_F64);
-    else if (prec == MOBIUS_F16 && prec_x == MOBIUS_F16) MOBIUS_XR(MOBIUS_F16, MOBIUS_F16);
-    else return hipErrorInvalidValue;
-#undef MOBIUS_XR
-    return hipGetLastError();
-}
-
-namespace {
-template <int PI>
-hipError_t convert_from(const Geometry &g, const char *in, int po, char *out, hipStream_t st)
-{
-    dim3 grid((unsigned)blas_blocks(g)), blk(BLAS_BLOCK);
-    switch (po) {
-    case MOBIUS_F64: hipLaunchKernelGGL((convert_kernel<PI, MOBIUS_F64>), grid, blk, 0, st, g.N5, in, out); break;
-    case MOBIUS_F32: hipLaunchKernelGGL((convert_kernel<PI, MOBIUS_F32>), grid, blk, 0, st, g.N5, in, out); break;
-    case MOBIUS_F16: hipLaunchKernelGGL((convert_kernel<PI, MOBIUS_F16>), grid, blk, 0, st, g.N5, in, out); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-}  // namespace
-
-hipError_t launch_convert(const Geometry &g, int prec_in, const void *in, int prec_out, void *out,
-                          hipStream_t st)
-{
-    const char *i = static_cast<const char *>(in);
-    char *o = static_cast<char *>(out);
-    switch (prec_in) {
-    case MOBIUS_F64: return convert_from<MOBIUS_F64>(g, i, prec_out, o, st);
-    case MOBIUS_F32: return convert_from<MOBIUS_F32>(g, i, prec_out, o, st);
-    case MOBIUS_F16: return convert_from<MOBIUS_F16>(g, i, prec_out, o, st);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_accumulate(const Geometry &g, int prec_lo, const void *x_lo, void *x_hi,
-                             hipStream_t st)
-{
-    dim3 grid((unsigned)blas_blocks(g)), blk(BLAS_BLOCK);
-    const char *lo = static_cast<const char *>(x_lo);
-    char *hi = static_cast<char *>(x_hi);
-    switch (prec_lo) {
-    case MOBIUS_F64: hipLaunchKernelGGL(accumulate_kernel<MOBIUS_F64>, grid, blk, 0, st, g.N5, lo, hi); break;
-    case MOBIUS_F32: hipLaunchKernelGGL(accumulate_kernel<MOBIUS_F32>, grid, blk, 0, st, g.N5, lo, hi); break;
-    case MOBIUS_F16: hipLaunchKernelGGL(accumulate_kernel<MOBIUS_F16>, grid, blk, 0, st, g.N5, lo, hi); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
 hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t st)
 {
     const int64_t n16 = bytes / 16;
@@ -1408,18 +1184,6 @@ hipError_t launch_cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t
 {
     hipLaunchKernelGGL(cg_scalar_batch, dim3((nsys + 63) / 64), dim3(64), 0, st, sc, nsys, op,
                        active, restart);
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce(const double *partials, int64_t n, double *out, hipStream_t st)
-{
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(RED_BLOCK), 0, st, partials, n, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_scalar(CgScalars *s, int op, hipStream_t st)
-{
-    hipLaunchKernelGGL(cg_scalar_kernel, dim3(1), dim3(64), 0, st, s, op);
     return hipGetLastError();
 }
 

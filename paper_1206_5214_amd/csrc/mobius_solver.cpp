@@ -57,6 +57,9 @@ enum Field { F_ETA_E, F_ETA_O, F_B, F_XH, F_RH, F_T64, F_U64, F_Q64, F_PE,  // F
              F_R, F_P, F_Q, F_S, F_T, F_U,                                 // precision lo
              NFIELDS, F_NONE = -1 };
 
+// CG iterations whose coefficients are kept for the condition-number estimate
+constexpr int64_t HIST_MAX = 8192;
+
 struct Group {
     mobius_ctx *ctx;
     int nrhs, sys0;
@@ -102,6 +105,7 @@ struct Batch {
     // device state (in the first context's buffers)
     double *part = nullptr;
     CgScalars *sc = nullptr;
+    double *hist = nullptr;         // [nsys][HIST_MAX][2] CG coefficients (kappa estimate)
     double *extra = nullptr;
     int32_t *active = nullptr, *restart = nullptr;
     HopParams *hop_tab = nullptr;   // [NHOP][ngroups]
@@ -174,6 +178,7 @@ struct Batch {
     hipError_t reliable_update();        // x_hi += x, r = b - D x_hi (FP64), r_lo = r
     hipError_t finalize_group(const Group &g);
     int fetch(std::vector<double> &out, int which);
+    int kappa(std::vector<double> &out);  // Lanczos estimate of cond(D_pre) per system
     void acct_hop(int prec, int epi, double fields, double n5);
 };
 
@@ -245,6 +250,7 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
     const size_t o_vec = carve(sizeof(VecSys) * NVEC * nsys);
     const size_t o_pre = carve(sizeof(int64_t) * NHOP * (ng + 1));
     const size_t o_coef = carve(sizeof(OpCoeffs) * ng);
+    const size_t o_hist = carve(sizeof(double) * 2 * HIST_MAX * nsys);
     CK(c0->scalars.ensure((int64_t)off));
     char *base = static_cast<char *>(c0->scalars.p);
     sc = reinterpret_cast<CgScalars *>(base + o_sc);
@@ -343,6 +349,14 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
     CK(hipMemcpyAsync(coef, h_coef.data(), sizeof(OpCoeffs) * ng, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(active, h_active.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(restart, h_restart.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st));
+    hist = reinterpret_cast<double *>(base + o_hist);
+    std::vector<CgScalars> h_sc(nsys, CgScalars{});
+    for (int j = 0; j < nsys; ++j) {
+        h_sc[j].hist = hist + (size_t)2 * HIST_MAX * j;
+        h_sc[j].nhist = 0;
+        h_sc[j].hmax = HIST_MAX;
+    }
+    CK(hipMemcpyAsync(sc, h_sc.data(), sizeof(CgScalars) * nsys, hipMemcpyHostToDevice, st));
     std::vector<double> h_extra((size_t)nsys * NEXTRA, 0.0);
     for (int j = 0; j < nsys; ++j) h_extra[(size_t)j * NEXTRA + X_MINUS1] = -1.0;
     CK(hipMemcpyAsync(extra, h_extra.data(), sizeof(double) * h_extra.size(), hipMemcpyHostToDevice, st));
@@ -593,6 +607,77 @@ int Batch::fetch(std::vector<double> &out, int which)
     return MOBIUS_OK;
 }
 
+// Eigenvalue bounds of a symmetric tridiagonal matrix (diagonal d, off-diagonal
+// e[k] between k-1 and k, e[0] unused): the smallest and the largest, by
+// bisection on the Sturm count (number of eigenvalues below x).
+static void tridiag_extremes(const std::vector<double> &d, const std::vector<double> &e,
+                             double &lmin, double &lmax)
+{
+    const size_t n = d.size();
+    double lo = INFINITY, hi = -INFINITY;
+    for (size_t k = 0; k < n; ++k) {  // Gershgorin
+        const double r = (k > 0 ? std::fabs(e[k]) : 0.0) + (k + 1 < n ? std::fabs(e[k + 1]) : 0.0);
+        lo = std::min(lo, d[k] - r);
+        hi = std::max(hi, d[k] + r);
+    }
+    auto below = [&](double x) {
+        size_t c = 0;
+        double q = 1.0;
+        for (size_t k = 0; k < n; ++k) {
+            q = d[k] - x - (k > 0 ? e[k] * e[k] / q : 0.0);
+            if (q == 0.0) q = -1e-300;
+            c += q < 0.0;
+        }
+        return c;
+    };
+    auto kth = [&](size_t want) {  // the eigenvalue with `want` eigenvalues below it
+        double a = lo, b = hi;
+        for (int it = 0; it < 200 && b - a > 1e-15 * std::max(std::fabs(a), std::fabs(b)); ++it) {
+            const double m = 0.5 * (a + b);
+            if (below(m) > want) b = m; else a = m;
+        }
+        return 0.5 * (a + b);
+    };
+    lmin = kth(0);
+    lmax = kth(n - 1);
+}
+
+// cond(D_pre) = sqrt(lambda_max / lambda_min) of the normal operator, from the
+// Lanczos tridiagonal that the CG coefficients define:
+//   T_kk = 1/alpha_k + beta_{k-1}/alpha_{k-1},  T_{k-1,k} = sqrt(beta_{k-1})/alpha_{k-1}
+// (beta = 0 where a Krylov segment restarts: T is then block diagonal and its
+// extreme eigenvalues are the extremes over the segments).  0 when no
+// iteration ran.
+int Batch::kappa(std::vector<double> &out)
+{
+    out.assign(nsys, 0.0);
+    std::vector<CgScalars> h(nsys);
+    CK(hipMemcpyAsync(h.data(), sc, sizeof(CgScalars) * nsys, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    std::vector<double> hb;
+    for (int j = 0; j < nsys; ++j) {
+        const int64_t n = h[j].nhist;
+        if (n < 1) continue;
+        hb.resize(2 * n);
+        CK(hipMemcpy(hb.data(), h[j].hist, sizeof(double) * 2 * n, hipMemcpyDeviceToHost));
+        std::vector<double> d, e;
+        double prev_a = 0;
+        for (int64_t k = 0; k < n; ++k) {
+            const double b = hb[2 * k], a = hb[2 * k + 1];
+            if (!(a > 0) || !std::isfinite(a)) break;
+            const bool link = !d.empty() && b > 0 && prev_a > 0;
+            d.push_back(1.0 / a + (link ? b / prev_a : 0.0));
+            e.push_back(link ? std::sqrt(b) / prev_a : 0.0);
+            prev_a = a;
+        }
+        if (d.empty()) continue;
+        double lmin, lmax;
+        tridiag_extremes(d, e, lmin, lmax);
+        out[j] = lmin > 0 ? std::sqrt(lmax / lmin) : INFINITY;
+    }
+    return MOBIUS_OK;
+}
+
 // The derivative pass of the pseudofermion action after the normal-equations
 // solve (one system, x_hi = X):
 //   Z = I^-1 D_eo X (even), Y = D_pre X, Yt = I^-+ Y, W = I^-+ (D_oe)^+ Yt (even),
@@ -632,6 +717,7 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
 {
     const int nrhs = o.nrhs > 0 ? o.nrhs : 1;
     const double tol = o.tol > 0 ? o.tol : 1e-10;
+    const double err_tol = o.err_tol > 0 ? o.err_tol : 0.0;
     const int maxiter = o.maxiter > 0 ? o.maxiter : 10000;
     const bool mixed = o.inner_prec != MOBIUS_F64;
     // Default update threshold per operator precision.  The binary16 Krylov
@@ -743,10 +829,12 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
                 for (int r = 0; r < g.nrhs; ++r) gp |= pending[g.sys0 + r] != 0;
                 if (gp && !B.normal) CK(B.finalize_group(g));
             }
-            std::vector<double> re, ro, hr;
+            std::vector<double> re, ro, hr, kap;
             if (int rc = B.fetch(re, X_RES_E)) return rc;
             if (int rc = B.fetch(ro, X_RES_O)) return rc;
             if (int rc = B.fetch(hr, X_HR)) return rc;
+            if (err_tol > 0)
+                if (int rc = B.kappa(kap)) return rc;
             for (int j = 0; j < nsys; ++j) {
                 if (!pending[j]) continue;
                 pending[j] = 0;
@@ -756,11 +844,15 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
                     true_res[j] = schur_res[j];
                 else
                     true_res[j] = en > 0 ? std::sqrt(re[j] + ro[j]) / en : 0.0;
-                if (true_res[j] <= tol || bnorm2[j] == 0.0) {
+                // bound on the relative error of the iterated unknown: cond(D_pre)
+                // times the Schur residual (cond(D_pre)^2 for the normal equations)
+                const double bound = err_tol > 0 ? (B.normal ? kap[j] * kap[j] : kap[j]) * schur_res[j] : 0.0;
+                if (bnorm2[j] == 0.0 || (true_res[j] <= tol && bound <= err_tol)) {
                     converged[j] = 1;
                     B.h_active[j] = 0;
                 } else {
-                    tol_s[j] *= std::max(0.05, 0.5 * tol / true_res[j]);
+                    const double f = true_res[j] > tol ? tol / true_res[j] : err_tol / bound;
+                    tol_s[j] *= std::max(0.05, 0.5 * f);
                     B.h_active[j] = 1;
                     B.h_restart[j] = 1;
                 }
@@ -862,6 +954,8 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
     CK(hipEventElapsedTime(&ms, own.ev0, own.ev1));
     CK(hipEventRecord(own.ev_in, st));
     CK(hipStreamWaitEvent(user, own.ev_in, 0));
+    std::vector<double> kap;
+    if (int rc = B.kappa(kap)) return rc;
     int status = MOBIUS_OK;
     for (int j = 0; j < nsys; ++j) {
         mobius_solve_info &inf = info[j];
@@ -873,6 +967,8 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
         inf.status = converged[j] ? MOBIUS_OK : MOBIUS_NOT_CONVERGED;
         inf.true_resid = true_res[j];
         inf.schur_resid = schur_res[j];
+        inf.kappa = kap[j];
+        inf.err_bound = (B.normal ? kap[j] * kap[j] : kap[j]) * schur_res[j];
         inf.seconds = ms * 1e-3;
         inf.algo_bytes = B.abytes;
         inf.flops = B.aflops;

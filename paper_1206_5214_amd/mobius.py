@@ -34,13 +34,15 @@ class MobiusError(RuntimeError):
 class _Params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32 * 4), ("Ls", ctypes.c_int32), ("M5", ctypes.c_double),
                 ("mf", ctypes.c_double), ("b5", ctypes.c_double), ("c5", ctypes.c_double),
-                ("mu", ctypes.c_double)]
+                ("mu", ctypes.c_double), ("b5s", ctypes.POINTER(ctypes.c_double)),
+                ("c5s", ctypes.POINTER(ctypes.c_double))]
 
 
 class _SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int32),
                 ("inner_prec", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
-                ("nrhs", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("nrhs", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("err_tol", ctypes.c_double)]
 
 
 class _TuneResult(ctypes.Structure):
@@ -54,7 +56,8 @@ class _SolveInfo(ctypes.Structure):
                 ("reliable_updates", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("true_resid", ctypes.c_double), ("schur_resid", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("algo_bytes", ctypes.c_double),
-                ("flops", ctypes.c_double)]
+                ("flops", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("err_bound", ctypes.c_double)]
 
 
 @dataclass
@@ -68,6 +71,8 @@ class SolveInfo:
     seconds: float
     algo_bytes: float
     flops: float
+    kappa: float
+    err_bound: float
 
 
 _lib = None
@@ -140,7 +145,9 @@ def _require_cuda(t, dtype=None, name="tensor"):
 class Operator:
     """A red/black Moebius operator on one lattice (owns the packed links)."""
 
-    def __init__(self, dims, Ls, M5, mf, b5, c5, links, mu=0.0):
+    def __init__(self, dims, Ls, M5, mf, b5, c5, links, mu=0.0, b5s=None, c5s=None):
+        """b5s, c5s: optional per-slice coefficients (Ls values each) of the
+        general operator; they replace b5, c5."""
         import torch
         _require_cuda(links, torch.complex128, "links")
         Lx, Ly, Lz, Lt = dims
@@ -148,8 +155,16 @@ class Operator:
             raise MobiusError(f"links have shape {tuple(links.shape)}")
         self.dims = tuple(int(d) for d in dims)
         self.Ls = int(Ls)
-        self.params = dict(M5=M5, mf=mf, b5=b5, c5=c5, mu=mu)
+        self.params = dict(M5=M5, mf=mf, b5=b5, c5=c5, mu=mu, b5s=b5s, c5s=c5s)
         p = _Params((ctypes.c_int32 * 4)(*self.dims), self.Ls, M5, mf, b5, c5, mu)
+        keep = []
+        for name, v in (("b5s", b5s), ("c5s", c5s)):
+            if v is not None:
+                if len(v) != self.Ls:
+                    raise MobiusError(f"{name} must hold Ls = {self.Ls} values")
+                a = (ctypes.c_double * self.Ls)(*[float(x) for x in v])
+                keep.append(a)
+                setattr(p, name, ctypes.cast(a, ctypes.POINTER(ctypes.c_double)))
         h = ctypes.c_void_p()
         _check(lib().mobius_create(ctypes.byref(h), ctypes.byref(p), _ptr(links), _stream()))
         self._h = h
@@ -260,21 +275,22 @@ class Operator:
         return out
 
     def solve(self, src, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.0,
-              check_every=0):
+              check_every=0, err_tol=0.0):
         """Solve D_DW psi = src (canonical complex128, optional leading nrhs).
-        reliable_delta <= 0 selects the library's default for inner_prec."""
+        reliable_delta <= 0 selects the library's default for inner_prec; err_tol > 0
+        also iterates until kappa * Schur residual <= err_tol."""
         import torch
         nrhs = 1 if src.dim() == 7 else int(src.shape[0])
         self._check_canon(src, nrhs, "source")
         sol = torch.empty_like(src)
-        opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, nrhs, check_every)
+        opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, nrhs, check_every, err_tol)
         infos = (_SolveInfo * nrhs)()
         rc = _check(lib().mobius_cg_solve(self._h, _ptr(src), _ptr(sol), ctypes.byref(opts), infos,
                                           _stream()))
         return sol, [_info(i) for i in infos], rc
 
     def propagator4d(self, src4, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.0,
-                     check_every=0):
+                     check_every=0, err_tol=0.0):
         """q = D_ov(m)^-1 b through the 5d solve D_DW(m) psi = D_DW(1) P b (see
         mobius_propagator4d); src4 canonical complex128 [t][z][y][x][4][3], with
         an optional leading nrhs."""
@@ -286,7 +302,7 @@ class Operator:
         if tuple(src4.shape[-6:]) != shape4 or src4.numel() != nrhs * Lt * Lz * Ly * Lx * 12:
             raise MobiusError(f"source has shape {tuple(src4.shape)}, expected [nrhs,] {shape4}")
         sol = torch.empty_like(src4)
-        opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, nrhs, check_every)
+        opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, nrhs, check_every, err_tol)
         infos = (_SolveInfo * nrhs)()
         rc = _check(lib().mobius_propagator4d(self._h, _ptr(src4), _ptr(sol), ctypes.byref(opts),
                                               infos, _stream()))
@@ -340,11 +356,11 @@ class Operator:
 
 def _info(i):
     return SolveInfo(i.iters, i.dirac_apps, i.reliable_updates, i.status, i.true_resid,
-                     i.schur_resid, i.seconds, i.algo_bytes, i.flops)
+                     i.schur_resid, i.seconds, i.algo_bytes, i.flops, i.kappa, i.err_bound)
 
 
 def batch_solve(ops, srcs, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.0,
-                check_every=0):
+                check_every=0, err_tol=0.0):
     """Solve D_DW psi_j = src_j for several lattices at once (one Operator per
     lattice, the same number of right-hand sides each).  Returns the list of
     solutions, a list (per lattice) of lists of SolveInfo, and the return code."""
@@ -363,7 +379,7 @@ def batch_solve(ops, srcs, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_de
     hs = (vp * n)(*[o._h for o in ops])
     ss = (vp * n)(*[s.data_ptr() for s in srcs])
     xs = (vp * n)(*[s.data_ptr() for s in sols])
-    opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, nrhs, check_every)
+    opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, nrhs, check_every, err_tol)
     infos = (_SolveInfo * (n * nrhs))()
     rc = _check(lib().mobius_batch_solve(n, hs, ss, xs, ctypes.byref(opts), infos, _stream()))
     out = [[_info(infos[j * nrhs + r]) for r in range(nrhs)] for j in range(n)]

@@ -84,3 +84,16 @@ def reflection(Ls):
     for s in range(Ls):
         R[4 * s:4 * s + 4, 4 * (Ls - 1 - s):4 * (Ls - 1 - s) + 4] = np.eye(4)
     return R
+
+
+def overlap_symbol_sdep(p, M5, b5s, c5s, m):
+    """D_ov(m) of the general operator with per-slice coefficients (Sec. 2.2):
+    (1+m)/2 + (1-m)/2 g5 (X - 1)(X + 1)^-1 with X = T_1^-1 T_2^-1 ... T_Ls^-1,
+    T_s = (1 - H_s)/(1 + H_s), H_s = g5 (b5(s)+c5(s)) D_W (2 + (b5(s)-c5(s)) D_W)^-1."""
+    Dw = wilson_symbol(p, M5)
+    I4 = np.eye(4)
+    X = I4.astype(complex)
+    for b, c in zip(b5s, c5s):
+        H = G5 @ np.linalg.solve(2 * I4 + (b - c) * Dw, (b + c) * Dw)
+        X = X @ np.linalg.solve(I4 - H, I4 + H)
+    return 0.5 * (1 + m) * I4 + 0.5 * (1 - m) * G5 @ (X - I4) @ np.linalg.inv(X + I4)

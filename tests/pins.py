@@ -532,9 +532,123 @@ def pin_dw_sites(orc):
                 assert _rel(got, want) < 1e-15, ("dw_sites", dims, in_parity, dag, _rel(got, want))
 
 
+# ---------------------------------------------------------------------------
+# s-dependent coefficients b5(s), c5(s) (the general operator of Sec. 2.1)
+
+def _sdep_params(dims, Ls, mf, sym=False, seed=0, M5=1.8):
+    """Per-slice coefficients with b5(s) - c5(s) varying (the general case) or,
+    with sym, reflection symmetric (b5(s) = b5(Ls+1-s), c5 likewise)."""
+    from oracle import Params
+    rng = np.random.default_rng(seed)
+    b = rng.uniform(1.0, 2.0, Ls)
+    c = rng.uniform(0.0, 0.8, Ls)
+    if sym:
+        b = 0.5 * (b + b[::-1])
+        c = 0.5 * (c + c[::-1])
+    return Params(tuple(dims), Ls, M5, mf, 1.5, 0.5, 0.0, tuple(b), tuple(c))
+
+
+def pin_sdep_free_identities(orc):
+    """Per-slice b5(s), c5(s) at unit links: det D(m)/det D(1) = det D_ov(m) and
+    [P^+ D(m)^-1 D(1) P]_11 = D_ov(m)^-1 per momentum, with D_ov built from the
+    ordered product T_1^-1 ... T_Ls^-1 of the per-slice transfer matrices
+    (Sec. 2.2).  The coefficients make H_s and H_s' non-commuting, so the
+    propagator identity also fixes the order of the product."""
+    from oracle import Params
+    rng = np.random.default_rng(14)
+    for dims, Ls, mf, seed in [((4, 4, 2, 4), 5, 0.05, 1), ((4, 2, 2, 4), 6, 0.2, 2)]:
+        p = _sdep_params(dims, Ls, mf, seed=seed)
+        p1 = Params(p.dims, p.Ls, p.M5, 1.0, p.b5, p.c5, 0.0, p.b5s, p.c5s)
+        P = ff.perm_matrix(Ls)
+        for mom in [np.zeros(4)] + ff.momenta(dims, rng, 2):
+            Dm = _dw_symbol(orc, p, mom)
+            D1 = _dw_symbol(orc, p1, mom)
+            Dov = ff.overlap_symbol_sdep(mom, p.M5, p.b5s, p.c5s, mf)
+            lhs = np.linalg.det(Dm) / np.linalg.det(D1)
+            rhs = np.linalg.det(Dov)
+            assert abs(lhs - rhs) < 1e-9 * max(1.0, abs(rhs)), ("s-dep det identity", mom, lhs, rhs)
+            A = np.conj(P.T) @ np.linalg.solve(Dm, D1 @ P)
+            # (the closed form passes through (1 - H_s)^-1, ill-conditioned where an
+            # eigenvalue of H_s nears 1: hence 1e-9 rather than roundoff)
+            assert _rel(A[:4, :4], np.linalg.inv(Dov)) < 1e-9, ("s-dep propagator identity", mom)
+            assert np.abs(A[:4, 4:]).max() < 1e-11
+
+
+def pin_sdep_m5_block(orc):
+    """Per-slice coefficients: the diagonal block of the oracle's D_DW is the
+    cyclic tridiagonal matrix with M+(s) = b5(s)(4-M5)+1 on the diagonal and
+    M-(s) = c5(s)(4-M5)-1 in row s (P- at (s,s+1), P+ at (s,s-1), corners
+    -m M-(1) P+ and -m M-(Ls) P-), and the O(Ls) elimination I^-1 (and I^-+)
+    equals a dense solve of that matrix (and of its transpose)."""
+    dims = (2, 2, 2, 2)
+    U = inputs.random_links(dims, 0.5, np.random.default_rng(15))
+    for Ls, mf, seed in [(6, 0.05, 3), (5, 0.3, 4), (2, 0.1, 5)]:
+        p = _sdep_params(dims, Ls, mf, seed=seed)
+        x = inputs.gaussian_spinor(dims, Ls, np.random.default_rng(seed))
+        Mp = [p.b5_at(s) * (4 - p.M5) + 1 for s in range(Ls)]
+        Mm = [p.c5_at(s) * (4 - p.M5) - 1 for s in range(Ls)]
+        Ib = np.zeros((4 * Ls, 4 * Ls))
+        for s in range(Ls):
+            Ib[4 * s:4 * s + 4, 4 * s:4 * s + 4] += Mp[s] * np.eye(4)
+            sp, sm = (s + 1) % Ls, (s - 1) % Ls
+            fp = -mf if s == Ls - 1 else 1.0
+            fm = -mf if s == 0 else 1.0
+            Ib[4 * s:4 * s + 4, 4 * sp:4 * sp + 4] += fp * Mm[s] * ff.PM.real
+            Ib[4 * s:4 * s + 4, 4 * sm:4 * sm + 4] += fm * Mm[s] * ff.PP.real
+        for dag in (False, True):
+            M = Ib.T if dag else Ib
+            want = np.einsum("suSv,Stzyxvc->stzyxuc", M.reshape(Ls, 4, Ls, 4), x)
+            assert _rel(orc.m5(p, U, x, dag=dag), want) < 1e-13, ("s-dep I block", Ls, dag)
+            Minv = np.linalg.inv(M)
+            want = np.einsum("suSv,Stzyxvc->stzyxuc", Minv.reshape(Ls, 4, Ls, 4), x)
+            assert _rel(orc.m5inv(p, x, dag=dag), want) < 1e-13, ("s-dep I^-1 vs dense", Ls, dag)
+
+
+def pin_sdep_adjoints_and_solve(orc):
+    """Per-slice coefficients with random links: <x, A y> = <A^+ x, y> for D_DW,
+    the hop blocks, I^-1 and D_pre; the red/black solve equals the dense LU
+    solution of D_DW psi = eta; and with reflection-symmetric coefficients
+    g5 R D-^-1 D_DW is Hermitian (the generalised g5-hermiticity of Sec. 2.1)."""
+    from oracle import restrict
+    dims = (2, 2, 2, 4)
+    U = inputs.random_links(dims, 0.5, np.random.default_rng(16))
+    rng = np.random.default_rng(17)
+    p = _sdep_params(dims, 5, 0.07, seed=6)
+    x = inputs.gaussian_spinor(dims, p.Ls, rng)
+    y = inputs.gaussian_spinor(dims, p.Ls, rng)
+    ops = {
+        "dw": (lambda v: orc.dw(p, U, v), lambda v: orc.dw(p, U, v, dag=True), x, y),
+        "m5inv": (lambda v: orc.m5inv(p, v), lambda v: orc.m5inv(p, v, dag=True), x, y),
+        "hop_eo": (lambda v: orc.hop(p, U, v, 0), lambda v: orc.hop(p, U, v, 1, dag=True),
+                   restrict(p, x, 0), restrict(p, y, 1)),
+        "schur": (lambda v: orc.schur(p, U, v), lambda v: orc.schur(p, U, v, dag=True),
+                  restrict(p, x, 1), restrict(p, y, 1)),
+    }
+    for name, (A, Ad, xx, yy) in ops.items():
+        e = _adjoint_err(orc, A, Ad, xx, yy)
+        assert e < 1e-12, ("s-dep adjoint", name, e)
+    ps = _sdep_params(dims, 4, 0.05, sym=True, seed=7)
+    D = _dense(lambda v: orc.dw(ps, U, v), int(np.prod(ps.shape5())), ps.shape5())
+    eta = inputs.gaussian_spinor(dims, ps.Ls, np.random.default_rng(18))
+    want = np.linalg.solve(D, eta.reshape(-1)).reshape(eta.shape)
+    psi, info = orc.solve(ps, U, eta, tol=1e-13, maxiter=5000)
+    assert info.converged and _rel(psi, want) < 1e-9, ("s-dep schur solve vs dense", _rel(psi, want))
+    n4 = int(np.prod(ps.shape4()))
+    Dw = _dense(lambda v: orc.wilson(ps, U, v), n4, ps.shape4())
+    g5 = np.tile(np.repeat(np.diag(ff.G5).real, 3), n4 // 12)
+    H = np.zeros_like(D)
+    for s in range(ps.Ls):
+        sr = ps.Ls - 1 - s
+        Dminus = ps.c5_at(sr) * Dw - np.eye(n4)
+        H[s * n4:(s + 1) * n4, :] = g5[:, None] * np.linalg.solve(Dminus, D[sr * n4:(sr + 1) * n4, :])
+    err = np.abs(H - np.conj(H.T)).max() / np.abs(H).max()
+    assert err < 1e-12, ("s-dep g5 R D-^-1 D hermiticity", err)
+
+
 ALL_PINS = [pin_wilson_free_symbol, pin_kernel_bound, pin_gauge_covariance,
             pin_wilson_gamma5_hermiticity, pin_adjoints, pin_free_determinant,
             pin_free_propagator, pin_gamma5_R_hermiticity, pin_m5_block, pin_schur_solve_dense,
             pin_rb_equals_unpreconditioned, pin_cgne_dense, pin_force_finite_difference,
             pin_propagator4d_free, pin_propagator4d_dense, pin_wilson_free_symbol_mu,
-            pin_adjoints_mu, pin_force_lie, pin_dw_sites]
+            pin_adjoints_mu, pin_force_lie, pin_dw_sites, pin_sdep_free_identities,
+            pin_sdep_m5_block, pin_sdep_adjoints_and_solve]

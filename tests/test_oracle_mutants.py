@@ -35,7 +35,7 @@ MUTANTS = [
      "                chiral_part(in + ((int64_t)sm1 * V + nb[j]) * SITE_DOF, +1, fm1, wb);",
      "chiral_part(in + ((int64_t)sp1 * V + nb[j]) * SITE_DOF, +1, fp1, wb);\n"
      "                chiral_part(in + ((int64_t)sm1 * V + nb[j]) * SITE_DOF, -1, fm1, wb);"),
-    ("c5_dropped_in_adjoint", "y[k] = p->c5 * t2[k] - in[((int64_t)sm1", "y[k] = 0.0 * t2[k] - in[((int64_t)sm1"),
+    ("c5_dropped_in_adjoint", "y[k] = c5_of(p, sm1) * t2[k]", "y[k] = 0.0 * t2[k]"),
     ("m5inv_transpose_swapped", "int transpose = dag ? minus : !minus;",
      "int transpose = dag ? !minus : minus;"),
     ("m5inv_corner_mass", "mu = p->mf * a;", "mu = p->mf;"),
@@ -62,6 +62,13 @@ MUTANTS = [
      "masked_copy(p, (const cplx *)ind, in_parity < 0 ? in_parity : 1 - in_parity);"),
     ("dw_sites_adjoint_dropped", "dw_site(p, U, in, sites[k], tmp, dag, buf);",
      "dw_site(p, U, in, sites[k], tmp, 0, buf);"),
+    ("sdep_adjoint_row_coefficient", "y[k] = c5_of(p, sm1) * t2[k]", "y[k] = c5_of(p, s) * t2[k]"),
+    ("sdep_forward_row_coefficient", "o[k] += c5_of(p, s) * t2[k]",
+     "o[k] += c5_of(p, (s + 1) % Ls) * t2[k]"),
+    ("sdep_corner_coefficients_swapped",
+     "km = -p->mf * Mm[Ls - 1];\n        kp = -p->mf * Mm[0];\n    } else {",
+     "km = -p->mf * Mm[0];\n        kp = -p->mf * Mm[Ls - 1];\n    } else {"),
+    ("sdep_adjoint_offdiagonal_index", "em[s] = s > 0 ? Mm[s - 1] : 0.0;", "em[s] = Mm[s];"),
     ("force_only_forward_site", "const int64_t sites[2] = {y, neighbour(p, y, mu, +1)};",
      "const int64_t sites[2] = {y, y};"),
 ]
