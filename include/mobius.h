@@ -181,6 +181,20 @@ int mobius_dslash(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
 int mobius_dslash_dag(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
                       const void *in, void *out, int32_t nrhs, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * operator blocks of mobius_dslash (dagger = 0) and mobius_dslash_dag
+ * (dagger = 1), same arguments and results, with no allocation of any kind.
+ * MOBIUS_OP_SCHUR keeps its two temporary packed fields per right-hand side in
+ * a fixed workspace of 64 MiB per GPU (a static device array that the library
+ * holds from the first mobius_create on that GPU until the process ends); a
+ * call needing more (2 * nrhs * mobius_field_bytes(ctx, prec) > 64 MiB)
+ * returns MOBIUS_EINVAL.  Every call on one GPU shares that workspace: calls
+ * that overlap in time on one GPU (different streams or threads) race and must
+ * be serialised by the caller.  Enqueued on stream, like mobius_dslash. */
+int mobius_dslash_noalloc(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
+                          int32_t dagger, const void *in, void *out, int32_t nrhs, void *stream);
+
 /* out = I^{-1} in (dagger = 0) or I^{-+} in (dagger = 1) on a packed half
  * field, by the closed-form elimination of Sec. 3 (I = A P- + A^T P+, each an
  * Ls x Ls cyclic bidiagonal solve per site, spin and colour). */

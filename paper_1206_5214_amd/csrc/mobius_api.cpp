@@ -230,6 +230,11 @@ extern "C" int mobius_create(mobius_ctx **out, const mobius_params *p, const voi
     };
     hipError_t e = hipGetDevice(&ctx->device);
     if (e != hipSuccess) return cleanup(fail(MOBIUS_EHIP, hipGetErrorString(e)));
+    // address of this device's workspace of mobius_dslash_noalloc (set up
+    // here, with the device current, so that the entry point allocates nothing)
+    e = noalloc_scratch_init(ctx->device);
+    if (e != hipSuccess)
+        return cleanup(fail(MOBIUS_EHIP, std::string("workspace address: ") + hipGetErrorString(e)));
     if (sdep) {
         e = ctx->ls_coef.ensure((int64_t)(tab.size() * sizeof(double)));
         if (e == hipSuccess)
@@ -380,8 +385,11 @@ hipError_t schur(mobius_ctx *ctx, int prec, int dag, const void *in, void *out, 
                st);
 }
 
+// fixed_scratch: caller-provided workspace of fixed_bytes for the SCHUR
+// temporaries (null: the context's own, allocated on first use)
 int dslash_common(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity, const void *in,
-                  void *out, int32_t nrhs, void *stream, int dag)
+                  void *out, int32_t nrhs, void *stream, int dag, void *fixed_scratch = nullptr,
+                  int64_t fixed_bytes = 0)
 {
     g_err.clear();
     if (int r = check_ctx(ctx)) return r;
@@ -411,8 +419,18 @@ int dslash_common(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
     case MOBIUS_OP_SCHUR: {
         if (out_parity != 1) return fail(MOBIUS_EINVAL, "SCHUR acts on the odd parity (out_parity = 1)");
         const int64_t fb = field_bytes(ctx->g, prec) * nrhs;
-        HIPCHK(ctx->scratch.ensure(2 * fb));
-        char *t = static_cast<char *>(ctx->scratch.p);
+        char *t;
+        if (fixed_scratch) {
+            if (2 * fb > fixed_bytes)
+                return fail(MOBIUS_EINVAL, "mobius_dslash_noalloc: SCHUR needs " + std::to_string(2 * fb) +
+                                               " bytes of workspace (two packed fields per right-hand "
+                                               "side), above the fixed maximum of " +
+                                               std::to_string(fixed_bytes));
+            t = static_cast<char *>(fixed_scratch);
+        } else {
+            HIPCHK(ctx->scratch.ensure(2 * fb));
+            t = static_cast<char *>(ctx->scratch.p);
+        }
         HIPCHK(schur(ctx, prec, dag, in, out, t, t + fb, nullptr, nrhs, st));
         return MOBIUS_OK;
     }
@@ -432,6 +450,18 @@ extern "C" int mobius_dslash_dag(mobius_ctx *ctx, int32_t prec, int32_t op, int3
                                  const void *in, void *out, int32_t nrhs, void *stream)
 {
     return dslash_common(ctx, prec, op, out_parity, in, out, nrhs, stream, 1);
+}
+
+extern "C" int mobius_dslash_noalloc(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
+                                     int32_t dagger, const void *in, void *out, int32_t nrhs,
+                                     void *stream)
+{
+    g_err.clear();
+    if (int r = check_ctx(ctx)) return r;
+    void *ws = noalloc_scratch(ctx->device);
+    if (!ws) return fail(MOBIUS_EHIP, "mobius_dslash_noalloc: no workspace on this device");
+    return dslash_common(ctx, prec, op, out_parity, in, out, nrhs, stream, dagger ? 1 : 0, ws,
+                         NOALLOC_SCRATCH_BYTES);
 }
 
 extern "C" int mobius_m5inv(mobius_ctx *ctx, int32_t prec, int32_t dagger, const void *in, void *out,

@@ -200,6 +200,12 @@ hipError_t launch_m5(const Geometry &g, const OpCoeffs &c, int prec, int kind, i
 // device memory, FP64 partial sums per block (deterministic fixed-order
 // reduction in launch_reduce_batch).
 int64_t blas_blocks(const Geometry &g);
+// Allocation-free workspace: a static device array of NOALLOC_SCRATCH_BYTES
+// per GPU.  noalloc_scratch_init (with `device` current) looks up its address
+// on that device once; noalloc_scratch returns it (null before init).
+constexpr int64_t NOALLOC_SCRATCH_BYTES = (int64_t)64 << 20;
+hipError_t noalloc_scratch_init(int device);
+void *noalloc_scratch(int device);
 // fill with zeros (kernel, not hipMemset, so it is safe under graph capture)
 hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t st);
 // Scalar updates of CGLS, on device (one thread per system):

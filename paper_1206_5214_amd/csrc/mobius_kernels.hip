@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <mutex>
 
 namespace mobius {
 namespace {
@@ -782,6 +783,39 @@ __global__ void cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t *
 int sites_per_wave(int Ls) { return 64 / Ls; }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free entry point (mobius_dslash_noalloc): one
+// statically sized array per GPU, held until the process ends.  In host code
+// `scratch` names a host-side stand-in, not device memory: only the address
+// that hipGetSymbolAddress returns for the current device is ever passed to a
+// kernel or a copy.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 HopTuning &hop_tuning()
 {

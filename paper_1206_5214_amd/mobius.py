@@ -24,7 +24,7 @@ OK, NOT_CONVERGED = 0, 1
 EXPORTS = ("mobius_create", "mobius_destroy", "mobius_field_bytes", "mobius_pack",
            "mobius_unpack", "mobius_dslash", "mobius_dslash_dag", "mobius_m5inv",
            "mobius_cg_solve", "mobius_batch_solve", "mobius_propagator4d", "mobius_force", "mobius_force_lie",
-           "mobius_tune", "mobius_set_tuning", "mobius_last_error")
+           "mobius_tune", "mobius_set_tuning", "mobius_last_error", "mobius_dslash_noalloc")
 
 
 class MobiusError(RuntimeError):
@@ -96,6 +96,7 @@ def lib():
         L.mobius_dslash.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp]
         L.mobius_dslash_dag.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp]
         L.mobius_m5inv.argtypes = [vp, i32, i32, vp, vp, i32, vp]
+        L.mobius_dslash_noalloc.argtypes = [vp, i32, i32, i32, i32, vp, vp, i32, vp]
         L.mobius_cg_solve.argtypes = [vp, vp, vp, ctypes.POINTER(_SolveOpts),
                                       ctypes.POINTER(_SolveInfo), vp]
         L.mobius_batch_solve.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -264,6 +265,17 @@ class Operator:
         self._check_packed(out, prec, nf, "output")
         f = lib().mobius_dslash_dag if dag else lib().mobius_dslash
         _check(f(self._h, prec, op, out_parity, _ptr(x), _ptr(out), nrhs, _stream()))
+        return out
+
+    def dslash_noalloc(self, x, out, out_parity, prec, op=OP_HOP, dag=False, nrhs=1):
+        """mobius_dslash_noalloc: the operator blocks of dslash into a caller's
+        output, with no allocation in the library (SCHUR uses its fixed
+        per-GPU workspace; see mobius.h)."""
+        nf = 2 * nrhs if op == OP_FULL else nrhs
+        self._check_packed(x, prec, nf, "input")
+        self._check_packed(out, prec, nf, "output")
+        _check(lib().mobius_dslash_noalloc(self._h, prec, op, out_parity, int(dag), _ptr(x),
+                                           _ptr(out), nrhs, _stream()))
         return out
 
     def m5inv(self, x, prec, dag=False, out=None, nrhs=1):
