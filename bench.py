@@ -11,9 +11,13 @@ value is the solve's algorithmic HBM traffic (every field read or written
 once per kernel, links once per hop) divided by that time.
 
 Also reported: the metered hop kernel (D_{p,1-p} = -1/2 H B, Sec. 3) per
-precision against the 8 TB/s HBM roofline, the plain-FP64 and mixed-FP32
-times to solution, and the CPU oracle (one application of the Schur
-operator) timed on the host cores.
+precision against the 8 TB/s HBM roofline (median of 2 x 100 per-launch
+event durations after 10 untimed launches), D_pre per precision, the
+plain-FP64, FP32- and FP16-operator times to solution with each solution's
+error against an FP64 solve to 1e-12 and the solver's condition-number
+estimate, the same on 16^3 x 32, Ls = 16 with a Gaussian source, multi-RHS and
+uneven-batch solves, the force, and the CPU oracle (hop, D_pre and CG on
+three lattices, all threads and one) timed on the host cores.
 
 Prints exactly one JSON line on stdout; progress goes to stderr.
 """
@@ -43,28 +47,31 @@ def hop_algo_bytes(op, prec):
     return 2 * op.field_bytes(prec) + 8 * 9 * (op.V // 2) * link_elem
 
 
-def time_hop(torch, op, prec, src_canon, reps):
-    """Average duration of the metered hop kernel, timed with events on the
-    stream the library launches on (torch's current stream)."""
-    from paper_1206_5214_amd import mobius
+def time_hop(torch, op, prec, src_canon, reps=100, warm=10):
+    """Duration of each of `reps` launches per parity of the metered hop kernel
+    after `warm` untimed ones, each bracketed by its own pair of events on
+    the stream the library launches on (torch's current stream).  Returns
+    (median, mean) in ms over the 2 reps launches."""
+    import statistics
     even, odd = op.pack(src_canon, prec)
     out_e = op.new_field(prec)
     out_o = op.new_field(prec)
-    for _ in range(5):
+    for _ in range(warm):
         op.dslash(odd, 0, prec, out=out_e)
         op.dslash(even, 1, prec, out=out_o)
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(reps):
-        op.dslash(odd, 0, prec, out=out_e)
-        op.dslash(even, 1, prec, out=out_o)
-    stop.record()
-    stop.synchronize()
-    ms = start.elapsed_time(stop) / (2 * reps)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(2 * reps)]
+    for k in range(reps):
+        for j, (x, outp, out) in enumerate(((odd, 0, out_e), (even, 1, out_o))):
+            a, b = ev[2 * k + j]
+            a.record()
+            op.dslash(x, outp, prec, out=out)
+            b.record()
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(b) for a, b in ev]
     del even, odd, out_e, out_o
-    return ms
+    return statistics.median(ms), statistics.fmean(ms)
 
 
 def time_schur(torch, op, prec, src_canon, reps):
@@ -121,25 +128,75 @@ def counters_for(kernel_key):
     return rec.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(U, eta, w):
-    """The FP64 oracle, as it stands, applying the red/black Schur operator
-    D_pre once to the odd half of the workload's source; GB/s by the same
-    algorithmic byte count as the GPU's two fused hop launches of D_pre."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(inputs, U2, eta2, w2):
+    """The FP64 oracle, as it stands, on the host cores: one hop block and one
+    D_pre application on the 4^4 (Ls 8), 16^3x32 (Ls 16) and 24^3x64 (Ls 12)
+    workloads and the complete red/black CG on 4^4 with every thread; then
+    one thread on the small ones (the large ones would take minutes).  value:
+    the hop on the headline lattice, GB/s by the GPU's algorithmic byte count."""
     import oracle
-    p = oracle.Params(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5)
-    x_odd = oracle.restrict(p, eta, 1)
-    t0 = time.perf_counter()
-    oracle.schur(p, U, x_odd)
-    dt = time.perf_counter() - t0
-    Vh = w.V // 2
-    fb = Vh * w.Ls * 192
-    links = 8 * 9 * Vh * 16
-    nbytes = 2 * (2 * fb + links) + fb
-    Lx, Ly, Lz, Lt = w.dims
-    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"one FP64 oracle application of D_pre = 1 - I^-1 D_oe I^-1 D_eo to the odd "
-                      f"half of the {Lx}x{Ly}x{Lz}x{Lt}, Ls={w.Ls} source ({dt:.1f} s)"}
+    nthreads = oracle.num_threads()
+    out = {"nproc": os.cpu_count(), "omp_threads": nthreads, "cpu_model": _cpu_model(),
+           "kind": "oracle", "runs": []}
+
+    def hop_bytes(w):
+        Vh = w.V // 2
+        return 2 * Vh * w.Ls * 192 + 8 * 9 * Vh * 16
+
+    def run(name, w, U, eta, what, threads):
+        p = oracle.Params(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5)
+        oracle.set_num_threads(threads)
+        t0 = time.perf_counter()
+        rec = {"workload": name, "what": what, "threads": threads}
+        if what == "hop":
+            oracle.hop(p, U, eta, 0)
+            rec["GBps"] = hop_bytes(w) / (time.perf_counter() - t0) / 1e9
+        elif what == "schur":
+            oracle.schur(p, U, oracle.restrict(p, eta, 1))
+            rec["GBps"] = (2 * hop_bytes(w) + w.V // 2 * w.Ls * 192) / (time.perf_counter() - t0) / 1e9
+        else:
+            _, info = oracle.solve(p, U, eta, tol=w.tol, maxiter=20000)
+            rec.update(iters=info.iters, true_resid=info.true_resid)
+        rec["seconds"] = time.perf_counter() - t0
+        out["runs"].append(rec)
+        log(f"cpu baseline: {name} {what} on {threads} threads: {rec['seconds']:.2f} s")
+        return rec
+
+    fields = {}
+    for name in ("shamir_4x4x4x4_ls8", "mobius_16x16x16x32_ls16"):
+        w = inputs.WORKLOADS[name]
+        fields[name] = (w,) + inputs.workload_fields(w)
+    fields[w2.name] = (w2, U2, eta2)
+    for name in ("shamir_4x4x4x4_ls8", "mobius_16x16x16x32_ls16", w2.name):
+        w, U, eta = fields[name]
+        head = run(name, w, U, eta, "hop", nthreads)
+        if name != w2.name:
+            run(name, w, U, eta, "schur", nthreads)
+    w, U, eta = fields["shamir_4x4x4x4_ls8"]
+    run("shamir_4x4x4x4_ls8", w, U, eta, "cg", nthreads)
+    for name in ("shamir_4x4x4x4_ls8", "mobius_16x16x16x32_ls16"):
+        w, U, eta = fields[name]
+        run(name, w, U, eta, "hop", 1)
+    w, U, eta = fields["shamir_4x4x4x4_ls8"]
+    run("shamir_4x4x4x4_ls8", w, U, eta, "schur", 1)
+    run("shamir_4x4x4x4_ls8", w, U, eta, "cg", 1)
+    oracle.set_num_threads(nthreads)
+    Lx, Ly, Lz, Lt = w2.dims
+    out.update(value=head["GBps"], unit="GB/s", cores=nthreads,
+               sample=f"one FP64 oracle hop block D_eo on the {Lx}x{Ly}x{Lz}x{Lt}, Ls={w2.Ls} "
+                      f"workload ({head['seconds']:.1f} s on {nthreads} threads); every run in 'runs'")
+    return out
 
 
 def point_sources_gpu(torch, dims, Ls):
@@ -171,7 +228,7 @@ def multi_rhs_runs(torch, inputs, mobius):
     hop = {}
     for prec in (mobius.F64, mobius.F32, mobius.F16):
         op.tune(prec)
-        ms = time_hop(torch, op, prec, gauss, 50)
+        ms, _ = time_hop(torch, op, prec, gauss)
         nbytes = hop_algo_bytes(op, prec)
         hop[PREC_NAMES[prec]] = {"us": ms * 1e3, "algo_bytes": nbytes,
                                  "GBps": nbytes / (ms * 1e-3) / 1e9,
@@ -290,6 +347,57 @@ def uneven_batch_runs(torch, inputs, mobius):
     return out
 
 
+def gaussian_c1_runs(torch, inputs, mobius):
+    """16^3 x 32, Ls = 16, b5 = 1.5, c5 = 0.5 with a Gaussian source: plain FP64
+    CG against the FP32- and FP16-operator CG with FP64 reliable updates, each
+    to a 1e-10 true residual, with every solve's error against an FP64 solve
+    to 1e-12."""
+    w = inputs.WORKLOADS["mobius_16x16x16x32_ls16"]
+    U, eta = inputs.workload_fields(w)
+    op = mobius.Operator(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, torch.from_numpy(U).cuda())
+    src = torch.from_numpy(eta).cuda()
+    del U, eta
+    for prec in (mobius.F64, mobius.F32, mobius.F16):
+        op.tune(prec)
+    out = {"workload": w.name}
+    ref, iref, rc = op.solve(src, tol=1e-12, maxiter=50000)
+    if rc != mobius.OK:
+        raise RuntimeError(f"reference solve failed: {iref}")
+    for prec in (mobius.F64, mobius.F32, mobius.F16):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sol, info, rc = op.solve(src, tol=w.tol, maxiter=50000, inner_prec=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        i = info[0]
+        if rc != mobius.OK:
+            raise RuntimeError(f"c1 solve failed: {i}")
+        out[PREC_NAMES[prec]] = {"seconds": dt, "iters": i.iters, "reliable_updates": i.reliable_updates,
+                                 "true_resid": i.true_resid, "kappa": i.kappa, "err_bound": i.err_bound,
+                                 "rel_error_vs_ref": _rel(torch, sol, ref)}
+        log(f"c1 gaussian {PREC_NAMES[prec]}: {dt:.3f} s, {i.iters} iters, resid {i.true_resid:.2e}, "
+            f"error {out[PREC_NAMES[prec]]['rel_error_vs_ref']:.2e}")
+        del sol
+    # the FP16 operator with the solution-error target 1e-8 as well
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol, info, rc = op.solve(src, tol=w.tol, maxiter=50000, inner_prec=mobius.F16, err_tol=1e-8)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    i = info[0]
+    if rc != mobius.OK:
+        raise RuntimeError(f"c1 solve with err_tol failed: {i}")
+    out["f16_err_tol_1e-8"] = {"seconds": dt, "iters": i.iters, "true_resid": i.true_resid, "kappa": i.kappa,
+                               "err_bound": i.err_bound, "rel_error_vs_ref": _rel(torch, sol, ref)}
+    log(f"c1 gaussian f16 with err_tol 1e-8: {dt:.3f} s, {i.iters} iters, bound {i.err_bound:.2e}, "
+        f"error {out['f16_err_tol_1e-8']['rel_error_vs_ref']:.2e}")
+    del sol, ref
+    for k in ("f32", "f16", "f16_err_tol_1e-8"):
+        out[k]["speedup_vs_f64"] = out["f64"]["seconds"] / out[k]["seconds"]
+    op.close()
+    return out
+
+
 def force_runs(torch, inputs, mobius):
     """Pseudofermion action S = phi_o^+ (D_pre^+ D_pre)^-1 phi_o with dS/dU and
     dS/dphi on the 24^3 x 64, Ls = 12 Moebius lattice (b5 = 1.5, c5 = 0.5):
@@ -333,7 +441,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mobius_24x24x24x64_ls12")
     ap.add_argument("--inner", default="f16", choices=["f64", "f32", "f16"])
-    ap.add_argument("--hop-reps", type=int, default=50)
+    ap.add_argument("--hop-reps", type=int, default=100,
+                    help="timed launches of the metered hop per parity (after 10 untimed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 / FP32 comparison solves")
@@ -371,14 +480,15 @@ def main():
     # -- metered hop kernel, every precision --------------------------------
     hop = {}
     for prec in (mobius.F64, mobius.F32, mobius.F16):
-        ms = time_hop(torch, op, prec, etad, args.hop_reps)
+        ms, ms_mean = time_hop(torch, op, prec, etad, args.hop_reps)
         nbytes = hop_algo_bytes(op, prec)
         gbs = nbytes / (ms * 1e-3) / 1e9
         flops = 1416.0 * (op.V // 2) * w.Ls
-        hop[PREC_NAMES[prec]] = {"us": ms * 1e3, "algo_bytes": nbytes, "GBps": gbs,
+        hop[PREC_NAMES[prec]] = {"us": ms * 1e3, "us_mean": ms_mean * 1e3, "launches": 2 * args.hop_reps,
+                                 "algo_bytes": nbytes, "GBps": gbs,
                                  "frac_hbm": gbs / HBM_PEAK_GBS,
                                  "GFLOPps": flops / (ms * 1e-3) / 1e9}
-        log(f"hop {PREC_NAMES[prec]}: {ms * 1e3:.1f} us  {gbs:.0f} GB/s  "
+        log(f"hop {PREC_NAMES[prec]}: median {ms * 1e3:.1f} us (mean {ms_mean * 1e3:.1f})  {gbs:.0f} GB/s  "
             f"({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
 
     # -- D_pre = 1 - I^-1 D_oe I^-1 D_eo (two fused hop launches) -----------
@@ -396,11 +506,11 @@ def main():
     log(f"device copy: {copy_gbs:.0f} GB/s")
 
     # -- the step: complete solves to 1e-10 ---------------------------------
-    def solve(prec):
-        sol, info, rc = op.solve(etad, tol=w.tol, maxiter=50000, inner_prec=prec)
+    def solve(prec, tol=w.tol, err_tol=0.0):
+        sol, info, rc = op.solve(etad, tol=tol, maxiter=50000, inner_prec=prec, err_tol=err_tol)
         i = info[0]
-        if rc != mobius.OK or i.true_resid > w.tol:
-            raise RuntimeError(f"solve did not reach {w.tol}: {i}")
+        if rc != mobius.OK or i.true_resid > tol:
+            raise RuntimeError(f"solve did not reach {tol}: {i}")
         return sol, i
 
     for k in range(args.warmup):
@@ -422,24 +532,41 @@ def main():
 
     compare = {}
     if not args.no_compare:
+        # reference: an FP64 solve to a 1e-12 true residual (its own error is
+        # bounded by its kappa times that residual); every solve's error is
+        # stated against it
+        ref, iref = solve(mobius.F64, tol=1e-12)
+        log(f"reference FP64 solve to 1e-12: {iref.iters} iters, kappa {iref.kappa:.1f}")
+
+        def err_vs_ref(x):
+            return (torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref)).item()
+
         for prec in (mobius.F64, mobius.F32, mobius.F16):
             if prec == inner:
-                compare[PREC_NAMES[prec]] = {"seconds": ms_per_step * 1e-3,
-                                            "iters": infos[-1].iters,
-                                            "true_resid": infos[-1].true_resid}
-                continue
-            s2, i2 = solve(prec)
-            err = (torch.linalg.vector_norm(s2 - sol) / torch.linalg.vector_norm(s2)).item()
-            compare[PREC_NAMES[prec]] = {"seconds": i2.seconds, "iters": i2.iters,
-                                         "true_resid": i2.true_resid,
-                                         "rel_diff_vs_headline": err}
-            log(f"compare {PREC_NAMES[prec]}: {i2.seconds:.3f} s, {i2.iters} iters, "
-                f"resid {i2.true_resid:.2e}, |diff|/|psi| {err:.2e}")
-            del s2
-        if "f64" in compare:
-            f64s = compare["f64"]["seconds"]
-            for k2, v in compare.items():
-                v["speedup_vs_f64"] = f64s / v["seconds"]
+                s2, i2, secs = sol, infos[-1], ms_per_step * 1e-3
+            else:
+                s2, i2 = solve(prec)
+                secs = i2.seconds
+            compare[PREC_NAMES[prec]] = {"seconds": secs, "iters": i2.iters,
+                                         "true_resid": i2.true_resid, "kappa": i2.kappa,
+                                         "err_bound": i2.err_bound, "rel_error_vs_ref": err_vs_ref(s2)}
+            log(f"compare {PREC_NAMES[prec]}: {secs:.3f} s, {i2.iters} iters, resid {i2.true_resid:.2e}, "
+                f"error {compare[PREC_NAMES[prec]]['rel_error_vs_ref']:.2e} (bound {i2.err_bound:.2e})")
+            if s2 is not sol:
+                del s2
+        f64s = compare["f64"]["seconds"]
+        for k2, v in compare.items():
+            v["speedup_vs_f64"] = f64s / v["seconds"]
+        # the headline operator with the solution-error target 1e-8 as well
+        s3, i3 = solve(inner, err_tol=1e-8)
+        compare[f"{PREC_NAMES[inner]}_err_tol_1e-8"] = {
+            "seconds": i3.seconds, "iters": i3.iters, "true_resid": i3.true_resid, "kappa": i3.kappa,
+            "err_bound": i3.err_bound, "rel_error_vs_ref": err_vs_ref(s3),
+            "speedup_vs_f64": f64s / i3.seconds}
+        log(f"{PREC_NAMES[inner]} with err_tol 1e-8: {i3.seconds:.3f} s, {i3.iters} iters, bound "
+            f"{i3.err_bound:.2e}, error {err_vs_ref(s3):.2e}")
+        del s3, ref
+    gaussian_c1 = None if args.no_compare else gaussian_c1_runs(torch, inputs, mobius)
 
     batch = None
     if not args.no_batch:
@@ -458,16 +585,19 @@ def main():
     traffic = counters_for(key)
     roofline = {"bound": "hbm", "achieved": hop[hname]["GBps"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": hop[hname]["GBps"] / HBM_PEAK_GBS,
-                "traffic": traffic, "kernel": f"hop_kernel {hname} (D_{{p,1-p}} = -1/2 H B)",
+                "traffic": traffic, "traffic_note": "L2-egress FETCH_SIZE + WRITE_SIZE per launch, "
+                "scaled by the same counters' reading for a plain device copy: an upper bound on the "
+                "HBM bytes (part of it is served by the Infinity Cache)",
+                "kernel": f"hop_kernel {hname} (D_{{p,1-p}} = -1/2 H B)",
+                "duration": "median of per-launch HIP-event durations",
                 "algo_bytes_per_launch": hop[hname]["algo_bytes"],
                 "copy_GBps": copy_gbs, "frac_of_copy": hop[hname]["GBps"] / copy_gbs}
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline: one oracle Schur-operator application on the same workload")
         del op
         torch.cuda.empty_cache()
-        cpu = cpu_baseline(U, eta, w)
+        cpu = cpu_baseline(inputs, U, eta, w)
         log(f"cpu baseline: {cpu['value']:.3f} GB/s on {cpu['cores']} threads ({cpu['sample']})")
 
     out = {
@@ -488,11 +618,15 @@ def main():
                    "b5": w.b5, "c5": w.c5, "link_eps": w.eps, "seed": w.seed, "tol": w.tol,
                    "inner_prec": hname, "reductions": "f64"},
         "solve": {"iters": infos[-1].iters, "reliable_updates": infos[-1].reliable_updates,
-                  "true_resid": infos[-1].true_resid, "algo_bytes": algo_bytes,
+                  "true_resid": infos[-1].true_resid, "kappa": infos[-1].kappa,
+                  "err_bound": infos[-1].err_bound, "algo_bytes": algo_bytes,
                   "GFLOPps": float(np.mean([i.flops for i in infos])) / (ms_per_step * 1e-3) / 1e9},
+        "dslash": {"kernel": f"hop {hname}", "GBps": hop[hname]["GBps"],
+                   "frac_hbm": hop[hname]["frac_hbm"], "GFLOPps": hop[hname]["GFLOPps"]},
         "hop": hop,
         "schur": schur,
         "time_to_solution": compare,
+        "gaussian_16x16x16x32_ls16": gaussian_c1,
         "batched": batch,
         "force": force,
         "tuning": tuning,

@@ -69,7 +69,9 @@ typedef enum {
     MOBIUS_OP_HOP = 0,   /* off-diagonal block D_{p,1-p} = -1/2 H B: parity 1-p -> p  (Sec. 3) */
     MOBIUS_OP_M5 = 1,    /* diagonal block I on one half field (parity-independent) (Sec. 3)  */
     MOBIUS_OP_SCHUR = 2, /* D_pre = 1 - I^-1 D_oe I^-1 D_eo, odd -> odd (out_parity must be 1)  */
-    MOBIUS_OP_FULL = 3   /* the unpreconditioned D_DW(m) on both halves (Sec. 2.1)            */
+    MOBIUS_OP_FULL = 3,  /* the unpreconditioned D_DW(m) on both halves (Sec. 2.1)            */
+    MOBIUS_OP_SCHUR_RIGHT = 4  /* D_R = 1 - D_oe I^-1 D_eo I^-1 = I D_pre I^-1, odd -> odd (Sec. 3,
+                                  the diagonal block taken out on the right; out_parity 1) */
 } mobius_op;
 
 typedef struct {
@@ -102,6 +104,11 @@ typedef struct {
     int32_t check_every;   /* iterations between host convergence checks (<= 0 selects 16) */
     double err_tol;        /* > 0: also iterate until err_bound (below) <= err_tol, tightening
                               the Schur target as needed; <= 0: the residual test alone */
+    int32_t form;          /* Schur system CGLS iterates on (Sec. 3): 0 = left-preconditioned
+                              D_pre psi_o = I^-1 (eta_o - D_oe I^-1 eta_e); 1 = right-preconditioned
+                              D_R z = eta_o - D_oe I^-1 eta_e, psi_o = I^-1 z (D_R = I D_pre I^-1).
+                              The same solution either way; schur_resid, kappa and err_bound refer
+                              to the system iterated on.  mobius_force uses 0. */
 } mobius_solve_opts;
 
 typedef struct {
@@ -161,6 +168,7 @@ int mobius_unpack(mobius_ctx *ctx, int32_t prec, const void *even, const void *o
  *                   gather s-1, s, s+1, then one Dirac application);
  *   MOBIUS_OP_M5    out = I in (both fields of parity out_parity);
  *   MOBIUS_OP_SCHUR out = D_pre in on the odd parity (out_parity must be 1);
+ *   MOBIUS_OP_SCHUR_RIGHT out = D_R in = in - D_oe I^-1 D_eo I^-1 in (odd, out_parity 1);
  *   MOBIUS_OP_FULL  out = D_DW(m) in, the whole 5d operator of Sec. 2.1 (the
  *                   block tridiagonal matrix in s with D+ = b5 D_W + 1 on the
  *                   diagonal), applied on both parities as
@@ -177,6 +185,7 @@ int mobius_dslash(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
  *                   = -1/2 B^+ H^+ in, H^+ = H with g_mu -> -g_mu;
  *   MOBIUS_OP_M5    out = I^+ in;
  *   MOBIUS_OP_SCHUR out = D_pre^+ in = in - (D_eo)^+ I^-+ (D_oe)^+ I^-+ in;
+ *   MOBIUS_OP_SCHUR_RIGHT out = D_R^+ in = in - I^-+ (D_eo)^+ I^-+ (D_oe)^+ in;
  *   MOBIUS_OP_FULL  out = D_DW(m)^+ in, out_p = (D^+)_{p,1-p} in_{1-p} + I^+ in_p. */
 int mobius_dslash_dag(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
                       const void *in, void *out, int32_t nrhs, void *stream);
@@ -209,6 +218,16 @@ int mobius_m5inv(mobius_ctx *ctx, int32_t prec, int32_t dagger, const void *in, 
 int mobius_cg_solve(mobius_ctx *ctx, const void *src_c128, void *sol_c128,
                     const mobius_solve_opts *opts, mobius_solve_info *info, void *stream);
 
+/* Solve the adjoint system D_DW(m)^+ psi = eta: the red/black decomposition of
+ * Sec. 3 applied to D_DW^+ (diagonal blocks I^+, off-diagonal blocks the
+ * adjoint hops), CGLS on its left-preconditioned Schur operator
+ * 1 - I^-+ (D^+)_oe I^-+ (D^+)_eo (whose adjoint is the right-preconditioned D_R
+ * of D_DW), the even half reconstructed, the FP64 true residual
+ * ||eta - D_DW^+ psi|| / ||eta||.  Arguments, precisions, reliable updates and
+ * return codes as mobius_cg_solve (opts->form is ignored). */
+int mobius_cg_solve_dag(mobius_ctx *ctx, const void *src_c128, void *sol_c128,
+                        const mobius_solve_opts *opts, mobius_solve_info *info, void *stream);
+
 /* 4d propagator of the overlap operator through the 5d solve (Sec. 2.2):
  *   q = [P^+ D_DW(m)^-1 D_DW(1) P b]_1 = D_ov(m)^-1 b,
  * with the chiral shift P_{ss'} = delta_{ss'} P- + delta_{s',s+1 mod Ls} P+
@@ -224,6 +243,25 @@ int mobius_cg_solve(mobius_ctx *ctx, const void *src_c128, void *sol_c128,
  * mobius_cg_solve. */
 int mobius_propagator4d(mobius_ctx *ctx, const void *src4_c128, void *sol4_c128,
                         const mobius_solve_opts *opts, mobius_solve_info *info, void *stream);
+
+/* Overlap to bulk domain-wall reconstruction (Sec. 2.3): given the overlap
+ * solution psi = D_ov(m)^-1 b (a 4d field, e.g. from mobius_propagator4d),
+ * the 5d field
+ *     Psi = P^+ D_DW(m)^-1 D_DW(1) P B,   B = b on slice 1 only,
+ * obtained with one Pauli-Villars solve instead of a D_DW(m) solve:
+ *     psi~ = psi on slice 1,  y = D_DW(1)^-1 D_DW(m) P psi~,  Omega = P^+ y,
+ *     Psi_1 = psi,  Psi_s = -Omega_s  (s = 2..Ls)
+ * (P the chiral shift of mobius_propagator4d, (P^+ y)_s = P- y_s + P+ y_{s-1}).
+ * The 5d solution of D_DW(m) X = D_DW(1) P B is X = P Psi.
+ * psi4_c128: canonical complex128 [t][z][y][x][spin][colour], opts->nrhs of
+ * them; Psi5_c128: canonical 5d fields (caller-owned device memory).  The
+ * Pauli-Villars solve runs as mobius_cg_solve with opts on a mass-1 view of
+ * the context (same links, M5, b5, c5, per-slice coefficients); info (opts->nrhs
+ * entries) describes it.  Temporaries (two canonical 5d fields and four packed
+ * FP64 half fields per right-hand side, and the view's solver buffers) stay
+ * with the context until mobius_destroy.  Returns as mobius_cg_solve. */
+int mobius_bulk5d(mobius_ctx *ctx, const void *psi4_c128, void *Psi5_c128,
+                  const mobius_solve_opts *opts, mobius_solve_info *info, void *stream);
 
 /* Solve a batch of independent systems on lattices of possibly different
  * sizes (one context each, opts->nrhs right-hand sides per context) in
@@ -258,6 +296,24 @@ int mobius_batch_solve(int32_t n, mobius_ctx *const *ctxs, const void *const *sr
 int mobius_force(mobius_ctx *ctx, const void *phi_c128, void *grad_links_c128, void *grad_phi_c128,
                  double *action, const mobius_solve_opts *opts, mobius_solve_info *info,
                  void *stream);
+
+/* 4d Hybrid Monte Carlo action with the pseudofermion on the wall (Sec. 2.4):
+ *     S = phi^+ [P^+ D_DW(m)^-1 D_DW(1) D_DW(1)^+ D_DW(m)^-+ P]_{11} phi
+ *       = phi^+ (D_ov(m)^+ D_ov(m))^-1 phi,
+ * phi a 4d field (P the chiral shift of mobius_propagator4d: phi enters as
+ * P- phi on slice 1 and P+ phi on slice Ls), and its link gradient from the
+ * two inversions of Sec. 2.4,
+ *     chi = D(m)^-+ P phi~ (mobius_cg_solve_dag),  psi = D(m)^-1 D(1) D(1)^+ chi,
+ *     S = |D(1)^+ chi|^2,  dS = -2 Re <chi, dD(m) psi> + 2 Re <chi, dD(1) D(1)^+ chi>
+ * (dD the change of the hopping part of D_DW, whose wall coupling carries the
+ * mass).  phi4_c128: canonical [t][z][y][x][spin][colour] complex128;
+ * grad_links_c128: canonical links layout, dS/dRe U + i dS/dIm U per entry as
+ * mobius_force (NULL: S only); action: host pointer.  opts as mobius_cg_solve
+ * for both solves (nrhs 0 or 1); info receives one record for the pair
+ * (iterations and Dirac applications summed, the larger residual, kappa and
+ * bound).  Requires mu = 0.  Synchronises.  Returns as mobius_cg_solve. */
+int mobius_force_wall(mobius_ctx *ctx, const void *phi4_c128, void *grad_links_c128, double *action,
+                      const mobius_solve_opts *opts, mobius_solve_info *info, void *stream);
 
 /* Lie-algebra form of a link gradient, for molecular-dynamics updates:
  *   F_mu(x) = TA(U_mu(x) G_mu(x)^+),  TA(M) = (M - M^+)/2 - tr(M - M^+)/6,

@@ -51,6 +51,8 @@ def _bind(path):
     P = ctypes.POINTER(_Params)
     vp = ctypes.c_void_p
     L.orc_num_threads.restype = ctypes.c_int
+    L.orc_set_num_threads.argtypes = [ctypes.c_int]
+    L.orc_set_num_threads.restype = None
     L.orc_wilson.argtypes = [P, vp, vp, vp, ctypes.c_int]
     L.orc_dw.argtypes = [P, vp, vp, vp, ctypes.c_int]
     L.orc_dw_sites.argtypes = [P, vp, vp, ctypes.c_int, ctypes.c_int64, vp, vp, ctypes.c_int]
@@ -66,6 +68,14 @@ def _bind(path):
     L.orc_force.argtypes = [P, vp, vp, vp, ctypes.c_int64, vp, vp, ctypes.c_double,
                             ctypes.c_int32, ctypes.POINTER(_Info)]
     L.orc_force.restype = ctypes.c_double
+    L.orc_schur_right.argtypes = [P, vp, vp, vp, ctypes.c_int]
+    L.orc_schur_right.restype = None
+    L.orc_solve_form.argtypes = [P, vp, vp, vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int,
+                                 ctypes.POINTER(_Info)]
+    L.orc_solve_form.restype = None
+    L.orc_force_wall.argtypes = [P, vp, vp, ctypes.c_int64, vp, vp, ctypes.c_double, ctypes.c_int32,
+                                 ctypes.POINTER(_Info)]
+    L.orc_force_wall.restype = ctypes.c_double
     for f in ("orc_wilson", "orc_dw", "orc_dw_sites", "orc_hop", "orc_m5", "orc_m5inv",
               "orc_schur", "orc_cgls", "orc_solve", "orc_cgne"):
         getattr(L, f).restype = None
@@ -168,6 +178,11 @@ def num_threads() -> int:
     return int(lib().orc_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """Number of OpenMP threads of later oracle calls in this process."""
+    lib().orc_set_num_threads(int(n))
+
+
 def wilson(p: Params, U, psi4, dag=False):
     U, psi4 = _c128(U), _c128(psi4)
     out = np.empty_like(psi4)
@@ -239,6 +254,42 @@ def solve(p: Params, U, eta, tol=1e-12, maxiter=10000):
     return psi, Info(info.iters, bool(info.converged), info.rel_resid, info.true_resid)
 
 
+def schur_right(p: Params, U, psi, dag=False):
+    """D_R = 1 - D_oe I^-1 D_eo I^-1 (or its adjoint) on an odd-parity field."""
+    U, psi = _c128(U), _c128(psi)
+    out = np.empty_like(psi)
+    lib().orc_schur_right(ctypes.byref(p.c()), _ptr(U), _ptr(psi), _ptr(out), int(dag))
+    return out
+
+
+def solve_form(p: Params, U, eta, form, tol=1e-12, maxiter=10000):
+    """Red/black solve in form 0 (left), 1 (right) or 2 (the adjoint system
+    D_DW^+ psi = eta); returns (psi, Info)."""
+    U, eta = _c128(U), _c128(eta)
+    psi = np.empty_like(eta)
+    info = _Info()
+    lib().orc_solve_form(ctypes.byref(p.c()), _ptr(U), _ptr(eta), _ptr(psi), float(tol), int(maxiter),
+                         int(form), ctypes.byref(info))
+    return psi, Info(info.iters, bool(info.converged), info.rel_resid, info.true_resid)
+
+
+def force_wall(p: Params, U, phi4, links=None, tol=1e-13, maxiter=20000):
+    """S = phi^+ [P^+ D(m)^-1 D(1) D(1)^+ D(m)^-+ P]_11 phi (phi 4d, on the wall;
+    Sec. 2.4) and its link gradient (as force()).  Returns (S, grad, Info)."""
+    U, phi4 = _c128(U), _c128(phi4)
+    info = _Info()
+    if links is None:
+        grad = np.empty(p.link_shape(), np.complex128)
+        lk, nl = None, 0
+    else:
+        ids = np.ascontiguousarray([mu * p.V + i for mu, i in links], dtype=np.int64)
+        grad = np.empty((len(ids), 3, 3), np.complex128)
+        lk, nl = _ptr(ids), len(ids)
+    S = lib().orc_force_wall(ctypes.byref(p.c()), _ptr(U), _ptr(phi4), nl, lk, _ptr(grad), float(tol),
+                             int(maxiter), ctypes.byref(info))
+    return float(S), grad, Info(info.iters, bool(info.converged), info.rel_resid, info.true_resid)
+
+
 def propagator4d(p: Params, U, b4, tol=1e-12, maxiter=20000):
     """q = [P^+ D_DW(m)^-1 D_DW(1) P b]_1, the overlap propagator D_ov(m)^-1 b
     obtained from the 5d solve (Sec. 2.2).  The chiral shift P puts b on the
@@ -262,6 +313,37 @@ def propagator4d(p: Params, U, b4, tol=1e-12, maxiter=20000):
         qs.append(q)
         infos.append(info)
     return (qs[0] if single else np.stack(qs)), infos
+
+
+def bulk5d(p: Params, U, psi4, tol=1e-12, maxiter=20000):
+    """Overlap to bulk domain-wall reconstruction (Sec. 2.3): from the overlap
+    solution psi = D_ov(m)^-1 b, the 5d field Psi = P^+ D_DW(m)^-1 D_DW(1) P B
+    (B = b on slice 1 only) with a Pauli-Villars solve instead of a D_DW(m)
+    solve:  psi~ = psi on slice 1,  Omega = P^+ D_DW(1)^-1 D_DW(m) P psi~,
+    Psi_1 = psi and Psi_s = -Omega_s for s = 2..Ls.  (Omega_1 = D_ov(m) psi = b.)
+    psi4: [t][z][y][x][4][3] (leading nrhs allowed).  Returns (Psi, Omega,
+    [Info of each Pauli-Villars solve])."""
+    psi4 = _c128(psi4)
+    single = psi4.ndim == 6
+    ps = psi4[None] if single else psi4
+    pv = Params(p.dims, p.Ls, p.M5, 1.0, p.b5, p.c5, p.mu, p.b5s, p.c5s)
+    Ps, Os, infos = [], [], []
+    for psi in ps:
+        wall = np.zeros(p.shape5(), complex)      # P psi~: P- psi on slice 1, P+ psi on slice Ls
+        wall[0, ..., 2:, :] = psi[..., 2:, :]
+        wall[p.Ls - 1, ..., :2, :] = psi[..., :2, :]
+        y, info = solve(pv, U, dw(p, U, wall), tol=tol, maxiter=maxiter)
+        omega = np.empty_like(y)                  # (P^+ y)_s = P- y_s + P+ y_{s-1}
+        omega[..., 2:, :] = y[..., 2:, :]
+        omega[..., :2, :] = np.roll(y, 1, axis=0)[..., :2, :]
+        Psi = -omega
+        Psi[0] = psi
+        Ps.append(Psi)
+        Os.append(omega)
+        infos.append(info)
+    if single:
+        return Ps[0], Os[0], infos
+    return np.stack(Ps), np.stack(Os), infos
 
 
 def cgne(p: Params, U, phi, tol=1e-12, maxiter=10000):

@@ -163,6 +163,15 @@ int orc_num_threads(void)
 #endif
 }
 
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 void orc_wilson(const orc_params *p, const double *Ud, const double *ind, double *outd, int dag)
 {
     init_gammas();
@@ -540,13 +549,54 @@ static double norm2(const cplx *v, int64_t n)
     return s;
 }
 
+/* Right-preconditioned Schur operator on the odd parity (the same Schur
+ * decomposition of Sec. 3 with the diagonal block taken out on the right):
+ *   D_R = 1 - D_oe I^{-1} D_eo I^{-1} = I D_pre I^{-1},
+ *   D_R^+ = 1 - I^{-+} (D_eo)^+ I^{-+} (D_oe)^+.
+ * D_R^+ is also the left-preconditioned Schur operator of the adjoint matrix
+ * D_DW^+ (whose blocks are I^+ and the adjoint hops). */
+static void schur_right(const orc_params *p, const double *U, const cplx *in, cplx *out, int dag)
+{
+    const int64_t n = field_len(p);
+    cplx *t1 = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *t2 = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *xo = masked_copy(p, in, 1);
+    if (!dag) {
+        orc_m5inv(p, (double *)xo, (double *)t1, 0);      /* I^-1        (odd)  */
+        orc_hop(p, U, 0, (double *)t1, (double *)t2, 0);  /* D_eo        (even) */
+        orc_m5inv(p, (double *)t2, (double *)t1, 0);      /* I^-1        (even) */
+        orc_hop(p, U, 1, (double *)t1, (double *)t2, 0);  /* D_oe        (odd)  */
+    } else {
+        orc_hop(p, U, 0, (double *)xo, (double *)t1, 1);  /* (D_oe)^+    (even) */
+        orc_m5inv(p, (double *)t1, (double *)t2, 1);      /* I^-+        (even) */
+        orc_hop(p, U, 1, (double *)t2, (double *)t1, 1);  /* (D_eo)^+    (odd)  */
+        orc_m5inv(p, (double *)t1, (double *)t2, 1);      /* I^-+        (odd)  */
+    }
+    for (int64_t k = 0; k < n; ++k) out[k] = xo[k] - t2[k];
+    zero_other_parity(p, out, 1);
+    free(t1);
+    free(t2);
+    free(xo);
+}
+
+void orc_schur_right(const orc_params *p, const double *U, const double *in, double *out, int dag)
+{
+    schur_right(p, U, (const cplx *)in, (cplx *)out, dag);
+}
+
+/* operators CGLS iterates on: 0 = D_pre (left), 1 = D_DW, 2 = D_R (right),
+ * 3 = the left Schur operator of D_DW^+, i.e. D_R^+ (with dag: D_R) */
 static void apply_op(const orc_params *p, const double *U, int which, const cplx *in, cplx *out,
                      int dag)
 {
     if (which == 0)
         orc_schur(p, U, (const double *)in, (double *)out, dag);
-    else
+    else if (which == 1)
         orc_dw(p, U, (const double *)in, (double *)out, dag);
+    else if (which == 2)
+        schur_right(p, U, in, out, dag);
+    else
+        schur_right(p, U, in, out, !dag);
 }
 
 /* Conjugate gradient on the normal equations A^+ A x = A^+ b (CGLS form):
@@ -635,6 +685,64 @@ void orc_solve(const orc_params *p, const double *U, const double *etad, double 
 
     /* true residual of the full system */
     orc_dw(p, U, (double *)psi, (double *)t2, 0);
+    for (int64_t k = 0; k < n; ++k) t2[k] = eta[k] - t2[k];
+    if (info) {
+        double en = sqrt(norm2(eta, n));
+        info->true_resid = en > 0 ? sqrt(norm2(t2, n)) / en : 0.0;
+    }
+    free(ee);
+    free(eo);
+    free(t1);
+    free(t2);
+    free(xo);
+}
+
+/* Red/black solves in the other forms of the same Schur decomposition:
+ *  form 1 (right): z = I psi_o,  D_R z = eta_o - D_oe I^{-1} eta_e,
+ *                  psi_o = I^{-1} z,  psi_e = I^{-1}(eta_e - D_eo psi_o);
+ *  form 2 (adjoint system D_DW^+ psi = eta): the decomposition of D_DW^+, whose
+ *                  diagonal blocks are I^+ and off-diagonal blocks the adjoint
+ *                  hops ((D^+)_{oe} = (D_eo)^+ maps even to odd):
+ *                  b'_o = I^{-+}(eta_o - (D^+)_{oe} I^{-+} eta_e),
+ *                  (1 - I^{-+} (D^+)_{oe} I^{-+} (D^+)_{eo}) psi_o = b'_o,
+ *                  psi_e = I^{-+}(eta_e - (D^+)_{eo} psi_o).
+ * info->true_resid is that of the system solved (D_DW or D_DW^+). */
+void orc_solve_form(const orc_params *p, const double *U, const double *etad, double *psid,
+                    double tol, int32_t maxiter, int form, orc_info *info)
+{
+    if (form == 0) {
+        orc_solve(p, U, etad, psid, tol, maxiter, info);
+        return;
+    }
+    const int64_t n = field_len(p);
+    const cplx *eta = (const cplx *)etad;
+    cplx *psi = (cplx *)psid;
+    const int dg = form == 2;
+    cplx *ee = masked_copy(p, eta, 0);
+    cplx *eo = masked_copy(p, eta, 1);
+    cplx *t1 = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *t2 = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *xo = (cplx *)malloc(sizeof(cplx) * n);
+
+    orc_m5inv(p, (double *)ee, (double *)t1, dg);          /* I^-1 eta_e (I^-+)       */
+    orc_hop(p, U, 1, (double *)t1, (double *)t2, dg);      /* odd <- even block       */
+    for (int64_t k = 0; k < n; ++k) t2[k] = eo[k] - t2[k];
+    zero_other_parity(p, t2, 1);
+    if (form == 1) {
+        orc_cgls(p, U, 2, (double *)t2, (double *)t1, tol, maxiter, info);  /* z     */
+        orc_m5inv(p, (double *)t1, (double *)xo, 0);                        /* psi_o */
+    } else {
+        orc_m5inv(p, (double *)t2, (double *)t1, 1);                        /* b'_o  */
+        zero_other_parity(p, t1, 1);
+        orc_cgls(p, U, 3, (double *)t1, (double *)xo, tol, maxiter, info);
+    }
+    zero_other_parity(p, xo, 1);
+    orc_hop(p, U, 0, (double *)xo, (double *)t2, dg);      /* even <- odd block       */
+    for (int64_t k = 0; k < n; ++k) t2[k] = ee[k] - t2[k];
+    orc_m5inv(p, (double *)t2, (double *)t1, dg);          /* psi_e                   */
+    zero_other_parity(p, t1, 0);
+    for (int64_t k = 0; k < n; ++k) psi[k] = t1[k] + xo[k];
+    orc_dw(p, U, (double *)psi, (double *)t2, dg);
     for (int64_t k = 0; k < n; ++k) t2[k] = eta[k] - t2[k];
     if (info) {
         double en = sqrt(norm2(eta, n));
@@ -809,5 +917,113 @@ double orc_force(const orc_params *p, const double *U, const double *phid, doubl
     free(Z);
     free(W);
     free(t);
+    return S;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 4d-HMC action with the pseudofermion on the wall (Sec. 2.4)               */
+
+/* 2 Re <a, H[E] b> summed over the listed 4d sites, H[E] the hopping part of
+ * D_DW built on the link field E (D_DW[E] - D_DW[0]: the link-free diagonal
+ * parts cancel). */
+static double hopping_overlap(const orc_params *p, const cplx *E, const cplx *Z, const cplx *a,
+                              const cplx *b, const int64_t *sites, int nsites, cplx *tmp,
+                              cplx *tmp0, cplx *buf)
+{
+    const int64_t V = vol4(p);
+    double acc = 0.0;
+    for (int j = 0; j < nsites; ++j) {
+        dw_site(p, E, b, sites[j], tmp, 0, buf);
+        dw_site(p, Z, b, sites[j], tmp0, 0, buf);
+        for (int s = 0; s < p->Ls; ++s)
+            for (int k = 0; k < SITE_DOF; ++k)
+                acc += 2.0 * creal(conj(a[((int64_t)s * V + sites[j]) * SITE_DOF + k]) *
+                                   (tmp[s * SITE_DOF + k] - tmp0[s * SITE_DOF + k]));
+    }
+    return acc;
+}
+
+/* S = phi^+ [P^+ D(m)^-1 D(1) D(1)^+ D(m)^-+ P]_{11} phi for a 4d pseudofermion
+ * phi on the wall (slice 1 of the propagator matrix: P phi~, phi~ = phi on s = 1),
+ * which equals phi^+ (D_ov^+ D_ov)^-1 phi.  With
+ *   chi = D(m)^-+ P phi~,   psi = D(m)^-1 D(1) D(1)^+ chi,
+ * S = |D(1)^+ chi|^2 and a change of the links changes it by
+ *   dS = -2 Re <chi, dD(m) psi> + 2 Re <chi, dD(1) D(1)^+ chi>
+ * (the two inversions of Sec. 2.4; dD the change of the hopping part, which
+ * depends on the mass through the wall coupling of B).  The gradient per link
+ * entry follows orc_force: directional derivatives along e_ab and i e_ab. */
+double orc_force_wall(const orc_params *p, const double *Ud, const double *phid, int64_t nlinks,
+                      const int64_t *links, double *gradd, double tol, int32_t maxiter,
+                      orc_info *info)
+{
+    init_gammas();
+    const cplx *phi = (const cplx *)phid;
+    cplx *grad = (cplx *)gradd;
+    const int64_t n = field_len(p);
+    const int64_t V = vol4(p);
+    const int Ls = p->Ls;
+    orc_params pv = *p;
+    pv.mf = 1.0;
+    cplx *w = (cplx *)calloc((size_t)n, sizeof(cplx));
+    cplx *chi = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *d1c = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *t = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *psi = (cplx *)malloc(sizeof(cplx) * n);
+    /* P phi~: P- phi on slice 1, P+ phi on slice Ls */
+    for (int64_t x = 0; x < V; ++x)
+        for (int sp = 0; sp < NSPIN; ++sp)
+            for (int a = 0; a < NCOL; ++a) {
+                const int64_t k = x * SITE_DOF + sp * NCOL + a;
+                const int s = chirality(sp) < 0 ? 0 : Ls - 1;
+                w[(int64_t)s * V * SITE_DOF + k] = phi[k];
+            }
+    orc_info i1, i2;
+    orc_solve_form(p, Ud, (double *)w, (double *)chi, tol, maxiter, 2, &i1);  /* D(m)^+ chi = P phi~ */
+    orc_dw(&pv, Ud, (double *)chi, (double *)d1c, 1);                         /* D(1)^+ chi          */
+    orc_dw(&pv, Ud, (double *)d1c, (double *)t, 0);                           /* D(1) D(1)^+ chi     */
+    orc_solve(p, Ud, (double *)t, (double *)psi, tol, maxiter, &i2);          /* psi                 */
+    const double S = norm2(d1c, n);
+    if (info) {
+        info->iters = i1.iters + i2.iters;
+        info->converged = i1.converged && i2.converged;
+        info->rel_resid = fmax(i1.rel_resid, i2.rel_resid);
+        info->true_resid = fmax(i1.true_resid, i2.true_resid);
+    }
+    const int64_t nl = links ? nlinks : 4 * V;
+#pragma omp parallel
+    {
+        cplx *E = (cplx *)calloc((size_t)4 * V * 9, sizeof(cplx));
+        cplx *Z = (cplx *)calloc((size_t)4 * V * 9, sizeof(cplx));
+        cplx *buf = (cplx *)calloc((size_t)V * SITE_DOF, sizeof(cplx));
+        cplx *tmp = (cplx *)malloc(sizeof(cplx) * Ls * SITE_DOF);
+        cplx *tmp0 = (cplx *)malloc(sizeof(cplx) * Ls * SITE_DOF);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t l = 0; l < nl; ++l) {
+            const int64_t lid = links ? links[l] : l;
+            const int mu = (int)(lid / V);
+            const int64_t y = lid % V;
+            const int64_t at[2] = {y, neighbour(p, y, mu, +1)};  /* the rows link l enters */
+            for (int e = 0; e < 9; ++e) {
+                double d[2];
+                for (int part = 0; part < 2; ++part) {
+                    E[lid * 9 + e] = part ? I : 1.0;
+                    d[part] = -hopping_overlap(p, E, Z, chi, psi, at, 2, tmp, tmp0, buf) +
+                              hopping_overlap(&pv, E, Z, chi, d1c, at, 2, tmp, tmp0, buf);
+                    E[lid * 9 + e] = 0.0;
+                }
+                grad[l * 9 + e] = d[0] + I * d[1];
+            }
+        }
+        free(E);
+        free(Z);
+        free(buf);
+        free(tmp);
+        free(tmp0);
+    }
+    free(w);
+    free(chi);
+    free(d1c);
+    free(t);
+    free(psi);
     return S;
 }

@@ -59,8 +59,9 @@ typedef struct {
     double  true_resid;  /* ||eta - D_DW psi|| / ||eta|| (full solves only) */
 } orc_info;
 
-/* number of OpenMP threads the oracle runs with */
+/* number of OpenMP threads the oracle runs with, and a way to change it */
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 /* 4d Wilson operator D_W (dag = 0) or its adjoint D_W^+ (dag = 1). */
 void orc_wilson(const orc_params *p, const double *U, const double *in, double *out, int dag);
@@ -114,6 +115,25 @@ void orc_cgne(const orc_params *p, const double *U, const double *phi, double *X
 double orc_force(const orc_params *p, const double *U, const double *phi, double *X,
                  int64_t nlinks, const int64_t *links, double *grad, double tol,
                  int32_t maxiter, orc_info *info);
+
+/* Right-preconditioned Schur operator D_R = 1 - D_oe I^{-1} D_eo I^{-1} (dag = 1:
+ * its adjoint) on odd-parity fields. */
+void orc_schur_right(const orc_params *p, const double *U, const double *in, double *out, int dag);
+
+/* Red/black solve in another form of the Schur decomposition: form 0 = left
+ * (orc_solve), 1 = right-preconditioned (D_R z = ..., psi_o = I^{-1} z),
+ * 2 = the adjoint system D_DW^+ psi = eta (left form of the decomposition of
+ * D_DW^+).  info->true_resid is that of the system solved. */
+void orc_solve_form(const orc_params *p, const double *U, const double *eta, double *psi,
+                    double tol, int32_t maxiter, int form, orc_info *info);
+
+/* 4d-HMC action of Sec. 2.4 with the pseudofermion on the wall:
+ * S = phi^+ [P^+ D(m)^-1 D(1) D(1)^+ D(m)^-+ P]_{11} phi (phi a 4d field
+ * [t][z][y][x][4][3]) and dS/dU for the listed links (as orc_force), from the
+ * two inversions chi = D(m)^-+ P phi~ and psi = D(m)^-1 D(1) D(1)^+ chi. */
+double orc_force_wall(const orc_params *p, const double *U, const double *phi, int64_t nlinks,
+                      const int64_t *links, double *grad, double tol, int32_t maxiter,
+                      orc_info *info);
 
 #ifdef __cplusplus
 }

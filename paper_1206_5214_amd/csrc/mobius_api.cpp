@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -289,16 +290,19 @@ extern "C" int mobius_destroy(mobius_ctx *ctx)
 {
     if (!ctx) return MOBIUS_OK;
     (void)hipDeviceSynchronize();
-    ctx->nbr.release();
-    ctx->canon_of.release();
-    for (auto &l : ctx->links) l.release();
-    for (auto &l : ctx->links_dag) l.release();
+    if (ctx->pv) mobius_destroy(ctx->pv);
+    if (!ctx->borrowed) {
+        ctx->nbr.release();
+        ctx->canon_of.release();
+        for (auto &l : ctx->links) l.release();
+        for (auto &l : ctx->links_dag) l.release();
+        ctx->ls_coef.release();
+    }
     ctx->scratch.release();
     ctx->work.release();
     ctx->partials.release();
     ctx->scalars.release();
     ctx->prop.release();
-    ctx->ls_coef.release();
     if (ctx->solve_stream) (void)hipStreamDestroy(ctx->solve_stream);
     delete ctx;
     return MOBIUS_OK;
@@ -416,6 +420,33 @@ int dslash_common(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
         HIPCHK(hop(ctx, hop_args(prec, dag, EPI_M5ADD, 1, ie, oo, nullptr, io, nullptr, nrhs), st));
         return MOBIUS_OK;
     }
+    case MOBIUS_OP_SCHUR_RIGHT: {
+        // D_R = 1 - D_oe I^-1 D_eo I^-1 (v = I^-1 in, t = B I^-1 D_eo v, out = in - D_oe t);
+        // D_R^+ = 1 - I^-+ D_eo^+ I^-+ D_oe^+ (t = I^-+ D_oe^+ in, out = in - I^-+ D_eo^+ t)
+        if (out_parity != 1) return fail(MOBIUS_EINVAL, "SCHUR_RIGHT acts on the odd parity (out_parity = 1)");
+        const int64_t fb = field_bytes(ctx->g, prec) * nrhs;
+        char *t;
+        if (fixed_scratch) {
+            if (2 * fb > fixed_bytes)
+                return fail(MOBIUS_EINVAL, "mobius_dslash_noalloc: SCHUR_RIGHT needs " + std::to_string(2 * fb) +
+                                               " bytes of workspace, above the fixed maximum of " +
+                                               std::to_string(fixed_bytes));
+            t = static_cast<char *>(fixed_scratch);
+        } else {
+            HIPCHK(ctx->scratch.ensure(2 * fb));
+            t = static_cast<char *>(ctx->scratch.p);
+        }
+        char *v = t + fb;
+        if (!dag) {
+            HIPCHK(launch_m5(ctx->g, ctx->c, prec, 1, 0, in, v, nrhs, st));
+            HIPCHK(hop(ctx, hop_args(prec, 0, EPI_M5INV | EPI_BMIX, 0, v, t, nullptr, nullptr, nullptr, nrhs), st));
+            HIPCHK(hop(ctx, hop_args(prec, 0, EPI_PREMIXED | EPI_POSTSUB, 1, t, out, in, nullptr, nullptr, nrhs), st));
+        } else {
+            HIPCHK(hop(ctx, hop_args(prec, 1, EPI_M5INV, 0, in, t, nullptr, nullptr, nullptr, nrhs), st));
+            HIPCHK(hop(ctx, hop_args(prec, 1, EPI_M5INV | EPI_POSTSUB, 1, t, out, in, nullptr, nullptr, nrhs), st));
+        }
+        return MOBIUS_OK;
+    }
     case MOBIUS_OP_SCHUR: {
         if (out_parity != 1) return fail(MOBIUS_EINVAL, "SCHUR acts on the odd parity (out_parity = 1)");
         const int64_t fb = field_bytes(ctx->g, prec) * nrhs;
@@ -490,6 +521,20 @@ extern "C" int mobius_cg_solve(mobius_ctx *ctx, const void *src, void *sol,
     return batch_solve(ctxs, 1, srcs, sols, *opts, info, S(stream));
 }
 
+extern "C" int mobius_cg_solve_dag(mobius_ctx *ctx, const void *src, void *sol,
+                                   const mobius_solve_opts *opts, mobius_solve_info *info, void *stream)
+{
+    g_err.clear();
+    if (int r = check_ctx(ctx)) return r;
+    if (!src || !sol || !opts || !info) return fail(MOBIUS_EINVAL, "null argument to mobius_cg_solve_dag");
+    if (src == sol) return fail(MOBIUS_EINVAL, "source and solution alias");
+    if (int r = check_prec(opts->inner_prec)) return r;
+    mobius_ctx *const ctxs[1] = {ctx};
+    const void *const srcs[1] = {src};
+    void *const sols[1] = {sol};
+    return batch_solve(ctxs, 1, srcs, sols, *opts, info, S(stream), true);
+}
+
 extern "C" int mobius_batch_solve(int32_t n, mobius_ctx *const *ctxs, const void *const *src,
                                   void *const *sol, const mobius_solve_opts *opts,
                                   mobius_solve_info *info, void *stream)
@@ -554,6 +599,72 @@ extern "C" int mobius_propagator4d(mobius_ctx *ctx, const void *src4, void *sol4
     return rc;
 }
 
+namespace {
+
+// The Pauli-Villars (mf = 1) view of a context: the same lattice, links and
+// per-slice coefficients, its own solver buffers (created on first use).
+mobius_ctx *pv_view(mobius_ctx *ctx)
+{
+    if (ctx->pv) return ctx->pv;
+    mobius_ctx *v = new mobius_ctx();
+    v->P = ctx->P;
+    v->P.mf = 1.0;
+    v->c = make_coeffs(v->P);
+    v->c.ls = ctx->c.ls;
+    v->g = ctx->g;
+    v->device = ctx->device;
+    v->canon_of = ctx->canon_of;
+    v->nbr = ctx->nbr;
+    for (int q = 0; q < 3; ++q) {
+        v->links[q] = ctx->links[q];
+        v->links_dag[q] = ctx->links_dag[q];
+        v->tune[q] = ctx->tune[q];
+    }
+    v->ls_coef = ctx->ls_coef;
+    v->has_mu = ctx->has_mu;
+    v->sdep = ctx->sdep;
+    v->borrowed = true;
+    ctx->pv = v;
+    return v;
+}
+
+}  // namespace
+
+extern "C" int mobius_bulk5d(mobius_ctx *ctx, const void *psi4, void *Psi5, const mobius_solve_opts *opts,
+                             mobius_solve_info *info, void *stream)
+{
+    g_err.clear();
+    if (int r = check_ctx(ctx)) return r;
+    if (!psi4 || !Psi5 || !opts || !info) return fail(MOBIUS_EINVAL, "null argument to mobius_bulk5d");
+    if (psi4 == Psi5) return fail(MOBIUS_EINVAL, "input and output alias");
+    if (int r = check_prec(opts->inner_prec)) return r;
+    const int nrhs = opts->nrhs > 0 ? opts->nrhs : 1;
+    hipStream_t st = S(stream);
+    const Geometry &g = ctx->g;
+    // temporaries: r = D(m) P psi~ and y (canonical 5d), the packed halves of
+    // P psi~ and of r (FP64); P psi~ itself lives in y's buffer until packed
+    const int64_t c5 = g.V * g.Ls * 12 * (int64_t)sizeof(double2) * nrhs;
+    const int64_t fb = field_bytes(g, MOBIUS_F64) * nrhs;
+    HIPCHK(ctx->prop.ensure(2 * c5 + 4 * fb));
+    char *rr = static_cast<char *>(ctx->prop.p), *y = rr + c5, *wall = y;
+    char *we = y + c5, *wo = we + fb, *re = wo + fb, *ro = re + fb;
+    HIPCHK(launch_wall_place(g, psi4, wall, nrhs, st));  // P psi~ (psi~ = psi on slice 1)
+    HIPCHK(launch_pack_spinor(g, MOBIUS_F64, wall, we, wo, nrhs, st));
+    HIPCHK(hop(ctx, hop_args(MOBIUS_F64, 0, EPI_M5ADD, 0, wo, re, nullptr, we, nullptr, nrhs), st));
+    HIPCHK(hop(ctx, hop_args(MOBIUS_F64, 0, EPI_M5ADD, 1, we, ro, nullptr, wo, nullptr, nrhs), st));
+    HIPCHK(launch_unpack_spinor(g, MOBIUS_F64, re, ro, rr, nrhs, st));
+    // D(1) y = r: the Pauli-Villars solve
+    mobius_solve_opts o = *opts;
+    o.nrhs = nrhs;
+    mobius_ctx *const ctxs[1] = {pv_view(ctx)};
+    const void *const srcs[1] = {rr};
+    void *const sols[1] = {y};
+    const int rc = batch_solve(ctxs, 1, srcs, sols, o, info, st);
+    if (rc < 0) return rc;
+    HIPCHK(launch_bulk_assemble(g, psi4, y, Psi5, nrhs, st));
+    return rc;
+}
+
 extern "C" int mobius_force_lie(mobius_ctx *ctx, const void *links_c128, const void *grad_links_c128,
                                 void *lie_c128, void *stream)
 {
@@ -580,6 +691,95 @@ extern "C" int mobius_force(mobius_ctx *ctx, const void *phi, void *grad_links, 
     if (phi == grad_phi || phi == grad_links || grad_phi == grad_links)
         return fail(MOBIUS_EINVAL, "mobius_force arguments alias");
     return mobius::force(ctx, phi, grad_links, grad_phi, action, *opts, info, S(stream));
+}
+
+extern "C" int mobius_force_wall(mobius_ctx *ctx, const void *phi4, void *grad_links, double *action,
+                                 const mobius_solve_opts *opts, mobius_solve_info *info, void *stream)
+{
+    g_err.clear();
+    if (int r = check_ctx(ctx)) return r;
+    if (!phi4 || !action || !opts || !info) return fail(MOBIUS_EINVAL, "null argument to mobius_force_wall");
+    if (opts->nrhs > 1) return fail(MOBIUS_EINVAL, "mobius_force_wall takes one source (nrhs <= 1)");
+    if (ctx->has_mu) return fail(MOBIUS_EINVAL, "mobius_force_wall: no chemical potential (mu must be 0)");
+    if (int r = check_prec(opts->inner_prec)) return r;
+    if (grad_links == phi4) return fail(MOBIUS_EINVAL, "mobius_force_wall arguments alias");
+    hipStream_t st = S(stream);
+    const Geometry &g = ctx->g;
+    // temporaries: three canonical 5d fields (P phi~ then D(1) D(1)^+ chi, chi,
+    // psi), the packed halves of chi, of psi and of D(1)^+ chi, norm partials
+    const int64_t c5 = g.V * g.Ls * 12 * (int64_t)sizeof(double2);
+    const int64_t fb = field_bytes(g, MOBIUS_F64);
+    const int64_t nb = norm2_blocks(2 * fb / 8);
+    HIPCHK(ctx->prop.ensure(3 * c5 + 6 * fb + (nb + 1) * (int64_t)sizeof(double)));
+    char *w = static_cast<char *>(ctx->prop.p), *chi = w + c5, *psi = chi + c5;
+    char *ce = psi + c5, *co = ce + fb, *pe = co + fb, *po = pe + fb, *de = po + fb, *dd = de + fb;
+    double *parts = reinterpret_cast<double *>(dd + fb), *snorm = parts + nb;
+    mobius_solve_opts o = *opts;
+    o.nrhs = 1;
+    mobius_ctx *const ctxs[1] = {ctx};
+    mobius_solve_info i1{}, i2{};
+    // chi = D(m)^-+ P phi~
+    HIPCHK(launch_wall_place(g, phi4, w, 1, st));
+    {
+        const void *const srcs[1] = {w};
+        void *const sols[1] = {chi};
+        const int rc = batch_solve(ctxs, 1, srcs, sols, o, &i1, st, true);
+        if (rc < 0) return rc;
+    }
+    // d = D(1)^+ chi, then w = D(1) d (the Pauli-Villars operator on the same links)
+    mobius_params pvp = ctx->P;
+    pvp.mf = 1.0;
+    OpCoeffs cpv = make_coeffs(pvp);
+    cpv.ls = ctx->c.ls;
+    const int32_t *nbr = static_cast<const int32_t *>(ctx->nbr.p);
+    HIPCHK(launch_pack_spinor(g, MOBIUS_F64, chi, ce, co, 1, st));
+    for (int dag = 1; dag >= 0; --dag) {
+        const char *ie = dag ? ce : de, *io = dag ? co : dd;
+        char *oe = dag ? de : pe, *oo = dag ? dd : po;
+        HopArgs a = hop_args(MOBIUS_F64, dag, EPI_M5ADD, 0, io, oe, nullptr, ie, nullptr, 1);
+        a.tune = &ctx->tune[MOBIUS_F64];
+        HIPCHK(launch_hop(g, cpv, hop_links(ctx, MOBIUS_F64, dag), nbr, a, st));
+        a = hop_args(MOBIUS_F64, dag, EPI_M5ADD, 1, ie, oo, nullptr, io, nullptr, 1);
+        a.tune = &ctx->tune[MOBIUS_F64];
+        HIPCHK(launch_hop(g, cpv, hop_links(ctx, MOBIUS_F64, dag), nbr, a, st));
+    }
+    HIPCHK(launch_norm2_f64(reinterpret_cast<const double *>(de), 2 * fb / 8, parts, snorm, st));  // S = |d|^2
+    HIPCHK(launch_unpack_spinor(g, MOBIUS_F64, pe, po, w, 1, st));
+    // psi = D(m)^-1 D(1) D(1)^+ chi
+    {
+        const void *const srcs[1] = {w};
+        void *const sols[1] = {psi};
+        const int rc = batch_solve(ctxs, 1, srcs, sols, o, &i2, st, false);
+        if (rc < 0) return rc;
+    }
+    if (grad_links) {
+        // G = -G[chi, psi; m] + G[chi, d; 1], G[L, R; c] the gradient of 2 Re <L, dD_hop R>
+        HIPCHK(launch_pack_spinor(g, MOBIUS_F64, psi, pe, po, 1, st));
+        for (int par = 0; par < 2; ++par) {
+            const char *Lp = par ? co : ce, *Ln = par ? ce : co;
+            HIPCHK(launch_force(g, ctx->c, par, nbr, Lp, par ? po : pe, Ln, par ? pe : po, grad_links, st,
+                                -1.0, false));
+            HIPCHK(launch_force(g, cpv, par, nbr, Lp, par ? dd : de, Ln, par ? de : dd, grad_links, st,
+                                1.0, true));
+        }
+    }
+    HIPCHK(hipMemcpyAsync(action, snorm, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    // one record for the pair of solves: iterations and Dirac applications
+    // summed, the worse residual, the larger condition number
+    *info = i2;
+    info->iters = i1.iters + i2.iters;
+    info->dirac_apps = i1.dirac_apps + i2.dirac_apps + 4;
+    info->reliable_updates = i1.reliable_updates + i2.reliable_updates;
+    info->status = (i1.status == MOBIUS_OK && i2.status == MOBIUS_OK) ? MOBIUS_OK : MOBIUS_NOT_CONVERGED;
+    info->true_resid = std::max(i1.true_resid, i2.true_resid);
+    info->schur_resid = std::max(i1.schur_resid, i2.schur_resid);
+    info->seconds = i1.seconds + i2.seconds;
+    info->algo_bytes = i1.algo_bytes + i2.algo_bytes;
+    info->flops = i1.flops + i2.flops;
+    info->kappa = std::max(i1.kappa, i2.kappa);
+    info->err_bound = std::max(i1.err_bound, i2.err_bound);
+    return info->status;
 }
 
 extern "C" int mobius_tune(mobius_ctx *ctx, int32_t prec, int32_t reps, mobius_tune_result *out,

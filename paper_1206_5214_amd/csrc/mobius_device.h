@@ -849,11 +849,34 @@ __device__ __forceinline__ MixW<T> mix_w(const Coef<T> &k, bool minv, const Site
     return {a, (T)t[su * LSC + ox + 1], (T)t[sl * LSC + ox + 1]};
 }
 
-// C5 mixing in s from the lanes of the same 4d site.
+// C5 mixing in s from the lanes of the same 4d site, constant coefficients.
 //   forward  (C5 v)_s  = P+ v_{s-1} + P- v_{s+1}
 //   adjoint  (C5^+ v)_s = P+ v_{s+1} + P- v_{s-1}
-// wrapped neighbours carry -mf.  Returns w.a v + (w.bu P+ + w.bl P-) C5(^+) v
-// (alpha v + beta C5(^+) v for constant coefficients).
+// wrapped neighbours carry -mf.  Returns alpha * v + beta * C5(^+) v.
+template <typename T>
+__device__ __forceinline__ void mix_s(cx<T> v[12], T alpha, T beta, T mf, const SiteMap &m, int Ls,
+                                      bool adjoint)
+{
+    const int src_up = adjoint ? m.lp : m.lm;  // lane whose P+ part we take
+    const int src_lo = adjoint ? m.lm : m.lp;  // lane whose P- part we take
+    const bool wrap_up = adjoint ? (m.s == Ls - 1) : (m.s == 0);
+    const bool wrap_lo = adjoint ? (m.s == 0) : (m.s == Ls - 1);
+    const T fu = beta * (wrap_up ? -mf : (T)1);
+    const T fl = beta * (wrap_lo ? -mf : (T)1);
+    cx<T> up[6], lo[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        up[c] = shfl(v[c], src_up);
+        lo[c] = shfl(v[6 + c], src_lo);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        v[c] = alpha * v[c] + fu * up[c];
+        v[6 + c] = alpha * v[6 + c] + fl * lo[c];
+    }
+}
+
+// The same with per-lane weights: w.a v + (w.bu P+ + w.bl P-) C5(^+) v.
 template <typename T>
 __device__ __forceinline__ void mix_s(cx<T> v[12], MixW<T> w, T mf, const SiteMap &m, int Ls,
                                       bool adjoint)

@@ -96,7 +96,12 @@ __device__ __forceinline__ void force_dir(const ForceParams &fp, const SiteMap &
         for (int e = m.s; e < 9; e += fp.Ls) {
             cx<double> acc = {0, 0};
             for (int t = 0; t < fp.Ls; ++t) acc = acc + w[(base + t) * ST + e];
-            fp.grad[link * 9 + e] = make_double2(-acc.r, -acc.i);
+            double2 gv = make_double2(-fp.scale * acc.r, -fp.scale * acc.i);
+            if (fp.accumulate) {
+                const double2 old = fp.grad[link * 9 + e];
+                gv = make_double2(old.x + gv.x, old.y + gv.y);
+            }
+            fp.grad[link * 9 + e] = gv;
         }
     }
     __syncthreads();
@@ -170,9 +175,11 @@ hipError_t launch_lie_force(int64_t nlinks, const void *U, const void *G, void *
 
 hipError_t launch_force(const Geometry &g, const OpCoeffs &c, int parity, const int32_t *nbr,
                         const void *Lp, const void *Rp, const void *Ln, const void *Rn,
-                        void *grad, hipStream_t st)
+                        void *grad, hipStream_t st, double scale, bool accumulate)
 {
     ForceParams fp{};
+    fp.scale = scale;
+    fp.accumulate = accumulate ? 1 : 0;
     fp.Lp = static_cast<const char *>(Lp);
     fp.Rp = static_cast<const char *>(Rp);
     fp.Ln = static_cast<const char *>(Ln);
@@ -188,6 +195,61 @@ hipError_t launch_force(const Geometry &g, const OpCoeffs &c, int parity, const 
     fp.c = c;
     const int64_t blocks = site_kernel_blocks(g);
     hipLaunchKernelGGL(force_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, st, fp);
+    return hipGetLastError();
+}
+
+
+namespace {
+
+constexpr int SQ_BLOCK = 256;
+
+__global__ __launch_bounds__(SQ_BLOCK) void sumsq_partials_kernel(const double *x, int64_t n,
+                                                                 double *partials)
+{
+    double v = 0;
+    for (int64_t k = (int64_t)blockIdx.x * SQ_BLOCK + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * SQ_BLOCK)
+        v += x[k] * x[k];
+    __shared__ double red[SQ_BLOCK / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int w = 0; w < SQ_BLOCK / 64; ++w) t += red[w];
+        partials[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(SQ_BLOCK) void sum_partials_kernel(const double *partials, int64_t n,
+                                                               double *out)
+{
+    __shared__ double sm[SQ_BLOCK];
+    double t = 0;
+    for (int64_t k = threadIdx.x; k < n; k += SQ_BLOCK) t += partials[k];
+    sm[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = SQ_BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sm[0];
+}
+
+}  // namespace
+
+int64_t norm2_blocks(int64_t n)
+{
+    const int64_t b = (n + SQ_BLOCK - 1) / SQ_BLOCK;
+    return b < 2048 ? (b > 0 ? b : 1) : 2048;
+}
+
+hipError_t launch_norm2_f64(const double *x, int64_t n, double *partials, double *out, hipStream_t st)
+{
+    const int64_t nb = norm2_blocks(n);
+    hipLaunchKernelGGL(sumsq_partials_kernel, dim3((unsigned)nb), dim3(SQ_BLOCK), 0, st, x, n, partials);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(SQ_BLOCK), 0, st, partials, nb, out);
     return hipGetLastError();
 }
 

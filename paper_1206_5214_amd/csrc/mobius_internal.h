@@ -178,6 +178,9 @@ hipError_t launch_lie_force(int64_t nlinks, const void *U, const void *G, void *
 // 4d field on the walls of the fifth dimension and back (canonical layouts)
 hipError_t launch_wall_place(const Geometry &g, const void *b4, void *eta5, int nrhs, hipStream_t st);
 hipError_t launch_wall_read(const Geometry &g, const void *psi5, void *q4, int nrhs, hipStream_t st);
+// bulk reconstruction: Psi_0 = psi4, Psi_s = -(P- y_s + P+ y_{s-1}) for s > 0 (canonical layouts)
+hipError_t launch_bulk_assemble(const Geometry &g, const void *psi4, const void *y5, void *Psi5,
+                                int nrhs, hipStream_t st);
 hipError_t launch_pack_spinor(const Geometry &g, int prec, const void *canon, void *even, void *odd,
                               int nrhs, hipStream_t st);
 hipError_t launch_unpack_spinor(const Geometry &g, int prec, const void *even, const void *odd,
@@ -254,11 +257,12 @@ hipError_t launch_reduce_batch(const VecSys *sys_dev, int nsys, const int32_t *a
 // op 0: alpha = gamma / qq;  op 1: beta, gamma;  op 2: alpha = 0
 hipError_t launch_cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t *active,
                                   int32_t *restart, hipStream_t st);
-// r = a -= s0 b (|r|^2 partials per site block) and c = I^-+ r, in the site-lane
-// mapping of the hop (one workgroup per site block and system); max_blocks is
-// the largest number of site blocks of any system
+// r = a -= s0 b (|r|^2 partials per site block) and c = I^-+ r (mode 0), c =
+// I^-1 r (mode 1) or nothing (mode 2), in the site-lane mapping of the hop
+// (one workgroup per site block and system); max_blocks is the largest number
+// of site blocks of any system
 hipError_t launch_rupd_m5inv_batch(int prec, const VecSys *sys_dev, int nsys, int64_t max_blocks,
-                                   const int32_t *active, hipStream_t st);
+                                   const int32_t *active, int mode, hipStream_t st);
 
 // Link derivative of the pseudofermion action (mobius_force.hip): for the
 // sites y of one parity p, grad[mu][canon(y)] (complex128 3x3, canonical link
@@ -270,11 +274,19 @@ struct ForceParams {
     double2 *grad;
     int64_t Vh, N5, V;
     int Ls, spw;
+    double scale;     // grad = scale * G (accumulate: grad += scale * G)
+    int accumulate;
     OpCoeffs c;
 };
+// G of 2 Re <L, dD_hop R> (D_hop = -1/2 H B, the hopping part of D_DW with the
+// coefficients c) for the links U_mu(y) of the sites y of parity `parity`
 hipError_t launch_force(const Geometry &g, const OpCoeffs &c, int parity, const int32_t *nbr,
                         const void *Lp, const void *Rp, const void *Ln, const void *Rn,
-                        void *grad, hipStream_t st);
+                        void *grad, hipStream_t st, double scale = 1.0, bool accumulate = false);
+// *out = sum of |x_k|^2 over n doubles (FP64 partial sums per block in
+// partials[nblocks], fixed-order reduction); nblocks = norm2_blocks(n)
+int64_t norm2_blocks(int64_t n);
+hipError_t launch_norm2_f64(const double *x, int64_t n, double *partials, double *out, hipStream_t st);
 
 // device buffer owned by a context
 struct DevBuf {
@@ -304,9 +316,16 @@ struct DevBuf {
 // error reporting shared by the host files (message readable through mobius_last_error)
 int set_error(int code, const std::string &msg);
 
-// Batched red/black CG: ngroups lattices (contexts), each with nrhs systems.
+// Forms of the Schur system the CG iterates on (Sec. 3): the left-preconditioned
+// D_pre, the right-preconditioned D_R = I D_pre I^-1 (on z = I psi_o), and the
+// left form of the adjoint matrix D_DW^+ (for D_DW^+ psi = eta).
+enum SchurForm { FORM_LEFT = 0, FORM_RIGHT = 1, FORM_ADJ = 2 };
+
+// Batched red/black CG: ngroups lattices (contexts), each with nrhs systems;
+// opts.form selects left or right preconditioning; adjoint solves D_DW^+ psi = eta.
 int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *const *sol,
-                const mobius_solve_opts &opts, mobius_solve_info *info, hipStream_t stream);
+                const mobius_solve_opts &opts, mobius_solve_info *info, hipStream_t stream,
+                bool adjoint = false);
 // Time the hop launch candidates for one precision; keep the best in ctx.
 int tune(mobius_ctx *ctx, int prec, int reps, mobius_tune_result *out, hipStream_t st);
 
@@ -336,6 +355,11 @@ struct mobius_ctx {
     hipStream_t solve_stream = nullptr;
     mobius::HopTuning tune[3];  // hop launch parameters per storage precision
     double tuned_us[3] = {0, 0, 0};  // hop time of the tuned parameters (0: not tuned)
+    // Pauli-Villars view (mf = 1) of the same lattice for the solves of the
+    // bulk reconstruction: shares (borrows) the site tables, links and
+    // coefficient table of its parent, owns its solver buffers
+    mobius_ctx *pv = nullptr;
+    bool borrowed = false;
 };
 
 // Link records a hop reads: with a chemical potential the adjoint hops use

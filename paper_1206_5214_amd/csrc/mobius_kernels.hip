@@ -235,7 +235,12 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
     // coefficients of the epilogue, converted here so that none of them is
     // held in a register across the direction loop
     const Coef<T> k = make_coef<T>(hp.c);
-    if constexpr (DAG) mix_s(acc, mix_w(k, false, m, Ls, true), k.mf, m, Ls, true);  // B^+ on the output
+    if constexpr (DAG) {  // B^+ on the output
+        if (!k.ls)
+            mix_s(acc, k.b5, k.c5, k.mf, m, Ls, true);
+        else
+            mix_s(acc, mix_w(k, false, m, Ls, true), k.mf, m, Ls, true);
+    }
     if constexpr ((EPI & EPI_M5ADD) != 0) {
         cx<T> yv[12];
         S::load(Buf(yr, fbytes), N5, k5, yv);
@@ -429,6 +434,33 @@ __global__ __launch_bounds__(256) void wall_read_kernel(int64_t V, int Ls, int64
     double2 *dst = q4 + t * 12;
 #pragma unroll
     for (int q = 0; q < 12; ++q) dst[q] = q < 6 ? hi[q] : lo[q];
+}
+
+// Bulk reconstruction from the overlap solution (Sec. 2.3): with y the
+// Pauli-Villars solution D_DW(1) y = D_DW(m) P psi~,  Omega = P^+ y,
+// (P^+ y)_s = P- y_s + P+ y_{s-1 mod Ls}, and Psi_0 = psi, Psi_s = -Omega_s.
+__global__ __launch_bounds__(256) void bulk_assemble_kernel(int64_t V, int Ls, int64_t n,
+                                                            const double2 *psi4, const double2 *y5,
+                                                            double2 *Psi5)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (rhs, s, x)
+    if (t >= n) return;
+    const int64_t x = t % V, rs = t / V;
+    const int s = (int)(rs % Ls);
+    const int64_t r = rs / Ls;
+    double2 *dst = Psi5 + t * 12;
+    if (s == 0) {
+        const double2 *src = psi4 + (r * V + x) * 12;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) dst[q] = src[q];
+        return;
+    }
+    const double2 *ys = y5 + t * 12, *ym = y5 + ((r * Ls + s - 1) * V + x) * 12;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        const double2 v = q < 6 ? ym[q] : ys[q];  // P+ from s-1, P- from s
+        dst[q] = make_double2(-v.x, -v.y);
+    }
 }
 
 // canonical [s][t][z][y][x][12] complex128 <-> packed halves
@@ -682,7 +714,8 @@ __global__ __launch_bounds__(BLAS_BLOCK) void xflush_batch(const VecSys *sys, co
 // site-lane mapping of the hop so that the Ls-direction solve stays inside a
 // wavefront.  a = r, b = q, c = u, s0 = alpha; one workgroup per site block.
 template <int P>
-__global__ __launch_bounds__(BLOCK) void rupd_m5inv_batch(const VecSys *sys, const int32_t *active)
+__global__ __launch_bounds__(BLOCK) void rupd_m5inv_batch(const VecSys *sys, const int32_t *active,
+                                                          int mode)
 {
     const VecSys v = sys[blockIdx.y];
     if (sys_inactive(v, active)) return;
@@ -707,8 +740,9 @@ __global__ __launch_bounds__(BLOCK) void rupd_m5inv_batch(const VecSys *sys, con
     if (m.site_ok) n = S::store_norm2_q(br, n5, k5, rv);
     vmem_drain();
     block_sum_store(n, v.partials, blockIdx.x);
+    if (mode == 2) return;  // uniform: no solve of the updated residual
     __shared__ M5Lds<T> lds;
-    m5inv_lanes(rv, k, m, Ls, true, lds);
+    m5inv_lanes(rv, k, m, Ls, mode == 0, lds);
     if (m.site_ok) S::store(Buf(v.c, fb), n5, k5, rv);
 }
 
@@ -885,6 +919,16 @@ hipError_t launch_wall_read(const Geometry &g, const void *psi5, void *q4, int n
     return hipGetLastError();
 }
 
+hipError_t launch_bulk_assemble(const Geometry &g, const void *psi4, const void *y5, void *Psi5,
+                                int nrhs, hipStream_t st)
+{
+    const int64_t n = (int64_t)nrhs * g.Ls * g.V;
+    hipLaunchKernelGGL(bulk_assemble_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.V,
+                       g.Ls, n, static_cast<const double2 *>(psi4), static_cast<const double2 *>(y5),
+                       static_cast<double2 *>(Psi5));
+    return hipGetLastError();
+}
+
 hipError_t launch_pack_spinor(const Geometry &g, int prec, const void *canon, void *even, void *odd,
                               int nrhs, hipStream_t st)
 {
@@ -985,6 +1029,12 @@ bool dispatch_hop(int prec, int dag, int epi, A &&...args)
         return !D;                                                                                 \
     case EPI_PREMIXED | EPI_M5INV | EPI_POSTSUB:                                                   \
         if constexpr (!D) F<P, D, EPI_PREMIXED | EPI_M5INV | EPI_POSTSUB>::run(args...);           \
+        return !D;                                                                                 \
+    case EPI_PREMIXED | EPI_POSTSUB | EPI_NORM:                                                    \
+        if constexpr (!D) F<P, D, EPI_PREMIXED | EPI_POSTSUB | EPI_NORM>::run(args...);            \
+        return !D;                                                                                 \
+    case EPI_PREMIXED | EPI_POSTSUB:                                                               \
+        if constexpr (!D) F<P, D, EPI_PREMIXED | EPI_POSTSUB>::run(args...);                       \
         return !D;                                                                                 \
     }                                                                                              \
     return false;
@@ -1201,13 +1251,13 @@ hipError_t launch_reduce_batch(const VecSys *sys_dev, int nsys, const int32_t *a
 }
 
 hipError_t launch_rupd_m5inv_batch(int prec, const VecSys *sys_dev, int nsys, int64_t max_blocks,
-                                   const int32_t *active, hipStream_t st)
+                                   const int32_t *active, int mode, hipStream_t st)
 {
     const dim3 grid((unsigned)max_blocks, (unsigned)nsys), blk(BLOCK);
     switch (prec) {
-    case MOBIUS_F64: hipLaunchKernelGGL(rupd_m5inv_batch<MOBIUS_F64>, grid, blk, 0, st, sys_dev, active); break;
-    case MOBIUS_F32: hipLaunchKernelGGL(rupd_m5inv_batch<MOBIUS_F32>, grid, blk, 0, st, sys_dev, active); break;
-    case MOBIUS_F16: hipLaunchKernelGGL(rupd_m5inv_batch<MOBIUS_F16>, grid, blk, 0, st, sys_dev, active); break;
+    case MOBIUS_F64: hipLaunchKernelGGL(rupd_m5inv_batch<MOBIUS_F64>, grid, blk, 0, st, sys_dev, active, mode); break;
+    case MOBIUS_F32: hipLaunchKernelGGL(rupd_m5inv_batch<MOBIUS_F32>, grid, blk, 0, st, sys_dev, active, mode); break;
+    case MOBIUS_F16: hipLaunchKernelGGL(rupd_m5inv_batch<MOBIUS_F16>, grid, blk, 0, st, sys_dev, active, mode); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -52,7 +52,7 @@ int env_int(const char *name, int dflt)
 }
 
 // fields of a group (each holds nrhs consecutive packed fields)
-enum Field { F_ETA_E, F_ETA_O, F_B, F_XH, F_RH, F_T64, F_U64, F_Q64, F_PE,  // FP64
+enum Field { F_ETA_E, F_ETA_O, F_B, F_XH, F_RH, F_T64, F_U64, F_Q64, F_PE, F_PO,  // FP64
              F_X,                                                          // correction
              F_R, F_P, F_Q, F_S, F_T, F_U,                                 // precision lo
              NFIELDS, F_NONE = -1 };
@@ -122,6 +122,16 @@ struct Batch {
     // normal: CG on D_pre^+ D_pre x = b (b = the odd half of the source)
     // instead of CGLS for D_DW psi = eta
     bool normal = false;
+    // form of the Schur system CGLS iterates on (FORM_LEFT: D_pre; FORM_RIGHT:
+    // D_R = I D_pre I^-1 on z = I psi_o; FORM_ADJ: the left form of the adjoint
+    // matrix, for D_DW^+ psi = eta)
+    int form = FORM_LEFT;
+    bool adj() const { return form == FORM_ADJ; }
+    // field holding psi_o (the right form iterates on z = I psi_o)
+    Field psi_o() const { return form == FORM_RIGHT ? F_PO : F_XH; }
+    // what the r update solves on the new residual: I^-+ r for the left
+    // form's adjoint hops, I^-1 r for the adjoint system's, nothing for the right form
+    int rupd_mode() const { return form == FORM_LEFT ? 0 : form == FORM_ADJ ? 1 : 2; }
     // accounting (count_only: account a graph replay without launching)
     bool count_only = false;
     // |out|^2 partial sums fused into the epilogue of the hops that produce q
@@ -171,7 +181,13 @@ struct Batch {
                          Field out, Field x, Field y, bool norm);
     hipError_t vec(int pid, int kind, int prec, int prec2, bool all = false);
     hipError_t reduce(int pid, double *out, int64_t stride, bool all = false);
-    hipError_t m5inv_dag_all(int prec, Field in, Field out, bool only_active = false);
+    hipError_t m5inv_dag_all(int prec, Field in, Field out, bool only_active = false)
+    {
+        return m5inv_all(prec, 1, in, out, only_active);
+    }
+    hipError_t m5inv_all(int prec, int dag, Field in, Field out, bool only_active = false);
+    hipError_t next_u(bool only_active);   // the solve of r the next step's A^+ starts from
+    hipError_t psi_odd();                  // psi_o from the iterate (right form: I^-1 z)
     hipError_t body();                   // one CG iteration
     hipError_t rupd();                   // r -= alpha q (|r|^2), u = I^-+ r
     hipError_t body_normal();            // one CG iteration on the normal equations
@@ -199,7 +215,7 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
         g.sol = static_cast<char *>(sol[j]);
         const Geometry &G = g.ctx->g;
         for (int k = 0; k < NFIELDS; ++k)
-            g.fb[k] = field_bytes(G, k <= F_PE ? MOBIUS_F64 : k == F_X ? px : lo);
+            g.fb[k] = field_bytes(G, k <= F_PO ? MOBIUS_F64 : k == F_X ? px : lo);
         int64_t need = 4096;
         for (int k = 0; k < NFIELDS; ++k) need += g.fb[k] * nrhs;
         CK(g.ctx->work.ensure(need));
@@ -227,6 +243,25 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
     hp[HP_D1C] = {lo, 1, EPI_POSTSUB | EPI_NORM, 1, F_T, F_S, F_R, F_NONE, true};
     hp[HP_H0A] = {MOBIUS_F64, 0, EPI_M5INV, 0, F_XH, F_T64, F_NONE, F_NONE, false};
     hp[HP_H0B] = {MOBIUS_F64, 0, EPI_M5INV | EPI_POSTSUB, 1, F_T64, F_Q64, F_XH, F_NONE, false};
+    if (form == FORM_RIGHT) {
+        // A = D_R = 1 - D_oe I^-1 D_eo I^-1: q = p - D_oe t, t = B I^-1 D_eo v, v = I^-1 p (in u);
+        // A^+ = 1 - I^-+ D_eo^+ I^-+ D_oe^+: s = r - I^-+ D_eo^+ t, t = I^-+ D_oe^+ r
+        hp[HP_D0A] = {lo, 0, EPI_M5INV | EPI_BMIX, 0, F_U, F_T, F_NONE, F_NONE, false};
+        hp[HP_D0B] = {lo, 0, EPI_PREMIXED | EPI_POSTSUB | EPI_NORM, 1, F_T, F_Q, F_P, F_NONE, true};
+        hp[HP_D1B] = {lo, 1, EPI_M5INV, 0, F_R, F_T, F_NONE, F_NONE, false};
+        hp[HP_D1C] = {lo, 1, EPI_M5INV | EPI_POSTSUB | EPI_NORM, 1, F_T, F_S, F_R, F_NONE, true};
+        hp[HP_H0A] = {MOBIUS_F64, 0, EPI_M5INV, 0, F_U64, F_T64, F_NONE, F_NONE, false};
+        hp[HP_H0B] = {MOBIUS_F64, 0, EPI_POSTSUB, 1, F_T64, F_Q64, F_XH, F_NONE, false};
+    } else if (form == FORM_ADJ) {
+        // D_DW^+: A = 1 - I^-+ (D^+)_oe I^-+ (D^+)_eo (adjoint hops, I^-+ epilogues),
+        // A^+ = D_R of D_DW, applied to r through u = I^-1 r
+        hp[HP_D0A] = {lo, 1, EPI_M5INV, 0, F_P, F_T, F_NONE, F_NONE, false};
+        hp[HP_D0B] = {lo, 1, EPI_M5INV | EPI_POSTSUB | EPI_NORM, 1, F_T, F_Q, F_P, F_NONE, true};
+        hp[HP_D1B] = {lo, 0, EPI_M5INV | EPI_BMIX, 0, F_U, F_T, F_NONE, F_NONE, false};
+        hp[HP_D1C] = {lo, 0, EPI_PREMIXED | EPI_POSTSUB | EPI_NORM, 1, F_T, F_S, F_R, F_NONE, true};
+        hp[HP_H0A] = {MOBIUS_F64, 1, EPI_M5INV, 0, F_XH, F_T64, F_NONE, F_NONE, false};
+        hp[HP_H0B] = {MOBIUS_F64, 1, EPI_M5INV | EPI_POSTSUB, 1, F_T64, F_Q64, F_XH, F_NONE, false};
+    }
     hp[HP_D1Q] = {lo, 1, EPI_POSTSUB, 1, F_T, F_S, F_Q, F_NONE, false};
     hp[HP_N64B] = {MOBIUS_F64, 1, EPI_M5INV, 0, F_U64, F_T64, F_NONE, F_NONE, false};
     hp[HP_N64C] = {MOBIUS_F64, 1, EPI_POSTSUB, 1, F_T64, F_PE, F_Q64, F_NONE, false};
@@ -470,7 +505,25 @@ hipError_t Batch::reduce(int pid, double *out, int64_t stride, bool all)
                                stride, st);
 }
 
-hipError_t Batch::m5inv_dag_all(int prec, Field in, Field out, bool only_active)
+hipError_t Batch::next_u(bool only_active)
+{
+    if (form == FORM_RIGHT) return hipSuccess;
+    return m5inv_all(lo, form == FORM_LEFT ? 1 : 0, F_R, F_U, only_active);
+}
+
+hipError_t Batch::psi_odd()
+{
+    if (form != FORM_RIGHT) return hipSuccess;
+    for (const Group &g : groups) {
+        abytes += 2.0 * g.fb[F_XH] * g.nrhs;
+        aflops += 96.0 * g.ctx->g.N5 * g.nrhs;
+        hipError_t e = launch_m5(g.ctx->g, g.ctx->c, MOBIUS_F64, 1, 0, g.f[F_XH], g.f[F_PO], g.nrhs, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t Batch::m5inv_all(int prec, int dag, Field in, Field out, bool only_active)
 {
     for (const Group &g : groups) {
         for (int r = 0; r < g.nrhs; ++r) {
@@ -480,7 +533,7 @@ hipError_t Batch::m5inv_dag_all(int prec, Field in, Field out, bool only_active)
             abytes += 2.0 * g.fb[in];
             aflops += 96.0 * g.ctx->g.N5;
             if (count_only) continue;
-            hipError_t e = launch_m5(g.ctx->g, g.ctx->c, prec, 1, 1, g.f[in] + r * g.fb[in],
+            hipError_t e = launch_m5(g.ctx->g, g.ctx->c, prec, 1, dag, g.f[in] + r * g.fb[in],
                                      g.f[out] + r * g.fb[out], 1, st);
             if (e != hipSuccess) return e;
         }
@@ -500,6 +553,7 @@ hipError_t Batch::body()
     if ((e = reduce(norm_red(), &sc[0].gamma_new, SC_STRIDE)) != hipSuccess) return e;
     if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 1, active, restart, st)) != hipSuccess) return e;
     if ((e = vec(VP_PUPD_X, VEC_PUPD_X, lo, px)) != hipSuccess) return e;
+    if (form == FORM_RIGHT && (e = m5inv_all(lo, 0, F_P, F_U)) != hipSuccess) return e;  // v = I^-1 p
     if ((e = hop(HP_D0A)) != hipSuccess) return e;
     if ((e = hop(HP_D0B)) != hipSuccess) return e;
     if ((e = reduce(norm_red(), &sc[0].qq, SC_STRIDE)) != hipSuccess) return e;
@@ -531,10 +585,12 @@ hipError_t Batch::body_normal()
 hipError_t Batch::rupd()
 {
     const double fb = sum_fb(lo, true), n5 = sum_n5(true);
-    abytes += 4 * fb;
-    aflops += (48 + 96 + 48) * n5;
+    const int mode = rupd_mode();
+    abytes += (mode == 2 ? 3 : 4) * fb;
+    aflops += (48 + (mode == 2 ? 0 : 96) + 48) * n5;
     if (count_only) return hipSuccess;
-    return launch_rupd_m5inv_batch(lo, vec_tab + (size_t)VP_RUPD * nsys, nsys, max_site_blocks, active, st);
+    return launch_rupd_m5inv_batch(lo, vec_tab + (size_t)VP_RUPD * nsys, nsys, max_site_blocks, active,
+                                   mode, st);
 }
 
 hipError_t Batch::reliable_update()
@@ -546,6 +602,7 @@ hipError_t Batch::reliable_update()
         if ((e = launch_cg_scalar_batch(sc, nsys, 2, active, restart, st)) != hipSuccess) return e;
     }
     if ((e = vec(VP_ACC, VEC_ACCUMULATE, px, MOBIUS_F64)) != hipSuccess) return e;
+    if (form == FORM_RIGHT && (e = m5inv_all(MOBIUS_F64, 0, F_XH, F_U64, true)) != hipSuccess) return e;
     if ((e = hop(HP_H0A)) != hipSuccess) return e;
     if ((e = hop(HP_H0B)) != hipSuccess) return e;
     if (normal) {  // r = b - D^+ D x_hi
@@ -560,7 +617,7 @@ hipError_t Batch::reliable_update()
         if ((e = reduce(VP_BLASRED, &extra[X_HR], NEXTRA)) != hipSuccess) return e;
     }
     if ((e = vec(VP_CONV_RH_R, VEC_CONVERT, MOBIUS_F64, lo)) != hipSuccess) return e;
-    return normal ? hipSuccess : m5inv_dag_all(lo, F_R, F_U, true);  // u = I^-+ r for the next step
+    return normal ? hipSuccess : next_u(true);  // the solve of r the next step starts from
 }
 
 // psi_e = I^-1 (eta_e - D_eo x_hi); |eta - D_DW psi|^2 per parity -> extra
@@ -582,10 +639,14 @@ hipError_t Batch::finalize_group(const Group &g)
         return launch_reduce_batch(vec_tab + (size_t)(fuse ? VP_HOPRED : VP_BLASRED) * nsys + g.sys0,
                                    g.nrhs, nullptr, 0, &extra[g.sys0 * NEXTRA + slot], NEXTRA, st);
     };
-    if ((e = hop_group(g, MOBIUS_F64, 0, EPI_PRESUB | EPI_M5INV, 0, F_XH, F_PE, F_ETA_E, F_NONE, false)) != hipSuccess) return e;
-    if ((e = hop_group(g, MOBIUS_F64, 0, EPI_M5ADD | EPI_PRESUB | nepi, 0, F_XH, F_T64, F_ETA_E, F_PE, fuse)) != hipSuccess) return e;
+    // psi_e = I^-1 (eta_e - D_eo psi_o) (the adjoint system: its own blocks),
+    // then eta - D psi on both parities
+    const int dg = adj() ? 1 : 0;
+    const Field po = psi_o();
+    if ((e = hop_group(g, MOBIUS_F64, dg, EPI_PRESUB | EPI_M5INV, 0, po, F_PE, F_ETA_E, F_NONE, false)) != hipSuccess) return e;
+    if ((e = hop_group(g, MOBIUS_F64, dg, EPI_M5ADD | EPI_PRESUB | nepi, 0, po, F_T64, F_ETA_E, F_PE, fuse)) != hipSuccess) return e;
     if ((e = norms(VP_NORM_T64, X_RES_E)) != hipSuccess) return e;
-    if ((e = hop_group(g, MOBIUS_F64, 0, EPI_M5ADD | EPI_PRESUB | nepi, 1, F_PE, F_Q64, F_ETA_O, F_XH, fuse)) != hipSuccess) return e;
+    if ((e = hop_group(g, MOBIUS_F64, dg, EPI_M5ADD | EPI_PRESUB | nepi, 1, F_PE, F_Q64, F_ETA_O, po, fuse)) != hipSuccess) return e;
     return norms(VP_NORM_Q64, X_RES_O);
 }
 
@@ -713,7 +774,8 @@ int force_pass(Batch &B, ForceOut &fo)
 }
 
 int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *const *sol,
-        const mobius_solve_opts &o, mobius_solve_info *info, hipStream_t user, ForceOut *fo)
+        const mobius_solve_opts &o, mobius_solve_info *info, hipStream_t user, ForceOut *fo,
+        int form)
 {
     const int nrhs = o.nrhs > 0 ? o.nrhs : 1;
     const double tol = o.tol > 0 ? o.tol : 1e-10;
@@ -755,6 +817,7 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
     CK(hipStreamWaitEvent(B.st, own.ev_in, 0));
     CK(hipEventRecord(own.ev0, B.st));
     B.normal = fo != nullptr;
+    B.form = form;
 
 
     if (int rc = B.setup(ctxs, ngroups, src, sol, nrhs, o.inner_prec)) return rc;
@@ -770,9 +833,13 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
             CK(launch_pack_spinor(g.ctx->g, MOBIUS_F64, g.src, g.f[F_ETA_E], g.f[F_B], g.nrhs, st));
             CK(launch_zero(g.f[F_ETA_O], g.fb[F_ETA_O] * g.nrhs, st));
         } else {
+            // left: b' = I^-1 (eta_o - D_oe I^-1 eta_e); right: b_R = eta_o - D_oe I^-1 eta_e;
+            // adjoint system: b' = I^-+ (eta_o - (D^+)_oe I^-+ eta_e)
+            const int dg = B.adj() ? 1 : 0;
             CK(launch_pack_spinor(g.ctx->g, MOBIUS_F64, g.src, g.f[F_ETA_E], g.f[F_ETA_O], g.nrhs, st));
-            CK(launch_m5(g.ctx->g, g.ctx->c, MOBIUS_F64, 1, 0, g.f[F_ETA_E], g.f[F_T64], g.nrhs, st));
-            CK(B.hop_group(g, MOBIUS_F64, 0, EPI_PRESUB | EPI_M5INV, 1, F_T64, F_B, F_ETA_O, F_NONE, false));
+            CK(launch_m5(g.ctx->g, g.ctx->c, MOBIUS_F64, 1, dg, g.f[F_ETA_E], g.f[F_T64], g.nrhs, st));
+            CK(B.hop_group(g, MOBIUS_F64, dg, B.form == FORM_RIGHT ? EPI_POSTSUB : EPI_PRESUB | EPI_M5INV, 1,
+                           F_T64, F_B, F_ETA_O, F_NONE, false));
             B.dirac += 1;
         }
         CK(launch_zero(g.f[F_XH], g.fb[F_XH] * g.nrhs, st));
@@ -788,8 +855,8 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
     CK(B.reduce(VP_BLASRED, &B.extra[X_ETA_O2], NEXTRA, true));
     CK(B.vec(VP_CONV_B_RH, VEC_CONVERT, MOBIUS_F64, MOBIUS_F64));
     CK(B.vec(VP_CONV_RH_R, VEC_CONVERT, MOBIUS_F64, B.lo));
-    if (!B.normal) {  // the iteration starts from u = I^-+ r and no pending x update
-        CK(B.m5inv_dag_all(B.lo, F_R, F_U));
+    if (!B.normal) {  // the iteration starts from the solve of r (left: u = I^-+ r) and no pending x update
+        CK(B.next_u(false));
         CK(launch_cg_scalar_batch(B.sc, nsys, 2, nullptr, nullptr, st));
     }
     std::vector<double> bnorm2, eta_e2, eta_o2;
@@ -824,6 +891,7 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
         bool any_pending = false;
         for (int j = 0; j < nsys; ++j) any_pending |= pending[j] != 0;
         if (any_pending) {
+            if (!B.normal) CK(B.psi_odd());
             for (const Group &g : B.groups) {
                 bool gp = false;
                 for (int r = 0; r < g.nrhs; ++r) gp |= pending[g.sys0 + r] != 0;
@@ -941,11 +1009,15 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
     if (B.normal) {
         if (int rc = force_pass(B, *fo)) return rc;
     }
-    // solutions: psi_e = I^-1 (eta_e - D_eo x_hi), psi_o = x_hi
+    // solutions: psi_e = I^-1 (eta_e - D_eo psi_o) (the adjoint system: its own
+    // blocks), psi_o = x_hi (right form: I^-1 x_hi)
+    if (!B.normal) CK(B.psi_odd());
     for (const Group &g : B.groups) {
         if (B.normal) break;
-        CK(B.hop_group(g, MOBIUS_F64, 0, EPI_PRESUB | EPI_M5INV, 0, F_XH, F_PE, F_ETA_E, F_NONE, false));
-        CK(launch_unpack_spinor(g.ctx->g, MOBIUS_F64, g.f[F_PE], g.f[F_XH], g.sol, g.nrhs, st));
+        const Field po = B.psi_o();
+        CK(B.hop_group(g, MOBIUS_F64, B.adj() ? 1 : 0, EPI_PRESUB | EPI_M5INV, 0, po, F_PE, F_ETA_E, F_NONE,
+                       false));
+        CK(launch_unpack_spinor(g.ctx->g, MOBIUS_F64, g.f[F_PE], g.f[po], g.sol, g.nrhs, st));
         B.abytes += 2.0 * g.ctx->g.N5 * 12 * 16 * g.nrhs + 2.0 * g.fb[F_XH] * g.nrhs;
     }
     CK(hipEventRecord(own.ev1, st));
@@ -980,9 +1052,10 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
 }  // namespace
 
 int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *const *sol,
-                const mobius_solve_opts &o, mobius_solve_info *info, hipStream_t user)
+                const mobius_solve_opts &o, mobius_solve_info *info, hipStream_t user, bool adjoint)
 {
-    return run(ctxs, ngroups, src, sol, o, info, user, nullptr);
+    const int form = adjoint ? FORM_ADJ : (o.form == 1 ? FORM_RIGHT : FORM_LEFT);
+    return run(ctxs, ngroups, src, sol, o, info, user, nullptr, form);
 }
 
 int force(mobius_ctx *ctx, const void *phi, void *grad_links, void *grad_phi, double *action,
@@ -992,7 +1065,7 @@ int force(mobius_ctx *ctx, const void *phi, void *grad_links, void *grad_phi, do
     mobius_solve_opts o1 = o;
     o1.nrhs = 1;
     void *sol = nullptr;
-    const int rc = run(&ctx, 1, &phi, &sol, o1, info, user, &fo);
+    const int rc = run(&ctx, 1, &phi, &sol, o1, info, user, &fo, FORM_LEFT);
     if (rc >= 0) *action = fo.action;
     return rc;
 }

@@ -18,13 +18,14 @@ LIB_PATH = os.path.join(_HERE, "libmobius.so")
 
 F64, F32, F16 = 0, 1, 2
 PREC = {"f64": F64, "f32": F32, "f16": F16}
-OP_HOP, OP_M5, OP_SCHUR, OP_FULL = 0, 1, 2, 3
+OP_HOP, OP_M5, OP_SCHUR, OP_FULL, OP_SCHUR_RIGHT = 0, 1, 2, 3, 4
 OK, NOT_CONVERGED = 0, 1
 
 EXPORTS = ("mobius_create", "mobius_destroy", "mobius_field_bytes", "mobius_pack",
            "mobius_unpack", "mobius_dslash", "mobius_dslash_dag", "mobius_m5inv",
            "mobius_cg_solve", "mobius_batch_solve", "mobius_propagator4d", "mobius_force", "mobius_force_lie",
-           "mobius_tune", "mobius_set_tuning", "mobius_last_error", "mobius_dslash_noalloc")
+           "mobius_tune", "mobius_set_tuning", "mobius_last_error", "mobius_dslash_noalloc",
+           "mobius_bulk5d", "mobius_cg_solve_dag", "mobius_force_wall")
 
 
 class MobiusError(RuntimeError):
@@ -42,7 +43,7 @@ class _SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int32),
                 ("inner_prec", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
                 ("nrhs", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("err_tol", ctypes.c_double)]
+                ("err_tol", ctypes.c_double), ("form", ctypes.c_int32)]
 
 
 class _TuneResult(ctypes.Structure):
@@ -104,6 +105,12 @@ def lib():
                                          ctypes.POINTER(_SolveInfo), vp]
         L.mobius_propagator4d.argtypes = [vp, vp, vp, ctypes.POINTER(_SolveOpts),
                                           ctypes.POINTER(_SolveInfo), vp]
+        L.mobius_bulk5d.argtypes = [vp, vp, vp, ctypes.POINTER(_SolveOpts),
+                                    ctypes.POINTER(_SolveInfo), vp]
+        L.mobius_cg_solve_dag.argtypes = [vp, vp, vp, ctypes.POINTER(_SolveOpts),
+                                          ctypes.POINTER(_SolveInfo), vp]
+        L.mobius_force_wall.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(_SolveOpts), ctypes.POINTER(_SolveInfo), vp]
         L.mobius_force.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(_SolveOpts), ctypes.POINTER(_SolveInfo), vp]
         L.mobius_force_lie.argtypes = [vp, vp, vp, vp, vp]
@@ -287,18 +294,19 @@ class Operator:
         return out
 
     def solve(self, src, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.0,
-              check_every=0, err_tol=0.0):
-        """Solve D_DW psi = src (canonical complex128, optional leading nrhs).
-        reliable_delta <= 0 selects the library's default for inner_prec; err_tol > 0
-        also iterates until kappa * Schur residual <= err_tol."""
+              check_every=0, err_tol=0.0, form=0, dagger=False):
+        """Solve D_DW psi = src (canonical complex128, optional leading nrhs), or
+        D_DW^+ psi = src with dagger.  reliable_delta <= 0 selects the library's
+        default for inner_prec; err_tol > 0 also iterates until kappa * Schur
+        residual <= err_tol; form 0/1 = left/right-preconditioned Schur system."""
         import torch
         nrhs = 1 if src.dim() == 7 else int(src.shape[0])
         self._check_canon(src, nrhs, "source")
         sol = torch.empty_like(src)
-        opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, nrhs, check_every, err_tol)
+        opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, nrhs, check_every, err_tol, form)
         infos = (_SolveInfo * nrhs)()
-        rc = _check(lib().mobius_cg_solve(self._h, _ptr(src), _ptr(sol), ctypes.byref(opts), infos,
-                                          _stream()))
+        f = lib().mobius_cg_solve_dag if dagger else lib().mobius_cg_solve
+        rc = _check(f(self._h, _ptr(src), _ptr(sol), ctypes.byref(opts), infos, _stream()))
         return sol, [_info(i) for i in infos], rc
 
     def propagator4d(self, src4, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.0,
@@ -319,6 +327,47 @@ class Operator:
         rc = _check(lib().mobius_propagator4d(self._h, _ptr(src4), _ptr(sol), ctypes.byref(opts),
                                               infos, _stream()))
         return sol, [_info(i) for i in infos], rc
+
+    def bulk5d(self, psi4, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.0,
+               check_every=0, err_tol=0.0):
+        """Psi = P^+ D_DW(m)^-1 D_DW(1) P B from the overlap solution psi =
+        D_ov(m)^-1 b with one Pauli-Villars solve (see mobius_bulk5d); psi4
+        canonical complex128 [t][z][y][x][4][3] with an optional leading nrhs.
+        Returns (Psi canonical 5d, [SolveInfo of the Pauli-Villars solve], rc)."""
+        import torch
+        Lx, Ly, Lz, Lt = self.dims
+        shape4 = (Lt, Lz, Ly, Lx, 4, 3)
+        nrhs = 1 if psi4.dim() == 6 else int(psi4.shape[0])
+        _require_cuda(psi4, torch.complex128, "psi4")
+        if tuple(psi4.shape[-6:]) != shape4 or psi4.numel() != nrhs * Lt * Lz * Ly * Lx * 12:
+            raise MobiusError(f"psi4 has shape {tuple(psi4.shape)}, expected [nrhs,] {shape4}")
+        Psi = torch.empty(self.canon_shape(nrhs if nrhs > 1 else None), dtype=torch.complex128,
+                          device=psi4.device)
+        opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, nrhs, check_every, err_tol)
+        infos = (_SolveInfo * nrhs)()
+        rc = _check(lib().mobius_bulk5d(self._h, _ptr(psi4), _ptr(Psi), ctypes.byref(opts), infos,
+                                        _stream()))
+        return Psi, [_info(i) for i in infos], rc
+
+    def force_wall(self, phi4, tol=1e-12, maxiter=20000, inner_prec=F64, reliable_delta=0.0,
+                   check_every=0, link_grad=True):
+        """S = phi^+ (D_ov^+ D_ov)^-1 phi for a 4d pseudofermion on the wall and
+        its link gradient by the two inversions of the 4d HMC (see
+        mobius_force_wall).  Returns (S, grad_links or None, SolveInfo, rc)."""
+        import torch
+        Lx, Ly, Lz, Lt = self.dims
+        _require_cuda(phi4, torch.complex128, "phi4")
+        if tuple(phi4.shape) != (Lt, Lz, Ly, Lx, 4, 3):
+            raise MobiusError(f"phi4 has shape {tuple(phi4.shape)}")
+        grad = (torch.empty(self.link_shape(), dtype=torch.complex128, device=phi4.device)
+                if link_grad else None)
+        action = ctypes.c_double(0.0)
+        opts = _SolveOpts(tol, maxiter, inner_prec, reliable_delta, 1, check_every)
+        info = _SolveInfo()
+        gl = _ptr(grad) if grad is not None else ctypes.c_void_p(None)
+        rc = _check(lib().mobius_force_wall(self._h, _ptr(phi4), gl, ctypes.byref(action),
+                                            ctypes.byref(opts), ctypes.byref(info), _stream()))
+        return action.value, grad, _info(info), rc
 
     def force_lie(self, links, grad):
         """F = TA(U G^+) per link (see mobius_force_lie): the su(3) form of a

@@ -532,6 +532,136 @@ def pin_dw_sites(orc):
                 assert _rel(got, want) < 1e-15, ("dw_sites", dims, in_parity, dag, _rel(got, want))
 
 
+def pin_bulk5d(orc):
+    """Overlap to bulk reconstruction (Sec. 2.3).  Free field: for a plane wave
+    b = e^{ipx} u, Psi from psi = D_ov(p)^-1 b equals e^{ipx} times the first
+    block column of P^+ D(m)^-1 D(1) P (the propagator matrix, from the
+    oracle's D_DW symbol) applied to u.  Random links on 2x2x2x4: Psi equals
+    P^+ D(m)^-1 D(1) P B from dense solves, and Omega_1 = b."""
+    from oracle import Params
+    rng = np.random.default_rng(19)
+    for p in _free_cases()[:2]:
+        U = inputs.unit_links(p.dims)
+        p1 = Params(p.dims, p.Ls, p.M5, 1.0, p.b5, p.c5)
+        P = ff.perm_matrix(p.Ls)
+        for mom in [np.zeros(4)] + ff.momenta(p.dims, rng, 1):
+            wave = ff.plane_wave(p.dims, mom)
+            u = rng.normal(size=(4, 3)) + 1j * rng.normal(size=(4, 3))
+            Dov = ff.overlap_symbol(mom, p.M5, p.b5, p.c5, p.Ls, p.mf)
+            psi = wave[..., None, None] * (np.linalg.inv(Dov) @ u)
+            Psi, Om, infos = orc.bulk5d(p, U, psi, tol=1e-13)
+            assert all(i.converged for i in infos)
+            A = np.conj(P.T) @ np.linalg.solve(_dw_symbol(orc, p, mom), _dw_symbol(orc, p1, mom) @ P)
+            col = (A[:, :4] @ u).reshape(p.Ls, 4, 3)
+            want = wave[None, ..., None, None] * col[:, None, None, None, None]
+            assert _rel(Psi, want) < 1e-9, ("free bulk reconstruction", mom, _rel(Psi, want))
+            assert _rel(Om[0], wave[..., None, None] * u) < 1e-9
+    dims = (2, 2, 2, 4)
+    p, U, rng = _setup(dims, 4, 1.5, 0.5, 0.05, seed=20)
+    p1 = Params(dims, 4, p.M5, 1.0, p.b5, p.c5)
+    n = int(np.prod(p.shape5()))
+    Dm = _dense(lambda v: orc.dw(p, U, v), n, p.shape5())
+    D1 = _dense(lambda v: orc.dw(p1, U, v), n, p.shape5())
+    b = rng.normal(size=p.shape4()) + 1j * rng.normal(size=p.shape4())
+    wall = np.zeros(p.shape5(), complex)            # P B
+    wall[0, ..., 2:, :] = b[..., 2:, :]
+    wall[-1, ..., :2, :] = b[..., :2, :]
+    X = np.linalg.solve(Dm, D1 @ wall.reshape(-1)).reshape(p.shape5())   # D(m)^-1 D(1) P B
+    want = X.copy()                                  # P^+ X
+    want[:, ..., :2, :] = np.roll(X, 1, axis=0)[:, ..., :2, :]
+    psi = want[0]                                    # = D_ov^-1 b
+    Psi, Om, infos = orc.bulk5d(p, U, psi, tol=1e-13)
+    assert _rel(Psi, want) < 1e-9, ("dense bulk reconstruction", _rel(Psi, want))
+    assert _rel(Om[0], b) < 1e-9
+
+
+def _dense_dov(orc, p, U):
+    """D_ov(m) built densely from the oracle's 4d Wilson operator: Moebius kernel
+    (b5+c5) D_W (2+(b5-c5) D_W)^-1, polar sign of Ls terms, (1+m)/2 + (1-m)/2 g5 eps
+    (App. A)."""
+    shape4 = p.shape4()
+    n = int(np.prod(shape4))
+    Dw = _dense(lambda v: orc.wilson(p, U, v), n, shape4)
+    g5 = np.tile(np.repeat([1.0, 1.0, -1.0, -1.0], 3), n // 12)
+    Dm = np.linalg.solve(2 * np.eye(n) + (p.b5 - p.c5) * Dw, (p.b5 + p.c5) * Dw)
+    H = g5[:, None] * Dm
+    A = np.linalg.matrix_power(np.eye(n) + H, p.Ls)
+    B = np.linalg.matrix_power(np.eye(n) - H, p.Ls)
+    eps = np.linalg.solve((A + B).T, (A - B).T).T
+    return 0.5 * (1 + p.mf) * np.eye(n) + 0.5 * (1 - p.mf) * g5[:, None] * eps
+
+
+def pin_schur_forms(orc):
+    """The right-preconditioned Schur operator D_R = 1 - D_oe I^-1 D_eo I^-1:
+    adjoint identity, D_R = I D_pre I^-1 (the same Schur decomposition, Sec. 3),
+    and its red/black solve equal to the left form's and to the dense LU
+    solution; the adjoint system D_DW^+ psi = eta solved through the
+    decomposition of D_DW^+ equal to the dense solution with the conjugate
+    transpose."""
+    from oracle import restrict
+    dims = (2, 2, 2, 4)
+    p, U, rng = _setup(dims, 4, 1.5, 0.5, 0.05, seed=22)
+    x = restrict(p, inputs.gaussian_spinor(dims, p.Ls, rng), 1)
+    y = restrict(p, inputs.gaussian_spinor(dims, p.Ls, rng), 1)
+    e = _adjoint_err(orc, lambda v: orc.schur_right(p, U, v), lambda v: orc.schur_right(p, U, v, dag=True),
+                     x, y)
+    assert e < 1e-12, ("D_R adjoint", e)
+    lhs = orc.schur_right(p, U, x)
+    rhs = restrict(p, orc.m5(p, U, orc.schur(p, U, orc.m5inv(p, x))), 1)
+    assert _rel(lhs, rhs) < 1e-13, ("D_R = I D_pre I^-1", _rel(lhs, rhs))
+    D = _dense(lambda v: orc.dw(p, U, v), int(np.prod(p.shape5())), p.shape5())
+    eta = inputs.gaussian_spinor(dims, p.Ls, rng)
+    want = np.linalg.solve(D, eta.reshape(-1)).reshape(eta.shape)
+    for form in (0, 1):
+        psi, info = orc.solve_form(p, U, eta, form, tol=1e-13, maxiter=5000)
+        assert info.converged and _rel(psi, want) < 1e-9, ("form", form, _rel(psi, want))
+    want = np.linalg.solve(np.conj(D.T), eta.reshape(-1)).reshape(eta.shape)
+    psi, info = orc.solve_form(p, U, eta, 2, tol=1e-13, maxiter=5000)
+    assert info.converged and info.true_resid < 1e-11
+    assert _rel(psi, want) < 1e-9, ("adjoint system", _rel(psi, want))
+
+
+def pin_force_wall(orc):
+    """4d-HMC action with the pseudofermion on the wall (Sec. 2.4), 2x2x2x4
+    with random links: S = phi^+ (D_ov^+ D_ov)^-1 phi with D_ov built densely
+    (the identity that puts the pseudofermion on the wall), and the link
+    gradient of the two-inversion form against central differences of S
+    computed with dense solves, along random complex directions (all links,
+    and one link at a time)."""
+    from oracle import Params
+    dims = (2, 2, 2, 4)
+    p, U, rng = _setup(dims, 4, 1.5, 0.5, 0.1, seed=23)
+    p1 = Params(dims, p.Ls, p.M5, 1.0, p.b5, p.c5)
+    phi = rng.normal(size=p.shape4()) + 1j * rng.normal(size=p.shape4())
+    S, G, info = orc.force_wall(p, U, phi, tol=1e-14)
+    assert info.converged
+    Dov = _dense_dov(orc, p, U)
+    f = phi.reshape(-1)
+    S_want = np.vdot(f, np.linalg.solve(np.conj(Dov.T) @ Dov, f)).real
+    assert abs(S - S_want) < 1e-10 * abs(S_want), ("wall action", S, S_want)
+    n = int(np.prod(p.shape5()))
+    wall = np.zeros(p.shape5(), complex)
+    wall[0, ..., 2:, :] = phi[..., 2:, :]
+    wall[-1, ..., :2, :] = phi[..., :2, :]
+    w = wall.reshape(-1)
+
+    def S_dense(Uh):
+        Dm = _dense(lambda v: orc.dw(p, Uh, v), n, p.shape5())
+        D1 = _dense(lambda v: orc.dw(p1, Uh, v), n, p.shape5())
+        chi = np.linalg.solve(np.conj(Dm.T), w)
+        return float(np.linalg.norm(np.conj(D1.T) @ chi) ** 2)
+
+    h = 1e-5
+    dirs = [rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape)]
+    E1 = np.zeros_like(U)
+    E1.reshape(4, p.V, 3, 3)[2, 5] = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+    dirs.append(E1)
+    for E in dirs:
+        fd = (S_dense(U + h * E) - S_dense(U - h * E)) / (2 * h)
+        want = np.sum(np.conj(G) * E).real
+        assert abs(fd - want) < 1e-6 * max(abs(want), 1e-3 * np.abs(G).max()), ("wall force FD", fd, want)
+
+
 # ---------------------------------------------------------------------------
 # s-dependent coefficients b5(s), c5(s) (the general operator of Sec. 2.1)
 
@@ -651,4 +781,5 @@ ALL_PINS = [pin_wilson_free_symbol, pin_kernel_bound, pin_gauge_covariance,
             pin_rb_equals_unpreconditioned, pin_cgne_dense, pin_force_finite_difference,
             pin_propagator4d_free, pin_propagator4d_dense, pin_wilson_free_symbol_mu,
             pin_adjoints_mu, pin_force_lie, pin_dw_sites, pin_sdep_free_identities,
-            pin_sdep_m5_block, pin_sdep_adjoints_and_solve]
+            pin_sdep_m5_block, pin_sdep_adjoints_and_solve, pin_bulk5d, pin_schur_forms,
+            pin_force_wall]

@@ -102,3 +102,39 @@ def test_propagator4d_rejects_bad_arguments(torch_cuda):
     assert L.mobius_propagator4d(op._h, None, mobius._ptr(b), ctypes.byref(opts), infos,
                                  None) == -22
     op.close()
+
+
+@pytest.mark.parametrize("inner", [0, 2], ids=["f64", "mixed_f16"])
+def test_bulk5d_vs_oracle(torch_cuda, orc, inner):
+    """Overlap to bulk reconstruction (mobius_bulk5d, Sec. 2.3): from the
+    overlap solution psi = D_ov^-1 b, the 5d field Psi = P^+ D(m)^-1 D(1) P B
+    with one Pauli-Villars solve, against the oracle's route and against the
+    5d equation D(m) P Psi = D(1) P B recomputed with the oracle's D_DW; two
+    right-hand sides in one call."""
+    from oracle import Params
+    from paper_1206_5214_amd import inputs, mobius
+    torch = torch_cuda
+    dims, Ls = (4, 4, 4, 4), 8
+    p = Params(dims, Ls, 1.8, 0.02, 1.5, 0.5)
+    rng = np.random.default_rng(61)
+    U = inputs.random_links(dims, 0.4, rng)
+    b = rng.normal(size=(2,) + p.shape4()) + 1j * rng.normal(size=(2,) + p.shape4())
+    psi, _ = orc.propagator4d(p, U, b, tol=1e-13)
+    op = mobius.Operator(dims, Ls, 1.8, 0.02, 1.5, 0.5, torch.from_numpy(U).cuda())
+    Psi, infos, rc = op.bulk5d(torch.from_numpy(psi).cuda(), tol=1e-12, inner_prec=inner)
+    assert rc == mobius.OK, infos
+    got = Psi.cpu().numpy()
+    want, _, _ = orc.bulk5d(p, U, psi, tol=1e-13)
+    p1 = Params(dims, Ls, 1.8, 1.0, 1.5, 0.5)
+    for r in range(2):
+        err = float(np.linalg.norm(got[r] - want[r]) / np.linalg.norm(want[r]))
+        X = got[r].copy()                                  # X = P Psi
+        X[:, ..., :2, :] = np.roll(got[r], -1, axis=0)[:, ..., :2, :]
+        B = np.zeros(p.shape5(), complex)                  # P B
+        B[0, ..., 2:, :] = b[r][..., 2:, :]
+        B[-1, ..., :2, :] = b[r][..., :2, :]
+        lhs, rhs = orc.dw(p, U, X), orc.dw(p1, U, B)
+        res = float(np.linalg.norm(lhs - rhs) / np.linalg.norm(rhs))
+        _flush(f"  rhs {r}: PV iters {infos[r].iters}, error vs oracle {err:.2e}, 5d residual {res:.2e}")
+        assert err <= 1e-9 and res <= 1e-9
+    op.close()

@@ -50,8 +50,8 @@ MUTANTS = [
     ("cgls_beta_sign", "pv[k] = s[k] + beta * pv[k];", "pv[k] = s[k] - beta * pv[k];"),
     ("cgne_alpha_uses_r", "const double alpha = rr / norm2(t, n);",
      "const double alpha = rr / norm2(q, n);"),
-    ("force_imaginary_direction_sign", "E[lid * 9 + e] = part ? I : 1.0;",
-     "E[lid * 9 + e] = part ? -I : 1.0;"),
+    ("force_imaginary_direction_sign", "E[lid * 9 + e] = part ? I : 1.0;\n                    double acc",
+     "E[lid * 9 + e] = part ? -I : 1.0;\n                    double acc"),
     ("force_Yt_without_dagger", "orc_m5inv(p, (double *)Y, (double *)Yt, 1);",
      "orc_m5inv(p, (double *)Y, (double *)Yt, 0);"),
     ("force_W_hop_not_adjoint", "orc_hop(p, U, 0, (double *)Yt, (double *)t, 1);",
@@ -69,6 +69,14 @@ MUTANTS = [
      "km = -p->mf * Mm[Ls - 1];\n        kp = -p->mf * Mm[0];\n    } else {",
      "km = -p->mf * Mm[0];\n        kp = -p->mf * Mm[Ls - 1];\n    } else {"),
     ("sdep_adjoint_offdiagonal_index", "em[s] = s > 0 ? Mm[s - 1] : 0.0;", "em[s] = Mm[s];"),
+    ("wall_force_pv_term_sign",
+     "d[part] = -hopping_overlap(p, E, Z, chi, psi, at, 2, tmp, tmp0, buf) +",
+     "d[part] = -hopping_overlap(p, E, Z, chi, psi, at, 2, tmp, tmp0, buf) -"),
+    ("wall_force_pv_mass", "hopping_overlap(&pv, E, Z, chi, d1c", "hopping_overlap(p, E, Z, chi, d1c"),
+    ("schur_right_inner_dagger", "orc_m5inv(p, (double *)xo, (double *)t1, 0);      /* I^-1        (odd)  */",
+     "orc_m5inv(p, (double *)xo, (double *)t1, 1);      /* I^-1        (odd)  */"),
+    ("adjoint_system_forward_block", "orc_hop(p, U, 1, (double *)t1, (double *)t2, dg);      /* odd <- even block",
+     "orc_hop(p, U, 1, (double *)t1, (double *)t2, 0);      /* odd <- even block"),
     ("force_only_forward_site", "const int64_t sites[2] = {y, neighbour(p, y, mu, +1)};",
      "const int64_t sites[2] = {y, y};"),
 ]
