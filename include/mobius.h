@@ -70,8 +70,12 @@ typedef enum {
     MOBIUS_OP_M5 = 1,    /* diagonal block I on one half field (parity-independent) (Sec. 3)  */
     MOBIUS_OP_SCHUR = 2, /* D_pre = 1 - I^-1 D_oe I^-1 D_eo, odd -> odd (out_parity must be 1)  */
     MOBIUS_OP_FULL = 3,  /* the unpreconditioned D_DW(m) on both halves (Sec. 2.1)            */
-    MOBIUS_OP_SCHUR_RIGHT = 4  /* D_R = 1 - D_oe I^-1 D_eo I^-1 = I D_pre I^-1, odd -> odd (Sec. 3,
+    MOBIUS_OP_SCHUR_RIGHT = 4, /* D_R = 1 - D_oe I^-1 D_eo I^-1 = I D_pre I^-1, odd -> odd (Sec. 3,
                                   the diagonal block taken out on the right; out_parity 1) */
+    MOBIUS_OP_HOP_LEFT = 5,    /* off-diagonal block of the left form D^ = D-^-1 D_DW D- of
+                                  Sec. 2.1: D^_{p,1-p} = -1/2 B H, parity 1-p -> p */
+    MOBIUS_OP_SCHUR_LEFT = 6   /* Schur operator of D^: 1 - I^-1 D^_oe I^-1 D^_eo = B D_pre B^-1,
+                                  odd -> odd (out_parity 1) */
 } mobius_op;
 
 typedef struct {
@@ -106,8 +110,11 @@ typedef struct {
                               the Schur target as needed; <= 0: the residual test alone */
     int32_t form;          /* Schur system CGLS iterates on (Sec. 3): 0 = left-preconditioned
                               D_pre psi_o = I^-1 (eta_o - D_oe I^-1 eta_e); 1 = right-preconditioned
-                              D_R z = eta_o - D_oe I^-1 eta_e, psi_o = I^-1 z (D_R = I D_pre I^-1).
-                              The same solution either way; schur_resid, kappa and err_bound refer
+                              D_R z = eta_o - D_oe I^-1 eta_e, psi_o = I^-1 z (D_R = I D_pre I^-1);
+                              2 = the left form D^ = D-^-1 D_DW D- of Sec. 2.1 (constant b5, c5):
+                              (B D_pre B^-1) y = B b', psi_o = B^-1 y, whose hops apply B after
+                              the hopping sum and so never gather the s-neighbours of their input.
+                              The same solution every way; schur_resid, kappa and err_bound refer
                               to the system iterated on.  mobius_force uses 0. */
 } mobius_solve_opts;
 
@@ -172,7 +179,12 @@ int mobius_unpack(mobius_ctx *ctx, int32_t prec, const void *even, const void *o
  *   MOBIUS_OP_FULL  out = D_DW(m) in, the whole 5d operator of Sec. 2.1 (the
  *                   block tridiagonal matrix in s with D+ = b5 D_W + 1 on the
  *                   diagonal), applied on both parities as
- *                   out_p = D_{p,1-p} in_{1-p} + I in_p; out_parity is ignored.
+ *                   out_p = D_{p,1-p} in_{1-p} + I in_p; out_parity is ignored;
+ *   MOBIUS_OP_HOP_LEFT   out(p) = -1/2 B H_{p,1-p} in(1-p), the hop block of the
+ *                   left form D^ = D-^-1 D_DW D- = B D_W + 1 - C5 (Sec. 2.1);
+ *   MOBIUS_OP_SCHUR_LEFT out = in - I^-1 D^_oe I^-1 D^_eo in (odd, out_parity 1).
+ * The two left-form operators need constant b5, c5 (MOBIUS_EINVAL otherwise:
+ * with per-slice coefficients B and I no longer commute) and b5 != 0.
  * in and out are packed fields of precision `prec`, nrhs consecutive fields
  * each; for MOBIUS_OP_FULL each holds 2 nrhs fields: the nrhs even halves, then
  * the nrhs odd halves (the two outputs of mobius_pack placed back to back), and
@@ -186,7 +198,9 @@ int mobius_dslash(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
  *   MOBIUS_OP_M5    out = I^+ in;
  *   MOBIUS_OP_SCHUR out = D_pre^+ in = in - (D_eo)^+ I^-+ (D_oe)^+ I^-+ in;
  *   MOBIUS_OP_SCHUR_RIGHT out = D_R^+ in = in - I^-+ (D_eo)^+ I^-+ (D_oe)^+ in;
- *   MOBIUS_OP_FULL  out = D_DW(m)^+ in, out_p = (D^+)_{p,1-p} in_{1-p} + I^+ in_p. */
+ *   MOBIUS_OP_FULL  out = D_DW(m)^+ in, out_p = (D^+)_{p,1-p} in_{1-p} + I^+ in_p;
+ *   MOBIUS_OP_HOP_LEFT   out(p) = (D^_{1-p,p})^+ in = -1/2 H^+ B^+ in;
+ *   MOBIUS_OP_SCHUR_LEFT out = in - (D^_eo)^+ I^-+ (D^_oe)^+ I^-+ in. */
 int mobius_dslash_dag(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
                       const void *in, void *out, int32_t nrhs, void *stream);
 
@@ -194,11 +208,12 @@ int mobius_dslash_dag(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_par
  * capture, tight serving loops, harnesses that forbid hipMalloc): the
  * operator blocks of mobius_dslash (dagger = 0) and mobius_dslash_dag
  * (dagger = 1), same arguments and results, with no allocation of any kind.
- * MOBIUS_OP_SCHUR keeps its two temporary packed fields per right-hand side in
- * a fixed workspace of 64 MiB per GPU (a static device array that the library
- * holds from the first mobius_create on that GPU until the process ends); a
- * call needing more (2 * nrhs * mobius_field_bytes(ctx, prec) > 64 MiB)
- * returns MOBIUS_EINVAL.  Every call on one GPU shares that workspace: calls
+ * MOBIUS_OP_SCHUR, SCHUR_RIGHT and SCHUR_LEFT keep their two temporary packed
+ * fields per right-hand side (HOP_LEFT with dagger = 1: one) in a fixed
+ * workspace of 64 MiB per GPU (a static device array that the library holds
+ * from the first mobius_create on that GPU until the process ends); a call
+ * needing more (2 * nrhs * mobius_field_bytes(ctx, prec) > 64 MiB) returns
+ * MOBIUS_EINVAL.  Every call on one GPU shares that workspace: calls
  * that overlap in time on one GPU (different streams or threads) race and must
  * be serialised by the caller.  Enqueued on stream, like mobius_dslash. */
 int mobius_dslash_noalloc(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,

@@ -68,6 +68,8 @@ def _bind(path):
     L.orc_force.argtypes = [P, vp, vp, vp, ctypes.c_int64, vp, vp, ctypes.c_double,
                             ctypes.c_int32, ctypes.POINTER(_Info)]
     L.orc_force.restype = ctypes.c_double
+    L.orc_dw_left.argtypes = [P, vp, vp, vp, ctypes.c_int]
+    L.orc_dw_left.restype = None
     L.orc_schur_right.argtypes = [P, vp, vp, vp, ctypes.c_int]
     L.orc_schur_right.restype = None
     L.orc_solve_form.argtypes = [P, vp, vp, vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int,
@@ -252,6 +254,35 @@ def solve(p: Params, U, eta, tol=1e-12, maxiter=10000):
     lib().orc_solve(ctypes.byref(p.c()), _ptr(U), _ptr(eta), _ptr(psi), float(tol), int(maxiter),
                     ctypes.byref(info))
     return psi, Info(info.iters, bool(info.converged), info.rel_resid, info.true_resid)
+
+
+def dw_left(p: Params, U, psi, dag=False):
+    """The left form D^ = D-^-1 D_DW D- (Sec. 2.1) or its adjoint."""
+    U, psi = _c128(U), _c128(psi)
+    out = np.empty_like(psi)
+    lib().orc_dw_left(ctypes.byref(p.c()), _ptr(U), _ptr(psi), _ptr(out), int(dag))
+    return out
+
+
+def hop_left(p: Params, U, psi, out_parity, dag=False):
+    """Off-diagonal block of the left form (parity 1-out_parity -> out_parity):
+    D^ restricted to the input parity, the output parity kept."""
+    out = dw_left(p, U, restrict(p, psi, 1 - out_parity), dag=dag)
+    return restrict(p, out, out_parity)
+
+
+def schur_left(p: Params, U, psi, dag=False):
+    """Left-preconditioned Schur operator of the left form on the odd parity,
+    1 - I^-1 D^_oe I^-1 D^_eo (its diagonal blocks are I), or its adjoint
+    1 - D^_eo^+ I^-+ D^_oe^+ I^-+."""
+    x = restrict(p, psi, 1)
+    if not dag:
+        t = m5inv(p, hop_left(p, U, x, 0))
+        t = m5inv(p, hop_left(p, U, t, 1))
+    else:
+        t = hop_left(p, U, m5inv(p, x, dag=True), 0, dag=True)
+        t = hop_left(p, U, m5inv(p, t, dag=True), 1, dag=True)
+    return restrict(p, x - t, 1)
 
 
 def schur_right(p: Params, U, psi, dag=False):

@@ -261,6 +261,79 @@ static void dw_site(const orc_params *p, const cplx *U, const cplx *in, int64_t 
     }
 }
 
+/* The left form of Sec. 2.1, D^ = D-^{-1} D_DW D- (D- = diag(D-(1), ..., D-(Ls))),
+ * which puts the chiral projectors to the left of D-.  Row s (0-based here):
+ *   (D^ psi)_s = D+(s) psi_s + P+ D-(s-1) psi_{s-1} + P- D-(s+1) psi_{s+1},
+ * the wrapped couplings carrying -m (corners -m P+ D-(Ls) at (1,Ls) and
+ * -m P- D-(1) at (Ls,1)).  Adjoint, (D^+)_{s,s'} = (D^_{s',s})^+:
+ *   (D^+ psi)_s = D+(s)^+ psi_s + D-(s)^+ (P+ psi_{s+1} + P- psi_{s-1}). */
+static void dw_left_site(const orc_params *p, const cplx *U, const cplx *in, int64_t x, cplx *out,
+                         int dag, cplx *slice_buf)
+{
+    const int64_t V = vol4(p);
+    const int Ls = p->Ls;
+    cplx *W = (cplx *)malloc(sizeof(cplx) * Ls * SITE_DOF);  /* D_W psi_t (or D_W^+) at x */
+    for (int t = 0; t < Ls; ++t) wilson_site(p, U, in + (int64_t)t * V * SITE_DOF, x, W + t * SITE_DOF, dag);
+    for (int s = 0; s < Ls; ++s) {
+        cplx *o = out + (int64_t)s * SITE_DOF;
+        const cplx *ps = in + ((int64_t)s * V + x) * SITE_DOF;
+        for (int k = 0; k < SITE_DOF; ++k) o[k] = b5_of(p, s) * W[s * SITE_DOF + k] + ps[k];
+        const int sm1 = (s - 1 + Ls) % Ls, sp1 = (s + 1) % Ls;
+        const double fm1 = (s == 0) ? -p->mf : 1.0, fp1 = (s == Ls - 1) ? -p->mf : 1.0;
+        if (!dag) {
+            cplx y[SITE_DOF];
+            for (int k = 0; k < SITE_DOF; ++k)   /* D-(s-1) psi_{s-1} */
+                y[k] = c5_of(p, sm1) * W[sm1 * SITE_DOF + k] - in[((int64_t)sm1 * V + x) * SITE_DOF + k];
+            chiral_part(y, +1, fm1, o);
+            for (int k = 0; k < SITE_DOF; ++k)   /* D-(s+1) psi_{s+1} */
+                y[k] = c5_of(p, sp1) * W[sp1 * SITE_DOF + k] - in[((int64_t)sp1 * V + x) * SITE_DOF + k];
+            chiral_part(y, -1, fp1, o);
+        } else {
+            /* D-(s)^+ applied to the mixed slice w = P+ psi_{s+1} + P- psi_{s-1} */
+            int64_t nb[9];
+            nb[0] = x;
+            for (int mu = 0; mu < 4; ++mu) {
+                nb[1 + 2 * mu] = neighbour(p, x, mu, +1);
+                nb[2 + 2 * mu] = neighbour(p, x, mu, -1);
+            }
+            for (int j = 0; j < 9; ++j) {
+                cplx *wb = slice_buf + nb[j] * SITE_DOF;
+                memset(wb, 0, sizeof(cplx) * SITE_DOF);
+                chiral_part(in + ((int64_t)sp1 * V + nb[j]) * SITE_DOF, +1, fp1, wb);
+                chiral_part(in + ((int64_t)sm1 * V + nb[j]) * SITE_DOF, -1, fm1, wb);
+            }
+            cplx t2[SITE_DOF];
+            wilson_site(p, U, slice_buf, x, t2, 1);
+            for (int k = 0; k < SITE_DOF; ++k)
+                o[k] += c5_of(p, s) * t2[k] - slice_buf[x * SITE_DOF + k];
+        }
+    }
+    free(W);
+}
+
+void orc_dw_left(const orc_params *p, const double *Ud, const double *ind, double *outd, int dag)
+{
+    init_gammas();
+    const cplx *U = (const cplx *)Ud;
+    const cplx *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+    const int64_t V = vol4(p);
+    const int Ls = p->Ls;
+#pragma omp parallel
+    {
+        cplx *buf = (cplx *)calloc((size_t)V * SITE_DOF, sizeof(cplx));
+        cplx *tmp = (cplx *)malloc(sizeof(cplx) * Ls * SITE_DOF);
+#pragma omp for schedule(static)
+        for (int64_t x = 0; x < V; ++x) {
+            dw_left_site(p, U, in, x, tmp, dag, buf);
+            for (int s = 0; s < Ls; ++s)
+                memcpy(out + ((int64_t)s * V + x) * SITE_DOF, tmp + s * SITE_DOF, sizeof(cplx) * SITE_DOF);
+        }
+        free(tmp);
+        free(buf);
+    }
+}
+
 /* copy of `in` with the other parity zeroed (in_parity < 0: plain copy) */
 static cplx *masked_copy(const orc_params *p, const cplx *in, int in_parity)
 {

@@ -116,6 +116,11 @@ double orc_force(const orc_params *p, const double *U, const double *phi, double
                  int64_t nlinks, const int64_t *links, double *grad, double tol,
                  int32_t maxiter, orc_info *info);
 
+/* The left form D^ = D-^{-1} D_DW D- of Sec. 2.1 (chiral projectors to the left
+ * of D-): row s holds D+(s) psi_s + P+ D-(s-1) psi_{s-1} + P- D-(s+1) psi_{s+1}
+ * (wrapped couplings -m); dag = 1 applies its adjoint. */
+void orc_dw_left(const orc_params *p, const double *U, const double *in, double *out, int dag);
+
 /* Right-preconditioned Schur operator D_R = 1 - D_oe I^{-1} D_eo I^{-1} (dag = 1:
  * its adjoint) on odd-parity fields. */
 void orc_schur_right(const orc_params *p, const double *U, const double *in, double *out, int dag);

@@ -59,6 +59,25 @@ OpCoeffs make_coeffs(const mobius_params &p)
     return c;
 }
 
+}  // namespace
+
+OpCoeffs mobius::b_coeffs(const OpCoeffs &c, int Ls)
+{
+    // B = b5 + c5 C5 has the shape of I = M+ + M- C5 (Sec. 3), so the same
+    // closed-form elimination inverts it with (M+, M-) -> (b5, c5)
+    OpCoeffs b = c;
+    b.Mp = c.b5;
+    b.Mm = c.c5;
+    b.a = c.c5 / c.b5;
+    b.mu = c.mf * b.a;
+    b.inv_Mp = 1.0 / c.b5;
+    b.inv_den = 1.0 / (c.b5 * (1.0 - b.mu * std::pow(-b.a, Ls - 1)));
+    b.ls = nullptr;
+    return b;
+}
+
+namespace {
+
 // Per-slice table of the general operator (Sec. 2.1) from the caller's
 // b5(s), c5(s); false if the Ls-direction block is singular: some M+(s) = 0,
 // or a vanishing pivot d + k g of the cyclic elimination of either chirality
@@ -444,6 +463,56 @@ int dslash_common(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
         } else {
             HIPCHK(hop(ctx, hop_args(prec, 1, EPI_M5INV, 0, in, t, nullptr, nullptr, nullptr, nrhs), st));
             HIPCHK(hop(ctx, hop_args(prec, 1, EPI_M5INV | EPI_POSTSUB, 1, t, out, in, nullptr, nullptr, nrhs), st));
+        }
+        return MOBIUS_OK;
+    }
+    case MOBIUS_OP_HOP_LEFT:
+    case MOBIUS_OP_SCHUR_LEFT: {
+        // blocks of the left form D^ = D-^-1 D_DW D- (Sec. 2.1): hop -1/2 B H,
+        // diagonal block I, Schur operator 1 - I^-1 D^_oe I^-1 D^_eo
+        if (ctx->sdep) return fail(MOBIUS_EINVAL, "the left-form blocks need constant b5, c5");
+        const OpCoeffs cb = b_coeffs(ctx->c, ctx->g.Ls);
+        if (!std::isfinite(cb.inv_den)) return fail(MOBIUS_EINVAL, "B = b5 + c5 C5 is singular");
+        const bool schur_op = op == MOBIUS_OP_SCHUR_LEFT;
+        if (schur_op && out_parity != 1)
+            return fail(MOBIUS_EINVAL, "SCHUR_LEFT acts on the odd parity (out_parity = 1)");
+        const int64_t fb = field_bytes(ctx->g, prec) * nrhs;
+        const int64_t need = schur_op ? 2 * fb : fb;
+        char *t;
+        if (fixed_scratch) {
+            if (need > fixed_bytes)
+                return fail(MOBIUS_EINVAL, "mobius_dslash_noalloc: the left-form operator needs " +
+                                               std::to_string(need) + " bytes of workspace, above the fixed maximum of " +
+                                               std::to_string(fixed_bytes));
+            t = static_cast<char *>(fixed_scratch);
+        } else {
+            HIPCHK(ctx->scratch.ensure(need));
+            t = static_cast<char *>(ctx->scratch.p);
+        }
+        if (!schur_op) {
+            if (!dag) {  // -1/2 B H in
+                HIPCHK(hop(ctx, hop_args(prec, 0, EPI_PREMIXED | EPI_BMIX, out_parity, in, out, nullptr, nullptr,
+                                         nullptr, nrhs), st));
+            } else {  // (D^_{1-p,p})^+ = -1/2 H^+ B^+
+                HIPCHK(launch_m5(ctx->g, cb, prec, 0, 1, in, t, nrhs, st));
+                HIPCHK(hop(ctx, hop_args(prec, 1, EPI_NOBOUT, out_parity, t, out, nullptr, nullptr, nullptr, nrhs),
+                           st));
+            }
+            return MOBIUS_OK;
+        }
+        char *v = t + fb;
+        if (!dag) {  // t = I^-1 B (-1/2 H in);  out = in - I^-1 B (-1/2 H t)
+            HIPCHK(hop(ctx, hop_args(prec, 0, EPI_PREMIXED | EPI_M5INV | EPI_BMIX, 0, in, t, nullptr, nullptr,
+                                     nullptr, nrhs), st));
+            HIPCHK(hop(ctx, hop_args(prec, 0, EPI_PREMIXED | EPI_M5INV | EPI_BMIX | EPI_POSTSUB, 1, t, out, in,
+                                     nullptr, nullptr, nrhs), st));
+        } else {  // v = B^+ I^-+ in;  t = B^+ I^-+ (-1/2 H^+ v);  out = in - (-1/2 H^+ t)
+            HIPCHK(launch_m5(ctx->g, ctx->c, prec, 1, 1, in, t, nrhs, st));
+            HIPCHK(launch_m5(ctx->g, cb, prec, 0, 1, t, v, nrhs, st));
+            HIPCHK(hop(ctx, hop_args(prec, 1, EPI_NOBOUT | EPI_M5INV | EPI_BMIX, 0, v, t, nullptr, nullptr, nullptr,
+                                     nrhs), st));
+            HIPCHK(hop(ctx, hop_args(prec, 1, EPI_NOBOUT | EPI_POSTSUB, 1, t, out, in, nullptr, nullptr, nrhs),
+                       st));
         }
         return MOBIUS_OK;
     }

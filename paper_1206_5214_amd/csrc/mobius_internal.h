@@ -95,6 +95,8 @@ enum Epilogue : int {
     EPI_NORM = 32,     // partial sums of |r|^2 (FP64)
     EPI_BMIX = 64,     // r = B r  (after EPI_M5INV; stores the input of a premixed hop)
     EPI_PREMIXED = 128,  // forward hop whose input already holds B in: r = -1/2 H in
+    EPI_NOBOUT = 256,  // adjoint hop without its output B^+: r = -1/2 H^+ in (the left form's
+                       // adjoint, whose B^+ acts on the input); EPI_BMIX then applies B^+
 };
 
 struct HopArgs {
@@ -258,7 +260,8 @@ hipError_t launch_reduce_batch(const VecSys *sys_dev, int nsys, const int32_t *a
 hipError_t launch_cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t *active,
                                   int32_t *restart, hipStream_t st);
 // r = a -= s0 b (|r|^2 partials per site block) and c = I^-+ r (mode 0), c =
-// I^-1 r (mode 1) or nothing (mode 2), in the site-lane mapping of the hop
+// I^-1 r (mode 1), nothing (mode 2) or c = B^+ I^-+ r (mode 3, constant
+// coefficients), in the site-lane mapping of the hop
 // (one workgroup per site block and system); max_blocks is the largest number
 // of site blocks of any system
 hipError_t launch_rupd_m5inv_batch(int prec, const VecSys *sys_dev, int nsys, int64_t max_blocks,
@@ -319,7 +322,14 @@ int set_error(int code, const std::string &msg);
 // Forms of the Schur system the CG iterates on (Sec. 3): the left-preconditioned
 // D_pre, the right-preconditioned D_R = I D_pre I^-1 (on z = I psi_o), and the
 // left form of the adjoint matrix D_DW^+ (for D_DW^+ psi = eta).
-enum SchurForm { FORM_LEFT = 0, FORM_RIGHT = 1, FORM_ADJ = 2 };
+// FORM_LHAT iterates on the Schur operator of the left form D^ = D-^-1 D_DW D-
+// of Sec. 2.1, 1 - I^-1 D^_oe I^-1 D^_eo = B D_pre B^-1 (constant coefficients),
+// on y = B psi_o: every hop of its CG step applies B after the hopping sum, so
+// none gathers the s-neighbours of its input.
+enum SchurForm { FORM_LEFT = 0, FORM_RIGHT = 1, FORM_LHAT = 2, FORM_ADJ = 3 };
+// coefficients of I with (M+, M-) replaced by (b5, c5): the same elimination
+// then applies B = b5 + c5 C5 (kind 0) or B^-1 (kind 1) through launch_m5
+OpCoeffs b_coeffs(const OpCoeffs &c, int Ls);
 
 // Batched red/black CG: ngroups lattices (contexts), each with nrhs systems;
 // opts.form selects left or right preconditioning; adjoint solves D_DW^+ psi = eta.

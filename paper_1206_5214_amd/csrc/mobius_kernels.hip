@@ -235,7 +235,7 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
     // coefficients of the epilogue, converted here so that none of them is
     // held in a register across the direction loop
     const Coef<T> k = make_coef<T>(hp.c);
-    if constexpr (DAG) {  // B^+ on the output
+    if constexpr (DAG && (EPI & EPI_NOBOUT) == 0) {  // B^+ on the output
         if (!k.ls)
             mix_s(acc, k.b5, k.c5, k.mf, m, Ls, true);
         else
@@ -258,7 +258,8 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
         __shared__ M5Lds<T> lds;
         m5inv_lanes(acc, k, m, Ls, DAG, lds);
     }
-    if constexpr ((EPI & EPI_BMIX) != 0) mix_s(acc, mix_w(k, false, m, Ls, false), k.mf, m, Ls, false);  // B r
+    if constexpr ((EPI & EPI_BMIX) != 0)  // B r (B^+ r in the adjoint hop)
+        mix_s(acc, mix_w(k, false, m, Ls, DAG), k.mf, m, Ls, DAG);
     if constexpr ((EPI & EPI_POSTSUB) != 0) {
         cx<T> xv[12];
         S::load(Buf(xr, fbytes), N5, k5, xv);
@@ -742,7 +743,8 @@ __global__ __launch_bounds__(BLOCK) void rupd_m5inv_batch(const VecSys *sys, con
     block_sum_store(n, v.partials, blockIdx.x);
     if (mode == 2) return;  // uniform: no solve of the updated residual
     __shared__ M5Lds<T> lds;
-    m5inv_lanes(rv, k, m, Ls, mode == 0, lds);
+    m5inv_lanes(rv, k, m, Ls, mode != 1, lds);
+    if (mode == 3) mix_s(rv, k.b5, k.c5, k.mf, m, Ls, true);  // B^+ I^-+ r (left form)
     if (m.site_ok) S::store(Buf(v.c, fb), n5, k5, rv);
 }
 
@@ -1036,6 +1038,31 @@ bool dispatch_hop(int prec, int dag, int epi, A &&...args)
     case EPI_PREMIXED | EPI_POSTSUB:                                                               \
         if constexpr (!D) F<P, D, EPI_PREMIXED | EPI_POSTSUB>::run(args...);                       \
         return !D;                                                                                 \
+    case EPI_PREMIXED | EPI_BMIX:                                                                  \
+        if constexpr (!D) F<P, D, EPI_PREMIXED | EPI_BMIX>::run(args...);                          \
+        return !D;                                                                                 \
+    case EPI_PREMIXED | EPI_M5INV | EPI_BMIX:                                                      \
+        if constexpr (!D) F<P, D, EPI_PREMIXED | EPI_M5INV | EPI_BMIX>::run(args...);              \
+        return !D;                                                                                 \
+    case EPI_PREMIXED | EPI_M5INV | EPI_BMIX | EPI_POSTSUB:                                        \
+        if constexpr (!D) F<P, D, EPI_PREMIXED | EPI_M5INV | EPI_BMIX | EPI_POSTSUB>::run(args...); \
+        return !D;                                                                                 \
+    case EPI_PREMIXED | EPI_M5INV | EPI_BMIX | EPI_POSTSUB | EPI_NORM:                             \
+        if constexpr (!D)                                                                          \
+            F<P, D, EPI_PREMIXED | EPI_M5INV | EPI_BMIX | EPI_POSTSUB | EPI_NORM>::run(args...);   \
+        return !D;                                                                                 \
+    case EPI_NOBOUT:                                                                               \
+        if constexpr (D) F<P, D, EPI_NOBOUT>::run(args...);                                        \
+        return D;                                                                                  \
+    case EPI_NOBOUT | EPI_M5INV | EPI_BMIX:                                                        \
+        if constexpr (D) F<P, D, EPI_NOBOUT | EPI_M5INV | EPI_BMIX>::run(args...);                 \
+        return D;                                                                                  \
+    case EPI_NOBOUT | EPI_POSTSUB:                                                                 \
+        if constexpr (D) F<P, D, EPI_NOBOUT | EPI_POSTSUB>::run(args...);                          \
+        return D;                                                                                  \
+    case EPI_NOBOUT | EPI_POSTSUB | EPI_NORM:                                                      \
+        if constexpr (D) F<P, D, EPI_NOBOUT | EPI_POSTSUB | EPI_NORM>::run(args...);               \
+        return D;                                                                                  \
     }                                                                                              \
     return false;
     if (dag) {

@@ -123,15 +123,20 @@ struct Batch {
     // instead of CGLS for D_DW psi = eta
     bool normal = false;
     // form of the Schur system CGLS iterates on (FORM_LEFT: D_pre; FORM_RIGHT:
-    // D_R = I D_pre I^-1 on z = I psi_o; FORM_ADJ: the left form of the adjoint
-    // matrix, for D_DW^+ psi = eta)
+    // D_R = I D_pre I^-1 on z = I psi_o; FORM_LHAT: B D_pre B^-1 on y = B psi_o;
+    // FORM_ADJ: the left form of the adjoint matrix, for D_DW^+ psi = eta)
     int form = FORM_LEFT;
     bool adj() const { return form == FORM_ADJ; }
-    // field holding psi_o (the right form iterates on z = I psi_o)
-    Field psi_o() const { return form == FORM_RIGHT ? F_PO : F_XH; }
+    // field holding psi_o (the right form iterates on z = I psi_o, the left
+    // form of D^ on y = B psi_o)
+    Field psi_o() const { return form == FORM_RIGHT || form == FORM_LHAT ? F_PO : F_XH; }
     // what the r update solves on the new residual: I^-+ r for the left
-    // form's adjoint hops, I^-1 r for the adjoint system's, nothing for the right form
-    int rupd_mode() const { return form == FORM_LEFT ? 0 : form == FORM_ADJ ? 1 : 2; }
+    // form's adjoint hops, I^-1 r for the adjoint system's, B^+ I^-+ r for the
+    // left form of D^, nothing for the right form
+    int rupd_mode() const
+    {
+        return form == FORM_LEFT ? 0 : form == FORM_ADJ ? 1 : form == FORM_LHAT ? 3 : 2;
+    }
     // accounting (count_only: account a graph replay without launching)
     bool count_only = false;
     // |out|^2 partial sums fused into the epilogue of the hops that produce q
@@ -185,7 +190,8 @@ struct Batch {
     {
         return m5inv_all(prec, 1, in, out, only_active);
     }
-    hipError_t m5inv_all(int prec, int dag, Field in, Field out, bool only_active = false);
+    hipError_t m5inv_all(int prec, int dag, Field in, Field out, bool only_active = false,
+                         bool bmix = false);
     hipError_t next_u(bool only_active);   // the solve of r the next step's A^+ starts from
     hipError_t psi_odd();                  // psi_o from the iterate (right form: I^-1 z)
     hipError_t body();                   // one CG iteration
@@ -261,6 +267,17 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
         hp[HP_D1C] = {lo, 0, EPI_PREMIXED | EPI_POSTSUB | EPI_NORM, 1, F_T, F_S, F_R, F_NONE, true};
         hp[HP_H0A] = {MOBIUS_F64, 1, EPI_M5INV, 0, F_XH, F_T64, F_NONE, F_NONE, false};
         hp[HP_H0B] = {MOBIUS_F64, 1, EPI_M5INV | EPI_POSTSUB, 1, F_T64, F_Q64, F_XH, F_NONE, false};
+    } else if (form == FORM_LHAT) {
+        // A = 1 - I^-1 D^_oe I^-1 D^_eo with D^ = -1/2 B H: q = p - I^-1 B (-1/2 H t),
+        // t = I^-1 B (-1/2 H p); A^+ = 1 - (D^_eo)^+ I^-+ (D^_oe)^+ I^-+:
+        // s = r - (-1/2 H^+ t), t = B^+ I^-+ (-1/2 H^+ u), u = B^+ I^-+ r
+        constexpr int FW = EPI_PREMIXED | EPI_M5INV | EPI_BMIX;
+        hp[HP_D0A] = {lo, 0, FW, 0, F_P, F_T, F_NONE, F_NONE, false};
+        hp[HP_D0B] = {lo, 0, FW | EPI_POSTSUB | EPI_NORM, 1, F_T, F_Q, F_P, F_NONE, true};
+        hp[HP_D1B] = {lo, 1, EPI_NOBOUT | EPI_M5INV | EPI_BMIX, 0, F_U, F_T, F_NONE, F_NONE, false};
+        hp[HP_D1C] = {lo, 1, EPI_NOBOUT | EPI_POSTSUB | EPI_NORM, 1, F_T, F_S, F_R, F_NONE, true};
+        hp[HP_H0A] = {MOBIUS_F64, 0, FW, 0, F_XH, F_T64, F_NONE, F_NONE, false};
+        hp[HP_H0B] = {MOBIUS_F64, 0, FW | EPI_POSTSUB, 1, F_T64, F_Q64, F_XH, F_NONE, false};
     }
     hp[HP_D1Q] = {lo, 1, EPI_POSTSUB, 1, F_T, F_S, F_Q, F_NONE, false};
     hp[HP_N64B] = {MOBIUS_F64, 1, EPI_M5INV, 0, F_U64, F_T64, F_NONE, F_NONE, false};
@@ -508,22 +525,31 @@ hipError_t Batch::reduce(int pid, double *out, int64_t stride, bool all)
 hipError_t Batch::next_u(bool only_active)
 {
     if (form == FORM_RIGHT) return hipSuccess;
+    if (form == FORM_LHAT) {  // u = B^+ I^-+ r, through t
+        hipError_t e = m5inv_all(lo, 1, F_R, F_T, only_active);
+        if (e != hipSuccess) return e;
+        return m5inv_all(lo, 1, F_T, F_U, only_active, true);
+    }
     return m5inv_all(lo, form == FORM_LEFT ? 1 : 0, F_R, F_U, only_active);
 }
 
 hipError_t Batch::psi_odd()
 {
-    if (form != FORM_RIGHT) return hipSuccess;
+    if (form != FORM_RIGHT && form != FORM_LHAT) return hipSuccess;
     for (const Group &g : groups) {
         abytes += 2.0 * g.fb[F_XH] * g.nrhs;
         aflops += 96.0 * g.ctx->g.N5 * g.nrhs;
-        hipError_t e = launch_m5(g.ctx->g, g.ctx->c, MOBIUS_F64, 1, 0, g.f[F_XH], g.f[F_PO], g.nrhs, st);
+        // right: psi_o = I^-1 z; left form of D^: psi_o = B^-1 y
+        const OpCoeffs c = form == FORM_RIGHT ? g.ctx->c : b_coeffs(g.ctx->c, g.ctx->g.Ls);
+        hipError_t e = launch_m5(g.ctx->g, c, MOBIUS_F64, 1, 0, g.f[F_XH], g.f[F_PO], g.nrhs, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t Batch::m5inv_all(int prec, int dag, Field in, Field out, bool only_active)
+// out = I^-1 in (I^-+ for dag), or with bmix B in (B^+ in) -- the left form's
+// s-direction factor, through the same kernel with B's coefficients
+hipError_t Batch::m5inv_all(int prec, int dag, Field in, Field out, bool only_active, bool bmix)
 {
     for (const Group &g : groups) {
         for (int r = 0; r < g.nrhs; ++r) {
@@ -533,8 +559,10 @@ hipError_t Batch::m5inv_all(int prec, int dag, Field in, Field out, bool only_ac
             abytes += 2.0 * g.fb[in];
             aflops += 96.0 * g.ctx->g.N5;
             if (count_only) continue;
-            hipError_t e = launch_m5(g.ctx->g, g.ctx->c, prec, 1, dag, g.f[in] + r * g.fb[in],
-                                     g.f[out] + r * g.fb[out], 1, st);
+            hipError_t e = bmix ? launch_m5(g.ctx->g, b_coeffs(g.ctx->c, g.ctx->g.Ls), prec, 0, dag,
+                                            g.f[in] + r * g.fb[in], g.f[out] + r * g.fb[out], 1, st)
+                                : launch_m5(g.ctx->g, g.ctx->c, prec, 1, dag, g.f[in] + r * g.fb[in],
+                                            g.f[out] + r * g.fb[out], 1, st);
             if (e != hipSuccess) return e;
         }
     }
@@ -587,7 +615,7 @@ hipError_t Batch::rupd()
     const double fb = sum_fb(lo, true), n5 = sum_n5(true);
     const int mode = rupd_mode();
     abytes += (mode == 2 ? 3 : 4) * fb;
-    aflops += (48 + (mode == 2 ? 0 : 96) + 48) * n5;
+    aflops += (48 + (mode == 2 ? 0 : 96) + (mode == 3 ? 48 : 0) + 48) * n5;
     if (count_only) return hipSuccess;
     return launch_rupd_m5inv_batch(lo, vec_tab + (size_t)VP_RUPD * nsys, nsys, max_site_blocks, active,
                                    mode, st);
@@ -839,7 +867,12 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
             CK(launch_pack_spinor(g.ctx->g, MOBIUS_F64, g.src, g.f[F_ETA_E], g.f[F_ETA_O], g.nrhs, st));
             CK(launch_m5(g.ctx->g, g.ctx->c, MOBIUS_F64, 1, dg, g.f[F_ETA_E], g.f[F_T64], g.nrhs, st));
             CK(B.hop_group(g, MOBIUS_F64, dg, B.form == FORM_RIGHT ? EPI_POSTSUB : EPI_PRESUB | EPI_M5INV, 1,
-                           F_T64, F_B, F_ETA_O, F_NONE, false));
+                           F_T64, B.form == FORM_LHAT ? F_Q64 : F_B, F_ETA_O, F_NONE, false));
+            if (B.form == FORM_LHAT) {  // left form of D^: b^ = B b'
+                B.abytes += 2.0 * g.fb[F_B] * g.nrhs;
+                CK(launch_m5(g.ctx->g, b_coeffs(g.ctx->c, g.ctx->g.Ls), MOBIUS_F64, 0, 0, g.f[F_Q64], g.f[F_B],
+                             g.nrhs, st));
+            }
             B.dirac += 1;
         }
         CK(launch_zero(g.f[F_XH], g.fb[F_XH] * g.nrhs, st));
@@ -1054,7 +1087,17 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
 int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *const *sol,
                 const mobius_solve_opts &o, mobius_solve_info *info, hipStream_t user, bool adjoint)
 {
-    const int form = adjoint ? FORM_ADJ : (o.form == 1 ? FORM_RIGHT : FORM_LEFT);
+    if (!adjoint && (o.form < 0 || o.form > 2))
+        return set_error(MOBIUS_EINVAL, "unknown solve form " + std::to_string(o.form));
+    if (!adjoint && o.form == 2) {
+        for (int j = 0; j < ngroups; ++j) {
+            if (ctxs[j]->sdep)
+                return set_error(MOBIUS_EINVAL, "solve form 2 (left form of D^) needs constant b5, c5");
+            if (!std::isfinite(b_coeffs(ctxs[j]->c, ctxs[j]->g.Ls).inv_den))
+                return set_error(MOBIUS_EINVAL, "solve form 2: B = b5 + c5 C5 is singular");
+        }
+    }
+    const int form = adjoint ? FORM_ADJ : o.form == 1 ? FORM_RIGHT : o.form == 2 ? FORM_LHAT : FORM_LEFT;
     return run(ctxs, ngroups, src, sol, o, info, user, nullptr, form);
 }
 

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmobius.so")
 
 F64, F32, F16 = 0, 1, 2
 PREC = {"f64": F64, "f32": F32, "f16": F16}
-OP_HOP, OP_M5, OP_SCHUR, OP_FULL, OP_SCHUR_RIGHT = 0, 1, 2, 3, 4
+OP_HOP, OP_M5, OP_SCHUR, OP_FULL, OP_SCHUR_RIGHT, OP_HOP_LEFT, OP_SCHUR_LEFT = 0, 1, 2, 3, 4, 5, 6
 OK, NOT_CONVERGED = 0, 1
 
 EXPORTS = ("mobius_create", "mobius_destroy", "mobius_field_bytes", "mobius_pack",
@@ -298,7 +298,8 @@ class Operator:
         """Solve D_DW psi = src (canonical complex128, optional leading nrhs), or
         D_DW^+ psi = src with dagger.  reliable_delta <= 0 selects the library's
         default for inner_prec; err_tol > 0 also iterates until kappa * Schur
-        residual <= err_tol; form 0/1 = left/right-preconditioned Schur system."""
+        residual <= err_tol; form 0/1 = left/right-preconditioned Schur system,
+        2 = the Schur system of the left form D^ = D-^-1 D_DW D- (constant b5, c5)."""
         import torch
         nrhs = 1 if src.dim() == 7 else int(src.shape[0])
         self._check_canon(src, nrhs, "source")

@@ -621,6 +621,54 @@ def pin_schur_forms(orc):
     assert _rel(psi, want) < 1e-9, ("adjoint system", _rel(psi, want))
 
 
+def pin_left_form(orc):
+    """The left form D^ = D-^-1 D_DW D- (Sec. 2.1): D- D^ = D_DW D- with D- the
+    block-diagonal c5(s) D_W - 1 built densely (constant and per-slice
+    coefficients), the adjoint identity, and for constant coefficients
+    D^ = g5 R D_DW^+ R g5 (the generalised g5-hermiticity); its diagonal blocks
+    equal those of D_DW (I), and its Schur operator equals B D_pre B^-1 with
+    B = b5 + c5 C5 (the mixing that D^ applies after the hop, Sec. 3)."""
+    from oracle import restrict
+    dims = (2, 2, 2, 4)
+    U = inputs.random_links(dims, 0.5, np.random.default_rng(24))
+    for p in (_setup(dims, 4, 1.5, 0.5, 0.05, seed=24)[0], _sdep_params(dims, 4, 0.07, seed=9)):
+        n = int(np.prod(p.shape5()))
+        n4 = n // p.Ls
+        D = _dense(lambda v: orc.dw(p, U, v), n, p.shape5())
+        Dl = _dense(lambda v: orc.dw_left(p, U, v), n, p.shape5())
+        Dw = _dense(lambda v: orc.wilson(p, U, v), n4, p.shape4())
+        Dm = np.zeros((n, n), complex)
+        for s in range(p.Ls):
+            Dm[s * n4:(s + 1) * n4, s * n4:(s + 1) * n4] = p.c5_at(s) * Dw - np.eye(n4)
+        err = np.abs(Dm @ Dl - D @ Dm).max() / np.abs(D @ Dm).max()
+        assert err < 1e-13, ("D- D^ = D D-", err)
+        Dld = _dense(lambda v: orc.dw_left(p, U, v, dag=True), n, p.shape5())
+        assert np.abs(Dld - np.conj(Dl.T)).max() < 1e-13 * np.abs(Dl).max(), "left form adjoint"
+    p, _, rng = _setup(dims, 5, 1.75, 0.75, 0.05, seed=25)
+    x = inputs.gaussian_spinor(dims, p.Ls, rng)
+    g5 = np.array([1, 1, -1, -1])[:, None]
+    want = g5 * orc.dw(p, U, (g5 * x)[::-1], dag=True)[::-1]
+    assert _rel(orc.dw_left(p, U, x), want) < 1e-13, "D^ = g5 R D^+ R g5"
+    # diagonal blocks: I
+    xe = restrict(p, x, 0)
+    assert _rel(restrict(p, orc.dw_left(p, U, xe), 0), restrict(p, orc.m5(p, U, x), 0)) < 1e-13
+    # Schur operator: B D_pre B^-1, i.e. (Schur of D^) B = B D_pre
+    xo = restrict(p, x, 1)
+
+    def Bmix(v):  # (B v)_s = b5 v_s + c5 (P+ v_{s-1} + P- v_{s+1}), wraps -m
+        out = p.b5 * v
+        up = np.roll(v, 1, axis=0).copy()
+        up[0] *= -p.mf
+        lo = np.roll(v, -1, axis=0).copy()
+        lo[-1] *= -p.mf
+        out[..., :2, :] += p.c5 * up[..., :2, :]
+        out[..., 2:, :] += p.c5 * lo[..., 2:, :]
+        return out
+    lhs = orc.schur_left(p, U, Bmix(xo))
+    rhs = Bmix(orc.schur(p, U, xo))
+    assert _rel(lhs, rhs) < 1e-13, ("left-form Schur = B D_pre B^-1", _rel(lhs, rhs))
+
+
 def pin_force_wall(orc):
     """4d-HMC action with the pseudofermion on the wall (Sec. 2.4), 2x2x2x4
     with random links: S = phi^+ (D_ov^+ D_ov)^-1 phi with D_ov built densely
@@ -782,4 +830,4 @@ ALL_PINS = [pin_wilson_free_symbol, pin_kernel_bound, pin_gauge_covariance,
             pin_propagator4d_free, pin_propagator4d_dense, pin_wilson_free_symbol_mu,
             pin_adjoints_mu, pin_force_lie, pin_dw_sites, pin_sdep_free_identities,
             pin_sdep_m5_block, pin_sdep_adjoints_and_solve, pin_bulk5d, pin_schur_forms,
-            pin_force_wall]
+            pin_force_wall, pin_left_form]

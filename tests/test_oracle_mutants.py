@@ -63,8 +63,8 @@ MUTANTS = [
     ("dw_sites_adjoint_dropped", "dw_site(p, U, in, sites[k], tmp, dag, buf);",
      "dw_site(p, U, in, sites[k], tmp, 0, buf);"),
     ("sdep_adjoint_row_coefficient", "y[k] = c5_of(p, sm1) * t2[k]", "y[k] = c5_of(p, s) * t2[k]"),
-    ("sdep_forward_row_coefficient", "o[k] += c5_of(p, s) * t2[k]",
-     "o[k] += c5_of(p, (s + 1) % Ls) * t2[k]"),
+    ("sdep_forward_row_coefficient", "o[k] += c5_of(p, s) * t2[k] - slice_buf[x * SITE_DOF + k];\n        } else {",
+     "o[k] += c5_of(p, (s + 1) % Ls) * t2[k] - slice_buf[x * SITE_DOF + k];\n        } else {"),
     ("sdep_corner_coefficients_swapped",
      "km = -p->mf * Mm[Ls - 1];\n        kp = -p->mf * Mm[0];\n    } else {",
      "km = -p->mf * Mm[0];\n        kp = -p->mf * Mm[Ls - 1];\n    } else {"),
@@ -77,6 +77,10 @@ MUTANTS = [
      "orc_m5inv(p, (double *)xo, (double *)t1, 1);      /* I^-1        (odd)  */"),
     ("adjoint_system_forward_block", "orc_hop(p, U, 1, (double *)t1, (double *)t2, dg);      /* odd <- even block",
      "orc_hop(p, U, 1, (double *)t1, (double *)t2, 0);      /* odd <- even block"),
+    ("left_form_coefficient_row", "y[k] = c5_of(p, sm1) * W[sm1 * SITE_DOF + k]",
+     "y[k] = c5_of(p, s) * W[sm1 * SITE_DOF + k]"),
+    ("left_form_projector_swapped", "chiral_part(y, +1, fm1, o);\n            for",
+     "chiral_part(y, -1, fm1, o);\n            for"),
     ("force_only_forward_site", "const int64_t sites[2] = {y, neighbour(p, y, mu, +1)};",
      "const int64_t sites[2] = {y, y};"),
 ]
