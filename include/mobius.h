@@ -347,6 +347,8 @@ typedef struct {
     int32_t stage_links; /* links of a workgroup's sites copied to LDS first (0/1) */
     int32_t xcd_remap;   /* workgroups of one XCD cover one contiguous range of sites (0/1) */
     int32_t nt_links;    /* non-temporal link loads (0/1) */
+    int32_t mfma;        /* FP16: the colour multiply on the matrix cores (0/1); used with
+                            stage_links = 1 when Ls is divisible by 4, ignored otherwise */
     double hop_us;       /* measured time of one hop application D_{p,1-p} (microseconds) */
 } mobius_tune_result;
 

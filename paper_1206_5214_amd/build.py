@@ -25,6 +25,9 @@ SOURCES = ["mobius_kernels.hip", "mobius_force.hip", "mobius_api.cpp", "mobius_s
 
 COMMON = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # matrix-core results in VGPRs (the FP16 hop reads them with VALU
+          # instructions right away; the AGPR form costs a copy per value)
+          "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 
 

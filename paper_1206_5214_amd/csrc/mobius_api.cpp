@@ -867,13 +867,14 @@ extern "C" int mobius_set_tuning(mobius_ctx *ctx, const mobius_tune_result *t)
     if (!t) return fail(MOBIUS_EINVAL, "null tuning");
     if (int r = check_prec(t->prec)) return r;
     if (t->prefetch < 0 || t->prefetch > 2 || (t->stage_links & ~1) || (t->xcd_remap & ~1) ||
-        (t->nt_links & ~1))
+        (t->nt_links & ~1) || (t->mfma & ~1))
         return fail(MOBIUS_EINVAL, "tuning value out of range");
     HopTuning h;
     h.prefetch = t->prefetch;
     h.stage_links = t->stage_links;
     h.xcd_remap = t->xcd_remap;
     h.nt_links = t->nt_links;
+    h.mfma = t->mfma;
     ctx->tune[t->prec] = h;
     ctx->tuned_us[t->prec] = 0;
     return MOBIUS_OK;

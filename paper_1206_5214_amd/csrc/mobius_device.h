@@ -73,6 +73,7 @@ typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 // zero load or a dropped store.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer, CDNA
 constexpr int CPOL_NT = 2;              // cache policy bit: non-temporal
@@ -247,7 +248,8 @@ struct Spin<MOBIUS_F16> {
 #pragma unroll
         for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].r), fabsf(v[c].i)));
         if (!(m >= __FLT_MIN__)) m = 0.f;
-        const float inv = m > 0.f ? 1.0f / m : 0.f;
+        // hardware reciprocal (within an ulp of 1/m, far below the binary16 step)
+        const float inv = m > 0.f ? __builtin_amdgcn_rcpf(m) : 0.f;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -292,15 +294,20 @@ struct Spin<MOBIUS_F16> {
 #pragma unroll
         for (int c = 0; c < 3; ++c) b.st16(__builtin_bit_cast(u32x4, h[c]), k * 16u, (uint32_t)c * N5 * 16u);
         b.st4(__builtin_bit_cast(uint32_t, m), k * 4u, 3u * N5 * 16u);
-        double n = 0;
+        // m^2 sum h^2: the binary16 squares are exact in FP32 and the 24 of
+        // them (each <= 1) are summed by packed dot products with an FP32
+        // accumulator (relative rounding below 24 ulp of FP32), then scaled
+        // by m^2 in FP64
+        float s = 0.f;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const double d = (double)(m * (float)h[c][j]);
-                n += d * d;
+            for (int j = 0; j < 4; ++j) {
+                const half2v p = {h[c][2 * j], h[c][2 * j + 1]};
+                s = __builtin_amdgcn_fdot2(p, p, s, false);
             }
-        return n;
+        const double md = (double)m;
+        return md * md * (double)s;
     }
 };
 
@@ -567,6 +574,53 @@ __device__ __forceinline__ void linkh2_to_words(const LinkH2 &x, u32x4 *q)
     }
 }
 
+// The same link as the A operand of the 4x4x4 matrix-core product
+// (v_mfma_f32_4x4x4_16b_f16: sixteen independent 4x4 blocks per wavefront;
+// lane l supplies row l%4 of block l/4's A and column l%4 of its B, and
+// receives column l%4 of its D).  For one 4d site, (M h)_a for the 2 x Ls half
+// spinors of its s-lanes is the real 8x8 by 8x1 product
+//   rows  (Re0, Im0, Re1, Im1 | Re2, Im2, 0, 0)
+//   Re_a = (pr[a*3+0], pr[a*3+1], pr[a*3+2], 0),  Im_a = (pi[a*3+0], ...)
+//   B    = (h_0, h_1 | h_2, 0)   (binary16 (re, im) pairs)
+// in two row halves (m) and two K halves (k): four products per spin row.
+// Four consecutive lanes of one site share the A operand, so the path needs
+// Ls divisible by 4.  Staged record: the eight rows, 16 bytes each, and 16
+// bytes of padding (a 144-byte stride puts the 16 records that one pass of
+// 16 lanes writes in distinct LDS banks; at 128 bytes they fall on eight);
+// lane l reads rows l%4 and 4 + l%4.
+typedef _Float16 half4v __attribute__((ext_vector_type(4)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+constexpr int LINKROW_REC = 144;
+
+struct LinkRows {
+    half4v a[4];  // (m0, k0), (m0, k1), (m1, k0), (m1, k1) of this lane's rows
+};
+
+__device__ __forceinline__ void linkrows_to_words(const LinkH2 &x, u32x4 *q)
+{
+    auto w = [](half2v v) { return __builtin_bit_cast(uint32_t, v); };
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        q[2 * a] = u32x4{w(x.pr[a * 3]), w(x.pr[a * 3 + 1]), w(x.pr[a * 3 + 2]), 0u};
+        q[2 * a + 1] = u32x4{w(x.pi[a * 3]), w(x.pi[a * 3 + 1]), w(x.pi[a * 3 + 2]), 0u};
+    }
+    q[6] = q[7] = u32x4{0u, 0u, 0u, 0u};
+}
+
+// One staged FP16 link record: the dot2 operand form, or the matrix-core rows
+// (each branch of the caller expands and stores on its own, so that the
+// expanded link stays in registers)
+template <bool FWD, bool ROWS>
+__device__ __forceinline__ void stage_link_f16(const half2v u[9], u32x4 *q)
+{
+    LinkH2 x;
+    expand_link<FWD>(u, x);
+    if constexpr (ROWS)
+        linkrows_to_words(x, q);
+    else
+        linkh2_to_words(x, q);
+}
+
 // The links of a block's sites, staged in LDS by one cooperative copy so
 // that each record crosses the vector-memory pipeline once instead of once
 // per s-lane.  Layout [d][site in block][record].
@@ -598,6 +652,17 @@ struct LinkSource {
             Link<P>::raw_load(*glob, i * (uint32_t)REC, (uint32_t)d * Vh * (uint32_t)REC, u);
             expand_link<FWD>(u, x);
         }
+    }
+    // FP16 links as matrix-core A rows (staged records of LINKROW_REC bytes
+    // only); quad = lane % 4
+    __device__ __forceinline__ void get_rows(int d, int quad, LinkRows &x) const
+    {
+        const u32x4 *q = reinterpret_cast<const u32x4 *>(lds + ((size_t)d * sites_blk + sib) * LINKROW_REC);
+        const u32x4 r0 = q[quad], r1 = q[4 + quad];
+        x.a[0] = __builtin_bit_cast(half4v, u32x2{r0[0], r0[1]});
+        x.a[1] = __builtin_bit_cast(half4v, u32x2{r0[2], r0[3]});
+        x.a[2] = __builtin_bit_cast(half4v, u32x2{r1[0], r1[1]});
+        x.a[3] = __builtin_bit_cast(half4v, u32x2{r1[2], r1[3]});
     }
 };
 
@@ -644,6 +709,40 @@ __device__ __forceinline__ void half_spinor_h2(const half2v o[12], const half2v 
         }
         h[a] = u0 + sg * A0;
         h[3 + a] = u1 + sg * A1;
+    }
+}
+
+// The colour multiply on the matrix cores (operand layout at LinkRows),
+// then the same FP32 reconstruction as link_accumulate_h2.
+template <int MU, int SIGMA>
+__device__ __forceinline__ void link_accumulate_mfma(const half2v h[6], float s, const LinkRows &x,
+                                                     cx<float> acc[12])
+{
+    const float4v z = {0.f, 0.f, 0.f, 0.f};
+    const _Float16 h0 = (_Float16)0;
+    cx<float> w[2][3];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+        const half2v *hs = h + 3 * sp;
+        const half4v k0 = {hs[0].x, hs[0].y, hs[1].x, hs[1].y};
+        const half4v k1 = {hs[2].x, hs[2].y, h0, h0};
+        float4v lo = __builtin_amdgcn_mfma_f32_4x4x4f16(x.a[0], k0, z, 0, 0, 0);
+        lo = __builtin_amdgcn_mfma_f32_4x4x4f16(x.a[1], k1, lo, 0, 0, 0);
+        float4v hi = __builtin_amdgcn_mfma_f32_4x4x4f16(x.a[2], k0, z, 0, 0, 0);
+        hi = __builtin_amdgcn_mfma_f32_4x4x4f16(x.a[3], k1, hi, 0, 0, 0);
+        w[sp][0] = {lo[0], lo[1]};
+        w[sp][1] = {lo[2], lo[3]};
+        w[sp][2] = {hi[0], hi[1]};
+    }
+    const float sg = (float)SIGMA * s;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        acc[a] = acc[a] + s * w[0][a];
+        acc[3 + a] = acc[3 + a] + s * w[1][a];
+        cx<float> o0, o1;
+        Adag_apply<float, MU>(w[0][a], w[1][a], o0, o1);
+        acc[6 + a] = acc[6 + a] + sg * o0;
+        acc[9 + a] = acc[9 + a] + sg * o1;
     }
 }
 

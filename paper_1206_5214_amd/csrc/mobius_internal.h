@@ -133,7 +133,8 @@ struct HopParams {
     int remap;              // XCD-contiguous block order
     int stage_links;        // copy the block's links to LDS first
     int nt;                 // non-temporal loads of the links
-    int pf;                 // prefetch depth of the direction loop (0, 1, 2)
+    int pf;                 // prefetch depth of the direction loop (0, 1, 2); 3: FP16 matrix-core
+                            // colour multiply (requires stage_links and Ls % 4 == 0)
     OpCoeffs c;
 };
 
@@ -148,6 +149,7 @@ struct HopTuning {
     int prefetch = -1;     // 0, 1 (next neighbour spinor), 2 (and its link); -1: per precision
     int stage_links = 1;   // copy each block's links to LDS once
     int nt_links = 0;      // non-temporal link loads
+    int mfma = 1;          // FP16: colour multiply on the matrix cores where the lane map allows
 };
 // prefetch depth used for a precision (measured at 24^3x64, Ls=12: the FP64
 // hop needs more than 256 VGPRs once a neighbour is prefetched, which halves
@@ -191,7 +193,7 @@ hipError_t launch_hop(const Geometry &g, const OpCoeffs &c, const void *links, c
                       const HopArgs &a, hipStream_t st);
 HopParams make_hop_params(const Geometry &g, const OpCoeffs &c, const void *links,
                           const int32_t *nbr, const HopArgs &a);
-size_t hop_link_lds_bytes(int prec, int Ls);
+size_t hop_link_lds_bytes(int prec, int Ls, bool rows);
 // persistent launch over groups (device array) with block prefix sums prefix[0..n]
 hipError_t launch_hop_batch(int prec, int dag, int epi, const HopParams *groups_dev, int ngroups,
                             const int64_t *prefix_dev, size_t lds_bytes, int grid, int pf,

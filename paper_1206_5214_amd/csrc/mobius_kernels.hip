@@ -68,12 +68,12 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
                              : blink.ld16((i0 + j) * REC + 16u * w, d * Vh * REC);
             half2v u[9];
             Link<MOBIUS_F16>::raw_from_words(q, u);
-            LinkH2 x;
+            constexpr uint32_t W = (PF == 3 ? LINKROW_REC : LINKH2_REC) / 16;
+            u32x4 *dst = dyn_lds + (size_t)(d * ls.sites_blk + j) * W;
             if (d < 4)
-                expand_link<true>(u, x);
+                stage_link_f16<true, PF == 3>(u, dst);
             else
-                expand_link<false>(u, x);
-            linkh2_to_words(x, dyn_lds + (size_t)(d * ls.sites_blk + j) * (LINKH2_REC / 16));
+                stage_link_f16<false, PF == 3>(u, dst);
         }
         ls.lds = reinterpret_cast<const char *>(dyn_lds);
     } else if (hp.stage_links) {
@@ -121,16 +121,37 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
         // forward block: B mixing weights of this lane (norms folded in per direction)
         const float wu = MIXIN ? (float)wB.bu * (m.s == 0 ? -(float)k.mf : 1.f) : 0.f;
         const float wl = MIXIN ? (float)wB.bl * (m.s == Ls - 1 ? -(float)k.mf : 1.f) : 0.f;
-        RawH nx;
+        // PF 3: the colour multiply on the matrix cores, links and neighbour
+        // spinors prefetched one direction ahead
+        constexpr bool MF = PF == 3;
+        const int quad = m.lane & 3;
+        // (its spinors two directions ahead: the registers the colour
+        // multiply frees hold one more direction in flight)
+        RawH nx, nx2;
         LinkH2 unx;
+        LinkRows rnx;
         load_raw_f16(bin, N5, jn[0], nx);
-        if constexpr (PF >= 2) ls.template get_h2<true>(0, unx);
+        if constexpr (MF) {
+            load_raw_f16(bin, N5, jn[1], nx2);
+            ls.get_rows(0, quad, rnx);
+        } else if constexpr (PF >= 2) {
+            ls.template get_h2<true>(0, unx);
+        }
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const RawH o = nx;
-            if (d < 7) load_raw_f16(bin, N5, jn[d + 1], nx);
+            if constexpr (MF) {
+                nx = nx2;
+                if (d < 6) load_raw_f16(bin, N5, jn[d + 2], nx2);
+            } else {
+                if (d < 7) load_raw_f16(bin, N5, jn[d + 1], nx);
+            }
             LinkH2 u;
-            if constexpr (PF >= 2) {
+            LinkRows ur;
+            if constexpr (MF) {
+                ur = rnx;
+                if (d < 7) ls.get_rows(d + 1, quad, rnx);
+            } else if constexpr (PF >= 2) {
                 u = unx;
                 if (d < 3)
                     ls.template get_h2<true>(d + 1, unx);
@@ -168,16 +189,22 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
             const half2v al2 = splat_h2(al * inv), bu2 = splat_h2(bu * inv), bl2 = splat_h2(bl * inv);
             half2v hh[6];
 #define MOBIUS_HS(MU, SG) half_spinor_h2<MU, SG, MIXIN>(o.c, um, lp, al2, bu2, bl2, hh)
+#define MOBIUS_LA(MU, SG)                                                                          \
+    if constexpr (MF)                                                                              \
+        link_accumulate_mfma<MU, SG>(hh, -0.5f * sc, ur, acc);                                     \
+    else                                                                                           \
+        link_accumulate_h2<MU, SG>(hh, -0.5f * sc, u, acc)
             switch (d) {
-            case 0: MOBIUS_HS(0, SF); link_accumulate_h2<0, SF>(hh, sc, u, acc); break;
-            case 1: MOBIUS_HS(1, SF); link_accumulate_h2<1, SF>(hh, sc, u, acc); break;
-            case 2: MOBIUS_HS(2, SF); link_accumulate_h2<2, SF>(hh, sc, u, acc); break;
-            case 3: MOBIUS_HS(3, SF); link_accumulate_h2<3, SF>(hh, sc, u, acc); break;
-            case 4: MOBIUS_HS(0, -SF); link_accumulate_h2<0, -SF>(hh, sc, u, acc); break;
-            case 5: MOBIUS_HS(1, -SF); link_accumulate_h2<1, -SF>(hh, sc, u, acc); break;
-            case 6: MOBIUS_HS(2, -SF); link_accumulate_h2<2, -SF>(hh, sc, u, acc); break;
-            default: MOBIUS_HS(3, -SF); link_accumulate_h2<3, -SF>(hh, sc, u, acc); break;
+            case 0: MOBIUS_HS(0, SF); MOBIUS_LA(0, SF); break;
+            case 1: MOBIUS_HS(1, SF); MOBIUS_LA(1, SF); break;
+            case 2: MOBIUS_HS(2, SF); MOBIUS_LA(2, SF); break;
+            case 3: MOBIUS_HS(3, SF); MOBIUS_LA(3, SF); break;
+            case 4: MOBIUS_HS(0, -SF); MOBIUS_LA(0, -SF); break;
+            case 5: MOBIUS_HS(1, -SF); MOBIUS_LA(1, -SF); break;
+            case 6: MOBIUS_HS(2, -SF); MOBIUS_LA(2, -SF); break;
+            default: MOBIUS_HS(3, -SF); MOBIUS_LA(3, -SF); break;
             }
+#undef MOBIUS_LA
 #undef MOBIUS_HS
 #pragma unroll
             for (int c = 0; c < 12; ++c) pin(acc[c]);
@@ -227,9 +254,13 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
         __builtin_amdgcn_sched_barrier(0);
     }
     }
-    const T mhalf = (T)-0.5;
+    // the -1/2 of the hopping term (the FP16 loop folds it into each
+    // direction's scale, a power of two, so the result is the same)
+    if constexpr (P != MOBIUS_F16) {
+        const T mhalf = (T)-0.5;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = mhalf * acc[c];
+        for (int c = 0; c < 12; ++c) acc[c] = mhalf * acc[c];
+    }
 
     {
     // coefficients of the epilogue, converted here so that none of them is
@@ -975,19 +1006,26 @@ namespace {
 
 // dynamic LDS of one block for the staged links: [8][sites per block][record]
 template <int P>
-size_t link_lds_bytes(int spw)
+size_t link_lds_bytes(int spw, bool rows)
 {
-    return (size_t)8 * WAVES * spw * (P == MOBIUS_F16 ? LINKH2_REC : Link<P>::REC);
+    // FP16: the dot2 operand form, or the matrix-core rows (pf 3)
+    return (size_t)8 * WAVES * spw * (P == MOBIUS_F16 ? (rows ? LINKROW_REC : LINKH2_REC) : Link<P>::REC);
 }
 
 template <int P, bool DAG, int EPI>
 void hop_launch(const HopParams &hp, hipStream_t st)
 {
-    const size_t dyn = hp.stage_links ? link_lds_bytes<P>(hp.spw) : 0;
+    const size_t dyn = hp.stage_links ? link_lds_bytes<P>(hp.spw, hp.pf == 3) : 0;
     const dim3 grid((unsigned)hp.nblocks), blk(BLOCK);
     switch (hp.pf) {
     case 0: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 0>), grid, blk, dyn, st, hp); break;
     case 1: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 1>), grid, blk, dyn, st, hp); break;
+    case 3:
+        if constexpr (P == MOBIUS_F16) {
+            hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 3>), grid, blk, dyn, st, hp);
+            break;
+        }
+        [[fallthrough]];
     default: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 2>), grid, blk, dyn, st, hp); break;
     }
 }
@@ -999,6 +1037,12 @@ void hop_batch_launch(const HopParams *groups, int n, const int64_t *prefix, siz
     switch (pf) {
     case 0: hipLaunchKernelGGL((hop_batch_kernel<P, DAG, EPI, 0>), dim3(grid), dim3(BLOCK), dyn, st, groups, n, prefix); break;
     case 1: hipLaunchKernelGGL((hop_batch_kernel<P, DAG, EPI, 1>), dim3(grid), dim3(BLOCK), dyn, st, groups, n, prefix); break;
+    case 3:
+        if constexpr (P == MOBIUS_F16) {
+            hipLaunchKernelGGL((hop_batch_kernel<P, DAG, EPI, 3>), dim3(grid), dim3(BLOCK), dyn, st, groups, n, prefix);
+            break;
+        }
+        [[fallthrough]];
     default: hipLaunchKernelGGL((hop_batch_kernel<P, DAG, EPI, 2>), dim3(grid), dim3(BLOCK), dyn, st, groups, n, prefix); break;
     }
 }
@@ -1093,13 +1137,13 @@ struct RunHopBatch {
 
 }  // namespace
 
-size_t hop_link_lds_bytes(int prec, int Ls)
+size_t hop_link_lds_bytes(int prec, int Ls, bool rows)
 {
     const int spw = sites_per_wave(Ls);
     switch (prec) {
-    case MOBIUS_F64: return link_lds_bytes<MOBIUS_F64>(spw);
-    case MOBIUS_F32: return link_lds_bytes<MOBIUS_F32>(spw);
-    default: return link_lds_bytes<MOBIUS_F16>(spw);
+    case MOBIUS_F64: return link_lds_bytes<MOBIUS_F64>(spw, false);
+    case MOBIUS_F32: return link_lds_bytes<MOBIUS_F32>(spw, false);
+    default: return link_lds_bytes<MOBIUS_F16>(spw, rows);
     }
 }
 
@@ -1126,9 +1170,14 @@ HopParams make_hop_params(const Geometry &g, const OpCoeffs &c, const void *link
     hp.nrhs = a.nrhs;
     const HopTuning &t = a.tune ? *a.tune : hop_tuning();
     hp.remap = t.xcd_remap;
-    hp.stage_links = t.stage_links && hop_link_lds_bytes(a.prec, g.Ls) <= 64 * 1024;
+    hp.stage_links = t.stage_links && hop_link_lds_bytes(a.prec, g.Ls, false) <= 64 * 1024;
     hp.nt = t.nt_links;
     hp.pf = prefetch_depth(t, a.prec);
+    // matrix-core colour multiply: FP16 with staged links and whole 4-lane
+    // groups of one site (Ls divisible by 4)
+    if (a.prec == MOBIUS_F16 && t.mfma && hp.stage_links && g.Ls % 4 == 0 &&
+        hop_link_lds_bytes(a.prec, g.Ls, true) <= 64 * 1024)
+        hp.pf = 3;
     hp.c = c;
     return hp;
 }

@@ -330,7 +330,7 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
             h_hop[(size_t)pid * ng + j] = h;
             h_prefix[(size_t)pid * (ng + 1) + j] = acc;
             acc += h.nblocks;
-            if (h.stage_links) hop_lds[pid] = std::max(hop_lds[pid], hop_link_lds_bytes(hp[pid].prec, g.ctx->g.Ls));
+            if (h.stage_links) hop_lds[pid] = 1;  // sized below, once the loop variant is known
         }
         h_prefix[(size_t)pid * (ng + 1) + ng] = acc;
     }
@@ -338,6 +338,21 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
     for (int pid = 0; pid < NHOP; ++pid)
         for (int j = 0; j < ng; ++j) h_hop[(size_t)pid * ng + j].stage_links = hop_lds[pid] > 0 &&
             h_hop[(size_t)pid * ng + j].stage_links;
+    // one launch takes the first group's loop variant: the matrix-core one
+    // only if every group can run it
+    for (int pid = 0; pid < NHOP; ++pid) {
+        bool all_mf = true;
+        for (int j = 0; j < ng; ++j) all_mf = all_mf && h_hop[(size_t)pid * ng + j].pf == 3;
+        if (!all_mf)
+            for (int j = 0; j < ng; ++j)
+                if (h_hop[(size_t)pid * ng + j].pf == 3) h_hop[(size_t)pid * ng + j].pf = 2;
+        // dynamic LDS of the launch: the largest staged record block of its groups
+        const bool rows = h_hop[(size_t)pid * ng].pf == 3;
+        hop_lds[pid] = 0;
+        for (int j = 0; j < ng; ++j)
+            if (h_hop[(size_t)pid * ng + j].stage_links)
+                hop_lds[pid] = std::max(hop_lds[pid], hop_link_lds_bytes(hp[pid].prec, groups[j].ctx->g.Ls, rows));
+    }
     h_vec.assign((size_t)NVEC * nsys, VecSys{});
     for (const Group &g : groups)
         for (int r = 0; r < g.nrhs; ++r) {

@@ -6,6 +6,7 @@
 //   link staging in LDS                    {off, on}
 //   XCD-contiguous block order             {off, on}
 //   non-temporal link loads                {off, on}
+//   FP16 colour multiply on the matrix cores {off, on} (with staging, Ls % 4 == 0)
 // and keeps the fastest in the context; every later operator application,
 // solve and force evaluation of the context launches with it.  Results can be
 // cached in a text file (one line per lattice, Ls, precision and device)
@@ -34,7 +35,7 @@ std::string cache_key(const mobius_ctx *ctx, int prec)
     std::ostringstream k;
     k << ctx->g.L[0] << 'x' << ctx->g.L[1] << 'x' << ctx->g.L[2] << 'x' << ctx->g.L[3] << " Ls"
       << ctx->g.Ls << " brick" << ctx->g.brick[0] << 'x' << ctx->g.brick[1] << 'x'
-      << ctx->g.brick[2] << " prec" << prec << ' ' << arch;
+      << ctx->g.brick[2] << " prec" << prec << ' ' << arch << " v2";
     return k.str();
 }
 
@@ -49,7 +50,7 @@ bool cache_lookup(const std::string &path, const std::string &key, HopTuning &t,
         std::istringstream v(line.substr(bar + 3));
         HopTuning c;
         double u;
-        if (v >> c.prefetch >> c.stage_links >> c.xcd_remap >> c.nt_links >> u) {
+        if (v >> c.prefetch >> c.stage_links >> c.xcd_remap >> c.nt_links >> c.mfma >> u) {
             t = c;
             us = u;
             found = true;
@@ -63,7 +64,7 @@ void cache_store(const std::string &path, const std::string &key, const HopTunin
     std::ofstream f(path, std::ios::app);
     f.precision(17);  // the time reads back exactly
     f << key << " | " << t.prefetch << ' ' << t.stage_links << ' ' << t.xcd_remap << ' '
-      << t.nt_links << ' ' << us << '\n';
+      << t.nt_links << ' ' << t.mfma << ' ' << us << '\n';
 }
 
 }  // namespace
@@ -92,15 +93,20 @@ int tune(mobius_ctx *ctx, int prec, int reps, mobius_tune_result *out, hipStream
         const int nrep = reps > 0 ? reps : 10;
         best_us = 1e300;
         int rc = MOBIUS_OK;
+        const int nmf = prec == MOBIUS_F16 && g.Ls % 4 == 0 ? 2 : 1;
+        for (int mf = 0; mf < nmf && rc == MOBIUS_OK; ++mf)
         for (int pf = 0; pf < 3 && rc == MOBIUS_OK; ++pf)
             for (int stage = 0; stage < 2 && rc == MOBIUS_OK; ++stage)
                 for (int remap = 0; remap < 2 && rc == MOBIUS_OK; ++remap)
                     for (int nt = 0; nt < 2 && rc == MOBIUS_OK; ++nt) {
+                        // the matrix-core loop has one prefetch depth and needs staging
+                        if (mf && (pf != 2 || !stage)) continue;
                         HopTuning c;
                         c.prefetch = pf;
                         c.stage_links = stage;
                         c.xcd_remap = remap;
                         c.nt_links = nt;
+                        c.mfma = mf;
                         HopArgs a;
                         a.prec = prec;
                         a.dag = 0;
@@ -146,6 +152,7 @@ int tune(mobius_ctx *ctx, int prec, int reps, mobius_tune_result *out, hipStream
         out->stage_links = best.stage_links;
         out->xcd_remap = best.xcd_remap;
         out->nt_links = best.nt_links;
+        out->mfma = best.mfma;
         out->hop_us = best_us;
     }
     return MOBIUS_OK;

@@ -49,7 +49,7 @@ class _SolveOpts(ctypes.Structure):
 class _TuneResult(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("prefetch", ctypes.c_int32),
                 ("stage_links", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("nt_links", ctypes.c_int32), ("hop_us", ctypes.c_double)]
+                ("nt_links", ctypes.c_int32), ("mfma", ctypes.c_int32), ("hop_us", ctypes.c_double)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -388,11 +388,11 @@ class Operator:
         r = _TuneResult()
         _check(lib().mobius_tune(self._h, prec, reps, ctypes.byref(r), _stream()))
         return {"prec": r.prec, "prefetch": r.prefetch, "stage_links": r.stage_links,
-                "xcd_remap": r.xcd_remap, "nt_links": r.nt_links, "hop_us": r.hop_us}
+                "xcd_remap": r.xcd_remap, "nt_links": r.nt_links, "mfma": r.mfma, "hop_us": r.hop_us}
 
-    def set_tuning(self, prec, prefetch, stage_links, xcd_remap, nt_links):
+    def set_tuning(self, prec, prefetch, stage_links, xcd_remap, nt_links, mfma=0):
         """Set the hop launch parameters for one precision explicitly."""
-        r = _TuneResult(prec, prefetch, stage_links, xcd_remap, nt_links, 0.0)
+        r = _TuneResult(prec, prefetch, stage_links, xcd_remap, nt_links, mfma, 0.0)
         _check(lib().mobius_set_tuning(self._h, ctypes.byref(r)))
 
     def force(self, phi, tol=1e-12, maxiter=20000, inner_prec=F64, reliable_delta=0.0,

@@ -48,6 +48,7 @@ def test_tune_keeps_results(torch_cuda, monkeypatch):
         print(f"prec {prec}: {r}", flush=True)
         assert r["prec"] == prec and r["prefetch"] in (0, 1, 2)
         assert r["stage_links"] in (0, 1) and r["xcd_remap"] in (0, 1) and r["nt_links"] in (0, 1)
+        assert r["mfma"] in (0, 1)
         assert r["hop_us"] > 0
         after = outputs()
         for a, b in zip(before, after):
@@ -84,14 +85,17 @@ def test_tune_rejects_bad_precision(torch_cuda):
     op.close()
 
 
-LAUNCH_VARIANTS = [(pf, st, rm, nt) for pf in (0, 1, 2) for st in (0, 1) for rm in (0, 1) for nt in (0, 1)]
+LAUNCH_VARIANTS = ([(pf, st, rm, nt, 0) for pf in (0, 1, 2) for st in (0, 1) for rm in (0, 1) for nt in (0, 1)]
+                   + [(2, 1, rm, nt, 1) for rm in (0, 1) for nt in (0, 1)])
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "f16"])
 def test_every_launch_variant_vs_oracle(torch_cuda, orc, prec):
-    """Each of the 24 candidates the tuner may pick, set explicitly, gives the
-    hop blocks (forward and adjoint, both parities) and the Schur operator
-    within the storage precision's tolerance of the FP64 oracle."""
+    """Each of the 28 candidates the tuner may pick (the last four: the FP16
+    matrix-core colour multiply, the launch parameters alone elsewhere), set
+    explicitly, gives the hop blocks (forward and adjoint, both parities) and
+    the Schur operator within the storage precision's tolerance of the FP64
+    oracle."""
     from oracle import Params
     from paper_1206_5214_amd import inputs, mobius
     torch = torch_cuda
@@ -121,4 +125,6 @@ def test_every_launch_variant_vs_oracle(torch_cuda, orc, prec):
         assert np.linalg.norm(s - want_schur) <= tol * np.linalg.norm(want_schur), (v, prec)
     with pytest.raises(mobius.MobiusError):
         op.set_tuning(prec, 3, 0, 0, 0)
+    with pytest.raises(mobius.MobiusError):
+        op.set_tuning(prec, 2, 1, 0, 0, 2)
     op.close()
