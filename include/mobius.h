@@ -74,7 +74,10 @@ typedef enum {
                                   the diagonal block taken out on the right; out_parity 1) */
     MOBIUS_OP_HOP_LEFT = 5,    /* off-diagonal block of the left form D^ = D-^-1 D_DW D- of
                                   Sec. 2.1: D^_{p,1-p} = -1/2 B H, parity 1-p -> p */
-    MOBIUS_OP_SCHUR_LEFT = 6   /* Schur operator of D^: 1 - I^-1 D^_oe I^-1 D^_eo = B D_pre B^-1,
+    MOBIUS_OP_SCHUR_LEFT = 6,  /* Schur operator of D^: 1 - I^-1 D^_oe I^-1 D^_eo = B D_pre B^-1,
+                                  odd -> odd (out_parity 1) */
+    MOBIUS_OP_SCHUR_COMPLEMENT = 7  /* the Schur complement of the even block itself (Sec. 3),
+                                  S = I - D_oe I^-1 D_eo = I D_pre, with no diagonal block taken out,
                                   odd -> odd (out_parity 1) */
 } mobius_op;
 
@@ -113,7 +116,9 @@ typedef struct {
                               D_R z = eta_o - D_oe I^-1 eta_e, psi_o = I^-1 z (D_R = I D_pre I^-1);
                               2 = the left form D^ = D-^-1 D_DW D- of Sec. 2.1 (constant b5, c5):
                               (B D_pre B^-1) y = B b', psi_o = B^-1 y, whose hops apply B after
-                              the hopping sum and so never gather the s-neighbours of their input.
+                              the hopping sum and so never gather the s-neighbours of their input;
+                              3 = the Schur complement itself, S psi_o = eta_o - D_oe I^-1 eta_e
+                              with S = I - D_oe I^-1 D_eo (no diagonal preconditioning).
                               The same solution every way; schur_resid, kappa and err_bound refer
                               to the system iterated on.  mobius_force uses 0. */
 } mobius_solve_opts;
@@ -182,7 +187,8 @@ int mobius_unpack(mobius_ctx *ctx, int32_t prec, const void *even, const void *o
  *                   out_p = D_{p,1-p} in_{1-p} + I in_p; out_parity is ignored;
  *   MOBIUS_OP_HOP_LEFT   out(p) = -1/2 B H_{p,1-p} in(1-p), the hop block of the
  *                   left form D^ = D-^-1 D_DW D- = B D_W + 1 - C5 (Sec. 2.1);
- *   MOBIUS_OP_SCHUR_LEFT out = in - I^-1 D^_oe I^-1 D^_eo in (odd, out_parity 1).
+ *   MOBIUS_OP_SCHUR_LEFT out = in - I^-1 D^_oe I^-1 D^_eo in (odd, out_parity 1);
+ *   MOBIUS_OP_SCHUR_COMPLEMENT out = I in - D_oe I^-1 D_eo in (odd, out_parity 1).
  * The two left-form operators need constant b5, c5 (MOBIUS_EINVAL otherwise:
  * with per-slice coefficients B and I no longer commute) and b5 != 0.
  * in and out are packed fields of precision `prec`, nrhs consecutive fields
@@ -200,7 +206,8 @@ int mobius_dslash(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
  *   MOBIUS_OP_SCHUR_RIGHT out = D_R^+ in = in - I^-+ (D_eo)^+ I^-+ (D_oe)^+ in;
  *   MOBIUS_OP_FULL  out = D_DW(m)^+ in, out_p = (D^+)_{p,1-p} in_{1-p} + I^+ in_p;
  *   MOBIUS_OP_HOP_LEFT   out(p) = (D^_{1-p,p})^+ in = -1/2 H^+ B^+ in;
- *   MOBIUS_OP_SCHUR_LEFT out = in - (D^_eo)^+ I^-+ (D^_oe)^+ I^-+ in. */
+ *   MOBIUS_OP_SCHUR_LEFT out = in - (D^_eo)^+ I^-+ (D^_oe)^+ I^-+ in;
+ *   MOBIUS_OP_SCHUR_COMPLEMENT out = I^+ in - (D_eo)^+ I^-+ (D_oe)^+ in. */
 int mobius_dslash_dag(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
                       const void *in, void *out, int32_t nrhs, void *stream);
 
@@ -209,7 +216,8 @@ int mobius_dslash_dag(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_par
  * operator blocks of mobius_dslash (dagger = 0) and mobius_dslash_dag
  * (dagger = 1), same arguments and results, with no allocation of any kind.
  * MOBIUS_OP_SCHUR, SCHUR_RIGHT and SCHUR_LEFT keep their two temporary packed
- * fields per right-hand side (HOP_LEFT with dagger = 1: one) in a fixed
+ * fields per right-hand side (HOP_LEFT with dagger = 1 and SCHUR_COMPLEMENT:
+ * one) in a fixed
  * workspace of 64 MiB per GPU (a static device array that the library holds
  * from the first mobius_create on that GPU until the process ends); a call
  * needing more (2 * nrhs * mobius_field_bytes(ctx, prec) > 64 MiB) returns

@@ -285,6 +285,15 @@ def schur_left(p: Params, U, psi, dag=False):
     return restrict(p, x - t, 1)
 
 
+def schur_complement(p: Params, U, psi, dag=False):
+    """The Schur complement of the even block on the odd parity (Sec. 3),
+    S = I - D_oe I^-1 D_eo, or its adjoint I^+ - D_eo^+ I^-+ D_oe^+, from the
+    blocks as the definition states them (no diagonal block taken out)."""
+    x = restrict(p, psi, 1)
+    t = hop(p, U, m5inv(p, hop(p, U, x, 0, dag=dag), dag=dag), 1, dag=dag)
+    return restrict(p, m5(p, U, x, dag=dag) - t, 1)
+
+
 def schur_right(p: Params, U, psi, dag=False):
     """D_R = 1 - D_oe I^-1 D_eo I^-1 (or its adjoint) on an odd-parity field."""
     U, psi = _c128(U), _c128(psi)

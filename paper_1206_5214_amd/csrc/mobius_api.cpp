@@ -516,6 +516,32 @@ int dslash_common(mobius_ctx *ctx, int32_t prec, int32_t op, int32_t out_parity,
         }
         return MOBIUS_OK;
     }
+    case MOBIUS_OP_SCHUR_COMPLEMENT: {
+        // S = I - D_oe I^-1 D_eo (t = B I^-1 D_eo in, out = I in - D_oe t);
+        // S^+ = I^+ - D_eo^+ I^-+ D_oe^+ (t = I^-+ D_oe^+ in, out = I^+ in - D_eo^+ t)
+        if (out_parity != 1)
+            return fail(MOBIUS_EINVAL, "SCHUR_COMPLEMENT acts on the odd parity (out_parity = 1)");
+        const int64_t fb = field_bytes(ctx->g, prec) * nrhs;
+        char *t;
+        if (fixed_scratch) {
+            if (fb > fixed_bytes)
+                return fail(MOBIUS_EINVAL, "mobius_dslash_noalloc: SCHUR_COMPLEMENT needs " + std::to_string(fb) +
+                                               " bytes of workspace, above the fixed maximum of " +
+                                               std::to_string(fixed_bytes));
+            t = static_cast<char *>(fixed_scratch);
+        } else {
+            HIPCHK(ctx->scratch.ensure(fb));
+            t = static_cast<char *>(ctx->scratch.p);
+        }
+        if (!dag) {
+            HIPCHK(hop(ctx, hop_args(prec, 0, EPI_M5INV | EPI_BMIX, 0, in, t, nullptr, nullptr, nullptr, nrhs), st));
+            HIPCHK(hop(ctx, hop_args(prec, 0, EPI_PREMIXED | EPI_M5SUB, 1, t, out, nullptr, in, nullptr, nrhs), st));
+        } else {
+            HIPCHK(hop(ctx, hop_args(prec, 1, EPI_M5INV, 0, in, t, nullptr, nullptr, nullptr, nrhs), st));
+            HIPCHK(hop(ctx, hop_args(prec, 1, EPI_M5SUB, 1, t, out, nullptr, in, nullptr, nrhs), st));
+        }
+        return MOBIUS_OK;
+    }
     case MOBIUS_OP_SCHUR: {
         if (out_parity != 1) return fail(MOBIUS_EINVAL, "SCHUR acts on the odd parity (out_parity = 1)");
         const int64_t fb = field_bytes(ctx->g, prec) * nrhs;

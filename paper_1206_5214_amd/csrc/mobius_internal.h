@@ -97,6 +97,7 @@ enum Epilogue : int {
     EPI_PREMIXED = 128,  // forward hop whose input already holds B in: r = -1/2 H in
     EPI_NOBOUT = 256,  // adjoint hop without its output B^+: r = -1/2 H^+ in (the left form's
                        // adjoint, whose B^+ acts on the input); EPI_BMIX then applies B^+
+    EPI_M5SUB = 512,   // r = I y - r (I^+ y - r in the adjoint hop): the Schur complement itself
 };
 
 struct HopArgs {
@@ -328,7 +329,9 @@ int set_error(int code, const std::string &msg);
 // of Sec. 2.1, 1 - I^-1 D^_oe I^-1 D^_eo = B D_pre B^-1 (constant coefficients),
 // on y = B psi_o: every hop of its CG step applies B after the hopping sum, so
 // none gathers the s-neighbours of its input.
-enum SchurForm { FORM_LEFT = 0, FORM_RIGHT = 1, FORM_LHAT = 2, FORM_ADJ = 3 };
+// FORM_PLAIN iterates on the Schur complement itself, S = I - D_oe I^-1 D_eo
+// (D_pre = I^-1 S), on psi_o.
+enum SchurForm { FORM_LEFT = 0, FORM_RIGHT = 1, FORM_LHAT = 2, FORM_ADJ = 3, FORM_PLAIN = 4 };
 // coefficients of I with (M+, M-) replaced by (b5, c5): the same elimination
 // then applies B = b5 + c5 C5 (kind 0) or B^-1 (kind 1) through launch_m5
 OpCoeffs b_coeffs(const OpCoeffs &c, int Ls);

@@ -279,6 +279,13 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] = acc[c] + yv[c];
     }
+    if constexpr ((EPI & EPI_M5SUB) != 0) {
+        cx<T> yv[12];
+        S::load(Buf(yr, fbytes), N5, k5, yv);
+        mix_s(yv, mix_w(k, true, m, Ls, DAG), k.mf, m, Ls, DAG);  // I y (I^+ y)
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = yv[c] - acc[c];
+    }
     if constexpr ((EPI & EPI_PRESUB) != 0) {
         cx<T> xv[12];
         S::load(Buf(xr, fbytes), N5, k5, xv);
@@ -1097,6 +1104,18 @@ bool dispatch_hop(int prec, int dag, int epi, A &&...args)
         return !D;                                                                                 \
     case EPI_NOBOUT:                                                                               \
         if constexpr (D) F<P, D, EPI_NOBOUT>::run(args...);                                        \
+        return D;                                                                                  \
+    case EPI_PREMIXED | EPI_M5SUB:                                                                 \
+        if constexpr (!D) F<P, D, EPI_PREMIXED | EPI_M5SUB>::run(args...);                         \
+        return !D;                                                                                 \
+    case EPI_PREMIXED | EPI_M5SUB | EPI_NORM:                                                      \
+        if constexpr (!D) F<P, D, EPI_PREMIXED | EPI_M5SUB | EPI_NORM>::run(args...);              \
+        return !D;                                                                                 \
+    case EPI_M5SUB:                                                                                \
+        if constexpr (D) F<P, D, EPI_M5SUB>::run(args...);                                         \
+        return D;                                                                                  \
+    case EPI_M5SUB | EPI_NORM:                                                                     \
+        if constexpr (D) F<P, D, EPI_M5SUB | EPI_NORM>::run(args...);                              \
         return D;                                                                                  \
     case EPI_NOBOUT | EPI_M5INV | EPI_BMIX:                                                        \
         if constexpr (D) F<P, D, EPI_NOBOUT | EPI_M5INV | EPI_BMIX>::run(args...);                 \

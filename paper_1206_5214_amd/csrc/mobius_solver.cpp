@@ -135,7 +135,7 @@ struct Batch {
     // left form of D^, nothing for the right form
     int rupd_mode() const
     {
-        return form == FORM_LEFT ? 0 : form == FORM_ADJ ? 1 : form == FORM_LHAT ? 3 : 2;
+        return form == FORM_LEFT ? 0 : form == FORM_ADJ ? 1 : form == FORM_LHAT ? 3 : 2;  // 2: right, plain
     }
     // accounting (count_only: account a graph replay without launching)
     bool count_only = false;
@@ -267,6 +267,15 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
         hp[HP_D1C] = {lo, 0, EPI_PREMIXED | EPI_POSTSUB | EPI_NORM, 1, F_T, F_S, F_R, F_NONE, true};
         hp[HP_H0A] = {MOBIUS_F64, 1, EPI_M5INV, 0, F_XH, F_T64, F_NONE, F_NONE, false};
         hp[HP_H0B] = {MOBIUS_F64, 1, EPI_M5INV | EPI_POSTSUB, 1, F_T64, F_Q64, F_XH, F_NONE, false};
+    } else if (form == FORM_PLAIN) {
+        // A = S = I - D_oe I^-1 D_eo: q = I p - D_oe t, t = B I^-1 D_eo p;
+        // A^+ = I^+ - D_eo^+ I^-+ D_oe^+: s = I^+ r - D_eo^+ t, t = I^-+ D_oe^+ r
+        hp[HP_D0A] = {lo, 0, EPI_M5INV | EPI_BMIX, 0, F_P, F_T, F_NONE, F_NONE, false};
+        hp[HP_D0B] = {lo, 0, EPI_PREMIXED | EPI_M5SUB | EPI_NORM, 1, F_T, F_Q, F_NONE, F_P, true};
+        hp[HP_D1B] = {lo, 1, EPI_M5INV, 0, F_R, F_T, F_NONE, F_NONE, false};
+        hp[HP_D1C] = {lo, 1, EPI_M5SUB | EPI_NORM, 1, F_T, F_S, F_NONE, F_R, true};
+        hp[HP_H0A] = {MOBIUS_F64, 0, EPI_M5INV | EPI_BMIX, 0, F_XH, F_T64, F_NONE, F_NONE, false};
+        hp[HP_H0B] = {MOBIUS_F64, 0, EPI_PREMIXED | EPI_M5SUB, 1, F_T64, F_Q64, F_NONE, F_XH, false};
     } else if (form == FORM_LHAT) {
         // A = 1 - I^-1 D^_oe I^-1 D^_eo with D^ = -1/2 B H: q = p - I^-1 B (-1/2 H t),
         // t = I^-1 B (-1/2 H p); A^+ = 1 - (D^_eo)^+ I^-+ (D^_oe)^+ I^-+:
@@ -458,10 +467,10 @@ HopArgs Batch::hop_args_for(const Group &g, const HopPattern &p) const
 void Batch::acct_hop(int prec, int epi, double fields, double n5)
 {
     // per active system: in + out (+ x, + y) spinors; links once per group
-    double nf = 2 + ((epi & (EPI_PRESUB | EPI_POSTSUB)) ? 1 : 0) + ((epi & EPI_M5ADD) ? 1 : 0);
+    double nf = 2 + ((epi & (EPI_PRESUB | EPI_POSTSUB)) ? 1 : 0) + ((epi & (EPI_M5ADD | EPI_M5SUB)) ? 1 : 0);
     abytes += nf * fields + sum_links(prec);
     aflops += n5 * (1416 + ((epi & EPI_M5INV) ? 96 : 0) + ((epi & (EPI_PRESUB | EPI_POSTSUB)) ? 24 : 0) +
-                    ((epi & EPI_M5ADD) ? 96 : 0) + ((epi & EPI_NORM) ? 48 : 0));
+                    ((epi & (EPI_M5ADD | EPI_M5SUB)) ? 96 : 0) + ((epi & EPI_NORM) ? 48 : 0));
 }
 
 hipError_t Batch::hop(int pid)
@@ -539,7 +548,7 @@ hipError_t Batch::reduce(int pid, double *out, int64_t stride, bool all)
 
 hipError_t Batch::next_u(bool only_active)
 {
-    if (form == FORM_RIGHT) return hipSuccess;
+    if (form == FORM_RIGHT || form == FORM_PLAIN) return hipSuccess;  // their A^+ starts from r itself
     if (form == FORM_LHAT) {  // u = B^+ I^-+ r, through t
         hipError_t e = m5inv_all(lo, 1, F_R, F_T, only_active);
         if (e != hipSuccess) return e;
@@ -876,12 +885,13 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
             CK(launch_pack_spinor(g.ctx->g, MOBIUS_F64, g.src, g.f[F_ETA_E], g.f[F_B], g.nrhs, st));
             CK(launch_zero(g.f[F_ETA_O], g.fb[F_ETA_O] * g.nrhs, st));
         } else {
-            // left: b' = I^-1 (eta_o - D_oe I^-1 eta_e); right: b_R = eta_o - D_oe I^-1 eta_e;
+            // left: b' = I^-1 (eta_o - D_oe I^-1 eta_e); right and plain: b_R = eta_o - D_oe I^-1 eta_e;
             // adjoint system: b' = I^-+ (eta_o - (D^+)_oe I^-+ eta_e)
             const int dg = B.adj() ? 1 : 0;
             CK(launch_pack_spinor(g.ctx->g, MOBIUS_F64, g.src, g.f[F_ETA_E], g.f[F_ETA_O], g.nrhs, st));
             CK(launch_m5(g.ctx->g, g.ctx->c, MOBIUS_F64, 1, dg, g.f[F_ETA_E], g.f[F_T64], g.nrhs, st));
-            CK(B.hop_group(g, MOBIUS_F64, dg, B.form == FORM_RIGHT ? EPI_POSTSUB : EPI_PRESUB | EPI_M5INV, 1,
+            const bool unprec = B.form == FORM_RIGHT || B.form == FORM_PLAIN;
+            CK(B.hop_group(g, MOBIUS_F64, dg, unprec ? EPI_POSTSUB : EPI_PRESUB | EPI_M5INV, 1,
                            F_T64, B.form == FORM_LHAT ? F_Q64 : F_B, F_ETA_O, F_NONE, false));
             if (B.form == FORM_LHAT) {  // left form of D^: b^ = B b'
                 B.abytes += 2.0 * g.fb[F_B] * g.nrhs;
@@ -1102,7 +1112,7 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
 int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *const *sol,
                 const mobius_solve_opts &o, mobius_solve_info *info, hipStream_t user, bool adjoint)
 {
-    if (!adjoint && (o.form < 0 || o.form > 2))
+    if (!adjoint && (o.form < 0 || o.form > 3))
         return set_error(MOBIUS_EINVAL, "unknown solve form " + std::to_string(o.form));
     if (!adjoint && o.form == 2) {
         for (int j = 0; j < ngroups; ++j) {
@@ -1112,7 +1122,11 @@ int batch_solve(mobius_ctx *const *ctxs, int ngroups, const void *const *src, vo
                 return set_error(MOBIUS_EINVAL, "solve form 2: B = b5 + c5 C5 is singular");
         }
     }
-    const int form = adjoint ? FORM_ADJ : o.form == 1 ? FORM_RIGHT : o.form == 2 ? FORM_LHAT : FORM_LEFT;
+    const int form = adjoint       ? FORM_ADJ
+                     : o.form == 1 ? FORM_RIGHT
+                     : o.form == 2 ? FORM_LHAT
+                     : o.form == 3 ? FORM_PLAIN
+                                   : FORM_LEFT;
     return run(ctxs, ngroups, src, sol, o, info, user, nullptr, form);
 }
 

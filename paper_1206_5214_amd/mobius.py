@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libmobius.so")
 
 F64, F32, F16 = 0, 1, 2
 PREC = {"f64": F64, "f32": F32, "f16": F16}
-OP_HOP, OP_M5, OP_SCHUR, OP_FULL, OP_SCHUR_RIGHT, OP_HOP_LEFT, OP_SCHUR_LEFT = 0, 1, 2, 3, 4, 5, 6
+(OP_HOP, OP_M5, OP_SCHUR, OP_FULL, OP_SCHUR_RIGHT, OP_HOP_LEFT, OP_SCHUR_LEFT,
+ OP_SCHUR_COMPLEMENT) = range(8)
 OK, NOT_CONVERGED = 0, 1
 
 EXPORTS = ("mobius_create", "mobius_destroy", "mobius_field_bytes", "mobius_pack",
@@ -299,7 +300,8 @@ class Operator:
         D_DW^+ psi = src with dagger.  reliable_delta <= 0 selects the library's
         default for inner_prec; err_tol > 0 also iterates until kappa * Schur
         residual <= err_tol; form 0/1 = left/right-preconditioned Schur system,
-        2 = the Schur system of the left form D^ = D-^-1 D_DW D- (constant b5, c5)."""
+        2 = the Schur system of the left form D^ = D-^-1 D_DW D- (constant b5, c5),
+        3 = the Schur complement S = I - D_oe I^-1 D_eo itself."""
         import torch
         nrhs = 1 if src.dim() == 7 else int(src.shape[0])
         self._check_canon(src, nrhs, "source")

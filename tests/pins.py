@@ -669,6 +669,28 @@ def pin_left_form(orc):
     assert _rel(lhs, rhs) < 1e-13, ("left-form Schur = B D_pre B^-1", _rel(lhs, rhs))
 
 
+def pin_schur_complement(orc):
+    """The Schur complement S = I - D_oe I^-1 D_eo of Sec. 3: S = I D_pre (the
+    oracle's left-preconditioned operator) and S = D_R I (its right-
+    preconditioned one), S^+ = D_pre^+ I^+, and the dense check that the odd
+    half of the solution of D_DW psi = eta solves S psi_o = eta_o - D_oe I^-1 eta_e."""
+    from oracle import restrict
+    dims = (2, 2, 2, 4)
+    p, U, rng = _setup(dims, 6, 1.5, 0.5, 0.04, seed=31)
+    x = restrict(p, inputs.gaussian_spinor(dims, p.Ls, rng), 1)
+    S = orc.schur_complement(p, U, x)
+    assert _rel(S, orc.m5(p, U, orc.schur(p, U, x))) < 1e-13, "S = I D_pre"
+    assert _rel(S, orc.schur_right(p, U, orc.m5(p, U, x))) < 1e-13, "S = D_R I"
+    Sd = orc.schur_complement(p, U, x, dag=True)
+    assert _rel(Sd, orc.schur(p, U, orc.m5(p, U, x, dag=True), dag=True)) < 1e-13, "S^+ = D_pre^+ I^+"
+    eta = inputs.gaussian_spinor(dims, p.Ls, rng)
+    n = int(np.prod(p.shape5()))
+    D = _dense(lambda v: orc.dw(p, U, v), n, p.shape5())
+    psi = np.linalg.solve(D, eta.ravel()).reshape(p.shape5())
+    eo = restrict(p, eta, 1) - orc.hop(p, U, orc.m5inv(p, restrict(p, eta, 0)), 1)
+    assert _rel(orc.schur_complement(p, U, restrict(p, psi, 1)), restrict(p, eo, 1)) < 1e-11, "S psi_o = b_S"
+
+
 def pin_force_wall(orc):
     """4d-HMC action with the pseudofermion on the wall (Sec. 2.4), 2x2x2x4
     with random links: S = phi^+ (D_ov^+ D_ov)^-1 phi with D_ov built densely
@@ -830,4 +852,4 @@ ALL_PINS = [pin_wilson_free_symbol, pin_kernel_bound, pin_gauge_covariance,
             pin_propagator4d_free, pin_propagator4d_dense, pin_wilson_free_symbol_mu,
             pin_adjoints_mu, pin_force_lie, pin_dw_sites, pin_sdep_free_identities,
             pin_sdep_m5_block, pin_sdep_adjoints_and_solve, pin_bulk5d, pin_schur_forms,
-            pin_force_wall, pin_left_form]
+            pin_force_wall, pin_left_form, pin_schur_complement]

@@ -1,7 +1,8 @@
 """Operator variants on the same data, on the GPU against the FP64 CPU oracle:
-the right-preconditioned Schur operator D_R = 1 - D_oe I^-1 D_eo I^-1 and its
-adjoint, the hop and Schur blocks of the left form D^ = D-^-1 D_DW D- of
-Sec. 2.1, red/black solves that iterate on either, the adjoint system
+the right-preconditioned Schur operator D_R = 1 - D_oe I^-1 D_eo I^-1, the
+Schur complement S = I - D_oe I^-1 D_eo itself, and their adjoints, the hop
+and Schur blocks of the left form D^ = D-^-1 D_DW D- of Sec. 2.1, red/black
+solves that iterate on each, the adjoint system
 D_DW^+ psi = eta, and the 4d-HMC action with the pseudofermion on the wall
 (Sec. 2.4) with its two-inversion link gradient."""
 import sys
@@ -64,6 +65,26 @@ def test_schur_right_vs_oracle(torch_cuda, orc, case, prec):
 
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-Ls{c[1]}" for c in CASES])
 @pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "f16"])
+def test_schur_complement_vs_oracle(torch_cuda, orc, case, prec):
+    from oracle import restrict
+    from paper_1206_5214_amd import mobius
+    torch = torch_cuda
+    dims, Ls = case
+    _flush(f"Schur complement {case} prec={prec}")
+    p, U, psi, op = _setup(torch, dims, Ls)
+    psi_o = restrict(p, psi, 1)
+    _, odd = op.pack(torch.from_numpy(psi_o).cuda(), prec)
+    zero = op.new_field(prec)
+    for dag in (False, True):
+        out = op.dslash(odd, 1, prec, op=mobius.OP_SCHUR_COMPLEMENT, dag=dag)
+        got = op.unpack(zero, out, prec).cpu().numpy()
+        check(got, orc.schur_complement(p, U, psi_o, dag=dag), TOL[prec] * (3 if prec == 2 else 1),
+              ("schur complement", dag))
+    op.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-Ls{c[1]}" for c in CASES])
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "f16"])
 def test_left_form_blocks_vs_oracle(torch_cuda, orc, case, prec):
     """OP_HOP_LEFT (-1/2 B H, both output parities) and OP_SCHUR_LEFT, each with
     its adjoint, against the oracle's left form D^ = B D_W + 1 - C5."""
@@ -107,18 +128,20 @@ def test_left_form_rejects_per_slice_coefficients(torch_cuda):
     op.close()
 
 
+@pytest.mark.parametrize("form", [2, 3], ids=["left_form_Dhat", "schur_complement"])
 @pytest.mark.parametrize("inner", [0, 1, 2], ids=["f64", "mixed_f32", "mixed_f16"])
-def test_left_form_solve(torch_cuda, orc, inner):
-    """form=2 iterates on B D_pre B^-1 and maps back with B^-1: the solution of
-    D_DW psi = eta to the oracle's (two right-hand sides)."""
+def test_form_solve(torch_cuda, orc, inner, form):
+    """form=2 iterates on B D_pre B^-1 and maps back with B^-1; form=3 on the
+    Schur complement S = I D_pre: the solution of D_DW psi = eta to the
+    oracle's (two right-hand sides)."""
     from paper_1206_5214_amd import inputs, mobius
     torch = torch_cuda
     dims, Ls = (4, 4, 4, 8), 12
-    _flush(f"left form of D^, inner={inner}")
+    _flush(f"solve form {form}, inner={inner}")
     p, U, psi, op = _setup(torch, dims, Ls, mf=0.01, b5=1.75, c5=0.75, seed=9, eps=0.5)
     eta = np.stack([psi, inputs.gaussian_spinor(dims, Ls, np.random.default_rng(11))])
     sol, info, rc = op.solve(torch.from_numpy(eta).cuda(), tol=1e-10, maxiter=20000, inner_prec=inner,
-                             form=2)
+                             form=form)
     assert rc == mobius.OK, info
     got = sol.cpu().numpy()
     for r in range(2):

@@ -39,7 +39,9 @@ def _compare_all_ops(torch, op, canon, nrhs):
         full = op.pack_full(canon, prec, nrhs)
         for dag in (False, True):
             cases = [(mobius.OP_SCHUR, 1, odd), (mobius.OP_HOP, 0, odd), (mobius.OP_HOP, 1, even),
-                     (mobius.OP_M5, 1, odd), (mobius.OP_FULL, 0, full)]
+                     (mobius.OP_M5, 1, odd), (mobius.OP_FULL, 0, full), (mobius.OP_SCHUR_RIGHT, 1, odd),
+                     (mobius.OP_HOP_LEFT, 0, odd), (mobius.OP_HOP_LEFT, 1, even),
+                     (mobius.OP_SCHUR_LEFT, 1, odd), (mobius.OP_SCHUR_COMPLEMENT, 1, odd)]
             for opk, outp, x in cases:
                 want = op.dslash(x, outp, prec, op=opk, dag=dag, nrhs=nrhs)
                 got = torch.full_like(want, 0xA5)  # stale contents must not matter
