@@ -133,6 +133,9 @@ struct HopParams {
     int Ls, spw, nrhs;
     int remap;              // XCD-contiguous block order
     int stage_links;        // copy the block's links to LDS first
+    int m5_off;             // byte offset in dynamic LDS of the I^-1 epilogue's buffer: 0 (it
+                            // reuses the staged links' space once the direction loop is done)
+                            // or past the links (nrhs > 1: the links serve every system)
     int nt;                 // non-temporal loads of the links
     int pf;                 // prefetch depth of the direction loop (0, 1, 2); 3: FP16 matrix-core
                             // colour multiply (requires stage_links and Ls % 4 == 0)
@@ -195,6 +198,8 @@ hipError_t launch_hop(const Geometry &g, const OpCoeffs &c, const void *links, c
 HopParams make_hop_params(const Geometry &g, const OpCoeffs &c, const void *links,
                           const int32_t *nbr, const HopArgs &a);
 size_t hop_link_lds_bytes(int prec, int Ls, bool rows);
+// bytes of the I^-1 epilogue's LDS buffer (one block) for a storage precision
+size_t m5_epilogue_lds_bytes(int prec);
 // persistent launch over groups (device array) with block prefix sums prefix[0..n]
 hipError_t launch_hop_batch(int prec, int dag, int epi, const HopParams *groups_dev, int ngroups,
                             const int64_t *prefix_dev, size_t lds_bytes, int grid, int pf,

@@ -16,6 +16,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <mutex>
 
@@ -44,6 +45,12 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
     const int64_t fbytes = S::bytes(hp.N5);
     const Buf blink(hp.links, (int64_t)8 * hp.Vh * Link<P>::REC);
     const Buf bnbr(hp.nbr, 8 * hp.Vh * 4);
+
+    if (hp.active) {  // a system group whose systems have all converged: nothing to stage
+        bool any = false;
+        for (int r = 0; r < hp.nrhs; ++r) any = any || hp.active[r];
+        if (!any) return;
+    }
 
     extern __shared__ u32x4 dyn_lds[];
     LinkSource<P> ls;
@@ -293,7 +300,10 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
         for (int c = 0; c < 12; ++c) acc[c] = xv[c] - acc[c];
     }
     if constexpr ((EPI & EPI_M5INV) != 0) {
-        __shared__ M5Lds<T> lds;
+        // the buffer lives in the dynamic LDS; where it overlays the staged
+        // links, every wave of the block must be past its direction loop
+        if (hp.m5_off == 0 && hp.stage_links) __syncthreads();
+        M5Lds<T> &lds = *reinterpret_cast<M5Lds<T> *>(reinterpret_cast<char *>(dyn_lds) + hp.m5_off);
         m5inv_lanes(acc, k, m, Ls, DAG, lds);
     }
     if constexpr ((EPI & EPI_BMIX) != 0)  // B r (B^+ r in the adjoint hop)
@@ -331,7 +341,14 @@ __global__ __launch_bounds__(BLOCK) void hop_batch_kernel(const HopParams *group
 {
     const int64_t total = prefix[ngroups];
     int j = 0;
-    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    // XCD-contiguous order (as the single-lattice launch with remap on) over
+    // the n = min(grid, items) workgroups that have work, so that every XCD
+    // takes an eighth of the items and each its own contiguous range
+    const int64_t n = total < (int64_t)gridDim.x ? total : (int64_t)gridDim.x;
+    const int64_t b = blockIdx.x;
+    if (b >= n) return;
+    const int64_t q = n / NUM_XCD, rem = n % NUM_XCD, x = b % NUM_XCD;
+    for (int64_t w = x * q + (x < rem ? x : rem) + b / NUM_XCD; w < total; w += n) {
         while (w >= prefix[j + 1]) ++j;
         hop_block<P, DAG, EPI, PF>(groups[j], w - prefix[j]);
         __syncthreads();  // LDS of this item is dead before the next item stages
@@ -1020,9 +1037,15 @@ size_t link_lds_bytes(int spw, bool rows)
 }
 
 template <int P, bool DAG, int EPI>
-void hop_launch(const HopParams &hp, hipStream_t st)
+void hop_launch(const HopParams &hp0, hipStream_t st)
 {
-    const size_t dyn = hp.stage_links ? link_lds_bytes<P>(hp.spw, hp.pf == 3) : 0;
+    HopParams hp = hp0;
+    const size_t links = hp.stage_links ? link_lds_bytes<P>(hp.spw, hp.pf == 3) : 0;
+    size_t dyn = links;
+    if constexpr ((EPI & EPI_M5INV) != 0) {
+        hp.m5_off = hp.nrhs > 1 ? (int)links : 0;
+        dyn = std::max(links, (size_t)hp.m5_off + sizeof(M5Lds<typename Spin<P>::T>));
+    }
     const dim3 grid((unsigned)hp.nblocks), blk(BLOCK);
     switch (hp.pf) {
     case 0: hipLaunchKernelGGL((hop_kernel<P, DAG, EPI, 0>), grid, blk, dyn, st, hp); break;
@@ -1155,6 +1178,11 @@ struct RunHopBatch {
 };
 
 }  // namespace
+
+size_t m5_epilogue_lds_bytes(int prec)
+{
+    return prec == MOBIUS_F64 ? sizeof(M5Lds<double>) : sizeof(M5Lds<float>);
+}
 
 size_t hop_link_lds_bytes(int prec, int Ls, bool rows)
 {

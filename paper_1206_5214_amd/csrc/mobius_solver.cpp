@@ -112,6 +112,7 @@ struct Batch {
     VecSys *vec_tab = nullptr;      // [NVEC][nsys]
     int64_t *prefix = nullptr;      // [NHOP][ngroups + 1]
     size_t hop_lds[NHOP] = {};
+    int hop_pf[NHOP] = {};          // loop variant of each batched launch
     int batch_grid = 0;
     HopPattern hp[NHOP];
     // host mirrors
@@ -347,20 +348,34 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
     for (int pid = 0; pid < NHOP; ++pid)
         for (int j = 0; j < ng; ++j) h_hop[(size_t)pid * ng + j].stage_links = hop_lds[pid] > 0 &&
             h_hop[(size_t)pid * ng + j].stage_links;
-    // one launch takes the first group's loop variant: the matrix-core one
-    // only if every group can run it
+    // one batched launch runs one loop variant for every group: that of the
+    // group with the most site blocks (the one its tuning was measured for
+    // matters most), the matrix-core one only if every group can run it
     for (int pid = 0; pid < NHOP; ++pid) {
         bool all_mf = true;
-        for (int j = 0; j < ng; ++j) all_mf = all_mf && h_hop[(size_t)pid * ng + j].pf == 3;
-        if (!all_mf)
-            for (int j = 0; j < ng; ++j)
-                if (h_hop[(size_t)pid * ng + j].pf == 3) h_hop[(size_t)pid * ng + j].pf = 2;
+        int big = 0;
+        for (int j = 0; j < ng; ++j) {
+            all_mf = all_mf && h_hop[(size_t)pid * ng + j].pf == 3;
+            if (h_hop[(size_t)pid * ng + j].nblocks > h_hop[(size_t)pid * ng + big].nblocks) big = j;
+        }
+        hop_pf[pid] = h_hop[(size_t)pid * ng + big].pf;
+        if (hop_pf[pid] == 3 && !all_mf) hop_pf[pid] = 2;
         // dynamic LDS of the launch: the largest staged record block of its groups
-        const bool rows = h_hop[(size_t)pid * ng].pf == 3;
+        const bool rows = hop_pf[pid] == 3;
         hop_lds[pid] = 0;
-        for (int j = 0; j < ng; ++j)
+        bool multi = false;
+        for (int j = 0; j < ng; ++j) {
             if (h_hop[(size_t)pid * ng + j].stage_links)
                 hop_lds[pid] = std::max(hop_lds[pid], hop_link_lds_bytes(hp[pid].prec, groups[j].ctx->g.Ls, rows));
+            multi = multi || h_hop[(size_t)pid * ng + j].nrhs > 1;
+        }
+        // the I^-1 epilogue's buffer: over the links (one system per group)
+        // or past them
+        if (hp[pid].epi & EPI_M5INV) {
+            const size_t off = multi ? hop_lds[pid] : 0;
+            for (int j = 0; j < ng; ++j) h_hop[(size_t)pid * ng + j].m5_off = (int)off;
+            hop_lds[pid] = std::max(hop_lds[pid], off + m5_epilogue_lds_bytes(hp[pid].prec));
+        }
     }
     h_vec.assign((size_t)NVEC * nsys, VecSys{});
     for (const Group &g : groups)
@@ -502,7 +517,7 @@ hipError_t Batch::launch_pattern(const HopPattern &p, int pid)
     }
     return launch_hop_batch(p.prec, p.dag, p.epi, hop_tab + (size_t)pid * ngroups(), ngroups(),
                             prefix + (size_t)pid * (ngroups() + 1), hop_lds[pid], batch_grid,
-                            h_hop[(size_t)pid * ngroups()].pf, st);
+                            hop_pf[pid], st);
 }
 
 hipError_t Batch::hop_group(const Group &g, int prec, int dag, int epi, int out_parity, Field in,
