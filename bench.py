@@ -47,18 +47,19 @@ def hop_algo_bytes(op, prec):
     return 2 * op.field_bytes(prec) + 8 * 9 * (op.V // 2) * link_elem
 
 
-def time_hop(torch, op, prec, src_canon, reps=100, warm=10):
+def time_hop(torch, op, prec, src_canon, reps=100, warm=10, opk=0):
     """Duration of each of `reps` launches per parity of the metered hop kernel
-    after `warm` untimed ones, each bracketed by its own pair of events on
-    the stream the library launches on (torch's current stream).  Returns
-    (median, mean) in ms over the 2 reps launches."""
+    (opk: the operator block, the hop D_{p,1-p} by default) after `warm`
+    untimed ones, each bracketed by its own pair of events on the stream the
+    library launches on (torch's current stream).  Returns (median, mean) in
+    ms over the 2 reps launches."""
     import statistics
     even, odd = op.pack(src_canon, prec)
     out_e = op.new_field(prec)
     out_o = op.new_field(prec)
     for _ in range(warm):
-        op.dslash(odd, 0, prec, out=out_e)
-        op.dslash(even, 1, prec, out=out_o)
+        op.dslash(odd, 0, prec, out=out_e, op=opk)
+        op.dslash(even, 1, prec, out=out_o, op=opk)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(2 * reps)]
@@ -66,7 +67,7 @@ def time_hop(torch, op, prec, src_canon, reps=100, warm=10):
         for j, (x, outp, out) in enumerate(((odd, 0, out_e), (even, 1, out_o))):
             a, b = ev[2 * k + j]
             a.record()
-            op.dslash(x, outp, prec, out=out)
+            op.dslash(x, outp, prec, out=out, op=opk)
             b.record()
     torch.cuda.synchronize()
     ms = [a.elapsed_time(b) for a, b in ev]
@@ -114,9 +115,10 @@ def copy_peak_gbs(torch, nbytes=1 << 31, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def counters_for(kernel_key):
+def counters_for(kernel_key, tuning):
     """HBM traffic per launch measured with rocprofv3 counters, if they were
-    taken on the current kernel source (profiles/<key>.json records its hash)."""
+    taken on the current kernel source (profiles/<key>.json records its hash)
+    with the launch parameters this run's tuner chose."""
     from paper_1206_5214_amd.profile_hop import hop_sources_sha256
     path = os.path.join(ROOT, "profiles", f"{kernel_key}.json")
     if not os.path.exists(path):
@@ -124,6 +126,9 @@ def counters_for(kernel_key):
     with open(path) as f:
         rec = json.load(f)
     if rec.get("kernel_source_sha256") != hop_sources_sha256():
+        return None
+    want = {k: v for k, v in tuning.items() if k != "hop_us"}
+    if rec.get("tuning") is not None and rec["tuning"] != want:
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -251,23 +256,24 @@ def multi_rhs_runs(torch, inputs, mobius):
     ref = torch.stack(ref)
     out["sequential_f64"] = {"seconds": seq, "iters_per_rhs": iters}
     log(f"multi-rhs: 12 sequential FP64 solves {seq:.3f} s")
-    for prec in (mobius.F64, mobius.F32, mobius.F16):
+    for prec, etol in ((mobius.F64, 0.0), (mobius.F32, 0.0), (mobius.F16, 0.0), (mobius.F16, 1e-8)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sol, info, rc = op.solve(src, tol=w.tol, maxiter=50000, inner_prec=prec)
+        sol, info, rc = op.solve(src, tol=w.tol, maxiter=50000, inner_prec=prec, err_tol=etol)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         if rc != mobius.OK:
             raise RuntimeError(f"batched solve failed: {info}")
         err = max(_rel(torch, sol[a], ref[a]) for a in range(12))
-        out[f"batched_{PREC_NAMES[prec]}"] = {
+        name = f"batched_{PREC_NAMES[prec]}" + ("_err_tol_1e-8" if etol else "")
+        out[name] = {
             "seconds": dt, "speedup_vs_sequential_f64": seq / dt,
             "max_iters": max(i.iters for i in info),
             "max_true_resid": max(i.true_resid for i in info),
-            "max_rel_diff_vs_f64": err,
+            "max_rel_diff_vs_f64": err, "max_err_bound": max(i.err_bound for i in info),
             "GBps": info[0].algo_bytes / dt / 1e9}
-        log(f"multi-rhs: batched {PREC_NAMES[prec]} {dt:.3f} s ({seq / dt:.2f}x), "
-            f"max resid {out[f'batched_{PREC_NAMES[prec]}']['max_true_resid']:.2e}, diff {err:.2e}")
+        log(f"multi-rhs: {name} {dt:.3f} s ({seq / dt:.2f}x), "
+            f"max resid {out[name]['max_true_resid']:.2e}, diff {err:.2e}")
         del sol
     # the 4d overlap propagator of the 12 spin-colour point sources at the
     # origin: D_DW(1) on the walls, one batched 5d solve, the walls read back
@@ -490,6 +496,16 @@ def main():
                                  "GFLOPps": flops / (ms * 1e-3) / 1e9}
         log(f"hop {PREC_NAMES[prec]}: median {ms * 1e3:.1f} us (mean {ms_mean * 1e3:.1f})  {gbs:.0f} GB/s  "
             f"({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+    # the hop block of the left form D^ = D-^-1 D_DW D- (Sec. 2.1), -1/2 B H:
+    # the same bytes, with B applied once after the hopping sum
+    hop_left = {}
+    for prec in (mobius.F64, mobius.F32, mobius.F16):
+        ms, ms_mean = time_hop(torch, op, prec, etad, args.hop_reps, opk=mobius.OP_HOP_LEFT)
+        nbytes = hop_algo_bytes(op, prec)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        hop_left[PREC_NAMES[prec]] = {"us": ms * 1e3, "us_mean": ms_mean * 1e3, "launches": 2 * args.hop_reps,
+                                      "algo_bytes": nbytes, "GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+        log(f"left-form hop {PREC_NAMES[prec]}: median {ms * 1e3:.1f} us  {gbs:.0f} GB/s")
 
     # -- D_pre = 1 - I^-1 D_oe I^-1 D_eo (two fused hop launches) -----------
     schur = {}
@@ -531,6 +547,7 @@ def main():
     value = algo_bytes / (ms_per_step * 1e-3) / 1e9
 
     compare = {}
+    forms = {}
     if not args.no_compare:
         # reference: an FP64 solve to a 1e-12 true residual (its own error is
         # bounded by its kappa times that residual); every solve's error is
@@ -565,7 +582,19 @@ def main():
             "speedup_vs_f64": f64s / i3.seconds}
         log(f"{PREC_NAMES[inner]} with err_tol 1e-8: {i3.seconds:.3f} s, {i3.iters} iters, bound "
             f"{i3.err_bound:.2e}, error {err_vs_ref(s3):.2e}")
-        del s3, ref
+        del s3
+        # the same solve iterating on each form of the Schur system (Sec. 2.1, 3)
+        for form, name in ((0, "left_preconditioned"), (1, "right_preconditioned"),
+                           (2, "left_form_Dhat"), (3, "schur_complement")):
+            s4, info4, rc4 = op.solve(etad, tol=w.tol, maxiter=50000, inner_prec=inner, form=form)
+            i4 = info4[0]
+            if rc4 != mobius.OK:
+                raise RuntimeError(f"form {form} solve failed: {i4}")
+            forms[name] = {"form": form, "seconds": i4.seconds, "iters": i4.iters, "true_resid": i4.true_resid,
+                           "kappa": i4.kappa, "rel_error_vs_ref": err_vs_ref(s4)}
+            log(f"form {form} ({name}): {i4.seconds:.3f} s, {i4.iters} iters, error {err_vs_ref(s4):.2e}")
+            del s4
+        del ref
     gaussian_c1 = None if args.no_compare else gaussian_c1_runs(torch, inputs, mobius)
 
     batch = None
@@ -582,13 +611,15 @@ def main():
 
     hname = PREC_NAMES[inner]
     key = f"hop_{hname}_{args.workload}"
-    traffic = counters_for(key)
+    traffic = counters_for(key, tuning[hname])
     roofline = {"bound": "hbm", "achieved": hop[hname]["GBps"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": hop[hname]["GBps"] / HBM_PEAK_GBS,
-                "traffic": traffic, "traffic_note": "L2-egress FETCH_SIZE + WRITE_SIZE per launch, "
-                "scaled by the same counters' reading for a plain device copy: an upper bound on the "
+                "traffic": traffic, "traffic_note": "L2-to-memory read and write requests per launch "
+                "(TCC_EA0_RDREQ / WRREQ by request size) times their sizes: an upper bound on the "
                 "HBM bytes (part of it is served by the Infinity Cache)",
-                "kernel": f"hop_kernel {hname} (D_{{p,1-p}} = -1/2 H B)",
+                "kernel": f"hop_kernel {hname} (D_{{p,1-p}} = -1/2 H B)"
+                          + (", colour multiply on the matrix cores" if tuning[hname].get("mfma") and
+                             inner == mobius.F16 and w.Ls % 4 == 0 else ""),
                 "duration": "median of per-launch HIP-event durations",
                 "algo_bytes_per_launch": hop[hname]["algo_bytes"],
                 "copy_GBps": copy_gbs, "frac_of_copy": hop[hname]["GBps"] / copy_gbs}
@@ -624,7 +655,9 @@ def main():
         "dslash": {"kernel": f"hop {hname}", "GBps": hop[hname]["GBps"],
                    "frac_hbm": hop[hname]["frac_hbm"], "GFLOPps": hop[hname]["GFLOPps"]},
         "hop": hop,
+        "hop_left_form": hop_left,
         "schur": schur,
+        "solve_forms": forms,
         "time_to_solution": compare,
         "gaussian_16x16x16x32_ls16": gaussian_c1,
         "batched": batch,

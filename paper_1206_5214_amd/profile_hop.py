@@ -2,17 +2,21 @@
 
     python -m paper_1206_5214_amd.profile_hop run --prec f16 --reps 20
         builds the 24^3 x 64, Ls = 12 workload, tunes the hop for the given
-        storage precision, runs a 1 GiB device copy (the calibration kernel for
-        the memory counters), then `reps` applications of each hop parity.
+        storage precision, runs `warm` untimed applications of each parity, a
+        1 GiB device copy (the calibration kernel for the memory counters),
+        then `reps` applications of each hop parity.
 
     python -m paper_1206_5214_amd.profile_hop summarize --prec f16 \\
-            --fetch DIR --write DIR [--stats DIR] --out profiles/NAME
-        reads the rocprofv3 outputs of a FETCH_SIZE pass and a WRITE_SIZE pass
-        (and optionally a --kernel-trace --stats run), scales each counter by
-        what it reads for the calibration copy of known size, and writes
-        NAME.json (the per-launch HBM traffic bench.py reports, keyed to the
-        kernel source it was measured on) and NAME.md (the figures and the
-        commands that produced them).
+            --rdreq DIR --wrreq DIR [--fetch DIR --write DIR] [--stats DIR] --out profiles/NAME
+        reads the rocprofv3 outputs of two request-count passes (L2-to-memory
+        read requests by size: TCC_EA0_RDREQ{,_32B,_64B,_128B}_sum; write
+        requests: TCC_EA0_WRREQ{,_64B}_sum), turns them into bytes per launch
+        by the request sizes, checks the rule on the calibration copy of known
+        size, optionally adds the FETCH_SIZE / WRITE_SIZE passes scaled by the
+        copy as a cross-check and a --kernel-trace --stats run for the
+        duration, and writes NAME.json (the per-launch traffic bench.py
+        reports, keyed to the kernel source it was measured on) and NAME.md
+        (the figures and the commands that produced them).
 """
 from __future__ import annotations
 
@@ -54,6 +58,9 @@ def run(args):
     tuned = op.tune(prec)
     even, odd = op.pack(torch.from_numpy(eta).cuda(), prec)
     oe, oo = op.new_field(prec), op.new_field(prec)
+    for _ in range(args.warm):  # untimed: the clocks settle before the counted launches
+        op.dslash(odd, 0, prec, out=oe)
+        op.dslash(even, 1, prec, out=oo)
     a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").normal_()
     b = torch.empty_like(a)
     torch.cuda.synchronize()
@@ -97,24 +104,67 @@ def _counter_per_kernel(d, counter):
     return {"copy": [per[c]], HOP_NAME: hops}
 
 
+def _requests(d, counters):
+    """Average per hop launch, and the calibration copy's value, of each counter."""
+    res = {}
+    for c in counters:
+        per = _counter_per_kernel(d, c)
+        hop = per[HOP_NAME]
+        res[c] = {"hop": sum(hop) / len(hop), "copy": max(per["copy"]), "launches": len(hop)}
+    return res
+
+
+RD = ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum")
+WR = ("TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum")
+
+
+def _read_bytes(r, which):
+    n32, n64, n128 = (r[c][which] for c in RD[1:])
+    other = max(r[RD[0]][which] - n32 - n64 - n128, 0.0)  # none expected; counted as 64 B
+    return 32 * n32 + 64 * (n64 + other) + 128 * n128, other
+
+
+def _write_bytes(w, which):
+    n, n64 = w[WR[0]][which], w[WR[1]][which]
+    return 64 * n64 + 32 * (n - n64)
+
+
 def summarize(args):
     sha = hop_sources_sha256()
     out = {"kernel": f"{HOP_NAME} ({args.prec}, D_{{p,1-p}} = -1/2 H B, 24^3x64 Ls=12)",
            "kernel_source_sha256": sha, "kernel_sources": list(HOP_SOURCES),
            "calibration_copy_bytes": COPY_BYTES}
+    r = _requests(args.rdreq, RD)
+    w = _requests(args.wrreq, WR)
+    rb, other = _read_bytes(r, "hop")
+    wb = _write_bytes(w, "hop")
+    crb, _ = _read_bytes(r, "copy")
+    cwb = _write_bytes(w, "copy")
+    out["requests"] = {"read": {c: r[c]["hop"] for c in RD}, "write": {c: w[c]["hop"] for c in WR},
+                       "read_bytes": rb, "write_bytes": wb, "unsized_read_requests": other,
+                       "launches": r[RD[0]]["launches"],
+                       "copy_check": {"read_bytes": crb, "write_bytes": cwb,
+                                      "read_over_true": crb / COPY_BYTES, "write_over_true": cwb / COPY_BYTES}}
+    out["traffic_bytes_per_launch"] = rb + wb
+    if args.run_log:  # the launch parameters the counted launches ran with
+        with open(args.run_log) as f:
+            for line in f:
+                if line.startswith("{") and '"tuning"' in line:
+                    out["tuning"] = {k: v for k, v in json.loads(line)["tuning"].items() if k != "hop_us"}
     traffic = {}
-    for counter, d in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
-        per = _counter_per_kernel(d, counter)
-        copy = max(per["copy"])               # KiB the counter reports for the 1 GiB copy
-        scale = COPY_BYTES / (copy * 1024.0)  # true bytes per reported byte
-        hop = per[HOP_NAME]
-        avg_kib = sum(hop) / len(hop)
-        traffic[counter] = {"raw_kib_per_launch": avg_kib, "copy_raw_kib": copy,
-                            "scale": scale, "bytes_per_launch": avg_kib * 1024.0 * scale,
-                            "launches": len(hop)}
-    out["counters"] = traffic
-    out["traffic_bytes_per_launch"] = (traffic["FETCH_SIZE"]["bytes_per_launch"] +
-                                       traffic["WRITE_SIZE"]["bytes_per_launch"])
+    if args.fetch and args.write:  # cross-check: FETCH_SIZE / WRITE_SIZE scaled by the copy
+        for counter, d in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
+            per = _counter_per_kernel(d, counter)
+            copy = max(per["copy"])               # KiB the counter reports for the 1 GiB copy
+            scale = COPY_BYTES / (copy * 1024.0)  # true bytes per reported byte
+            hop = per[HOP_NAME]
+            avg_kib = sum(hop) / len(hop)
+            traffic[counter] = {"raw_kib_per_launch": avg_kib, "copy_raw_kib": copy,
+                                "scale": scale, "bytes_per_launch": avg_kib * 1024.0 * scale,
+                                "launches": len(hop)}
+        out["counters"] = traffic
+        out["fetch_write_bytes_per_launch"] = (traffic["FETCH_SIZE"]["bytes_per_launch"] +
+                                               traffic["WRITE_SIZE"]["bytes_per_launch"])
     if args.algo_bytes:
         out["algo_bytes_per_launch"] = args.algo_bytes
         out["traffic_over_algo"] = out["traffic_bytes_per_launch"] / args.algo_bytes
@@ -139,11 +189,24 @@ def summarize(args):
     lines += ["Commands (repository root, one MI355X, `export TMPDIR=/tmp`):", "", "```"]
     lines += args.command or []
     lines += ["```", ""]
-    lines += ["| counter | raw KiB / launch | copy raw KiB (1 GiB) | scale | bytes / launch |",
-              "|---|---:|---:|---:|---:|"]
-    for c, t in traffic.items():
-        lines.append(f"| {c} | {t['raw_kib_per_launch']:.0f} | {t['copy_raw_kib']:.0f} | "
-                     f"{t['scale']:.3f} | {t['bytes_per_launch'] / 1e6:.1f} MB |")
+    lines += ["L2-to-memory requests per launch, by size (bytes = 32, 64 or 128 per request;",
+              "writes: 64 for the 64-byte ones, 32 for the rest; the Infinity Cache sits behind",
+              "these requests, so the figure bounds the HBM bytes from above):", "",
+              "| counter | requests / launch | calibration copy (1 GiB) |", "|---|---:|---:|"]
+    for c in RD:
+        lines.append(f"| {c} | {r[c]['hop']:.0f} | {r[c]['copy']:.0f} |")
+    for c in WR:
+        lines.append(f"| {c} | {w[c]['hop']:.0f} | {w[c]['copy']:.0f} |")
+    lines.append("")
+    lines.append(f"Read {rb / 1e6:.1f} MB + write {wb / 1e6:.1f} MB per launch; the same rule gives "
+                 f"{crb / 2**30:.3f} GiB read and {cwb / 2**30:.3f} GiB written for the 1 GiB copy.")
+    if traffic:
+        lines += ["", "Cross-check, FETCH_SIZE / WRITE_SIZE scaled by their reading for the copy:", "",
+                  "| counter | raw KiB / launch | copy raw KiB (1 GiB) | scale | bytes / launch |",
+                  "|---|---:|---:|---:|---:|"]
+        for c, t in traffic.items():
+            lines.append(f"| {c} | {t['raw_kib_per_launch']:.0f} | {t['copy_raw_kib']:.0f} | "
+                         f"{t['scale']:.3f} | {t['bytes_per_launch'] / 1e6:.1f} MB |")
     lines.append("")
     lines.append(f"Traffic per launch: {out['traffic_bytes_per_launch'] / 1e6:.1f} MB"
                  + (f" against {args.algo_bytes / 1e6:.1f} MB algorithmic "
@@ -185,12 +248,16 @@ def main():
     r = sub.add_parser("run")
     r.add_argument("--prec", default="f16", choices=list(PREC))
     r.add_argument("--reps", type=int, default=20)
+    r.add_argument("--warm", type=int, default=50, help="untimed launches per parity before the copy")
     r.add_argument("--workload", default="mobius_24x24x24x64_ls12")
     s = sub.add_parser("summarize")
     s.add_argument("--prec", default="f16", choices=list(PREC))
-    s.add_argument("--fetch", required=True)
-    s.add_argument("--write", required=True)
+    s.add_argument("--rdreq", required=True)
+    s.add_argument("--wrreq", required=True)
+    s.add_argument("--fetch")
+    s.add_argument("--write")
     s.add_argument("--stats")
+    s.add_argument("--run-log", help="stdout of a `run` pass (its tuning line)")
     s.add_argument("--algo-bytes", type=float)
     s.add_argument("--out", required=True)
     s.add_argument("--command", action="append")
