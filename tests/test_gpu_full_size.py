@@ -96,3 +96,47 @@ def test_solve_full_size_true_residual(torch_cuda, orc, workload):
     _flush(f"  iters {info[0].iters}, oracle true residual {res:.3e} (solver {info[0].true_resid:.3e})")
     assert res <= w.tol
     assert abs(res - info[0].true_resid) <= 0.05 * res
+
+
+@pytest.fixture(scope="module")
+def c1(torch_cuda):
+    from oracle import Params
+    from paper_1206_5214_amd import inputs, mobius
+    w = inputs.WORKLOADS["mobius_16x16x16x32_ls16"]
+    _flush(f"generating {w.name}")
+    U, eta = inputs.workload_fields(w)
+    op = mobius.Operator(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, torch_cuda.from_numpy(U).cuda())
+    p = Params(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5)
+    src = torch_cuda.from_numpy(eta).cuda()
+    ref, iref, rc = op.solve(src, tol=1e-12, maxiter=50000)  # FP64 to 1e-12: the error reference
+    assert rc == mobius.OK, iref
+    yield w, p, U, eta, op, src, ref
+    op.close()
+
+
+@pytest.mark.parametrize("inner,err_tol", [(0, 0.0), (1, 0.0), (2, 0.0), (2, 1e-8)],
+                         ids=["f64", "f32", "f16", "f16_err_tol"])
+def test_c1_gaussian_solve(torch_cuda, orc, c1, inner, err_tol):
+    """16^3 x 32, Ls = 16, b5 = 1.5, c5 = 0.5 with a Gaussian source, each
+    inner precision to a 1e-10 true residual that the oracle recomputes over
+    the whole lattice; the solution error against an FP64 solve to 1e-12 stays
+    within the solver's own bound (kappa times the Schur residual, plus the
+    reference's), and below 1e-8 when that target is requested."""
+    from paper_1206_5214_amd import mobius
+    torch = torch_cuda
+    w, p, U, eta, op, src, ref = c1
+    op.tune(inner)
+    _flush(f"c1 Gaussian solve, inner {inner}, err_tol {err_tol}")
+    sol, info, rc = op.solve(src, tol=w.tol, maxiter=50000, inner_prec=inner, err_tol=err_tol)
+    assert rc == mobius.OK, info
+    i = info[0]
+    err = (torch.linalg.vector_norm(sol - ref) / torch.linalg.vector_norm(ref)).item()
+    psi = sol.cpu().numpy()
+    del sol
+    res = float(np.linalg.norm((orc.dw(p, U, psi) - eta).ravel()) / np.linalg.norm(eta.ravel()))
+    _flush(f"  iters {i.iters}, oracle true residual {res:.3e} (solver {i.true_resid:.3e}), "
+           f"error {err:.2e}, bound {i.err_bound:.2e}, kappa {i.kappa:.1f}")
+    assert res <= w.tol and abs(res - i.true_resid) <= 0.05 * res
+    assert err <= i.err_bound + 1e-9
+    if err_tol:
+        assert i.err_bound <= err_tol and err <= err_tol
