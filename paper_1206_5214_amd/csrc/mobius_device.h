@@ -81,9 +81,14 @@ constexpr int CPOL_NT = 2;              // cache policy bit: non-temporal
 // Store-data guard.  Without it, gfx950 code in which a VALU instruction
 // rewrote the data registers of a buffer store issued just before it (store
 // with an SGPR offset) left wrong values in memory: FP16 fields written by the
-// fused CG updates diverged at 12^4 x 16 and larger.  Keeping the data live
-// across two wait states after each store removes the corruption; a full
-// vmcnt(0) drain does too but costs about 3% in the hop.
+// fused CG updates diverged at 12^4 x 16 and larger.  The published wait-state
+// rule for stores of more than 64 bits of data (the data registers may not be
+// rewritten in the next cycle) exempts buffer stores whose offset is an SGPR,
+// and code generation follows the exemption: without the guard this file
+// compiles to 11 such stores immediately followed by a VALU write of their
+// data registers.  On gfx950 the exempt case corrupts; keeping the data live
+// across two wait states after each store removes it; a full vmcnt(0) drain
+// does too but costs about 3% in the hop.
 // Field stores are non-temporal: a field written by one kernel is hundreds of
 // MB and is read back by the next kernel, not from L2, and streaming it past
 // the L2 leaves more room there for the neighbour spinors a hop re-reads
