@@ -221,6 +221,8 @@ hipError_t noalloc_scratch_init(int device);
 void *noalloc_scratch(int device);
 // fill with zeros (kernel, not hipMemset, so it is safe under graph capture)
 hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t st);
+// a packed field of n5 5d sites with seeded values of Gaussian-field magnitude
+hipError_t launch_fill_random(int prec, void *ptr, int64_t n5, uint32_t seed, hipStream_t st);
 // Scalar updates of CGLS, on device (one thread per system):
 struct CgScalars {
     double gamma;      // |s|^2 of the current direction

@@ -576,6 +576,48 @@ __global__ __launch_bounds__(256) void unpack_spinor_kernel(int64_t Vh, int Ls,
 
 constexpr int BLAS_BLOCK = 256;
 
+// A packed field of `n5` 5d sites filled with seeded pseudo-random values in
+// [-1, 1) (FP16: binary16 components with site norms in [1, 2)), from a
+// 32-bit hash of the word index: launch-parameter timing on data with the
+// magnitudes of a Gaussian field rather than on zeros.
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+template <int P>
+__global__ void fill_random_kernel(char *out, int64_t n5, uint32_t seed)
+{
+    const int64_t words = Spin<P>::bytes(n5) / 4;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < words;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t h = mix32((uint32_t)w * 2654435761u ^ seed);
+        const float u = (float)(h >> 8) * (1.0f / 8388608.0f) - 1.0f;  // [-1, 1)
+        uint32_t v;
+        if constexpr (P == MOBIUS_F64) {
+            // the high word of a double in [-1, 1) with this word's low 32 bits
+            const double d = (double)u;
+            const uint64_t b = __builtin_bit_cast(uint64_t, d);
+            v = (w & 1) ? (uint32_t)(b >> 32) : h;
+        } else if constexpr (P == MOBIUS_F32) {
+            v = __builtin_bit_cast(uint32_t, u);
+        } else {
+            if (w >= 3 * 4 * n5) {  // the site norms
+                v = __builtin_bit_cast(uint32_t, 1.5f + 0.5f * u);
+            } else {
+                const _Float16 a = (_Float16)u, b = (_Float16)(-0.5f * u);
+                v = (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+            }
+        }
+        reinterpret_cast<uint32_t *>(out)[w] = v;
+    }
+}
+
 __global__ void zero_kernel(uint4 *p, int64_t n16, unsigned char *tail, int64_t ntail)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1275,6 +1317,19 @@ hipError_t launch_m5(const Geometry &g, const OpCoeffs &c, int prec, int kind, i
         case MOBIUS_F16: m5_launch<MOBIUS_F16>(kind, dag, i, o, g, c, blocks, st); break;
         default: return hipErrorInvalidValue;
         }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_random(int prec, void *ptr, int64_t n5, uint32_t seed, hipStream_t st)
+{
+    const dim3 grid(2048), blk(256);
+    char *p = static_cast<char *>(ptr);
+    switch (prec) {
+    case MOBIUS_F64: hipLaunchKernelGGL(fill_random_kernel<MOBIUS_F64>, grid, blk, 0, st, p, n5, seed); break;
+    case MOBIUS_F32: hipLaunchKernelGGL(fill_random_kernel<MOBIUS_F32>, grid, blk, 0, st, p, n5, seed); break;
+    case MOBIUS_F16: hipLaunchKernelGGL(fill_random_kernel<MOBIUS_F16>, grid, blk, 0, st, p, n5, seed); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

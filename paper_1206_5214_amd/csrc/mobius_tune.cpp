@@ -85,7 +85,10 @@ int tune(mobius_ctx *ctx, int prec, int reps, mobius_tune_result *out, hipStream
         if (e != hipSuccess) return set_error(MOBIUS_ENOMEM, hipGetErrorString(e));
         char *in = static_cast<char *>(ctx->scratch.p);
         char *outf = in + fb;
-        e = launch_zero(in, 2 * fb, st);
+        // timed on a seeded field of Gaussian magnitudes (zeros would take
+        // the FP16 path's zero-norm shortcut), output cleared
+        e = launch_fill_random(prec, in, g.N5, 12345u, st);
+        if (e == hipSuccess) e = launch_zero(outf, fb, st);
         if (e != hipSuccess) return set_error(MOBIUS_EHIP, hipGetErrorString(e));
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
