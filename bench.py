@@ -148,7 +148,10 @@ def cpu_baseline(inputs, U2, eta2, w2):
     """The FP64 oracle, as it stands, on the host cores: one hop block and one
     D_pre application on the 4^4 (Ls 8), 16^3x32 (Ls 16) and 24^3x64 (Ls 12)
     workloads and the complete red/black CG on 4^4 with every thread; then
-    one thread on the small ones (the large ones would take minutes).  value:
+    one thread on the small ones (the large ones would take minutes).  A CG on
+    the larger lattices takes two D_pre applications per iteration: with the
+    measured D_pre and the GPU's iteration counts that is about half an hour
+    (16^3x32) and hours (24^3x64) on these cores, so it is not run.  value:
     the hop on the headline lattice, GB/s by the GPU's algorithmic byte count."""
     import oracle
     nthreads = oracle.num_threads()
@@ -186,8 +189,7 @@ def cpu_baseline(inputs, U2, eta2, w2):
     for name in ("shamir_4x4x4x4_ls8", "mobius_16x16x16x32_ls16", w2.name):
         w, U, eta = fields[name]
         head = run(name, w, U, eta, "hop", nthreads)
-        if name != w2.name:
-            run(name, w, U, eta, "schur", nthreads)
+        run(name, w, U, eta, "schur", nthreads)
     w, U, eta = fields["shamir_4x4x4x4_ls8"]
     run("shamir_4x4x4x4_ls8", w, U, eta, "cg", nthreads)
     for name in ("shamir_4x4x4x4_ls8", "mobius_16x16x16x32_ls16"):
