@@ -90,7 +90,8 @@ typedef struct {
     double c5;    /* Moebius c5 (Shamir: 0) */
     double mu;    /* chemical potential (Sec. "Baryon current and Chemical Potential"): the
                      time-like hops of D_W carry e^{+mu} forward (x -> x + t) and e^{-mu}
-                     backward; 0 = none; |mu| <= 10.  mobius_force requires mu = 0. */
+                     backward; 0 = none; |mu| <= 10.  The forces differentiate the hops
+                     with these factors (gradient with respect to U itself). */
     const double *b5s, *c5s; /* optional HOST arrays of Ls per-slice coefficients b5(s), c5(s),
                      s = 1..Ls, of the general operator of Sec. 2.1 (row s of D_DW holds
                      D+(s) = b5(s) D_W + 1 and D-(s) = c5(s) D_W - 1; e.g. Zolotarev
@@ -334,7 +335,7 @@ int mobius_force(mobius_ctx *ctx, const void *phi_c128, void *grad_links_c128, v
  * mobius_force (NULL: S only); action: host pointer.  opts as mobius_cg_solve
  * for both solves (nrhs 0 or 1); info receives one record for the pair
  * (iterations and Dirac applications summed, the larger residual, kappa and
- * bound).  Requires mu = 0.  Synchronises.  Returns as mobius_cg_solve. */
+ * bound).  Synchronises.  Returns as mobius_cg_solve. */
 int mobius_force_wall(mobius_ctx *ctx, const void *phi4_c128, void *grad_links_c128, double *action,
                       const mobius_solve_opts *opts, mobius_solve_info *info, void *stream);
 

@@ -781,7 +781,6 @@ extern "C" int mobius_force(mobius_ctx *ctx, const void *phi, void *grad_links, 
     if (!phi || !grad_phi || !action || !opts || !info)
         return fail(MOBIUS_EINVAL, "null argument to mobius_force");
     if (opts->nrhs > 1) return fail(MOBIUS_EINVAL, "mobius_force takes one source (nrhs <= 1)");
-    if (ctx->has_mu) return fail(MOBIUS_EINVAL, "mobius_force: no chemical potential (mu must be 0)");
     if (int r = check_prec(opts->inner_prec)) return r;
     if (phi == grad_phi || phi == grad_links || grad_phi == grad_links)
         return fail(MOBIUS_EINVAL, "mobius_force arguments alias");
@@ -795,7 +794,6 @@ extern "C" int mobius_force_wall(mobius_ctx *ctx, const void *phi4, void *grad_l
     if (int r = check_ctx(ctx)) return r;
     if (!phi4 || !action || !opts || !info) return fail(MOBIUS_EINVAL, "null argument to mobius_force_wall");
     if (opts->nrhs > 1) return fail(MOBIUS_EINVAL, "mobius_force_wall takes one source (nrhs <= 1)");
-    if (ctx->has_mu) return fail(MOBIUS_EINVAL, "mobius_force_wall: no chemical potential (mu must be 0)");
     if (int r = check_prec(opts->inner_prec)) return r;
     if (grad_links == phi4) return fail(MOBIUS_EINVAL, "mobius_force_wall arguments alias");
     hipStream_t st = S(stream);
@@ -853,9 +851,9 @@ extern "C" int mobius_force_wall(mobius_ctx *ctx, const void *phi4, void *grad_l
         for (int par = 0; par < 2; ++par) {
             const char *Lp = par ? co : ce, *Ln = par ? ce : co;
             HIPCHK(launch_force(g, ctx->c, par, nbr, Lp, par ? po : pe, Ln, par ? pe : po, grad_links, st,
-                                -1.0, false));
+                                -1.0, false, ctx->P.mu));
             HIPCHK(launch_force(g, cpv, par, nbr, Lp, par ? dd : de, Ln, par ? de : dd, grad_links, st,
-                                1.0, true));
+                                1.0, true, ctx->P.mu));
         }
     }
     HIPCHK(hipMemcpyAsync(action, snorm, sizeof(double), hipMemcpyDeviceToHost, st));

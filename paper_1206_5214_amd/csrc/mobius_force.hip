@@ -18,6 +18,10 @@
 // spin sum collapses onto the two rows of the half spinors:
 //   sum_spin x_a conj(((1 + sigma g_mu) y)_b) = sum_{t=0,1} h^sigma(x)_{t,a} conj(h^sigma(y)_{t,b}).
 //
+// With a chemical potential the time-like forward hop carries e^{+mu} and the
+// backward one e^{-mu} (on U_4(y) and U_4(y)^+), so the two terms of G for
+// mu = t are weighted by those factors.
+//
 // Thread mapping as in the hop kernel: one lane per (site y, s), the Ls lanes
 // of a site in one wavefront, B applied by cross-lane shuffles, and the sum
 // over s through LDS; one launch per parity p covers the four links U_mu(y)
@@ -25,6 +29,8 @@
 #include "mobius_device.h"
 
 #include <hip/hip_runtime.h>
+
+#include <cmath>
 
 namespace mobius {
 namespace {
@@ -69,6 +75,10 @@ __device__ __forceinline__ void force_dir(const ForceParams &fp, const SiteMap &
     // forward term: L_p(y) against (1 - g_mu) B R_{1-p}(y + mu)
     half_of<MU, -1>(Lo, hL);
     half_of<MU, -1>(Rn, hR);
+    if constexpr (MU == 3) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) hR[q] = fp.ef * hR[q];
+    }
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -78,6 +88,10 @@ __device__ __forceinline__ void force_dir(const ForceParams &fp, const SiteMap &
     // backward term: (1 + g_mu) B R_p(y) against L_{1-p}(y + mu)
     half_of<MU, +1>(BRo, hR);
     half_of<MU, +1>(Ln, hL);
+    if constexpr (MU == 3) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) hR[q] = fp.eb * hR[q];
+    }
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -175,10 +189,12 @@ hipError_t launch_lie_force(int64_t nlinks, const void *U, const void *G, void *
 
 hipError_t launch_force(const Geometry &g, const OpCoeffs &c, int parity, const int32_t *nbr,
                         const void *Lp, const void *Rp, const void *Ln, const void *Rn,
-                        void *grad, hipStream_t st, double scale, bool accumulate)
+                        void *grad, hipStream_t st, double scale, bool accumulate, double mu)
 {
     ForceParams fp{};
     fp.scale = scale;
+    fp.ef = std::exp(mu);
+    fp.eb = std::exp(-mu);
     fp.accumulate = accumulate ? 1 : 0;
     fp.Lp = static_cast<const char *>(Lp);
     fp.Rp = static_cast<const char *>(Rp);

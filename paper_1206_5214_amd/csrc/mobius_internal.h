@@ -289,13 +289,16 @@ struct ForceParams {
     int Ls, spw;
     double scale;     // grad = scale * G (accumulate: grad += scale * G)
     int accumulate;
+    double ef, eb;    // e^{+mu}, e^{-mu}: the chemical potential's factors of the
+                      // forward and backward time-like hop of D_DW
     OpCoeffs c;
 };
 // G of 2 Re <L, dD_hop R> (D_hop = -1/2 H B, the hopping part of D_DW with the
 // coefficients c) for the links U_mu(y) of the sites y of parity `parity`
 hipError_t launch_force(const Geometry &g, const OpCoeffs &c, int parity, const int32_t *nbr,
                         const void *Lp, const void *Rp, const void *Ln, const void *Rn,
-                        void *grad, hipStream_t st, double scale = 1.0, bool accumulate = false);
+                        void *grad, hipStream_t st, double scale = 1.0, bool accumulate = false,
+                        double mu = 0.0);
 // *out = sum of |x_k|^2 over n doubles (FP64 partial sums per block in
 // partials[nblocks], fixed-order reduction); nblocks = norm2_blocks(n)
 int64_t norm2_blocks(int64_t n);

@@ -823,8 +823,10 @@ int force_pass(Batch &B, ForceOut &fo)
         CK(B.hop_group(g, MOBIUS_F64, 0, EPI_M5INV | EPI_POSTSUB, 1, F_PE, F_Q64, F_XH, F_NONE, false));
         CK(launch_m5(G, g.ctx->c, MOBIUS_F64, 1, 1, g.f[F_Q64], g.f[F_U64], 1, st));
         CK(B.hop_group(g, MOBIUS_F64, 1, EPI_M5INV, 0, F_U64, F_T64, F_NONE, F_NONE, false));
-        CK(launch_force(G, g.ctx->c, 1, nbr, g.f[F_U64], g.f[F_XH], g.f[F_T64], g.f[F_PE], fo.grad_links, st));
-        CK(launch_force(G, g.ctx->c, 0, nbr, g.f[F_T64], g.f[F_PE], g.f[F_U64], g.f[F_XH], fo.grad_links, st));
+        CK(launch_force(G, g.ctx->c, 1, nbr, g.f[F_U64], g.f[F_XH], g.f[F_T64], g.f[F_PE], fo.grad_links, st,
+                        1.0, false, g.ctx->P.mu));
+        CK(launch_force(G, g.ctx->c, 0, nbr, g.f[F_T64], g.f[F_PE], g.f[F_U64], g.f[F_XH], fo.grad_links, st,
+                        1.0, false, g.ctx->P.mu));
         B.abytes += 2.0 * 4 * g.fb[F_XH] + 4.0 * G.V * 9 * 16;
         B.aflops += 2.0 * G.N5 * 4 * (2 * 24 + 2 * 2 * 9 * 8 + 96);
     }

@@ -732,6 +732,58 @@ def pin_force_wall(orc):
         assert abs(fd - want) < 1e-6 * max(abs(want), 1e-3 * np.abs(G).max()), ("wall force FD", fd, want)
 
 
+def pin_force_mu(orc):
+    """Both forces with a chemical potential (time-like hops e^{+-mu} U_{+-4}):
+    the pseudofermion force of S = phi^+ (D_pre^+ D_pre)^-1 phi and the
+    two-inversion wall force against central differences of their actions
+    (CG on the normal operator, and dense solves), along a random direction of
+    all links and along one time-like link.  (mf = 0.2: at small masses a
+    chemical potential makes the 2x2x2x4 system nearly singular, and the
+    differences' O(h^2) term then reaches 1e-6 of the action.)"""
+    from oracle import Params
+    dims = (2, 2, 2, 4)
+    for mu in (0.25, -0.2):
+        p0, U, rng = _setup(dims, 4, 1.5, 0.5, 0.2, seed=41)
+        p = Params(dims, p0.Ls, p0.M5, p0.mf, p0.b5, p0.c5, mu)
+        h = 1e-6
+        E = rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape)
+        E1 = np.zeros_like(U)
+        E1.reshape(4, p.V, 3, 3)[3, 6] = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+        # pseudofermion force
+        phi = orc.restrict(p, inputs.gaussian_spinor(dims, p.Ls, rng), 1)
+        S, X, G, info = orc.force(p, U, phi, tol=1e-14)
+        assert info.converged
+        for D in (E, E1):
+            Xp, ip = orc.cgne(p, U + h * D, phi, tol=1e-14, maxiter=5000)
+            Xm, im = orc.cgne(p, U - h * D, phi, tol=1e-14, maxiter=5000)
+            assert ip.converged and im.converged
+            dS = _vdot(Xp, _normal(orc, p, U - h * D, Xm) - _normal(orc, p, U + h * D, Xm)).real / (2 * h)
+            want = np.sum(np.conj(G) * D).real
+            assert abs(dS - want) < 1e-7 * max(abs(dS), 1e-3 * np.abs(G).max()), ("force with mu", mu, dS, want)
+        # wall force
+        p1 = Params(dims, p.Ls, p.M5, 1.0, p.b5, p.c5, mu)
+        phi4 = rng.normal(size=p.shape4()) + 1j * rng.normal(size=p.shape4())
+        Sw, Gw, infow = orc.force_wall(p, U, phi4, tol=1e-14)
+        assert infow.converged
+        n = int(np.prod(p.shape5()))
+        wall = np.zeros(p.shape5(), complex)
+        wall[0, ..., 2:, :] = phi4[..., 2:, :]
+        wall[-1, ..., :2, :] = phi4[..., :2, :]
+        w = wall.reshape(-1)
+
+        def S_dense(Uh):
+            Dm = _dense(lambda v: orc.dw(p, Uh, v), n, p.shape5())
+            D1 = _dense(lambda v: orc.dw(p1, Uh, v), n, p.shape5())
+            chi = np.linalg.solve(np.conj(Dm.T), w)
+            return float(np.linalg.norm(np.conj(D1.T) @ chi) ** 2)
+
+        assert abs(S_dense(U) - Sw) < 1e-10 * abs(Sw), ("wall action with mu", mu)
+        for D in (E, E1):
+            fd = (S_dense(U + h * D) - S_dense(U - h * D)) / (2 * h)
+            want = np.sum(np.conj(Gw) * D).real
+            assert abs(fd - want) < 1e-6 * max(abs(want), 1e-3 * np.abs(Gw).max()), ("wall force with mu", mu, fd, want)
+
+
 # ---------------------------------------------------------------------------
 # s-dependent coefficients b5(s), c5(s) (the general operator of Sec. 2.1)
 
@@ -852,4 +904,4 @@ ALL_PINS = [pin_wilson_free_symbol, pin_kernel_bound, pin_gauge_covariance,
             pin_propagator4d_free, pin_propagator4d_dense, pin_wilson_free_symbol_mu,
             pin_adjoints_mu, pin_force_lie, pin_dw_sites, pin_sdep_free_identities,
             pin_sdep_m5_block, pin_sdep_adjoints_and_solve, pin_bulk5d, pin_schur_forms,
-            pin_force_wall, pin_left_form, pin_schur_complement]
+            pin_force_wall, pin_left_form, pin_schur_complement, pin_force_mu]

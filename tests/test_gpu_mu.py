@@ -1,7 +1,7 @@
 """Chemical potential (time-like hops e^{+mu} forward, e^{-mu} backward; the
 adjoint with the opposite factors) on the GPU against the FP64 CPU oracle:
 hop blocks and D_pre with their adjoints in every storage precision, the
-solve, and the 4d propagator."""
+solve, the 4d propagator, and both forces (pseudofermion and wall)."""
 import sys
 
 import numpy as np
@@ -105,13 +105,34 @@ def test_propagator4d_with_mu(torch_cuda, orc):
     op.close()
 
 
-def test_force_rejects_mu(torch_cuda):
+@pytest.mark.parametrize("mu", [0.3, -0.25])
+def test_forces_with_mu_vs_oracle(torch_cuda, orc, mu):
+    """The pseudofermion force and the wall-pseudofermion force with a chemical
+    potential: actions and link gradients against the oracle's (whose
+    derivative is pinned against central differences at mu != 0)."""
+    from oracle import Params
     from paper_1206_5214_amd import inputs, mobius
     torch = torch_cuda
-    dims, Ls = (4, 4, 4, 4), 4
-    op = mobius.Operator(dims, Ls, 1.8, 0.1, 1.0, 0.0, torch.from_numpy(inputs.unit_links(dims)).cuda(),
-                         mu=0.2)
-    phi = torch.zeros(op.canon_shape(), dtype=torch.complex128, device="cuda")
-    with pytest.raises(mobius.MobiusError):
-        op.force(phi)
+    dims, Ls, mf = (4, 4, 2, 4), 6, 0.2
+    _flush(f"forces with mu={mu}")
+    p = Params(dims, Ls, 1.8, mf, 1.5, 0.5, mu)
+    rng = np.random.default_rng(61)
+    U = inputs.random_links(dims, 0.5, rng)
+    phi = inputs.gaussian_spinor(dims, Ls, rng)
+    op = mobius.Operator(dims, Ls, 1.8, mf, 1.5, 0.5, torch.from_numpy(U).cuda(), mu=mu)
+    S_o, X_o, G_o, info_o = orc.force(p, U, orc.restrict(p, phi, 1), tol=1e-14)
+    assert info_o.converged
+    S, G, gphi, info, rc = op.force(torch.from_numpy(phi).cuda(), tol=1e-12)
+    assert rc == mobius.OK, info
+    err = np.abs(G.cpu().numpy() - G_o).max() / np.abs(G_o).max()
+    _flush(f"  force: S {S:.12e} oracle {S_o:.12e}, gradient error {err:.1e}")
+    assert abs(S - S_o) <= 1e-10 * abs(S_o) and err <= 1e-9
+    assert _rel(gphi.cpu().numpy(), 2 * X_o) <= 1e-10
+    phi4 = rng.normal(size=p.shape4()) + 1j * rng.normal(size=p.shape4())
+    Sw, Gw, infow, rc = op.force_wall(torch.from_numpy(phi4).cuda(), tol=1e-13)
+    assert rc == mobius.OK, infow
+    Sw_o, Gw_o, _ = orc.force_wall(p, U, phi4, tol=1e-14)
+    errw = np.abs(Gw.cpu().numpy() - Gw_o).max() / np.abs(Gw_o).max()
+    _flush(f"  wall force: S {Sw:.12e} oracle {Sw_o:.12e}, gradient error {errw:.1e}")
+    assert abs(Sw - Sw_o) <= 1e-10 * abs(Sw_o) and errw <= 1e-9
     op.close()
