@@ -109,7 +109,12 @@ typedef struct {
                               last update); <= 0 selects the default of the inner precision:
                               0.3 for FP16, 0.1 for FP32 */
     int32_t nrhs;          /* number of right-hand sides in src/sol (>= 1) */
-    int32_t check_every;   /* iterations between host convergence checks (<= 0 selects 16) */
+    int32_t check_every;   /* iterations between host convergence checks (<= 0 selects 8 with a
+                              lower-precision inner operator, 16 for FP64).  With F32/F16 on one
+                              context and check_every <= 16, the FP32 correction to the iterate
+                              is updated once per check_every iterations from that many stored
+                              search directions (check_every - 1 more inner-precision fields
+                              per right-hand side in the context's workspace) */
     double err_tol;        /* > 0: also iterate until err_bound (below) <= err_tol, tightening
                               the Schur target as needed; <= 0: the residual test alone */
     int32_t form;          /* Schur system CGLS iterates on (Sec. 3): 0 = left-preconditioned

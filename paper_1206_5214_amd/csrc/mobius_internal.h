@@ -224,6 +224,10 @@ hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t st);
 // a packed field of n5 5d sites with seeded values of Gaussian-field magnitude
 hipError_t launch_fill_random(int prec, void *ptr, int64_t n5, uint32_t seed, hipStream_t st);
 // Scalar updates of CGLS, on device (one thread per system):
+// Most search directions one chunk of a mixed-precision CGLS keeps for its
+// deferred x update.
+constexpr int RING_MAX = 16;
+
 struct CgScalars {
     double gamma;      // |s|^2 of the current direction
     double qq;         // |q|^2
@@ -235,6 +239,9 @@ struct CgScalars {
     // first step of a Krylov segment), kept for the first hmax iterations.
     double *hist;
     int64_t nhist, hmax;
+    // alpha of each iteration of a chunk whose x update is deferred to the
+    // chunk's end (slot = the iteration's index in the chunk)
+    double aring[RING_MAX];
 };
 
 // One system (one lattice, one right-hand side) of a batched vector kernel.
@@ -247,9 +254,12 @@ struct CgScalars {
 //   VEC_DOT         Re <a, b> partials (a and b in precision prec)
 //   VEC_PUPD_X      c (prec2) += s0 b;  b = a + s1 b          (x += alpha p_old; p = s + beta p_old)
 //   VEC_XFLUSH      c (prec2) += s0 a                          (x += alpha p)
+//   VEC_PUPD_RING   p[slot] = a + s1 p[prev]                   (b = p[0]; slots sstride bytes apart)
+//   VEC_XRING       c (prec2) += sum_{i < n} s0[i] p[i]        (b = p[0]; slots sstride bytes apart)
 struct VecSys {
     char *a, *b, *c, *d;
     const double *s0, *s1;
+    int64_t sstride;       // bytes between the slots of a ring of directions
     double *partials;      // this system's partial slots
     int64_t nparts;        // number of valid partial slots (for the reduction)
     int64_t N5;
@@ -258,7 +268,7 @@ struct VecSys {
     const OpCoeffs *coef;  // operator coefficients of the system's lattice (device)
 };
 enum VecKind { VEC_CG_XR, VEC_AXPBY, VEC_AXPBY_NORM, VEC_NORM2, VEC_CONVERT, VEC_ACCUMULATE,
-               VEC_DOT, VEC_PUPD_X, VEC_XFLUSH };
+               VEC_DOT, VEC_PUPD_X, VEC_XFLUSH, VEC_PUPD_RING, VEC_XRING };
 hipError_t launch_vec_batch(int kind, int prec, int prec2, const VecSys *sys_dev, int nsys,
                             int64_t max_n5, const int32_t *active, hipStream_t st);
 // out[sys * out_stride] = sum of partials[0 .. count) of each system (count_override > 0)
@@ -266,9 +276,14 @@ hipError_t launch_vec_batch(int kind, int prec, int prec2, const VecSys *sys_dev
 hipError_t launch_reduce_batch(const VecSys *sys_dev, int nsys, const int32_t *active,
                                int64_t count_override, double *out, int64_t out_stride,
                                hipStream_t st);
-// op 0: alpha = gamma / qq;  op 1: beta, gamma;  op 2: alpha = 0
+// VEC_PUPD_RING (a0 = slot, a1 = prev) or VEC_XRING (a0 = n) over a ring of
+// directions; prec: the directions, prec2: x
+hipError_t launch_ring_batch(int kind, int prec, int prec2, const VecSys *sys_dev, int nsys,
+                             int64_t max_n5, const int32_t *active, int a0, int a1, hipStream_t st);
+// op 0: alpha = gamma / qq (also kept in aring[slot] when slot >= 0);
+// op 1: beta, gamma;  op 2: alpha = 0
 hipError_t launch_cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t *active,
-                                  int32_t *restart, hipStream_t st);
+                                  int32_t *restart, hipStream_t st, int slot = -1);
 // r = a -= s0 b (|r|^2 partials per site block) and c = I^-+ r (mode 0), c =
 // I^-1 r (mode 1), nothing (mode 2) or c = B^+ I^-+ r (mode 3, constant
 // coefficients), in the site-lane mapping of the hop

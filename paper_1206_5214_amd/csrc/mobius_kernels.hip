@@ -326,8 +326,14 @@ __device__ __forceinline__ void hop_block(const HopParams &hp, int64_t lb)
     }  // rhs
 }
 
+// The binary16 matrix-core loop is held to 128 VGPRs (four waves per SIMD):
+// its adjoint hop with the I^-+ epilogue needs 130 on its own and then runs
+// three waves (the cap costs it one spilled dword pair; the FP16 solve runs
+// about 1 % faster).  The FP64 hop spills heavily under a three-wave cap and
+// keeps two.
 template <int P, bool DAG, int EPI, int PF>
-__global__ __launch_bounds__(BLOCK) void hop_kernel(HopParams hp)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(P == MOBIUS_F16 && PF == 3 ? 4 : 1)))
+void hop_kernel(HopParams hp)
 {
     hop_block<P, DAG, EPI, PF>(hp, logical_block(hp.remap));
 }
@@ -808,6 +814,63 @@ __global__ __launch_bounds__(BLAS_BLOCK) void xflush_batch(const VecSys *sys, co
     SX::store(bx, n5, kk, xv);
 }
 
+// p[slot] = s + beta p[prev] in a ring of directions (the deferred x update
+// keeps one chunk's directions).  a = s, b = p[0], slots sstride bytes apart,
+// s1 = beta.
+template <int P>
+__global__ __launch_bounds__(BLAS_BLOCK) void pupd_ring_batch(const VecSys *sys, const int32_t *active,
+                                                              int slot, int prev)
+{
+    const VecSys v = sys[blockIdx.y];
+    if (sys_inactive(v, active)) return;
+    using S = Spin<P>;
+    using T = typename S::T;
+    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (k >= v.N5) return;
+    const T be = (T)*v.s1;
+    const int64_t fb = S::bytes(v.N5);
+    const uint32_t n5 = (uint32_t)v.N5, kk = (uint32_t)k;
+    cx<T> sv[12], pv[12];
+    S::load(Buf(v.b + prev * v.sstride, fb), n5, kk, pv);
+    S::load(Buf(v.a, fb), n5, kk, sv);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) pv[c] = sv[c] + be * pv[c];
+    S::store(Buf(v.b + slot * v.sstride, fb), n5, kk, pv);
+}
+
+// x (PX) += sum_{i < n} alpha_i p[i]: the x update of a chunk in one pass.
+// b = p[0], slots sstride bytes apart, s0 = the alphas, c = x.
+template <int P, int PX>
+__global__ __launch_bounds__(BLAS_BLOCK) void xring_batch(const VecSys *sys, const int32_t *active, int n)
+{
+    const VecSys v = sys[blockIdx.y];
+    if (sys_inactive(v, active)) return;
+    using S = Spin<P>;
+    using SX = Spin<PX>;
+    using TX = typename SX::T;
+    const int64_t k = (int64_t)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (k >= v.N5) return;
+    const int64_t fb = S::bytes(v.N5);
+    const uint32_t n5 = (uint32_t)v.N5, kk = (uint32_t)k;
+    cx<TX> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = cx<TX>{0, 0};
+#pragma unroll 2
+    for (int i = 0; i < n; ++i) {
+        const TX al = (TX)v.s0[i];
+        cx<typename S::T> pv[12];
+        S::load(Buf(v.b + i * v.sstride, fb), n5, kk, pv);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = acc[c] + al * cx<TX>{(TX)pv[c].r, (TX)pv[c].i};
+    }
+    const Buf bx(v.c, SX::bytes(v.N5));
+    cx<TX> xv[12];
+    SX::load(bx, n5, kk, xv);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) xv[c] = xv[c] + acc[c];
+    SX::store(bx, n5, kk, xv);
+}
+
 // r -= alpha q, |r|^2 per site block, and u = I^-+ r of the stored r, in the
 // site-lane mapping of the hop so that the Ls-direction solve stays inside a
 // wavefront.  a = r, b = q, c = u, s0 = alpha; one workgroup per site block.
@@ -892,7 +955,7 @@ __global__ __launch_bounds__(1024) void reduce_batch(const VecSys *sys, const in
 // gamma (0 when the system restarts), gamma = gamma_new.  Inactive systems get
 // alpha = beta = 0.
 __global__ void cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t *active,
-                                int32_t *restart)
+                                int32_t *restart, int slot)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nsys) return;
@@ -904,6 +967,7 @@ __global__ void cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t *
     } else if (op == 0) {
         s.alpha = (on && s.qq > 0) ? s.gamma / s.qq : 0.0;
         if (rec) s.hist[2 * s.nhist++ + 1] = s.alpha;
+        if (slot >= 0) s.aring[slot] = s.alpha;
     } else {
         const bool rs = restart && restart[j];
         s.beta = (on && !rs && s.gamma > 0) ? s.gamma_new / s.gamma : 0.0;
@@ -1442,10 +1506,35 @@ hipError_t launch_rupd_m5inv_batch(int prec, const VecSys *sys_dev, int nsys, in
 }
 
 hipError_t launch_cg_scalar_batch(CgScalars *sc, int nsys, int op, const int32_t *active,
-                                  int32_t *restart, hipStream_t st)
+                                  int32_t *restart, hipStream_t st, int slot)
 {
+    if (slot >= RING_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(cg_scalar_batch, dim3((nsys + 63) / 64), dim3(64), 0, st, sc, nsys, op,
-                       active, restart);
+                       active, restart, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_ring_batch(int kind, int prec, int prec2, const VecSys *sys_dev, int nsys,
+                             int64_t max_n5, const int32_t *active, int a0, int a1, hipStream_t st)
+{
+    const dim3 grid((unsigned)((max_n5 + BLAS_BLOCK - 1) / BLAS_BLOCK), (unsigned)nsys), blk(BLAS_BLOCK);
+    if (kind == VEC_PUPD_RING) {
+        if (a0 < 0 || a0 >= RING_MAX || a1 < 0 || a1 >= RING_MAX) return hipErrorInvalidValue;
+        switch (prec) {
+        case MOBIUS_F32: hipLaunchKernelGGL(pupd_ring_batch<MOBIUS_F32>, grid, blk, 0, st, sys_dev, active, a0, a1); break;
+        case MOBIUS_F16: hipLaunchKernelGGL(pupd_ring_batch<MOBIUS_F16>, grid, blk, 0, st, sys_dev, active, a0, a1); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else if (kind == VEC_XRING) {
+        if (a0 < 1 || a0 > RING_MAX || prec2 != MOBIUS_F32) return hipErrorInvalidValue;
+        switch (prec) {
+        case MOBIUS_F32: hipLaunchKernelGGL((xring_batch<MOBIUS_F32, MOBIUS_F32>), grid, blk, 0, st, sys_dev, active, a0); break;
+        case MOBIUS_F16: hipLaunchKernelGGL((xring_batch<MOBIUS_F16, MOBIUS_F32>), grid, blk, 0, st, sys_dev, active, a0); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -66,7 +66,8 @@ struct Group {
     const char *src;
     char *sol;
     int64_t fb[NFIELDS];      // bytes of one field of each kind
-    char *f[NFIELDS];
+    char *f[NFIELDS];         // (f[F_P]: the ring slot of the current iteration)
+    char *pring;              // slot 0 of the ring of directions
     int64_t hop_blocks, blas_blocks;
 };
 
@@ -87,7 +88,7 @@ enum HopPid { HP_D0A, HP_D0B, HP_D1B, HP_D1C, HP_H0A, HP_H0B, HP_D1Q, HP_N64B, H
 enum VecPid { VP_CONV_RH_R, VP_ACC, VP_RES, VP_HOPRED, VP_BLASRED, VP_NORM_B,
               VP_NORM_EE, VP_NORM_EO, VP_CONV_B_RH, VP_XR_N, VP_PUPD_N, VP_RES_N, VP_DOT_B_XH,
               VP_TWO_XH, VP_PUPD_X, VP_XFLUSH, VP_RUPD, VP_NORM_Q, VP_NORM_S, VP_NORM_T64, VP_NORM_Q64,
-              NVEC };
+              VP_PUPD_R, VP_XRING, NVEC };
 
 // Outputs of a force evaluation (normal-equations mode, one system).
 struct ForceOut {
@@ -100,6 +101,13 @@ struct Batch {
     std::vector<Group> groups;
     int nsys = 0;
     int lo = MOBIUS_F64, px = MOBIUS_F64;
+    // Deferred x update: with ring > 1 the directions of one chunk of `ring`
+    // iterations go to consecutive slots of a ring (iteration q of a chunk
+    // writes p to slot q, reading the previous one from slot q - 1, or from
+    // slot ring - 1 at q = 0), and x += sum_q alpha_q p_q runs once at the
+    // chunk's end: the FP32 x is read and written once per chunk instead of
+    // once per iteration.  ring = 1: x += alpha p_old in every iteration.
+    int ring = 1;
     hipStream_t st = nullptr;
     int64_t pstride = 0, max_n5 = 0, max_site_blocks = 0;
     // device state (in the first context's buffers)
@@ -186,6 +194,7 @@ struct Batch {
     hipError_t hop_group(const Group &g, int prec, int dag, int epi, int out_parity, Field in,
                          Field out, Field x, Field y, bool norm);
     hipError_t vec(int pid, int kind, int prec, int prec2, bool all = false);
+    hipError_t ring_vec(int pid, int kind, int a0, int a1);
     hipError_t reduce(int pid, double *out, int64_t stride, bool all = false);
     hipError_t m5inv_dag_all(int prec, Field in, Field out, bool only_active = false)
     {
@@ -195,7 +204,7 @@ struct Batch {
                          bool bmix = false);
     hipError_t next_u(bool only_active);   // the solve of r the next step's A^+ starts from
     hipError_t psi_odd();                  // psi_o from the iterate (right form: I^-1 z)
-    hipError_t body();                   // one CG iteration
+    hipError_t body(int q, int k);       // iteration q of a chunk of k CG iterations
     hipError_t rupd();                   // r -= alpha q (|r|^2), u = I^-+ r
     hipError_t body_normal();            // one CG iteration on the normal equations
     hipError_t reliable_update();        // x_hi += x, r = b - D x_hi (FP64), r_lo = r
@@ -223,14 +232,17 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
         const Geometry &G = g.ctx->g;
         for (int k = 0; k < NFIELDS; ++k)
             g.fb[k] = field_bytes(G, k <= F_PO ? MOBIUS_F64 : k == F_X ? px : lo);
+        // p: `ring` slots of nrhs fields each
+        auto slots = [&](int k) { return k == F_P ? (int64_t)ring : 1; };
         int64_t need = 4096;
-        for (int k = 0; k < NFIELDS; ++k) need += g.fb[k] * nrhs;
+        for (int k = 0; k < NFIELDS; ++k) need += g.fb[k] * nrhs * slots(k);
         CK(g.ctx->work.ensure(need));
         char *w = static_cast<char *>(g.ctx->work.p);
         for (int k = 0; k < NFIELDS; ++k) {
             g.f[k] = w;
-            w += g.fb[k] * nrhs;
+            w += g.fb[k] * nrhs * slots(k);
         }
+        g.pring = g.f[F_P];
         g.hop_blocks = site_kernel_blocks(G);
         max_site_blocks = std::max(max_site_blocks, g.hop_blocks);
         g.blas_blocks = blas_blocks(G);
@@ -421,6 +433,12 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
             h_vec[(size_t)VP_PUPD_X * nsys + j] = t;
             t = v; t.a = F(F_P); t.c = F(F_X); t.s0 = &sc[j].alpha;
             h_vec[(size_t)VP_XFLUSH * nsys + j] = t;
+            t = v; t.a = F(F_S); t.b = g.pring + r * g.fb[F_P]; t.sstride = g.fb[F_P] * g.nrhs;
+            t.s1 = &sc[j].beta;
+            h_vec[(size_t)VP_PUPD_R * nsys + j] = t;
+            t = v; t.b = g.pring + r * g.fb[F_P]; t.sstride = g.fb[F_P] * g.nrhs; t.c = F(F_X);
+            t.s0 = &sc[j].aring[0];
+            h_vec[(size_t)VP_XRING * nsys + j] = t;
             t = v; t.a = F(F_R); t.b = F(F_Q); t.c = F(F_U); t.s0 = &sc[j].alpha; t.nparts = g.hop_blocks;
             h_vec[(size_t)VP_RUPD * nsys + j] = t;
             t = v; t.a = F(F_Q);
@@ -554,6 +572,24 @@ hipError_t Batch::vec(int pid, int kind, int prec, int prec2, bool all)
                             all ? nullptr : active, st);
 }
 
+// p[slot] = s + beta p[prev] (kind VEC_PUPD_RING: reads s and p[prev], writes
+// p[slot]) or x += sum_{i < a0} alpha_i p[i] (VEC_XRING: reads a0 directions
+// and x, writes x)
+hipError_t Batch::ring_vec(int pid, int kind, int a0, int a1)
+{
+    const double fb = sum_fb(lo, true), fb2 = sum_fb(px, true), n5 = sum_n5(true);
+    if (kind == VEC_PUPD_RING) {
+        abytes += 3 * fb;
+        aflops += 48 * n5;
+    } else {
+        abytes += a0 * fb + 2 * fb2;
+        aflops += 48.0 * a0 * n5;
+    }
+    if (count_only) return hipSuccess;
+    return launch_ring_batch(kind, lo, px, vec_tab + (size_t)pid * nsys, nsys, max_n5, active, a0, a1,
+                             st);
+}
+
 hipError_t Batch::reduce(int pid, double *out, int64_t stride, bool all)
 {
     if (count_only) return hipSuccess;
@@ -611,7 +647,8 @@ hipError_t Batch::m5inv_all(int prec, int dag, Field in, Field out, bool only_ac
 constexpr int64_t SC_STRIDE = sizeof(CgScalars) / sizeof(double);
 
 // s = D^+ r (gamma_new); beta; p = s + beta p;  q = D p (qq); alpha;  x += alpha p, r -= alpha q (rr)
-hipError_t Batch::body()
+// (with a ring of directions, x += sum alpha p once at the end of the chunk)
+hipError_t Batch::body(int q, int k)
 {
     hipError_t e;
     dirac += 4;
@@ -619,14 +656,24 @@ hipError_t Batch::body()
     if ((e = hop(HP_D1C)) != hipSuccess) return e;
     if ((e = reduce(norm_red(), &sc[0].gamma_new, SC_STRIDE)) != hipSuccess) return e;
     if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 1, active, restart, st)) != hipSuccess) return e;
-    if ((e = vec(VP_PUPD_X, VEC_PUPD_X, lo, px)) != hipSuccess) return e;
+    const int slot = ring > 1 ? q : -1;
+    if (ring > 1) {
+        for (Group &g : groups) g.f[F_P] = g.pring + (int64_t)slot * g.fb[F_P] * g.nrhs;
+        if ((e = ring_vec(VP_PUPD_R, VEC_PUPD_RING, slot, q == 0 ? ring - 1 : q - 1)) != hipSuccess)
+            return e;
+    } else if ((e = vec(VP_PUPD_X, VEC_PUPD_X, lo, px)) != hipSuccess) {
+        return e;
+    }
     if (form == FORM_RIGHT && (e = m5inv_all(lo, 0, F_P, F_U)) != hipSuccess) return e;  // v = I^-1 p
     if ((e = hop(HP_D0A)) != hipSuccess) return e;
     if ((e = hop(HP_D0B)) != hipSuccess) return e;
     if ((e = reduce(norm_red(), &sc[0].qq, SC_STRIDE)) != hipSuccess) return e;
-    if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 0, active, restart, st)) != hipSuccess) return e;
+    if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 0, active, restart, st, slot)) != hipSuccess)
+        return e;
     if ((e = rupd()) != hipSuccess) return e;
-    return reduce(VP_RUPD, &sc[0].rr, SC_STRIDE);
+    if ((e = reduce(VP_RUPD, &sc[0].rr, SC_STRIDE)) != hipSuccess) return e;
+    if (ring > 1 && q == k - 1) return ring_vec(VP_XRING, VEC_XRING, k, 0);
+    return hipSuccess;
 }
 
 // Normal equations, p = r + beta p;  q = D p (|q|^2 -> alpha);  s = D^+ q;
@@ -664,7 +711,7 @@ hipError_t Batch::reliable_update()
 {
     hipError_t e;
     dirac += normal ? 4 : 2;
-    if (!normal) {  // the last alpha p of the iteration, then no pending update
+    if (!normal && ring == 1) {  // the last alpha p of the iteration, then no pending update
         if ((e = vec(VP_XFLUSH, VEC_XFLUSH, lo, px)) != hipSuccess) return e;
         if ((e = launch_cg_scalar_batch(sc, nsys, 2, active, restart, st)) != hipSuccess) return e;
     }
@@ -887,6 +934,12 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
     CK(hipEventRecord(own.ev0, B.st));
     B.normal = fo != nullptr;
     B.form = form;
+    // the deferred x update: CGLS with a lower-precision inner operator on one
+    // lattice (the FP32 x against FP32 or binary16 directions), one slot per
+    // iteration of a chunk; MOBIUS_DEFER_X=0 updates x in every iteration
+    if (!B.normal && ngroups == 1 && mixed && check >= 2 && check <= RING_MAX &&
+        env_int("MOBIUS_DEFER_X", 1) != 0)
+        B.ring = check;
 
 
     if (int rc = B.setup(ctxs, ngroups, src, sol, nrhs, o.inner_prec)) return rc;
@@ -919,7 +972,8 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
         }
         CK(launch_zero(g.f[F_XH], g.fb[F_XH] * g.nrhs, st));
         CK(launch_zero(g.f[F_X], g.fb[F_X] * g.nrhs, st));
-        CK(launch_zero(g.f[F_P], g.fb[F_P] * g.nrhs, st));  // beta = 0 times p must be 0
+        // beta = 0 times p must be 0 (every slot of the ring)
+        CK(launch_zero(g.pring, g.fb[F_P] * g.nrhs * B.ring, st));
     }
     CK(B.vec(VP_NORM_B, VEC_NORM2, MOBIUS_F64, MOBIUS_F64));
     CK(B.reduce(VP_BLASRED, &B.extra[X_BNORM2], NEXTRA, true));
@@ -1010,7 +1064,7 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
             if (!gexec) {
                 CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
                 hipError_t e = hipSuccess;
-                for (int q = 0; q < k && e == hipSuccess; ++q) e = B.normal ? B.body_normal() : B.body();
+                for (int q = 0; q < k && e == hipSuccess; ++q) e = B.normal ? B.body_normal() : B.body(q, k);
                 hipError_t e2 = hipStreamEndCapture(st, &graph);
                 CK(e);
                 CK(e2);
@@ -1018,12 +1072,13 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
             } else {
                 // account the replay without launching anything
                 B.count_only = true;
-                for (int q = 0; q < k; ++q) (void)(B.normal ? B.body_normal() : B.body());
+                for (int q = 0; q < k; ++q) (void)(B.normal ? B.body_normal() : B.body(q, k));
                 B.count_only = false;
             }
             CK(hipGraphLaunch(gexec, st));
         } else {
-            for (int q = 0; q < k; ++q) CK(B.normal ? B.body_normal() : B.body());
+            // (a chunk shorter than check is the last one: it reaches maxiter)
+            for (int q = 0; q < k; ++q) CK(B.normal ? B.body_normal() : B.body(q, k));
         }
         it += k;
         for (int j = 0; j < nsys; ++j)

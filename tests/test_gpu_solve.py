@@ -161,3 +161,61 @@ def test_kappa_estimate_and_error_bound(torch_cuda, orc, case):
         assert abs(i.err_bound - i.kappa * i.schur_resid) <= 1e-12 * i.err_bound
         assert err_o <= i.err_bound
     op.close()
+
+
+DEFER_CASES = [
+    # inner, check_every, nrhs, form
+    (2, 0, 1, 0),
+    (1, 0, 1, 0),
+    (2, 5, 3, 0),
+    (2, 16, 1, 1),
+    (1, 8, 2, 1),
+    (2, 17, 1, 0),  # above the ring's 16 slots: x updated in every iteration
+]
+
+
+@pytest.mark.parametrize("case", DEFER_CASES, ids=lambda c: f"inner{c[0]}-check{c[1]}-nrhs{c[2]}-form{c[3]}")
+def test_deferred_x_update(torch_cuda, orc, monkeypatch, case):
+    """Mixed-precision CGLS with the x update deferred to the end of each chunk
+    (one stored direction per iteration) against the update in every iteration
+    (MOBIUS_DEFER_X=0) and against the oracle: both converge, their solutions
+    agree to the solve's accuracy, and a run cut by maxiter in the middle of a
+    chunk returns the same iterate."""
+    from oracle import Params
+    from paper_1206_5214_amd import inputs, mobius
+    torch = torch_cuda
+    inner, check, nrhs, form = case
+    dims, Ls = (4, 4, 4, 8), 8
+    _flush(f"deferred x update: inner {inner} check_every {check} nrhs {nrhs} form {form}")
+    p = Params(dims, Ls, 1.8, 0.02, 1.5, 0.5)
+    rng = np.random.default_rng(71)
+    U = inputs.random_links(dims, 0.5, rng)
+    eta = np.stack([inputs.gaussian_spinor(dims, Ls, rng) for _ in range(nrhs)])
+    op = mobius.Operator(dims, Ls, 1.8, 0.02, 1.5, 0.5, torch.from_numpy(U).cuda())
+    src = torch.from_numpy(eta if nrhs > 1 else eta[0]).cuda()
+    out = {}
+    for d in ("1", "0"):
+        monkeypatch.setenv("MOBIUS_DEFER_X", d)
+        sol, info, rc = op.solve(src, tol=1e-10, maxiter=20000, inner_prec=inner, check_every=check,
+                                 form=form)
+        assert rc == mobius.OK, info
+        cut, cinfo, crc = op.solve(src, tol=1e-10, maxiter=13, inner_prec=inner, check_every=check,
+                                   form=form)
+        assert crc == mobius.NOT_CONVERGED and all(i.iters == 13 for i in cinfo)
+        out[d] = (sol.cpu().numpy().reshape(eta.shape), info, cut.cpu().numpy().reshape(eta.shape), cinfo)
+    psi_orc = [orc.solve(p, U, eta[r], tol=1e-13, maxiter=20000)[0] for r in range(nrhs)]
+    for r in range(nrhs):
+        for d in ("1", "0"):
+            psi = out[d][0][r]
+            res = _rel(orc.dw(p, U, psi), eta[r])
+            err = _rel(psi, psi_orc[r])
+            _flush(f"  defer {d} rhs {r}: iters {out[d][1][r].iters}, resid {res:.2e}, error {err:.2e}")
+            assert res <= 1e-10 and err <= 1e-8
+        diff = _rel(out["1"][0][r], out["0"][0][r])
+        cdiff = _rel(out["1"][2][r], out["0"][2][r])
+        _flush(f"  rhs {r}: solutions differ by {diff:.1e}, 13-iteration iterates by {cdiff:.1e}")
+        # each solution is within 1e-8 of the exact one, and after a chunk
+        # boundary the two runs' reliable updates see x rounded differently,
+        # so their iteration paths (and counts) part slightly
+        assert diff <= 1e-8 and cdiff <= 1e-5
+    op.close()
