@@ -246,7 +246,7 @@ struct CgScalars {
 
 // One system (one lattice, one right-hand side) of a batched vector kernel.
 // Field roles per kernel:
-//   VEC_CG_XR       a = x (prec2), b = p, c = r, d = q, s0 = alpha; |r|^2 partials
+//   VEC_CG_XR       a = x (prec2; null: no x update), b = p, c = r, d = q, s0 = alpha; |r|^2 partials
 //   VEC_AXPBY(_NORM) d = s0 a + s1 b (null scalar = 1) [; |d|^2 partials]
 //   VEC_NORM2       |a|^2 partials
 //   VEC_CONVERT     b (prec2) = a (prec)

@@ -640,7 +640,8 @@ __device__ __forceinline__ bool sys_inactive(const VecSys &v, const int32_t *act
     return v.flag >= 0 && active && active[v.flag] == 0;
 }
 
-// x (PX) += alpha p;  r -= alpha q;  partials of |r|^2.  a = x, b = p, c = r, d = q, s0 = alpha.
+// x (PX) += alpha p;  r -= alpha q;  partials of |r|^2.  a = x, b = p, c = r, d = q, s0 = alpha
+// (a null: r and its norm only, x is updated elsewhere).
 template <int P, int PX>
 __global__ __launch_bounds__(BLAS_BLOCK) void cg_xr_batch(const VecSys *sys, const int32_t *active)
 {
@@ -661,11 +662,13 @@ __global__ __launch_bounds__(BLAS_BLOCK) void cg_xr_batch(const VecSys *sys, con
         const Buf bx(v.a, SX::bytes(v.N5)), bp(v.b, fb), br(v.c, fb), bq(v.d, fb);
         cx<TX> xv[12];
         cx<T> pv[12], rv[12];
-        SX::load(bx, n5, kk, xv);
-        S::load(bp, n5, kk, pv);
+        if (v.a) {
+            SX::load(bx, n5, kk, xv);
+            S::load(bp, n5, kk, pv);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) xv[c] = xv[c] + alx * cx<TX>{(TX)pv[c].r, (TX)pv[c].i};
-        SX::store(bx, n5, kk, xv);
+            for (int c = 0; c < 12; ++c) xv[c] = xv[c] + alx * cx<TX>{(TX)pv[c].r, (TX)pv[c].i};
+            SX::store(bx, n5, kk, xv);
+        }
         S::load(br, n5, kk, rv);
         S::load(bq, n5, kk, pv);
 #pragma unroll

@@ -88,7 +88,7 @@ enum HopPid { HP_D0A, HP_D0B, HP_D1B, HP_D1C, HP_H0A, HP_H0B, HP_D1Q, HP_N64B, H
 enum VecPid { VP_CONV_RH_R, VP_ACC, VP_RES, VP_HOPRED, VP_BLASRED, VP_NORM_B,
               VP_NORM_EE, VP_NORM_EO, VP_CONV_B_RH, VP_XR_N, VP_PUPD_N, VP_RES_N, VP_DOT_B_XH,
               VP_TWO_XH, VP_PUPD_X, VP_XFLUSH, VP_RUPD, VP_NORM_Q, VP_NORM_S, VP_NORM_T64, VP_NORM_Q64,
-              VP_PUPD_R, VP_XRING, NVEC };
+              VP_PUPD_R, VP_XRING, VP_PUPD_RN, VP_R_N, NVEC };
 
 // Outputs of a force evaluation (normal-equations mode, one system).
 struct ForceOut {
@@ -206,7 +206,7 @@ struct Batch {
     hipError_t psi_odd();                  // psi_o from the iterate (right form: I^-1 z)
     hipError_t body(int q, int k);       // iteration q of a chunk of k CG iterations
     hipError_t rupd();                   // r -= alpha q (|r|^2), u = I^-+ r
-    hipError_t body_normal();            // one CG iteration on the normal equations
+    hipError_t body_normal(int q, int k);  // the same on the normal equations
     hipError_t reliable_update();        // x_hi += x, r = b - D x_hi (FP64), r_lo = r
     hipError_t finalize_group(const Group &g);
     int fetch(std::vector<double> &out, int which);
@@ -439,6 +439,11 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
             t = v; t.b = g.pring + r * g.fb[F_P]; t.sstride = g.fb[F_P] * g.nrhs; t.c = F(F_X);
             t.s0 = &sc[j].aring[0];
             h_vec[(size_t)VP_XRING * nsys + j] = t;
+            t = v; t.a = F(F_R); t.b = g.pring + r * g.fb[F_P]; t.sstride = g.fb[F_P] * g.nrhs;
+            t.s1 = &sc[j].beta;
+            h_vec[(size_t)VP_PUPD_RN * nsys + j] = t;
+            t = v; t.c = F(F_R); t.d = F(F_S); t.s0 = &sc[j].alpha;
+            h_vec[(size_t)VP_R_N * nsys + j] = t;
             t = v; t.a = F(F_R); t.b = F(F_Q); t.c = F(F_U); t.s0 = &sc[j].alpha; t.nparts = g.hop_blocks;
             h_vec[(size_t)VP_RUPD * nsys + j] = t;
             t = v; t.a = F(F_Q);
@@ -555,7 +560,15 @@ hipError_t Batch::vec(int pid, int kind, int prec, int prec2, bool all)
 {
     const double fb = sum_fb(prec, true), fb2 = sum_fb(prec2, true), n5 = sum_n5(true);
     switch (kind) {
-    case VEC_CG_XR: abytes += 2 * fb2 + 4 * fb; aflops += 144 * n5; break;
+    case VEC_CG_XR:
+        if (pid == VP_R_N) {  // r -= alpha s only
+            abytes += 3 * fb;
+            aflops += 96 * n5;
+        } else {
+            abytes += 2 * fb2 + 4 * fb;
+            aflops += 144 * n5;
+        }
+        break;
     case VEC_AXPBY: abytes += 3 * fb; aflops += 48 * n5; break;
     case VEC_AXPBY_NORM: abytes += 3 * fb; aflops += 96 * n5; break;
     case VEC_NORM2: abytes += fb; aflops += 48 * n5; break;
@@ -677,23 +690,34 @@ hipError_t Batch::body(int q, int k)
 }
 
 // Normal equations, p = r + beta p;  q = D p (|q|^2 -> alpha);  s = D^+ q;
-// x += alpha p, r -= alpha s (|r|^2 -> the next gamma).
-hipError_t Batch::body_normal()
+// x += alpha p, r -= alpha s (|r|^2 -> the next gamma); with a ring of
+// directions, x += sum alpha p once at the end of the chunk.
+hipError_t Batch::body_normal(int q, int k)
 {
     hipError_t e;
     dirac += 4;
     if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 1, active, restart, st)) != hipSuccess) return e;
-    if ((e = vec(VP_PUPD_N, VEC_AXPBY, lo, lo)) != hipSuccess) return e;
+    const int slot = ring > 1 ? q : -1;
+    if (ring > 1) {
+        for (Group &g : groups) g.f[F_P] = g.pring + (int64_t)slot * g.fb[F_P] * g.nrhs;
+        if ((e = ring_vec(VP_PUPD_RN, VEC_PUPD_RING, slot, q == 0 ? ring - 1 : q - 1)) != hipSuccess)
+            return e;
+    } else if ((e = vec(VP_PUPD_N, VEC_AXPBY, lo, lo)) != hipSuccess) {
+        return e;
+    }
     if ((e = hop(HP_D0A)) != hipSuccess) return e;
     if ((e = hop(HP_D0B)) != hipSuccess) return e;
     if ((e = reduce(norm_red(), &sc[0].qq, SC_STRIDE)) != hipSuccess) return e;
-    if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 0, active, restart, st)) != hipSuccess) return e;
+    if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 0, active, restart, st, slot)) != hipSuccess)
+        return e;
     if ((e = m5inv_dag_all(lo, F_Q, F_U)) != hipSuccess) return e;
     if ((e = hop(HP_D1B)) != hipSuccess) return e;
     if ((e = hop(HP_D1Q)) != hipSuccess) return e;
-    if ((e = vec(VP_XR_N, VEC_CG_XR, lo, px)) != hipSuccess) return e;
+    if ((e = vec(ring > 1 ? VP_R_N : VP_XR_N, VEC_CG_XR, lo, px)) != hipSuccess) return e;
     if ((e = reduce(VP_BLASRED, &sc[0].rr, SC_STRIDE)) != hipSuccess) return e;
-    return reduce(VP_BLASRED, &sc[0].gamma_new, SC_STRIDE);
+    if ((e = reduce(VP_BLASRED, &sc[0].gamma_new, SC_STRIDE)) != hipSuccess) return e;
+    if (ring > 1 && q == k - 1) return ring_vec(VP_XRING, VEC_XRING, k, 0);
+    return hipSuccess;
 }
 
 hipError_t Batch::rupd()
@@ -934,11 +958,10 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
     CK(hipEventRecord(own.ev0, B.st));
     B.normal = fo != nullptr;
     B.form = form;
-    // the deferred x update: CGLS with a lower-precision inner operator on one
+    // the deferred x update: CG with a lower-precision inner operator on one
     // lattice (the FP32 x against FP32 or binary16 directions), one slot per
     // iteration of a chunk; MOBIUS_DEFER_X=0 updates x in every iteration
-    if (!B.normal && ngroups == 1 && mixed && check >= 2 && check <= RING_MAX &&
-        env_int("MOBIUS_DEFER_X", 1) != 0)
+    if (ngroups == 1 && mixed && check >= 2 && check <= RING_MAX && env_int("MOBIUS_DEFER_X", 1) != 0)
         B.ring = check;
 
 
@@ -1064,7 +1087,7 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
             if (!gexec) {
                 CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
                 hipError_t e = hipSuccess;
-                for (int q = 0; q < k && e == hipSuccess; ++q) e = B.normal ? B.body_normal() : B.body(q, k);
+                for (int q = 0; q < k && e == hipSuccess; ++q) e = B.normal ? B.body_normal(q, k) : B.body(q, k);
                 hipError_t e2 = hipStreamEndCapture(st, &graph);
                 CK(e);
                 CK(e2);
@@ -1072,13 +1095,13 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
             } else {
                 // account the replay without launching anything
                 B.count_only = true;
-                for (int q = 0; q < k; ++q) (void)(B.normal ? B.body_normal() : B.body(q, k));
+                for (int q = 0; q < k; ++q) (void)(B.normal ? B.body_normal(q, k) : B.body(q, k));
                 B.count_only = false;
             }
             CK(hipGraphLaunch(gexec, st));
         } else {
             // (a chunk shorter than check is the last one: it reaches maxiter)
-            for (int q = 0; q < k; ++q) CK(B.normal ? B.body_normal() : B.body(q, k));
+            for (int q = 0; q < k; ++q) CK(B.normal ? B.body_normal(q, k) : B.body(q, k));
         }
         it += k;
         for (int j = 0; j < nsys; ++j)

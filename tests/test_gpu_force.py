@@ -203,3 +203,30 @@ def test_force_lie_vs_oracle(torch_cuda, orc):
     assert mobius.lib().mobius_force_lie(op._h, mobius._ptr(u), mobius._ptr(u), mobius._ptr(u),
                                          None) == -22  # output aliases an input
     op.close()
+
+
+@pytest.mark.parametrize("check", [0, 5], ids=["check8", "check5"])
+def test_force_deferred_x_update(torch_cuda, monkeypatch, check):
+    """The force's normal-equations CG with the x update deferred to the end of
+    each chunk (FP16 inner operator) against the update in every iteration
+    (MOBIUS_DEFER_X=0): same action and gradient to the solve's accuracy."""
+    from paper_1206_5214_amd import inputs, mobius
+    torch = torch_cuda
+    dims, Ls = (4, 4, 4, 8), 8
+    rng = np.random.default_rng(7)
+    U = torch.from_numpy(inputs.random_links(dims, 0.5, rng)).cuda()
+    phi = torch.from_numpy(inputs.gaussian_spinor(dims, Ls, rng)).cuda()
+    op = mobius.Operator(dims, Ls, 1.8, 0.02, 1.5, 0.5, U)
+    res = {}
+    for d in ("1", "0"):
+        monkeypatch.setenv("MOBIUS_DEFER_X", d)
+        S, G, gp, info, rc = op.force(phi, tol=1e-12, inner_prec=mobius.F16, check_every=check)
+        assert rc == mobius.OK, info
+        res[d] = (S, G, info)
+    S1, G1, i1 = res["1"]
+    S0, G0, i0 = res["0"]
+    dg = ((G1 - G0).abs().max() / G0.abs().max()).item()
+    _flush(f"  check {check}: iters {i1.iters} / {i0.iters}, action diff {abs(S1 - S0) / abs(S0):.1e}, "
+           f"gradient diff {dg:.1e}")
+    assert abs(S1 - S0) <= 1e-10 * abs(S0) and dg <= 1e-9
+    op.close()
