@@ -1085,29 +1085,50 @@ __device__ __forceinline__ void m5inv_lanes(cx<T> r[12], const Coef<T> &k, const
             }
         }
     } else if (g * Ls + Ls <= 64) {
+        // Both recurrences walk the slices in order; the loads of four slices
+        // are issued together (a load never depends on the recurrence), so a
+        // wave waits for LDS once per four steps instead of once per step.
+        // The arithmetic and its order are those of the plain loop.
         const int base = g * Ls;
         for (int c = s0; c < 12; c += Ls) {
             const bool plus = c < 6;
             const bool transpose = plus != dag;
             const T na = -k.a;
-            if (!transpose) {
-                cx<T> sum = {0, 0};
-                for (int t = Ls - 2; t >= 0; --t) sum = w[(base + t) * ST + c] + na * sum;
-                cx<T> psi = k.inv_den * (w[(base + Ls - 1) * ST + c] + k.mu * sum);
-                w[(base + Ls - 1) * ST + c] = psi;
-                for (int t = Ls - 2; t >= 0; --t) {
-                    psi = k.inv_Mp * w[(base + t) * ST + c] - k.a * psi;
-                    w[(base + t) * ST + c] = psi;
-                }
-            } else {
-                cx<T> sum = {0, 0};
-                for (int t = 1; t < Ls; ++t) sum = na * sum + w[(base + t) * ST + c];
-                cx<T> psi = k.inv_den * (w[base * ST + c] + k.mu * sum);
-                w[base * ST + c] = psi;
-                for (int t = 1; t < Ls; ++t) {
-                    psi = k.inv_Mp * w[(base + t) * ST + c] - k.a * psi;
-                    w[(base + t) * ST + c] = psi;
-                }
+            // slice t of this component; dt = -1 walks down from Ls - 2, +1 up from 1
+            const int dt = transpose ? 1 : -1;
+            const int t0 = transpose ? 1 : Ls - 2;   // first slice of both loops
+            const int tl = transpose ? 0 : Ls - 1;   // the slice solved first
+            cx<T> *col = w + base * ST + c;
+            cx<T> sum = {0, 0};
+            int n = Ls - 1, t = t0;
+            for (; n >= 4; n -= 4, t += 4 * dt) {
+                const cx<T> w0 = col[t * ST], w1 = col[(t + dt) * ST], w2 = col[(t + 2 * dt) * ST],
+                            w3 = col[(t + 3 * dt) * ST];
+                sum = w0 + na * sum;
+                sum = w1 + na * sum;
+                sum = w2 + na * sum;
+                sum = w3 + na * sum;
+            }
+            for (; n > 0; --n, t += dt) sum = col[t * ST] + na * sum;
+            cx<T> psi = k.inv_den * (col[tl * ST] + k.mu * sum);
+            col[tl * ST] = psi;
+            n = Ls - 1;
+            t = t0;
+            for (; n >= 4; n -= 4, t += 4 * dt) {
+                const cx<T> w0 = col[t * ST], w1 = col[(t + dt) * ST], w2 = col[(t + 2 * dt) * ST],
+                            w3 = col[(t + 3 * dt) * ST];
+                psi = k.inv_Mp * w0 - k.a * psi;
+                col[t * ST] = psi;
+                psi = k.inv_Mp * w1 - k.a * psi;
+                col[(t + dt) * ST] = psi;
+                psi = k.inv_Mp * w2 - k.a * psi;
+                col[(t + 2 * dt) * ST] = psi;
+                psi = k.inv_Mp * w3 - k.a * psi;
+                col[(t + 3 * dt) * ST] = psi;
+            }
+            for (; n > 0; --n, t += dt) {
+                psi = k.inv_Mp * col[t * ST] - k.a * psi;
+                col[t * ST] = psi;
             }
         }
     }
