@@ -110,8 +110,8 @@ typedef struct {
                               0.3 for FP16, 0.1 for FP32 */
     int32_t nrhs;          /* number of right-hand sides in src/sol (>= 1) */
     int32_t check_every;   /* iterations between host convergence checks (<= 0 selects 8 with a
-                              lower-precision inner operator, 16 for FP64).  With F32/F16 on one
-                              context and check_every <= 16, the FP32 correction to the iterate
+                              lower-precision inner operator, 16 for FP64).  With F32/F16 and
+                              check_every <= 16, the FP32 correction to the iterate
                               is updated once per check_every iterations from that many stored
                               search directions (check_every - 1 more inner-precision fields
                               per right-hand side in the context's workspace) */

@@ -117,6 +117,11 @@ struct Batch {
     double *extra = nullptr;
     int32_t *active = nullptr, *restart = nullptr;
     HopParams *hop_tab = nullptr;   // [NHOP][ngroups]
+    // several lattices with a ring of directions: the D0A and D0B descriptors
+    // of each slot (p read from that slot), [ring][2][ngroups]
+    HopParams *hop_ring_tab = nullptr;
+    std::vector<HopParams> h_hop_ring;
+    int cur_slot = 0;               // ring slot of the iteration being issued
     VecSys *vec_tab = nullptr;      // [NVEC][nsys]
     int64_t *prefix = nullptr;      // [NHOP][ngroups + 1]
     size_t hop_lds[NHOP] = {};
@@ -321,6 +326,7 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
     const size_t o_ac = carve(sizeof(int32_t) * nsys);
     const size_t o_rs = carve(sizeof(int32_t) * nsys);
     const size_t o_hop = carve(sizeof(HopParams) * NHOP * ng);
+    const size_t o_hring = carve(sizeof(HopParams) * 2 * RING_MAX * ng);
     const size_t o_vec = carve(sizeof(VecSys) * NVEC * nsys);
     const size_t o_pre = carve(sizeof(int64_t) * NHOP * (ng + 1));
     const size_t o_coef = carve(sizeof(OpCoeffs) * ng);
@@ -332,6 +338,7 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
     active = reinterpret_cast<int32_t *>(base + o_ac);
     restart = reinterpret_cast<int32_t *>(base + o_rs);
     hop_tab = reinterpret_cast<HopParams *>(base + o_hop);
+    hop_ring_tab = reinterpret_cast<HopParams *>(base + o_hring);
     vec_tab = reinterpret_cast<VecSys *>(base + o_vec);
     prefix = reinterpret_cast<int64_t *>(base + o_pre);
     OpCoeffs *coef = reinterpret_cast<OpCoeffs *>(base + o_coef);
@@ -458,6 +465,25 @@ int Batch::setup(mobius_ctx *const *ctxs, int n, const void *const *src, void *c
     h_active.assign(nsys, 1);
     h_restart.assign(nsys, 1);
     CK(hipMemcpyAsync(hop_tab, h_hop.data(), sizeof(HopParams) * h_hop.size(), hipMemcpyHostToDevice, st));
+    if (ring > 1 && ng > 1) {
+        // per slot: the same descriptors with every operand that is p moved to the slot
+        h_hop_ring.assign((size_t)2 * ring * ng, HopParams{});
+        for (int s = 0; s < ring; ++s)
+            for (int j2 = 0; j2 < 2; ++j2) {
+                const int pid = j2 == 0 ? HP_D0A : HP_D0B;
+                for (int j = 0; j < ng; ++j) {
+                    const Group &g = groups[j];
+                    const char *ps = g.pring + (int64_t)s * g.fb[F_P] * g.nrhs;
+                    HopParams h = h_hop[(size_t)pid * ng + j];
+                    if (hp[pid].in == F_P) h.in = ps;
+                    if (hp[pid].x == F_P) h.x = ps;
+                    if (hp[pid].y == F_P) h.y = ps;
+                    h_hop_ring[((size_t)s * 2 + j2) * ng + j] = h;
+                }
+            }
+        CK(hipMemcpyAsync(hop_ring_tab, h_hop_ring.data(), sizeof(HopParams) * h_hop_ring.size(),
+                          hipMemcpyHostToDevice, st));
+    }
     CK(hipMemcpyAsync(vec_tab, h_vec.data(), sizeof(VecSys) * h_vec.size(), hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(prefix, h_prefix.data(), sizeof(int64_t) * h_prefix.size(), hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(coef, h_coef.data(), sizeof(OpCoeffs) * ng, hipMemcpyHostToDevice, st));
@@ -538,9 +564,11 @@ hipError_t Batch::launch_pattern(const HopPattern &p, int pid)
         return launch_hop(g.ctx->g, g.ctx->c, hop_links(g.ctx, p.prec, p.dag),
                           static_cast<const int32_t *>(g.ctx->nbr.p), hop_args_for(g, p), st);
     }
-    return launch_hop_batch(p.prec, p.dag, p.epi, hop_tab + (size_t)pid * ngroups(), ngroups(),
-                            prefix + (size_t)pid * (ngroups() + 1), hop_lds[pid], batch_grid,
-                            hop_pf[pid], st);
+    const HopParams *tab = hop_tab + (size_t)pid * ngroups();
+    if (ring > 1 && (pid == HP_D0A || pid == HP_D0B))
+        tab = hop_ring_tab + ((size_t)cur_slot * 2 + (pid == HP_D0B ? 1 : 0)) * ngroups();
+    return launch_hop_batch(p.prec, p.dag, p.epi, tab, ngroups(), prefix + (size_t)pid * (ngroups() + 1),
+                            hop_lds[pid], batch_grid, hop_pf[pid], st);
 }
 
 hipError_t Batch::hop_group(const Group &g, int prec, int dag, int epi, int out_parity, Field in,
@@ -671,6 +699,7 @@ hipError_t Batch::body(int q, int k)
     if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 1, active, restart, st)) != hipSuccess) return e;
     const int slot = ring > 1 ? q : -1;
     if (ring > 1) {
+        cur_slot = slot;
         for (Group &g : groups) g.f[F_P] = g.pring + (int64_t)slot * g.fb[F_P] * g.nrhs;
         if ((e = ring_vec(VP_PUPD_R, VEC_PUPD_RING, slot, q == 0 ? ring - 1 : q - 1)) != hipSuccess)
             return e;
@@ -699,6 +728,7 @@ hipError_t Batch::body_normal(int q, int k)
     if (!count_only && (e = launch_cg_scalar_batch(sc, nsys, 1, active, restart, st)) != hipSuccess) return e;
     const int slot = ring > 1 ? q : -1;
     if (ring > 1) {
+        cur_slot = slot;
         for (Group &g : groups) g.f[F_P] = g.pring + (int64_t)slot * g.fb[F_P] * g.nrhs;
         if ((e = ring_vec(VP_PUPD_RN, VEC_PUPD_RING, slot, q == 0 ? ring - 1 : q - 1)) != hipSuccess)
             return e;
@@ -958,10 +988,10 @@ int run(mobius_ctx *const *ctxs, int ngroups, const void *const *src, void *cons
     CK(hipEventRecord(own.ev0, B.st));
     B.normal = fo != nullptr;
     B.form = form;
-    // the deferred x update: CG with a lower-precision inner operator on one
-    // lattice (the FP32 x against FP32 or binary16 directions), one slot per
-    // iteration of a chunk; MOBIUS_DEFER_X=0 updates x in every iteration
-    if (ngroups == 1 && mixed && check >= 2 && check <= RING_MAX && env_int("MOBIUS_DEFER_X", 1) != 0)
+    // the deferred x update: CG with a lower-precision inner operator (the FP32
+    // x against FP32 or binary16 directions), one slot per iteration of a
+    // chunk; MOBIUS_DEFER_X=0 updates x in every iteration
+    if (mixed && check >= 2 && check <= RING_MAX && env_int("MOBIUS_DEFER_X", 1) != 0)
         B.ring = check;
 
 
