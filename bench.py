@@ -115,10 +115,11 @@ def copy_peak_gbs(torch, nbytes=1 << 31, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def counters_for(kernel_key, tuning):
+def counters_for(kernel_key, tuning, brick=None, auto_brick=None):
     """HBM traffic per launch measured with rocprofv3 counters, if they were
     taken on the current kernel source (profiles/<key>.json records its hash)
-    with the launch parameters this run's tuner chose."""
+    with the launch parameters this run's tuner chose and the same site-order
+    brick (brick None or equal to auto_brick: the automatic one)."""
     from paper_1206_5214_amd.profile_hop import hop_sources_sha256
     path = os.path.join(ROOT, "profiles", f"{kernel_key}.json")
     if not os.path.exists(path):
@@ -129,6 +130,12 @@ def counters_for(kernel_key, tuning):
         return None
     want = {k: v for k, v in tuning.items() if k != "hop_us"}
     if rec.get("tuning") is not None and rec["tuning"] != want:
+        return None
+    used = None if brick is None or list(brick) == list(auto_brick or []) else list(brick)
+    rb = rec.get("brick")
+    if rb is not None and list(rb) == list(auto_brick or []):
+        rb = None
+    if rb != used:
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -452,6 +459,10 @@ def main():
     ap.add_argument("--hop-reps", type=int, default=100,
                     help="timed launches of the metered hop per parity (after 10 untimed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-brick-tune", action="store_true",
+                    help="keep the automatic site order instead of timing candidate bricks")
+    ap.add_argument("--brick", default="",
+                    help="site-order brick bx,by,bz to use without timing candidates")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 / FP32 comparison solves")
     ap.add_argument("--no-force", action="store_true",
@@ -478,7 +489,22 @@ def main():
     log(f"fields ready in {time.perf_counter() - t0:.1f} s")
     Ud = torch.from_numpy(U).cuda()
     etad = torch.from_numpy(eta).cuda()
-    op = mobius.Operator(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, Ud)
+    # site order: the layout tuner times candidate bricks with the inner
+    # operator's precision (the automatic brick unless one is > 3 % faster)
+    site_order = None
+    brick = None
+    if args.brick:
+        brick = tuple(int(b) for b in args.brick.split(","))
+        site_order = {"brick": list(brick), "automatic": None, "given": True}
+        log(f"site order: brick {brick} (given)")
+    elif not args.no_brick_tune:
+        brick, brick_us, trials = mobius.tune_brick(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, Ud, prec=inner)
+        site_order = {"brick": list(brick), "automatic": list(trials[0][0]), "hop_us": brick_us,
+                      "prec": PREC_NAMES[inner],
+                      "trials": [{"brick": list(b), "hop_us": u} for b, u in trials]}
+        log(f"site order: brick {brick} ({brick_us:.1f} us); candidates "
+            + ", ".join(f"{b}: {u:.1f}" for b, u in trials))
+    op = mobius.Operator(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, Ud, brick=brick)
     torch.cuda.synchronize()
     tuning = {}
     for prec in (mobius.F64, mobius.F32, mobius.F16):
@@ -613,7 +639,8 @@ def main():
 
     hname = PREC_NAMES[inner]
     key = f"hop_{hname}_{args.workload}"
-    traffic = counters_for(key, tuning[hname])
+    traffic = counters_for(key, tuning[hname], site_order and site_order["brick"],
+                           site_order and site_order["automatic"])
     roofline = {"bound": "hbm", "achieved": hop[hname]["GBps"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": hop[hname]["GBps"] / HBM_PEAK_GBS,
                 "traffic": traffic, "traffic_note": "L2-to-memory read and write requests per launch "
@@ -665,6 +692,7 @@ def main():
         "batched": batch,
         "force": force,
         "tuning": tuning,
+        "site_order": site_order,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -97,6 +97,12 @@ typedef struct {
                      D+(s) = b5(s) D_W + 1 and D-(s) = c5(s) D_W - 1; e.g. Zolotarev
                      coefficients, Sec. 4.3); read by mobius_create only.  NULL: the
                      constant b5 (c5) above; one NULL and one not: the NULL one constant. */
+    int32_t brick[3]; /* site order: bricks of Bx x By x Bz spatial sites, each extended over
+                     all t, are the columns the packed traversal (and so every hop's
+                     workgroups) walks; each side in 1..L of its direction.  All zero: chosen
+                     automatically (the largest brick dividing the lattice whose one-site
+                     FP64 slice fits half of one XCD's L2; MOBIUS_BRICK="bx,by,bz" overrides
+                     that choice); mobius_tune_brick measures candidates. */
 } mobius_params;
 
 typedef struct {
@@ -376,6 +382,28 @@ typedef struct {
  * The tuner uses context scratch memory only; caller fields are untouched.
  * Synchronises.  out may be NULL. */
 int mobius_tune(mobius_ctx *ctx, int32_t prec, int32_t reps, mobius_tune_result *out, void *stream);
+
+/* One candidate site order timed by mobius_tune_brick. */
+typedef struct {
+    int32_t brick[3]; /* Bx, By, Bz */
+    double hop_us;    /* tuned hop time D_{p,1-p} with this site order (microseconds) */
+} mobius_brick_trial;
+
+/* Autotune the site order, the tile of sites the hop's workgroups walk, which
+ * is fixed for a context at its creation.  Candidates: the automatic brick
+ * (first) and the bricks whose sides are half, once or twice its sides and
+ * divide the lattice, nearest in volume first, at most 12.  For each, a
+ * temporary context is created from p (p->brick ignored) and links_c128, its
+ * hop for `prec` is tuned as by mobius_tune (`reps` as there, the same cache
+ * file) and its time recorded.  brick_out[3] receives the automatic brick
+ * unless a candidate's hop is more than 3 % faster, then the fastest one; us_out
+ * (may be NULL) its time; trials (may be NULL, room for max_trials) every
+ * candidate in the order timed, *ntrials (may be NULL) how many.  One
+ * temporary context (its links in all three precisions) exists at a time.
+ * Synchronises.  Create the context to use with p->brick = brick_out. */
+int mobius_tune_brick(const mobius_params *p, const void *links_c128, int32_t prec, int32_t reps,
+                      mobius_brick_trial *trials, int32_t max_trials, int32_t *ntrials,
+                      int32_t *brick_out, double *us_out, void *stream);
 
 /* Set the hop launch parameters of a context for precision t->prec directly
  * (for example those an earlier mobius_tune reported; t->hop_us is ignored).

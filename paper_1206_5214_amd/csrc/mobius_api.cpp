@@ -223,6 +223,10 @@ extern "C" int mobius_create(mobius_ctx **out, const mobius_params *p, const voi
     if (!sdep && !std::isfinite(c.inv_den)) return fail(MOBIUS_EINVAL, "the Ls-direction block I is singular");
     if (!std::isfinite(p->mu) || std::fabs(p->mu) > 10.0)
         return fail(MOBIUS_EINVAL, "the chemical potential must be finite with |mu| <= 10");
+    const bool own_brick = p->brick[0] || p->brick[1] || p->brick[2];
+    for (int k = 0; k < 3 && own_brick; ++k)
+        if (p->brick[k] < 1 || p->brick[k] > p->L[k])
+            return fail(MOBIUS_EINVAL, "each side of the site-order brick must lie in 1..L");
 
     mobius_ctx *ctx = new mobius_ctx();
     ctx->P = *p;
@@ -264,6 +268,8 @@ extern "C" int mobius_create(mobius_ctx **out, const mobius_params *p, const voi
     }
     // site order and neighbour table
     choose_brick(g.L, g.Ls, g.brick);
+    if (own_brick)
+        for (int k = 0; k < 3; ++k) g.brick[k] = p->brick[k];
     std::vector<int32_t> canon_of, packed_of;
     site_order(g, canon_of, packed_of);
     DevBuf packed_dev;
@@ -882,6 +888,81 @@ extern "C" int mobius_tune(mobius_ctx *ctx, int32_t prec, int32_t reps, mobius_t
     if (int r = check_ctx(ctx)) return r;
     if (int r = check_prec(prec)) return r;
     return mobius::tune(ctx, prec, reps, out, S(stream));
+}
+
+extern "C" int mobius_tune_brick(const mobius_params *p, const void *links_c128, int32_t prec,
+                                 int32_t reps, mobius_brick_trial *trials, int32_t max_trials,
+                                 int32_t *ntrials, int32_t *brick_out, double *us_out, void *stream)
+{
+    g_err.clear();
+    if (!p || !links_c128 || !brick_out) return fail(MOBIUS_EINVAL, "null argument to mobius_tune_brick");
+    if (int r = check_prec(prec)) return r;
+    if (trials && max_trials < 0) return fail(MOBIUS_EINVAL, "max_trials must be >= 0");
+    for (int mu = 0; mu < 4; ++mu)
+        if (p->L[mu] < 2 || (p->L[mu] & 1))
+            return fail(MOBIUS_EINVAL, "every lattice extent must be even and >= 2");
+    if (p->Ls < 2 || p->Ls > 64) return fail(MOBIUS_EINVAL, "Ls must be in [2, 64]");
+    int base[3];
+    choose_brick(p->L, p->Ls, base);
+    // candidates: each side halved, kept or doubled where it still divides the lattice
+    struct Cand {
+        int b[3];
+        double dist, surf;
+    };
+    std::vector<Cand> cands;
+    const double vol0 = (double)base[0] * base[1] * base[2];
+    for (int i = 0; i < 27; ++i) {
+        Cand c;
+        int f = i;
+        bool ok = true;
+        for (int k = 0; k < 3; ++k, f /= 3) {
+            const int s = f % 3 == 0 ? base[k] : f % 3 == 1 ? base[k] / 2 : base[k] * 2;
+            // (the automatic brick itself is always a candidate, also an
+            // override that does not divide the lattice)
+            ok = ok && (i == 0 || (s >= 1 && s <= p->L[k] && p->L[k] % s == 0 && (f % 3 != 1 || base[k] % 2 == 0)));
+            c.b[k] = s;
+        }
+        if (!ok) continue;
+        bool dup = false;
+        for (const Cand &d : cands) dup = dup || (d.b[0] == c.b[0] && d.b[1] == c.b[1] && d.b[2] == c.b[2]);
+        if (dup) continue;
+        c.dist = std::fabs(std::log2((double)c.b[0] * c.b[1] * c.b[2] / vol0));
+        c.surf = 1.0 / c.b[0] + 1.0 / c.b[1] + 1.0 / c.b[2];
+        cands.push_back(c);
+    }
+    // the automatic brick first (i = 0), then nearest in volume, then most compact
+    std::stable_sort(cands.begin() + 1, cands.end(), [](const Cand &x, const Cand &y) {
+        return x.dist != y.dist ? x.dist < y.dist : x.surf < y.surf;
+    });
+    if (cands.size() > 12) cands.resize(12);
+    int best = 0;
+    double best_us = 0, base_us = 0;
+    int n = 0;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        mobius_params q = *p;
+        for (int k = 0; k < 3; ++k) q.brick[k] = cands[i].b[k];
+        mobius_ctx *ctx = nullptr;
+        if (int r = mobius_create(&ctx, &q, links_c128, stream)) return r;
+        mobius_tune_result res;
+        const int r = mobius::tune(ctx, prec, reps, &res, S(stream));
+        mobius_destroy(ctx);
+        if (r != MOBIUS_OK) return r;
+        if (trials && n < max_trials) {
+            for (int k = 0; k < 3; ++k) trials[n].brick[k] = cands[i].b[k];
+            trials[n].hop_us = res.hop_us;
+        }
+        ++n;
+        if (i == 0) {
+            base_us = best_us = res.hop_us;
+        } else if (res.hop_us < best_us && res.hop_us < 0.97 * base_us) {
+            best = (int)i;
+            best_us = res.hop_us;
+        }
+    }
+    for (int k = 0; k < 3; ++k) brick_out[k] = cands[best].b[k];
+    if (us_out) *us_out = best_us;
+    if (ntrials) *ntrials = trials ? std::min(n, (int)max_trials) : n;
+    return MOBIUS_OK;
 }
 
 extern "C" int mobius_set_tuning(mobius_ctx *ctx, const mobius_tune_result *t)

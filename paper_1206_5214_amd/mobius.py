@@ -26,7 +26,7 @@ EXPORTS = ("mobius_create", "mobius_destroy", "mobius_field_bytes", "mobius_pack
            "mobius_unpack", "mobius_dslash", "mobius_dslash_dag", "mobius_m5inv",
            "mobius_cg_solve", "mobius_batch_solve", "mobius_propagator4d", "mobius_force", "mobius_force_lie",
            "mobius_tune", "mobius_set_tuning", "mobius_last_error", "mobius_dslash_noalloc",
-           "mobius_bulk5d", "mobius_cg_solve_dag", "mobius_force_wall")
+           "mobius_bulk5d", "mobius_cg_solve_dag", "mobius_force_wall", "mobius_tune_brick")
 
 
 class MobiusError(RuntimeError):
@@ -37,7 +37,30 @@ class _Params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32 * 4), ("Ls", ctypes.c_int32), ("M5", ctypes.c_double),
                 ("mf", ctypes.c_double), ("b5", ctypes.c_double), ("c5", ctypes.c_double),
                 ("mu", ctypes.c_double), ("b5s", ctypes.POINTER(ctypes.c_double)),
-                ("c5s", ctypes.POINTER(ctypes.c_double))]
+                ("c5s", ctypes.POINTER(ctypes.c_double)), ("brick", ctypes.c_int32 * 3)]
+
+
+class _BrickTrial(ctypes.Structure):
+    _fields_ = [("brick", ctypes.c_int32 * 3), ("hop_us", ctypes.c_double)]
+
+
+def _make_params(dims, Ls, M5, mf, b5, c5, mu=0.0, b5s=None, c5s=None, brick=None):
+    """mobius_params for a lattice; returns it with the arrays it points to
+    (kept alive by the caller for as long as the struct is used)."""
+    p = _Params((ctypes.c_int32 * 4)(*[int(d) for d in dims]), int(Ls), M5, mf, b5, c5, mu)
+    keep = []
+    for name, v in (("b5s", b5s), ("c5s", c5s)):
+        if v is not None:
+            if len(v) != int(Ls):
+                raise MobiusError(f"{name} must hold Ls = {int(Ls)} values")
+            a = (ctypes.c_double * int(Ls))(*[float(x) for x in v])
+            keep.append(a)
+            setattr(p, name, ctypes.cast(a, ctypes.POINTER(ctypes.c_double)))
+    if brick is not None:
+        if len(brick) != 3:
+            raise MobiusError("brick must hold (Bx, By, Bz)")
+        p.brick = (ctypes.c_int32 * 3)(*[int(b) for b in brick])
+    return p, keep
 
 
 class _SolveOpts(ctypes.Structure):
@@ -115,6 +138,9 @@ def lib():
         L.mobius_force.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(_SolveOpts), ctypes.POINTER(_SolveInfo), vp]
         L.mobius_force_lie.argtypes = [vp, vp, vp, vp, vp]
+        L.mobius_tune_brick.argtypes = [ctypes.POINTER(_Params), vp, i32, i32, ctypes.POINTER(_BrickTrial),
+                                        i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                        ctypes.POINTER(ctypes.c_double), vp]
         L.mobius_tune.argtypes = [vp, i32, i32, ctypes.POINTER(_TuneResult), vp]
         L.mobius_set_tuning.argtypes = [vp, ctypes.POINTER(_TuneResult)]
         L.mobius_last_error.restype = ctypes.c_char_p
@@ -154,9 +180,10 @@ def _require_cuda(t, dtype=None, name="tensor"):
 class Operator:
     """A red/black Moebius operator on one lattice (owns the packed links)."""
 
-    def __init__(self, dims, Ls, M5, mf, b5, c5, links, mu=0.0, b5s=None, c5s=None):
+    def __init__(self, dims, Ls, M5, mf, b5, c5, links, mu=0.0, b5s=None, c5s=None, brick=None):
         """b5s, c5s: optional per-slice coefficients (Ls values each) of the
-        general operator; they replace b5, c5."""
+        general operator; they replace b5, c5.  brick: (Bx, By, Bz) of the
+        site order (None: the library's choice; see tune_brick)."""
         import torch
         _require_cuda(links, torch.complex128, "links")
         Lx, Ly, Lz, Lt = dims
@@ -165,15 +192,8 @@ class Operator:
         self.dims = tuple(int(d) for d in dims)
         self.Ls = int(Ls)
         self.params = dict(M5=M5, mf=mf, b5=b5, c5=c5, mu=mu, b5s=b5s, c5s=c5s)
-        p = _Params((ctypes.c_int32 * 4)(*self.dims), self.Ls, M5, mf, b5, c5, mu)
-        keep = []
-        for name, v in (("b5s", b5s), ("c5s", c5s)):
-            if v is not None:
-                if len(v) != self.Ls:
-                    raise MobiusError(f"{name} must hold Ls = {self.Ls} values")
-                a = (ctypes.c_double * self.Ls)(*[float(x) for x in v])
-                keep.append(a)
-                setattr(p, name, ctypes.cast(a, ctypes.POINTER(ctypes.c_double)))
+        self.brick = None if brick is None else tuple(int(b) for b in brick)
+        p, keep = _make_params(self.dims, self.Ls, M5, mf, b5, c5, mu, b5s, c5s, brick)
         h = ctypes.c_void_p()
         _check(lib().mobius_create(ctypes.byref(h), ctypes.byref(p), _ptr(links), _stream()))
         self._h = h
@@ -421,6 +441,23 @@ class Operator:
 def _info(i):
     return SolveInfo(i.iters, i.dirac_apps, i.reliable_updates, i.status, i.true_resid,
                      i.schur_resid, i.seconds, i.algo_bytes, i.flops, i.kappa, i.err_bound)
+
+
+def tune_brick(dims, Ls, M5, mf, b5, c5, links, prec=F16, reps=10, mu=0.0, b5s=None, c5s=None):
+    """Time the tuned hop for candidate site-order bricks (mobius_tune_brick) and
+    return (brick, hop_us, trials): the brick to pass to Operator, its hop time
+    and every candidate as ((Bx, By, Bz), hop_us) in the order timed."""
+    import torch
+    _require_cuda(links, torch.complex128, "links")
+    p, keep = _make_params(dims, Ls, M5, mf, b5, c5, mu, b5s, c5s)
+    trials = (_BrickTrial * 12)()
+    n = ctypes.c_int32()
+    brick = (ctypes.c_int32 * 3)()
+    us = ctypes.c_double()
+    _check(lib().mobius_tune_brick(ctypes.byref(p), _ptr(links), int(prec), int(reps), trials, 12,
+                                   ctypes.byref(n), brick, ctypes.byref(us), _stream()))
+    return (tuple(brick), us.value,
+            [(tuple(trials[i].brick), trials[i].hop_us) for i in range(n.value)])
 
 
 def batch_solve(ops, srcs, tol=1e-10, maxiter=10000, inner_prec=F64, reliable_delta=0.0,

@@ -54,7 +54,8 @@ def run(args):
     w = inputs.WORKLOADS[args.workload]
     prec = PREC[args.prec]
     U, eta = inputs.workload_fields(w)
-    op = mobius.Operator(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, torch.from_numpy(U).cuda())
+    brick = None if not args.brick else tuple(int(b) for b in args.brick.split(","))
+    op = mobius.Operator(w.dims, w.Ls, w.M5, w.mf, w.b5, w.c5, torch.from_numpy(U).cuda(), brick=brick)
     tuned = op.tune(prec)
     even, odd = op.pack(torch.from_numpy(eta).cuda(), prec)
     oe, oo = op.new_field(prec), op.new_field(prec)
@@ -72,6 +73,7 @@ def run(args):
     torch.cuda.synchronize()
     nbytes = 2 * op.field_bytes(prec) + 72 * (op.V // 2) * {0: 16, 1: 8, 2: 4}[prec]
     print(json.dumps({"workload": w.name, "prec": args.prec, "tuning": tuned,
+                      "brick": None if brick is None else list(brick),
                       "algo_bytes_per_launch": nbytes, "reps": args.reps}), flush=True)
 
 
@@ -150,7 +152,10 @@ def summarize(args):
         with open(args.run_log) as f:
             for line in f:
                 if line.startswith("{") and '"tuning"' in line:
-                    out["tuning"] = {k: v for k, v in json.loads(line)["tuning"].items() if k != "hop_us"}
+                    rec = json.loads(line)
+                    out["tuning"] = {k: v for k, v in rec["tuning"].items() if k != "hop_us"}
+                    # site-order brick of the run (None: the library's automatic choice)
+                    out["brick"] = rec.get("brick")
     traffic = {}
     if args.fetch and args.write:  # cross-check: FETCH_SIZE / WRITE_SIZE scaled by the copy
         for counter, d in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
@@ -250,6 +255,7 @@ def main():
     r.add_argument("--reps", type=int, default=20)
     r.add_argument("--warm", type=int, default=50, help="untimed launches per parity before the copy")
     r.add_argument("--workload", default="mobius_24x24x24x64_ls12")
+    r.add_argument("--brick", default="", help="site-order brick bx,by,bz (default: automatic)")
     s = sub.add_parser("summarize")
     s.add_argument("--prec", default="f16", choices=list(PREC))
     s.add_argument("--rdreq", required=True)

@@ -62,3 +62,21 @@ def test_error_paths_without_gpu():
     # null context
     assert L.mobius_dslash(None, 0, 0, 0, ctypes.c_void_p(1), ctypes.c_void_p(2), 1, None) == -22
     assert L.mobius_field_bytes(None, 0) == -1
+
+
+def test_brick_validation_without_gpu():
+    """A site-order brick with a side outside 1..L is rejected before any device
+    work, by mobius_create and by the layout tuner's own checks."""
+    from paper_1206_5214_amd import mobius
+    L = mobius.lib()
+    h = ctypes.c_void_p()
+    for brick in ((0, 2, 2), (2, 2, 5), (-2, 2, 2)):
+        p, _ = mobius._make_params((4, 4, 4, 4), 8, 1.8, 0.01, 1.0, 0.0, brick=brick)
+        assert L.mobius_create(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(1), None) == -22
+        assert b"brick" in L.mobius_last_error()
+    p, _ = mobius._make_params((4, 3, 4, 4), 8, 1.8, 0.01, 1.0, 0.0)
+    b = (ctypes.c_int32 * 3)()
+    assert L.mobius_tune_brick(ctypes.byref(p), ctypes.c_void_p(1), 2, 1, None, 0, None, b, None, None) == -22
+    p, _ = mobius._make_params((4, 4, 4, 4), 8, 1.8, 0.01, 1.0, 0.0)
+    assert L.mobius_tune_brick(ctypes.byref(p), ctypes.c_void_p(1), 7, 1, None, 0, None, b, None, None) == -22
+    assert L.mobius_tune_brick(ctypes.byref(p), None, 2, 1, None, 0, None, b, None, None) == -22

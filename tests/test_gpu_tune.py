@@ -128,3 +128,43 @@ def test_every_launch_variant_vs_oracle(torch_cuda, orc, prec):
     with pytest.raises(mobius.MobiusError):
         op.set_tuning(prec, 2, 1, 0, 0, 2)
     op.close()
+
+
+def test_tune_brick_and_explicit_site_order(torch_cuda, monkeypatch):
+    """The layout tuner (mobius_tune_brick) times candidate site-order bricks,
+    the automatic one first, and returns one of them; an operator created with
+    an explicit brick, including one that does not divide the lattice, gives
+    per site exactly the hops of the automatic order in every precision (the
+    order only moves sites between workgroups) and solves to the same accuracy."""
+    from paper_1206_5214_amd import inputs, mobius
+    torch = torch_cuda
+    monkeypatch.delenv("MOBIUS_TUNE_CACHE", raising=False)
+    dims, Ls = (8, 8, 4, 4), 8
+    rng = np.random.default_rng(21)
+    U = torch.from_numpy(inputs.random_links(dims, 0.5, rng)).cuda()
+    psi = torch.from_numpy(inputs.gaussian_spinor(dims, Ls, rng)).cuda()
+    args = (dims, Ls, 1.8, 0.05, 1.5, 0.5)
+    brick, us, trials = mobius.tune_brick(*args, U, prec=mobius.F16, reps=2)
+    print(f"brick {brick} {us:.1f} us; trials {trials}", flush=True)
+    assert 2 <= len(trials) <= 12 and all(t[1] > 0 for t in trials)
+    assert brick in [t[0] for t in trials]
+    for b, _ in trials[1:]:
+        assert all(1 <= b[k] <= dims[k] and dims[k] % b[k] == 0 for k in range(3))
+    auto_us = trials[0][1]
+    assert (brick == trials[0][0] and us == auto_us) or us < 0.97 * auto_us
+    op0 = mobius.Operator(*args, U)
+    for b in ((2, 2, 2), (4, 8, 2), (6, 8, 4), brick):
+        op1 = mobius.Operator(*args, U, brick=b)
+        for prec in (mobius.F64, mobius.F32, mobius.F16):
+            outs = []
+            for op in (op0, op1):
+                e, o = op.pack(psi, prec)
+                zero = op.new_field(prec)
+                outs.append([op.unpack(op.dslash(o, 0, prec), zero, prec),
+                             op.unpack(zero, op.dslash(e, 1, prec, dag=True), prec)])
+            for a, c in zip(*outs):
+                assert torch.equal(a, c), (b, prec)
+        sol, info, rc = op1.solve(psi, tol=1e-10, inner_prec=mobius.F16)
+        assert rc == mobius.OK and info[0].true_resid <= 1e-10
+        op1.close()
+    op0.close()
