@@ -121,7 +121,10 @@ def counters_for(kernel_key, tuning, brick=None, auto_brick=None):
     with the launch parameters this run's tuner chose and the same site-order
     brick (brick None or equal to auto_brick: the automatic one)."""
     from paper_1206_5214_amd.profile_hop import hop_sources_sha256
-    path = os.path.join(ROOT, "profiles", f"{kernel_key}.json")
+    used = None if brick is None or list(brick) == list(auto_brick or []) else list(brick)
+    # profiles/<key>.json: the automatic site order; <key>_brick<bx>x<by>x<bz>.json: another
+    name = kernel_key if used is None else f"{kernel_key}_brick{'x'.join(str(b) for b in used)}"
+    path = os.path.join(ROOT, "profiles", f"{name}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -131,7 +134,6 @@ def counters_for(kernel_key, tuning, brick=None, auto_brick=None):
     want = {k: v for k, v in tuning.items() if k != "hop_us"}
     if rec.get("tuning") is not None and rec["tuning"] != want:
         return None
-    used = None if brick is None or list(brick) == list(auto_brick or []) else list(brick)
     rb = rec.get("brick")
     if rb is not None and list(rb) == list(auto_brick or []):
         rb = None
