@@ -904,7 +904,9 @@ extern "C" int mobius_tune_brick(const mobius_params *p, const void *links_c128,
     if (p->Ls < 2 || p->Ls > 64) return fail(MOBIUS_EINVAL, "Ls must be in [2, 64]");
     int base[3];
     choose_brick(p->L, p->Ls, base);
-    // candidates: each side halved, kept or doubled where it still divides the lattice
+    // candidates: each side kept, halved or doubled (side k of candidate i
+    // by the k-th base-3 digit of i; i = 0 is the automatic brick) where it
+    // still divides the lattice
     struct Cand {
         int b[3];
         double dist, surf;
