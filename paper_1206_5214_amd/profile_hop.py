@@ -231,6 +231,43 @@ def summarize(args):
     print(json.dumps(out, indent=1))
 
 
+SQ_PASSES = (("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY", "SQ_WAIT_ANY",
+              "SQ_ACTIVE_INST_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_VALU"),
+             ("SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_SALU", "SQ_ACTIVE_INST_LDS",
+              "SQ_LDS_BANK_CONFLICT", "SQ_INSTS_VMEM_WR", "TCC_HIT_sum", "TCC_MISS_sum"))
+
+
+def sq_md(args):
+    """Per-launch shader-sequencer counters of the metered hop (two --pmc
+    passes of `run`) as per-wave instruction counts and cycle ratios."""
+    v = {}
+    for d, counters in zip(args.passes, SQ_PASSES):
+        for c in counters:
+            hop = _counter_per_kernel(d, c)[HOP_NAME]
+            v[c] = sum(hop) / len(hop)
+    waves = v["SQ_WAVES"]
+    lines = [f"# Shader-sequencer counters of the hop kernel, {args.prec}, 24^3x64 Ls=12", "",
+             "Commands (repository root, one MI355X, `export TMPDIR=/tmp`):", "", "```"]
+    lines += (args.command or []) + ["```", "",
+              "| counter | per launch | per wave |", "|---|---:|---:|"]
+    for c in SQ_PASSES[0] + SQ_PASSES[1]:
+        lines.append(f"| {c} | {v[c]:.4g} | {v[c] / waves:.4g} |")
+    hit = v["TCC_HIT_sum"] / (v["TCC_HIT_sum"] + v["TCC_MISS_sum"])
+    lines += ["", "Ratios (the SQ cycle counters share one unit, so their ratios are exact):", "",
+              f"- waiting on a dependency (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES): "
+              f"{v['SQ_WAIT_INST_ANY'] / v['SQ_WAVE_CYCLES']:.3f} of the waves' lifetime",
+              f"- waiting on anything (SQ_WAIT_ANY / SQ_WAVE_CYCLES): {v['SQ_WAIT_ANY'] / v['SQ_WAVE_CYCLES']:.3f}",
+              f"- issuing VALU (SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES): "
+              f"{v['SQ_ACTIVE_INST_VALU'] / v['SQ_WAVE_CYCLES']:.3f}",
+              f"- LDS bank conflicts per active LDS cycle: "
+              f"{v['SQ_LDS_BANK_CONFLICT'] / max(v['SQ_ACTIVE_INST_LDS'], 1):.3f}",
+              f"- L2 hit rate (TCC_HIT / (TCC_HIT + TCC_MISS)): {hit:.3f}",
+              f"- {waves:.0f} waves per launch"]
+    with open(args.out, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def stats_md(args):
     """Markdown table of a rocprofv3 --kernel-trace --stats run."""
     rows = _csv_rows(args.stats, "*kernel_stats.csv")
@@ -273,8 +310,13 @@ def main():
     t.add_argument("--out", required=True)
     t.add_argument("--top", type=int, default=20)
     t.add_argument("--command", action="append")
+    q = sub.add_parser("sq")
+    q.add_argument("--prec", default="f16", choices=list(PREC))
+    q.add_argument("--passes", nargs=2, required=True, help="the two --pmc run directories")
+    q.add_argument("--out", required=True)
+    q.add_argument("--command", action="append")
     args = ap.parse_args()
-    {"run": run, "summarize": summarize, "stats": stats_md}[args.cmd](args)
+    {"run": run, "summarize": summarize, "stats": stats_md, "sq": sq_md}[args.cmd](args)
 
 
 if __name__ == "__main__":
